@@ -1,0 +1,98 @@
+"""Write the stored expected values for the R-MAT configurations.
+
+Every value here comes from the CPU oracle (``oracle/``) run on graphs from
+the seeded input generator (``graphgen``); nothing is taken from the GPU
+library.  Usage::
+
+    python tests/golden/make_golden.py 10 20        # scales to (re)write
+    python tests/golden/make_golden.py --batch       # per-graph batch counts
+
+Output: ``tests/golden/rmat_s<scale>.json`` with n, m, |H|, T (Alg. 1 count,
+direct-address mode), the edge-iterator count, level statistics and SHA-256
+digests of the level array and of the horizontal-edge list, plus
+``batch_mix.json`` with every graph's (n, m, |H|, T).
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import graphgen  # noqa: E402
+import oracle  # noqa: E402
+
+
+def digest(*arrays) -> str:
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+def rmat_golden(scale: int, with_edge_count: bool = True) -> dict:
+    t0 = time.time()
+    g = graphgen.rmat(scale, 16, seed=1)
+    c = oracle.from_graph(g)
+    t1 = time.time()
+    lv = oracle.bfs_levels(c)
+    hu, hv = oracle.cover_edges(c, lv.levels)
+    t2 = time.time()
+    res = oracle.count(c, lv.levels, 0)
+    t3 = time.time()
+    out = dict(
+        config=f"R-MAT scale {scale}, edge factor 16, (a,b,c,d)=(0.57,0.19,0.19,0.05), seed 1, "
+               "relabelled; root = largest degree (smallest id on ties)",
+        source="CPU oracle (oracle/oracle.c) on graphgen.rmat(scale, 16, seed=1)",
+        scale=scale, n=c.n, m=c.m, nnz=c.nnz, max_degree=int(c.degrees().max()),
+        root=oracle.default_root(c), num_levels=lv.num_levels, num_roots=lv.num_roots,
+        h=int(hu.size), triangles=res.triangles,
+        levels_sha256=digest(lv.levels.astype("<i4")),
+        h_sha256=digest(hu.astype("<i4"), hv.astype("<i4")),
+        csr_sha256=digest(c.row_offsets.astype("<i8"), c.cols.astype("<i4")),
+        oracle_seconds=dict(build=t1 - t0, bfs_and_h=t2 - t1, count=t3 - t2),
+    )
+    if with_edge_count:
+        t4 = time.time()
+        out["edge_iterator_triangles"] = oracle.edge_count(c)
+        out["oracle_seconds"]["edge_iterator"] = time.time() - t4
+    return out
+
+
+def batch_golden() -> dict:
+    specs = graphgen.batch_specs(4096)
+    rows = []
+    t0 = time.time()
+    for i, s in enumerate(specs):
+        c = oracle.from_graph(graphgen.from_spec(s))
+        lv = oracle.bfs_levels(c)
+        hu, _ = oracle.cover_edges(c, lv.levels)
+        T = oracle.count(c, lv.levels, 0).triangles
+        rows.append(dict(i=i, n=c.n, m=c.m, h=int(hu.size), triangles=T,
+                         levels_sha256=digest(lv.levels.astype("<i4"))))
+        if i % 256 == 0:
+            print(f"batch {i}/4096 {time.time() - t0:.1f}s", flush=True)
+    return dict(source="CPU oracle on graphgen.batch_specs(4096)", graphs=rows,
+                oracle_seconds=time.time() - t0)
+
+
+def main(argv):
+    if "--batch" in argv:
+        out = batch_golden()
+        with open(os.path.join(HERE, "batch_mix.json"), "w") as f:
+            json.dump(out, f, indent=1)
+        argv = [a for a in argv if a != "--batch"]
+    for a in argv:
+        scale = int(a)
+        out = rmat_golden(scale, with_edge_count=scale <= 22)
+        with open(os.path.join(HERE, f"rmat_s{scale}.json"), "w") as f:
+            json.dump(out, f, indent=1)
+        print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
