@@ -1,0 +1,237 @@
+/*
+ * tc.h -- C ABI of libtc, exact triangle counting through cover edges on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Bader, Li, Ganeshan, Gundogdu, Lew, Alvarado Rodriguez, Du,
+ * "Triangle Counting Through Cover-Edges" (arXiv 2210.00389).
+ *   - BFS levels L(v) (Def. 2), one BFS per component in the scan order of
+ *     Alg. 1;
+ *   - the horizontal edges H = {(u,v) : L(u) = L(v), u < v}, a cover-edge set
+ *     (Def. 1, Lemma 1, Thm. 1);
+ *   - T = sum over (u,v) in H of |{w in N(u) ∩ N(v) : L(w) != L(u) or w > v}|
+ *     (Alg. 1, counting test; exact by Lemma 2 and Thm. 2).
+ *
+ * Conventions for every entry point:
+ *   - Graphs are simple and undirected, in CSR form: row_offsets is int64
+ *     [n+1] with row_offsets[0] = 0, cols is int32 [nnz], every row strictly
+ *     ascending, no self loops, and (u,v) present iff (v,u) present.  nnz is
+ *     twice the edge count m.  Vertex ids are the integers 0..n-1, and "u < v"
+ *     in the method is integer order on these ids.
+ *   - Pointers marked "device" are HIP device (or managed) memory; "host"
+ *     pointers are ordinary host memory.  The caller owns every buffer; the
+ *     library allocates and frees no memory and keeps no state between calls
+ *     except the thread-local error text and the profiling switch.
+ *   - `ws` is a caller-provided device workspace of at least
+ *     tc_workspace_bytes(op, ...) bytes, 256-byte aligned.  Its contents on
+ *     entry are ignored; on return they are scratch.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *     it in order; device outputs are valid once the stream has been
+ *     synchronised.  Entry points that return a value through a host pointer
+ *     synchronise the stream themselves, as documented per function.
+ *   - Return value: TC_OK (0) or a negative tc_status.  No entry point aborts
+ *     or throws; tc_last_error() gives a thread-local description of the last
+ *     failure.  Structural checks of the input graph (sorted, duplicate-free,
+ *     loop-free, symmetric, ids in range) run only when TC_VALIDATE is set in
+ *     `flags`; without it a non-simple graph gives unspecified counts (never
+ *     an out-of-bounds access as long as ids are in range and offsets are
+ *     monotone).
+ *   - All counts are exact 64-bit integers; results do not depend on the
+ *     scheduling of the GPU or on the tuning parameters.
+ */
+#ifndef TC_H_
+#define TC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* tc_stream_t; /* a hipStream_t */
+
+typedef enum tc_status {
+  TC_OK = 0,
+  TC_ERR_INVALID_ARG = -1,   /* null pointer, negative size, bad root, ... */
+  TC_ERR_WORKSPACE = -2,     /* ws_bytes smaller than tc_workspace_bytes() */
+  TC_ERR_NOT_SORTED = -3,    /* a row is not ascending (TC_VALIDATE) */
+  TC_ERR_DUPLICATE = -4,     /* a row repeats an id (TC_VALIDATE) */
+  TC_ERR_SELF_LOOP = -5,     /* u in N(u) (TC_VALIDATE) */
+  TC_ERR_NOT_SYMMETRIC = -6, /* v in N(u) but u not in N(v) (TC_VALIDATE) */
+  TC_ERR_OUT_OF_RANGE = -7,  /* an id outside [0, n) */
+  TC_ERR_TOO_LARGE = -8,     /* n or nnz beyond the int32-id / int64 limits */
+  TC_ERR_HIP = -9,           /* a HIP runtime call failed */
+  TC_ERR_BAD_OFFSETS = -10   /* row_offsets not monotone or not from 0 to nnz */
+} tc_status;
+
+/* flags */
+#define TC_VALIDATE 1u       /* check the CSR structure before counting */
+#define TC_PER_VERTEX 2u     /* tc_count: also fill per_vertex */
+
+/* Workspace query operations. */
+typedef enum tc_op {
+  TC_OP_BUILD_CSR = 1,
+  TC_OP_BFS_LEVELS = 2,
+  TC_OP_COVER_EDGES = 3,
+  TC_OP_COUNT = 4,
+  TC_OP_COUNT_BATCH = 5,
+  TC_OP_EDGE_BASELINE = 6,
+  TC_OP_VALIDATE = 7
+} tc_op;
+
+/* A graph in CSR form (all pointers device). */
+typedef struct tc_csr {
+  int64_t n;                  /* vertices, 0 <= n <= 2^31 - 1 */
+  int64_t nnz;                /* directed entries = 2 m */
+  const int64_t* row_offsets; /* [n + 1] */
+  const int32_t* cols;        /* [nnz] */
+} tc_csr;
+
+/* Many independent graphs side by side (all pointers device).  Graph g owns
+ * the vertices vbase[g] .. vbase[g+1]-1 of the concatenated vertex range;
+ * row_offsets indexes the concatenated cols array; cols hold LOCAL ids
+ * (0 .. n_g - 1) of the same graph. */
+typedef struct tc_batch {
+  int32_t num_graphs;         /* G >= 0 */
+  int64_t total_vertices;     /* vbase[G] */
+  int64_t total_nnz;          /* row_offsets[total_vertices] */
+  const int64_t* vbase;       /* [G + 1], vbase[0] = 0 */
+  const int64_t* row_offsets; /* [total_vertices + 1] */
+  const int32_t* cols;        /* [total_nnz] */
+  int32_t max_graph_vertices; /* max_g n_g (host value, bounds the per-graph
+                                 on-chip state); must be <= TC_BATCH_MAX_N */
+} tc_batch;
+
+#define TC_BATCH_MAX_N 65536
+
+/* Tuning knobs; a NULL tc_tuning* means the compiled-in defaults. */
+typedef struct tc_tuning {
+  int32_t light_probe_max;    /* probe lists up to this length use the
+                                 per-task merge path (default 32) */
+  int32_t heavy_chunk;        /* descriptors per heavy work item (1024) */
+  int32_t batch_block;        /* threads per block of the batched kernel (256) */
+  int32_t batch_blocks_per_cu;/* resident blocks per CU for the batched
+                                 persistent launch (0 = occupancy query) */
+  int32_t reserved[4];
+} tc_tuning;
+
+/* Bytes of workspace `op` needs for a graph with n vertices and nnz entries
+ * (for TC_OP_BUILD_CSR, nnz = number of input pairs; for TC_OP_COUNT_BATCH,
+ * n and nnz are the batch totals and num_graphs its graph count).  Returns 0
+ * for an unknown op or negative sizes. */
+size_t tc_workspace_bytes(int op, int64_t n, int64_t nnz, int32_t num_graphs);
+
+/* Builds a simple undirected CSR from raw pairs (data layout of the input of
+ * Sec. III: CSR with both orientations).  Pairs (src[i], dst[i]) with
+ * src[i] == dst[i] are dropped; every other pair contributes both (s,d) and
+ * (d,s); repeats are merged; rows come out sorted ascending.
+ *   n                vertex count (ids must lie in [0, n); else
+ *                    TC_ERR_OUT_OF_RANGE)
+ *   num_pairs        length of src / dst (device int32)
+ *   row_offsets      device int64 [n + 1] (output)
+ *   cols             device int32, capacity 2 * num_pairs (output)
+ *   nnz_out          host int64 (output); the call synchronises `stream`.
+ */
+int tc_build_csr(int64_t n, int64_t num_pairs, const int32_t* src, const int32_t* dst,
+                 int64_t* row_offsets, int32_t* cols, int64_t* nnz_out, void* ws,
+                 size_t ws_bytes, tc_stream_t stream);
+
+/* Checks the CSR structure (offsets monotone from 0 to nnz, ids in range,
+ * rows strictly ascending, no loops, symmetric).  Returns TC_OK or the first
+ * violated property's status.  Synchronises `stream`. */
+int tc_validate_csr(const tc_csr* g, void* ws, size_t ws_bytes, tc_stream_t stream);
+
+/* BFS levels as in Alg. 1 (Def. 2): a BFS from `root` (root < 0: the vertex
+ * of largest degree, smallest id on ties), then, in increasing id order,
+ * one more BFS from every vertex not yet reached, so each further component
+ * is levelled from its smallest id.  Isolated vertices get level 0.
+ *   levels       device int32 [n] (output)
+ *   num_levels   host int32 (nullable): the largest level count of any one
+ *                BFS (max level + 1; 0 for n = 0)
+ * Synchronises `stream` once per BFS level (frontier sizes are read back). */
+int tc_bfs_levels(const tc_csr* g, int64_t root, uint32_t flags, int32_t* levels,
+                  int32_t* num_levels, void* ws, size_t ws_bytes, tc_stream_t stream);
+
+/* The horizontal edges of a given level function (Alg. 1, edge selection;
+ * Thm. 1): every (u, v) with u < v and levels[u] == levels[v], in
+ * lexicographic order.  `levels` may be any int32 array (not only BFS
+ * levels).
+ *   h_u, h_v     device int32, capacity nnz / 2 each (output)
+ *   h_count      device int64 [1] (output): |H|
+ * Asynchronous. */
+int tc_cover_edges(const tc_csr* g, const int32_t* levels, int32_t* h_u, int32_t* h_v,
+                   int64_t* h_count, void* ws, size_t ws_bytes, tc_stream_t stream);
+
+/* Cover-edge triangle count (Alg. 1): levels as in tc_bfs_levels, H, then
+ * the count over H with the paper's test.
+ *   triangles    device int64 [1] (output): T
+ *   h_count      device int64 [1] (nullable output): |H|
+ *   levels       device int32 [n] (nullable output): the BFS levels used
+ *   per_vertex   device int64 [n] (output iff flags & TC_PER_VERTEX): the
+ *                number of triangles through each vertex (sums to 3T)
+ * Synchronises `stream` once per BFS level; the count itself is
+ * asynchronous. */
+int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles,
+             int64_t* h_count, int32_t* levels, int64_t* per_vertex, void* ws,
+             size_t ws_bytes, tc_stream_t stream);
+
+/* Comparator: the plain direction-oriented edge iterator (related-work
+ * section: every edge (u, v) with u < v counts the w in N(u) ∩ N(v) with
+ * w > v), on the same intersection kernels as tc_count.
+ *   triangles    device int64 [1] (output)
+ * Asynchronous. */
+int tc_count_edge_baseline(const tc_csr* g, uint32_t flags, int64_t* triangles, void* ws,
+                           size_t ws_bytes, tc_stream_t stream);
+
+/* Cover-edge counts of many small graphs in one persistent launch: per graph,
+ * the levels of tc_bfs_levels (root = largest degree), H and T.
+ *   triangles    device int64 [G] (output)
+ *   h_count      device int64 [G] (nullable output)
+ *   levels       device int32 [total_vertices] (nullable output)
+ * Issues no host synchronisation (capturable in a hipGraph). */
+int tc_count_batch(const tc_batch* b, const tc_tuning* tuning, uint32_t flags,
+                   int64_t* triangles, int64_t* h_count, int32_t* levels, void* ws,
+                   size_t ws_bytes, tc_stream_t stream);
+
+/* Text of a status code (static storage). */
+const char* tc_status_string(int status);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* tc_last_error(void);
+
+/* Profiling: when enabled, every entry point records a HIP event before and
+ * after each of its stages on `stream`; tc_profile_read synchronises the
+ * stream of the last call and returns, for the calling thread's last call,
+ * the number of stages and for each its name and elapsed milliseconds. */
+#define TC_PROFILE_MAX_STAGES 32
+typedef struct tc_profile {
+  int32_t num_stages;
+  char names[TC_PROFILE_MAX_STAGES][24];
+  float ms[TC_PROFILE_MAX_STAGES];
+} tc_profile;
+
+void tc_profile_enable(int on);
+int tc_profile_read(tc_profile* out);
+
+/* Work statistics of the calling thread's last tc_count /
+ * tc_count_edge_baseline call (read back from the workspace; synchronises
+ * `stream`).  Element counts are exact and drive the algorithmic-byte figures
+ * of the roofline. */
+typedef struct tc_stats {
+  int64_t n, nnz;
+  int64_t h;               /* |H| (baseline: number of edges u < v) */
+  int64_t num_levels;      /* BFS level count (baseline: 0) */
+  int64_t stream_elems;    /* list elements streamed by the intersections */
+  int64_t light_tasks;     /* tasks on the per-task merge path */
+  int64_t heavy_items;     /* work items of the anchored (LDS hash) path */
+  int64_t heavy_desc;      /* descriptors processed on the anchored path */
+  int64_t reserved[8];
+} tc_stats;
+
+int tc_read_stats(const void* ws, tc_stats* out, tc_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_H_ */

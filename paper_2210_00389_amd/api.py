@@ -1,0 +1,233 @@
+"""Torch-facing wrappers of libtc.
+
+PyTorch provides device memory and streams; every computation is a libtc
+entry point (include/tc.h).  Graphs live on the device as int64 row offsets
+and int32 sorted columns.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+
+class TcError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = L.load()
+        detail = lib.tc_last_error().decode(errors="replace")
+        name = L.STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{where}: {name}: {detail}")
+        self.status = status
+
+
+def _check(rc: int, where: str):
+    if rc != L.TC_OK:
+        raise TcError(rc, where)
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Workspace:
+    """A growable device byte buffer (torch allocation) handed to libtc."""
+
+    def __init__(self, device=None):
+        self.device = torch.device(device or "cuda")
+        self.buf = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        nbytes = max(int(nbytes), 256)
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+_default_ws: dict = {}
+
+
+def default_workspace(device=None) -> Workspace:
+    dev = torch.device(device or "cuda")
+    key = (dev.type, dev.index if dev.index is not None else torch.cuda.current_device())
+    if key not in _default_ws:
+        _default_ws[key] = Workspace(dev)
+    return _default_ws[key]
+
+
+@dataclass
+class Graph:
+    """A simple undirected graph in device CSR form."""
+    n: int
+    row_offsets: torch.Tensor  # int64 [n+1]
+    cols: torch.Tensor         # int32 [nnz]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.cols.numel())
+
+    @property
+    def m(self) -> int:
+        return self.nnz // 2
+
+    def csr(self) -> L.TcCsr:
+        return L.TcCsr(self.n, self.nnz, self.row_offsets.data_ptr() if self.n > 0 else None,
+                       self.cols.data_ptr() if self.nnz > 0 else None)
+
+    def nbytes(self) -> int:
+        return self.row_offsets.numel() * 8 + self.cols.numel() * 4
+
+
+def workspace_bytes(op: int, n: int, nnz: int, num_graphs: int = 0) -> int:
+    return int(L.load().tc_workspace_bytes(op, n, nnz, num_graphs))
+
+
+def build_csr(n: int, src: torch.Tensor, dst: torch.Tensor, ws: Workspace | None = None,
+              stream=None) -> Graph:
+    """Simple undirected CSR from raw device pairs (tc_build_csr)."""
+    lib = L.load()
+    src = src.to(torch.int32).contiguous()
+    dst = dst.to(torch.int32).contiguous()
+    dev = src.device
+    P = int(src.numel())
+    off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    cols = torch.empty(max(2 * P, 1), dtype=torch.int32, device=dev)
+    nnz = ctypes.c_int64(0)
+    need = workspace_bytes(L.OP_BUILD_CSR, n, P)
+    buf = (ws or default_workspace(dev)).get(need)
+    _check(lib.tc_build_csr(n, P, _ptr(src), _ptr(dst), _ptr(off), _ptr(cols), ctypes.byref(nnz),
+                            _ptr(buf), buf.numel(), _stream(stream)), "tc_build_csr")
+    return Graph(n, off, cols[: nnz.value])
+
+
+def from_host_pairs(n: int, src, dst, device="cuda", ws=None, stream=None) -> Graph:
+    s = torch.as_tensor(src, dtype=torch.int32).to(device)
+    d = torch.as_tensor(dst, dtype=torch.int32).to(device)
+    return build_csr(n, s, d, ws, stream)
+
+
+def from_host_csr(n: int, row_offsets, cols, device="cuda") -> Graph:
+    off = torch.as_tensor(row_offsets, dtype=torch.int64).to(device)
+    c = torch.as_tensor(cols, dtype=torch.int32).to(device)
+    return Graph(n, off, c)
+
+
+def validate(g: Graph, ws: Workspace | None = None, stream=None) -> int:
+    """0 if g is a simple undirected CSR, else the negative status."""
+    lib = L.load()
+    buf = (ws or default_workspace(g.cols.device)).get(workspace_bytes(L.OP_VALIDATE, g.n, g.nnz))
+    csr = g.csr()
+    return int(lib.tc_validate_csr(ctypes.byref(csr), _ptr(buf), buf.numel(), _stream(stream)))
+
+
+def bfs_levels(g: Graph, root: int = -1, validate: bool = False, ws: Workspace | None = None,
+               stream=None):
+    """(levels int32 tensor, num_levels) as in Alg. 1 (tc_bfs_levels)."""
+    lib = L.load()
+    levels = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.cols.device)
+    nl = ctypes.c_int32(0)
+    buf = (ws or default_workspace(g.cols.device)).get(workspace_bytes(L.OP_BFS_LEVELS, g.n, g.nnz))
+    csr = g.csr()
+    _check(lib.tc_bfs_levels(ctypes.byref(csr), root, L.TC_VALIDATE if validate else 0, _ptr(levels),
+                             ctypes.byref(nl), _ptr(buf), buf.numel(), _stream(stream)), "tc_bfs_levels")
+    return levels[: g.n], int(nl.value)
+
+
+def cover_edges(g: Graph, levels: torch.Tensor, ws: Workspace | None = None, stream=None):
+    """(h_u, h_v): the cover edges of `levels`, lexicographic (tc_cover_edges)."""
+    lib = L.load()
+    dev = g.cols.device
+    cap = max(g.nnz // 2, 1)
+    hu = torch.empty(cap, dtype=torch.int32, device=dev)
+    hv = torch.empty(cap, dtype=torch.int32, device=dev)
+    hc = torch.zeros(1, dtype=torch.int64, device=dev)
+    levels = levels.to(torch.int32).contiguous()
+    buf = (ws or default_workspace(dev)).get(workspace_bytes(L.OP_COVER_EDGES, g.n, g.nnz))
+    csr = g.csr()
+    _check(lib.tc_cover_edges(ctypes.byref(csr), _ptr(levels), _ptr(hu), _ptr(hv), _ptr(hc), _ptr(buf),
+                              buf.numel(), _stream(stream)), "tc_cover_edges")
+    h = int(hc.item())
+    return hu[:h], hv[:h]
+
+
+@dataclass
+class CountResult:
+    triangles: torch.Tensor        # int64 [1], device
+    h_count: torch.Tensor          # int64 [1], device
+    levels: torch.Tensor | None
+    per_vertex: torch.Tensor | None
+
+    @property
+    def T(self) -> int:
+        return int(self.triangles.item())
+
+    @property
+    def h(self) -> int:
+        return int(self.h_count.item())
+
+
+def count(g: Graph, root: int = -1, per_vertex: bool = False, validate: bool = False,
+          return_levels: bool = False, ws: Workspace | None = None, stream=None,
+          out: CountResult | None = None) -> CountResult:
+    """Cover-edge triangle count (tc_count); results stay on the device."""
+    lib = L.load()
+    dev = g.cols.device
+    res = out or CountResult(torch.zeros(1, dtype=torch.int64, device=dev),
+                             torch.zeros(1, dtype=torch.int64, device=dev),
+                             torch.empty(max(g.n, 1), dtype=torch.int32, device=dev) if return_levels else None,
+                             torch.empty(max(g.n, 1), dtype=torch.int64, device=dev) if per_vertex else None)
+    flags = (L.TC_VALIDATE if validate else 0) | (L.TC_PER_VERTEX if per_vertex else 0)
+    buf = (ws or default_workspace(dev)).get(workspace_bytes(L.OP_COUNT, g.n, g.nnz))
+    csr = g.csr()
+    _check(lib.tc_count(ctypes.byref(csr), root, flags, _ptr(res.triangles), _ptr(res.h_count),
+                        _ptr(res.levels), _ptr(res.per_vertex), _ptr(buf), buf.numel(), _stream(stream)),
+           "tc_count")
+    if res.levels is not None:
+        res.levels = res.levels[: g.n]
+    if res.per_vertex is not None:
+        res.per_vertex = res.per_vertex[: g.n]
+    return res
+
+
+def count_edge_baseline(g: Graph, validate: bool = False, ws: Workspace | None = None, stream=None,
+                        out: torch.Tensor | None = None) -> torch.Tensor:
+    """Plain direction-oriented edge-iterator count (tc_count_edge_baseline)."""
+    lib = L.load()
+    dev = g.cols.device
+    t = out if out is not None else torch.zeros(1, dtype=torch.int64, device=dev)
+    buf = (ws or default_workspace(dev)).get(workspace_bytes(L.OP_EDGE_BASELINE, g.n, g.nnz))
+    csr = g.csr()
+    _check(lib.tc_count_edge_baseline(ctypes.byref(csr), L.TC_VALIDATE if validate else 0, _ptr(t),
+                                      _ptr(buf), buf.numel(), _stream(stream)), "tc_count_edge_baseline")
+    return t
+
+
+def read_stats(ws: Workspace | None = None, device=None, stream=None) -> dict:
+    """Work statistics of the last tc_count / tc_count_edge_baseline call
+    that used this workspace."""
+    lib = L.load()
+    w = ws or default_workspace(device)
+    st = L.TcStats()
+    _check(lib.tc_read_stats(_ptr(w.buf), ctypes.byref(st), _stream(stream)), "tc_read_stats")
+    return {k: int(getattr(st, k)) for k in ("n", "nnz", "h", "num_levels", "stream_elems", "light_tasks",
+                                              "heavy_items", "heavy_desc")}
+
+
+def profile_enable(on: bool = True):
+    L.load().tc_profile_enable(1 if on else 0)
+
+
+def profile_read() -> list:
+    """[(stage name, ms)] of the calling thread's last libtc call."""
+    lib = L.load()
+    p = L.TcProfile()
+    _check(lib.tc_profile_read(ctypes.byref(p)), "tc_profile_read")
+    return [(bytes(p.names[i]).split(b"\0")[0].decode(), float(p.ms[i])) for i in range(p.num_stages)]

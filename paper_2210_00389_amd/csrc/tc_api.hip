@@ -1,0 +1,303 @@
+// tc_api.hip -- the C ABI declared in include/tc.h: argument checks,
+// workspace carving, stage sequencing.  No device memory is allocated here.
+#include <stdint.h>
+#include <string.h>
+
+#include "tc_internal.h"
+
+using namespace tc;
+
+namespace {
+
+constexpr int64_t kMaxN = 0x7FFFFFFFLL;
+
+int check_csr(const tc_csr* g, const char* fn) {
+  if (!g) return fail(TC_ERR_INVALID_ARG, "%s: graph is NULL", fn);
+  if (g->n < 0 || g->nnz < 0) return fail(TC_ERR_INVALID_ARG, "%s: negative n or nnz", fn);
+  if (g->n > kMaxN) return fail(TC_ERR_TOO_LARGE, "%s: n = %lld exceeds 2^31 - 1", fn, (long long)g->n);
+  if (g->n > 0 && !g->row_offsets) return fail(TC_ERR_INVALID_ARG, "%s: row_offsets is NULL", fn);
+  if (g->nnz > 0 && !g->cols) return fail(TC_ERR_INVALID_ARG, "%s: cols is NULL", fn);
+  if (g->n == 0 && g->nnz != 0) return fail(TC_ERR_INVALID_ARG, "%s: nnz > 0 with n = 0", fn);
+  return TC_OK;
+}
+
+int check_ws(void* ws, size_t ws_bytes, size_t need, const char* fn) {
+  if (ws_bytes < need)
+    return fail(TC_ERR_WORKSPACE, "%s: workspace of %zu bytes, %zu needed", fn, ws_bytes, need);
+  if (need > 0 && !ws) return fail(TC_ERR_INVALID_ARG, "%s: workspace is NULL", fn);
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(TC_ERR_INVALID_ARG, "%s: workspace not 256-byte aligned", fn);
+  return TC_OK;
+}
+
+// ------------------------------------------------------- workspace plans
+struct CountPlan {
+  int64_t* stats;
+  int32_t* L;
+  char* region;  // BFS first, then layout + count
+  BfsWs bfs;
+  SplitWs split;
+  CountWs count;
+  size_t bytes;
+};
+
+CountPlan plan_count(void* base, int64_t n, int64_t nnz) {
+  CountPlan p;
+  Carver c(base);
+  p.stats = c.take<int64_t>(16);
+  p.L = c.take<int32_t>(n + 1);
+  p.region = c.take<char>(0);
+  const size_t head = c.used();
+  Carver a(p.region);
+  p.bfs = bfs_reserve(a, n);
+  Carver b(p.region);
+  p.split = split_reserve(b, n, nnz);
+  p.count = count_reserve(b, n, nnz);
+  p.count.stats = p.stats;
+  p.bytes = head + (a.used() > b.used() ? a.used() : b.used());
+  return p;
+}
+
+struct BaselinePlan {
+  int64_t* stats;
+  VMeta* meta;
+  CountWs count;
+  size_t bytes;
+};
+
+BaselinePlan plan_baseline(void* base, int64_t n, int64_t nnz) {
+  BaselinePlan p;
+  Carver c(base);
+  p.stats = c.take<int64_t>(16);
+  p.meta = c.take<VMeta>(n + 1);
+  p.count = count_reserve(c, n, nnz);
+  p.count.stats = p.stats;
+  p.bytes = c.used();
+  return p;
+}
+
+struct CoverPlan {
+  SplitWs split;
+  int64_t* h_off;
+  char* hscratch;
+  size_t bytes;
+};
+
+CoverPlan plan_cover(void* base, int64_t n, int64_t nnz) {
+  CoverPlan p;
+  Carver c(base);
+  p.split = split_reserve(c, n, nnz);
+  p.h_off = c.take<int64_t>(n + 2);
+  p.hscratch = c.take<char>(scan_ws_bytes(n + 1) + (n + 1) * sizeof(int32_t) + 512);
+  p.bytes = c.used();
+  return p;
+}
+
+size_t bfs_bytes(int64_t n) {
+  Carver c(nullptr);
+  bfs_reserve(c, n);
+  return c.used();
+}
+
+__global__ void stats_kernel(int64_t* stats, int64_t n, int64_t nnz, int64_t levels) {
+  stats[0] = n;
+  stats[1] = nnz;
+  stats[3] = levels;
+}
+
+int maybe_validate(const tc_csr* g, uint32_t flags, void* ws, hipStream_t s) {
+  if (!(flags & TC_VALIDATE)) return TC_OK;
+  return validate_run(g, ws, s);
+}
+
+struct CallScope {
+  explicit CallScope(hipStream_t s) { prof_begin_call(s); }
+  ~CallScope() { prof_end_call(); }
+};
+
+}  // namespace
+
+extern "C" {
+
+size_t tc_workspace_bytes(int op, int64_t n, int64_t nnz, int32_t num_graphs) {
+  if (n < 0 || nnz < 0 || num_graphs < 0) return 0;
+  size_t b = 0;
+  switch (op) {
+    case TC_OP_BUILD_CSR: b = build_ws_bytes(n, nnz); break;
+    case TC_OP_BFS_LEVELS: b = bfs_bytes(n); break;
+    case TC_OP_COVER_EDGES: b = plan_cover(nullptr, n, nnz).bytes; break;
+    case TC_OP_COUNT: b = plan_count(nullptr, n, nnz).bytes; break;
+    case TC_OP_COUNT_BATCH: b = batch_ws_bytes(n, nnz, num_graphs); break;
+    case TC_OP_EDGE_BASELINE: b = plan_baseline(nullptr, n, nnz).bytes; break;
+    case TC_OP_VALIDATE: b = validate_ws_bytes(n, nnz); break;
+    default: return 0;
+  }
+  const size_t v = validate_ws_bytes(n, nnz);
+  return b > v ? b : v;
+}
+
+int tc_build_csr(int64_t n, int64_t num_pairs, const int32_t* src, const int32_t* dst, int64_t* row_offsets,
+                 int32_t* cols, int64_t* nnz_out, void* ws, size_t ws_bytes, tc_stream_t stream) {
+  if (n < 0 || num_pairs < 0) return fail(TC_ERR_INVALID_ARG, "tc_build_csr: negative size");
+  if (n > kMaxN) return fail(TC_ERR_TOO_LARGE, "tc_build_csr: n exceeds 2^31 - 1");
+  if (!row_offsets || !nnz_out) return fail(TC_ERR_INVALID_ARG, "tc_build_csr: NULL output");
+  if (num_pairs > 0 && (!src || !dst || !cols)) return fail(TC_ERR_INVALID_ARG, "tc_build_csr: NULL pairs/cols");
+  TC_TRY(check_ws(ws, ws_bytes, build_ws_bytes(n, num_pairs), "tc_build_csr"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CallScope scope(s);
+  prof_stage("build_csr");
+  return build_run(n, num_pairs, src, dst, row_offsets, cols, nnz_out, ws, ws_bytes, s);
+}
+
+int tc_validate_csr(const tc_csr* g, void* ws, size_t ws_bytes, tc_stream_t stream) {
+  TC_TRY(check_csr(g, "tc_validate_csr"));
+  TC_TRY(check_ws(ws, ws_bytes, validate_ws_bytes(g->n, g->nnz), "tc_validate_csr"));
+  return validate_run(g, ws, static_cast<hipStream_t>(stream));
+}
+
+int tc_bfs_levels(const tc_csr* g, int64_t root, uint32_t flags, int32_t* levels, int32_t* num_levels, void* ws,
+                  size_t ws_bytes, tc_stream_t stream) {
+  TC_TRY(check_csr(g, "tc_bfs_levels"));
+  if (root >= g->n || root < -1) return fail(TC_ERR_INVALID_ARG, "tc_bfs_levels: root %lld out of range", (long long)root);
+  if (g->n > 0 && !levels) return fail(TC_ERR_INVALID_ARG, "tc_bfs_levels: levels is NULL");
+  TC_TRY(check_ws(ws, ws_bytes, tc_workspace_bytes(TC_OP_BFS_LEVELS, g->n, g->nnz, 0), "tc_bfs_levels"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CallScope scope(s);
+  TC_TRY(maybe_validate(g, flags, ws, s));
+  Carver c(ws);
+  BfsWs w = bfs_reserve(c, g->n);
+  prof_stage("bfs");
+  return bfs_run(g, root, levels, num_levels, w, s);
+}
+
+int tc_cover_edges(const tc_csr* g, const int32_t* levels, int32_t* h_u, int32_t* h_v, int64_t* h_count, void* ws,
+                   size_t ws_bytes, tc_stream_t stream) {
+  TC_TRY(check_csr(g, "tc_cover_edges"));
+  if (!h_count || (g->n > 0 && !levels) || (g->nnz > 0 && (!h_u || !h_v)))
+    return fail(TC_ERR_INVALID_ARG, "tc_cover_edges: NULL argument");
+  TC_TRY(check_ws(ws, ws_bytes, plan_cover(nullptr, g->n, g->nnz).bytes, "tc_cover_edges"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CallScope scope(s);
+  if (g->n == 0) return fill_i64(h_count, 0, 1, s);
+  CoverPlan p = plan_cover(ws, g->n, g->nnz);
+  prof_stage("split");
+  TC_TRY(split_run(g, levels, true, p.split, s));
+  prof_stage("hlist");
+  return hlist_run(g, p.split.meta, p.split.scols, p.h_off, h_u, h_v, g->nnz / 2, h_count, p.hscratch, s);
+}
+
+int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles, int64_t* h_count, int32_t* levels,
+             int64_t* per_vertex, void* ws, size_t ws_bytes, tc_stream_t stream) {
+  TC_TRY(check_csr(g, "tc_count"));
+  if (!triangles) return fail(TC_ERR_INVALID_ARG, "tc_count: triangles is NULL");
+  if (root >= g->n || root < -1) return fail(TC_ERR_INVALID_ARG, "tc_count: root %lld out of range", (long long)root);
+  const bool pv = flags & TC_PER_VERTEX;
+  if (pv && g->n > 0 && !per_vertex) return fail(TC_ERR_INVALID_ARG, "tc_count: per_vertex is NULL");
+  const size_t need = plan_count(nullptr, g->n, g->nnz).bytes;
+  TC_TRY(check_ws(ws, ws_bytes, need, "tc_count"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CallScope scope(s);
+  TC_TRY(maybe_validate(g, flags, ws, s));
+  CountPlan p = plan_count(ws, g->n, g->nnz);
+  int32_t* L = levels ? levels : p.L;
+  int32_t nl = 0;
+  prof_stage("bfs");
+  TC_TRY(bfs_run(g, root, L, &nl, p.bfs, s));
+  if (pv) TC_TRY(fill_i64(per_vertex, 0, g->n, s));
+  if (g->n > 0) {
+    prof_stage("split");
+    TC_TRY(split_run(g, L, false, p.split, s));
+  }
+  CountArgs a;
+  a.g = g;
+  a.cols = p.split.scols;
+  a.meta = p.split.meta;
+  a.cover = true;
+  a.per_vertex = pv;
+  a.per_vertex_out = per_vertex;
+  a.light_max = 32;
+  a.heavy_chunk = 1024;
+  TC_TRY(count_run(a, p.count, triangles, h_count, s));
+  stats_kernel<<<1, 1, 0, s>>>(p.stats, g->n, g->nnz, nl);
+  TC_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int tc_count_edge_baseline(const tc_csr* g, uint32_t flags, int64_t* triangles, void* ws, size_t ws_bytes,
+                           tc_stream_t stream) {
+  TC_TRY(check_csr(g, "tc_count_edge_baseline"));
+  if (!triangles) return fail(TC_ERR_INVALID_ARG, "tc_count_edge_baseline: triangles is NULL");
+  const size_t need = plan_baseline(nullptr, g->n, g->nnz).bytes;
+  TC_TRY(check_ws(ws, ws_bytes, need, "tc_count_edge_baseline"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CallScope scope(s);
+  TC_TRY(maybe_validate(g, flags, ws, s));
+  BaselinePlan p = plan_baseline(ws, g->n, g->nnz);
+  prof_stage("forward_lists");
+  TC_TRY(forward_meta_run(g, p.meta, s));
+  CountArgs a;
+  a.g = g;
+  a.cols = g->cols;
+  a.meta = p.meta;
+  a.cover = false;
+  a.per_vertex = false;
+  a.per_vertex_out = nullptr;
+  a.light_max = 32;
+  a.heavy_chunk = 1024;
+  TC_TRY(count_run(a, p.count, triangles, nullptr, s));
+  stats_kernel<<<1, 1, 0, s>>>(p.stats, g->n, g->nnz, 0);
+  TC_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+int tc_count_batch(const tc_batch* b, const tc_tuning* tuning, uint32_t flags, int64_t* triangles,
+                   int64_t* h_count, int32_t* levels, void* ws, size_t ws_bytes, tc_stream_t stream) {
+  if (!b || !triangles) return fail(TC_ERR_INVALID_ARG, "tc_count_batch: NULL argument");
+  if (b->num_graphs < 0 || b->total_vertices < 0 || b->total_nnz < 0)
+    return fail(TC_ERR_INVALID_ARG, "tc_count_batch: negative size");
+  if (b->max_graph_vertices > TC_BATCH_MAX_N)
+    return fail(TC_ERR_TOO_LARGE, "tc_count_batch: a graph has more than %d vertices", TC_BATCH_MAX_N);
+  if (b->num_graphs > 0 && (!b->vbase || !b->row_offsets || (b->total_nnz > 0 && !b->cols)))
+    return fail(TC_ERR_INVALID_ARG, "tc_count_batch: NULL batch array");
+  TC_TRY(check_ws(ws, ws_bytes, batch_ws_bytes(b->total_vertices, b->total_nnz, b->num_graphs), "tc_count_batch"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CallScope scope(s);
+  prof_stage("batch");
+  return batch_run(b, tuning, flags, triangles, h_count, levels, ws, ws_bytes, s);
+}
+
+const char* tc_status_string(int status) {
+  switch (status) {
+    case TC_OK: return "ok";
+    case TC_ERR_INVALID_ARG: return "invalid argument";
+    case TC_ERR_WORKSPACE: return "workspace too small";
+    case TC_ERR_NOT_SORTED: return "row not sorted";
+    case TC_ERR_DUPLICATE: return "duplicate entry";
+    case TC_ERR_SELF_LOOP: return "self loop";
+    case TC_ERR_NOT_SYMMETRIC: return "not symmetric";
+    case TC_ERR_OUT_OF_RANGE: return "id out of range";
+    case TC_ERR_TOO_LARGE: return "too large";
+    case TC_ERR_HIP: return "HIP runtime error";
+    case TC_ERR_BAD_OFFSETS: return "bad row offsets";
+    default: return "unknown status";
+  }
+}
+
+const char* tc_last_error(void) { return last_error(); }
+
+void tc_profile_enable(int on) { prof_enable(on); }
+
+int tc_profile_read(tc_profile* out) {
+  if (!out) return fail(TC_ERR_INVALID_ARG, "tc_profile_read: NULL");
+  return prof_read(out);
+}
+
+int tc_read_stats(const void* ws, tc_stats* out, tc_stream_t stream) {
+  if (!ws || !out) return fail(TC_ERR_INVALID_ARG, "tc_read_stats: NULL");
+  memset(out, 0, sizeof *out);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TC_HIP(hipMemcpyAsync(out, ws, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipStreamSynchronize(s));
+  return TC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// tc_internal.h -- interfaces between the libtc sources.
+#pragma once
+
+#include "tc_common.h"
+
+namespace tc {
+
+void clear_error();
+const char* last_error();
+int prof_read(tc_profile* out);
+void prof_enable(int on);
+
+// ---------------------------------------------------------------- BFS
+struct BfsWs {
+  uint32_t* vis;
+  uint32_t* fbits;
+  uint32_t* nbits;
+  int32_t* q0;
+  int32_t* q1;
+  int64_t* fdeg;
+  int64_t* pre;
+  int32_t* parent;
+  int64_t* ctr;
+  unsigned long long* key;
+  int64_t* root;
+  char* scratch;
+  size_t scratch_bytes;
+};
+BfsWs bfs_reserve(Carver& c, int64_t n);
+int bfs_run(const tc_csr* g, int64_t root, int32_t* L, int32_t* num_levels, BfsWs& w,
+            hipStream_t s);
+
+// ------------------------------------------------ level-class layout
+// Per vertex x, relative to row_offsets[x] in the re-laid-out columns:
+//   Up    = [0, up)    neighbours one level closer to the root
+//   Same  = [up, sfe)  neighbours on the same level; Hfwd = [hfb, sfe) are
+//                      those with a larger id (the cover edges (x, v), x < v)
+//   Down  = [sfe, deg) neighbours one level further
+// Each class is ascending.  For the comparator the same record describes the
+// plain forward lists: up = 0, hfb = first neighbour > x, sfe = deg.
+struct VMeta {
+  int32_t up, hfb, sfe, deg;
+};
+
+struct SplitWs {
+  VMeta* meta;
+  int32_t* scols;     // re-laid-out columns [nnz]
+  uint32_t* res;      // packed 2-bit level residues (L mod 4)
+  int32_t* nseg;      // per vertex: segments of a long row
+  int64_t* seg_off;   // scan of nseg
+  int32_t* seg_vtx;   // segment -> vertex
+  int32_t* seg_cnt;   // per segment: up, same, same-below-x counts (x3)
+  int32_t* seg_pre;   // per segment: prefix of the three counts (x3)
+  int64_t* ctr;
+  char* scratch;
+};
+SplitWs split_reserve(Carver& c, int64_t n, int64_t nnz);
+// full_levels: classify by comparing int32 levels (any level function);
+// otherwise use packed residues (requires |L(u) - L(v)| <= 1 on edges).
+int split_run(const tc_csr* g, const int32_t* L, bool full_levels, SplitWs& w, hipStream_t s);
+
+// Explicit horizontal-edge list from the layout: h_off = scan of
+// (sfe - hfb), then (x, scols[..]) for every cover edge, lexicographic.
+// At most `cap` entries are written (the caller's capacity); h_off[n] and
+// *h_count report the full count.
+int hlist_run(const tc_csr* g, const VMeta* meta, const int32_t* cols, int64_t* h_off,
+              int32_t* h_u, int32_t* h_v, int64_t cap, int64_t* h_count, char* scratch,
+              hipStream_t s);
+
+// ------------------------------------------------------------ count
+struct CountWs {
+  int64_t* h_off;     // [n + 1]
+  int32_t* h_u;       // [nnz / 2]
+  int32_t* h_v;
+  int32_t* ecnt;      // per anchor: emitted tasks
+  int32_t* ecur;
+  int64_t* task_off;  // [n + 1]
+  int64_t* task_begin;
+  int32_t* task_len;
+  int32_t* task_owner;
+  int2* items;        // heavy work items (anchor, chunk)
+  unsigned long long* acc;  // [8]: T, stream elems, light tasks, items, descs, ...
+  int64_t* stats;     // tc_stats mirror
+  char* scratch;
+};
+CountWs count_reserve(Carver& c, int64_t n, int64_t nnz);
+
+struct CountArgs {
+  const tc_csr* g;
+  const int32_t* cols;  // layout columns (cover: split; comparator: original)
+  const VMeta* meta;
+  bool cover;           // cover edges (three classes) or the comparator
+  bool per_vertex;
+  int64_t* per_vertex_out;
+  int32_t light_max;
+  int32_t heavy_chunk;
+};
+int count_run(const CountArgs& a, CountWs& w, int64_t* triangles, int64_t* h_count,
+              hipStream_t s);
+
+// Comparator layout: meta with up = 0, hfb = first neighbour > x, sfe = deg.
+int forward_meta_run(const tc_csr* g, VMeta* meta, hipStream_t s);
+
+// -------------------------------------------------------- CSR build
+size_t build_ws_bytes(int64_t n, int64_t num_pairs);
+int build_run(int64_t n, int64_t num_pairs, const int32_t* src, const int32_t* dst,
+              int64_t* row_offsets, int32_t* cols, int64_t* nnz_out, void* ws, size_t ws_bytes,
+              hipStream_t s);
+
+size_t validate_ws_bytes(int64_t n, int64_t nnz);
+int validate_run(const tc_csr* g, void* ws, hipStream_t s);
+
+// ------------------------------------------------------------ batch
+size_t batch_ws_bytes(int64_t total_n, int64_t total_nnz, int32_t num_graphs);
+int batch_run(const tc_batch* b, const tc_tuning* t, uint32_t flags, int64_t* triangles,
+              int64_t* h_count, int32_t* levels, void* ws, size_t ws_bytes, hipStream_t s);
+
+}  // namespace tc

@@ -1,0 +1,77 @@
+"""The C-ABI library loads and exports every entry point of include/tc.h;
+host-side logic that needs no GPU (workspace sizing, status strings)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2210_00389_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2210_00389_amd import build
+        build.build()
+    return _lib.load()
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "tc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tc_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_match_header(lib):
+    from paper_2210_00389_amd import _lib
+    names = header_functions()
+    assert names, "no functions found in tc.h"
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (tc_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    assert sorted(_lib.EXPORTS) == names
+    for n in names:
+        assert hasattr(lib, n)
+
+
+def test_status_strings(lib):
+    from paper_2210_00389_amd import _lib
+    for code in _lib.STATUS_NAMES:
+        s = lib.tc_status_string(code).decode()
+        assert s and s != "unknown status"
+    assert lib.tc_status_string(12345).decode() == "unknown status"
+
+
+def test_workspace_sizes(lib):
+    from paper_2210_00389_amd import _lib
+    for op in (_lib.OP_BUILD_CSR, _lib.OP_BFS_LEVELS, _lib.OP_COVER_EDGES, _lib.OP_COUNT,
+               _lib.OP_EDGE_BASELINE, _lib.OP_VALIDATE, _lib.OP_COUNT_BATCH):
+        small = lib.tc_workspace_bytes(op, 1000, 20000, 4)
+        big = lib.tc_workspace_bytes(op, 100000, 2000000, 400)
+        assert 0 < small <= big
+        assert lib.tc_workspace_bytes(op, 0, 0, 0) > 0
+    assert lib.tc_workspace_bytes(99, 10, 10, 0) == 0
+    assert lib.tc_workspace_bytes(_lib.OP_COUNT, -1, 10, 0) == 0
+    # R-MAT scale 24 (16.7 M vertices, ~0.52 G entries) fits easily in 288 GB
+    assert lib.tc_workspace_bytes(_lib.OP_COUNT, 1 << 24, 520_000_000, 0) < 40 * 2**30
+
+
+def test_argument_errors_without_gpu(lib):
+    """Argument checks run before any device work."""
+    import ctypes
+    from paper_2210_00389_amd import _lib
+    assert lib.tc_count(None, -1, 0, None, None, None, None, None, 0, None) == -1
+    csr = _lib.TcCsr(-1, 0, None, None)
+    assert lib.tc_bfs_levels(ctypes.byref(csr), -1, 0, None, None, None, 0, None) == -1
+    csr = _lib.TcCsr(1 << 31, 0, 1, None)
+    assert lib.tc_count(ctypes.byref(csr), -1, 0, 1, None, None, None, None, 0, None) == -8
+    csr = _lib.TcCsr(10, 20, 1, 1)
+    t = ctypes.c_int64(0)
+    # workspace too small
+    assert lib.tc_count(ctypes.byref(csr), -1, 0, ctypes.byref(t), None, None, None, None, 16, None) == -2
+    assert "workspace" in lib.tc_last_error().decode()
+    # root out of range
+    assert lib.tc_count(ctypes.byref(csr), 10, 0, ctypes.byref(t), None, None, None, None, 1 << 30, None) == -1

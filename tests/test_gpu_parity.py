@@ -1,0 +1,242 @@
+"""GPU parity: every libtc entry point against the CPU oracle, element by
+element, on seeded inputs (bit-exact: all outputs are integers)."""
+import hashlib
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tc():
+    import torch
+    from paper_2210_00389_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2210_00389_amd import build
+        build.build()
+    import paper_2210_00389_amd as tc
+    torch.cuda.set_device(0)
+    return tc
+
+
+def to_gpu(tc, g):
+    return tc.from_host_pairs(g.n, g.src, g.dst, device="cuda")
+
+
+def check_graph(tc, g, name="", root=-1, baseline=True, per_vertex=True):
+    """Full parity of one raw graph: CSR, levels, |H|, H list, T, per-vertex
+    counts and the comparator."""
+    say(f"[parity] {name} n={g.n} pairs={g.num_pairs} root={root}")
+    c = oracle.from_graph(g)
+    G = to_gpu(tc, g)
+    assert G.n == c.n and G.nnz == c.nnz
+    assert np.array_equal(G.row_offsets.cpu().numpy(), c.row_offsets)
+    assert np.array_equal(G.cols.cpu().numpy(), c.cols)
+    lv = oracle.bfs_levels(c, root)
+    L, nl = tc.bfs_levels(G, root)
+    assert np.array_equal(L.cpu().numpy(), lv.levels), name
+    assert nl == lv.num_levels
+    hu, hv = oracle.cover_edges(c, lv.levels)
+    gu, gv = tc.cover_edges(G, L)
+    assert np.array_equal(gu.cpu().numpy(), hu) and np.array_equal(gv.cpu().numpy(), hv)
+    want = oracle.count(c, lv.levels, per_vertex=per_vertex)
+    res = tc.count(G, root=root, per_vertex=per_vertex, return_levels=True)
+    assert res.T == want.triangles, (name, res.T, want.triangles)
+    assert res.h == len(hu)
+    assert np.array_equal(res.levels.cpu().numpy(), lv.levels)
+    if per_vertex:
+        assert np.array_equal(res.per_vertex.cpu().numpy(), want.per_vertex)
+    if baseline:
+        assert int(tc.count_edge_baseline(G).item()) == want.triangles
+    return c, G, want.triangles
+
+
+# ---------------------------------------------------------- CSR build
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_build_csr_matches_oracle(tc, seed):
+    for g in [graphgen.rmat(9, 8, seed=seed), graphgen.erdos_renyi(700, 0.01, seed),
+              graphgen.barabasi_albert(900, 5, seed),
+              graphgen.Graph(5, np.array([0, 1, 1, 2, 3, 2, 0, 3], np.int32),
+                             np.array([1, 0, 1, 0, 3, 3, 2, 0], np.int32))]:
+        say(f"[build] {g.name} seed={seed}")
+        c = oracle.from_graph(g)
+        G = to_gpu(tc, g)
+        assert np.array_equal(G.row_offsets.cpu().numpy(), c.row_offsets)
+        assert np.array_equal(G.cols.cpu().numpy(), c.cols)
+        assert tc.validate(G) == 0
+
+
+def test_build_csr_empty_and_out_of_range(tc):
+    import torch
+    G = tc.from_host_pairs(7, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert G.nnz == 0 and G.row_offsets.cpu().tolist() == [0] * 8
+    G = tc.from_host_pairs(0, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert G.n == 0 and G.nnz == 0
+    with pytest.raises(tc.TcError) as e:
+        tc.from_host_pairs(4, np.array([0, 1], np.int32), np.array([2, 9], np.int32))
+    assert e.value.status == -7
+    torch.cuda.synchronize()
+
+
+# ----------------------------------------------------------- validate
+@pytest.mark.parametrize("mutate,code", [
+    ("offsets", -10), ("range", -7), ("unsorted", -3), ("dup", -4), ("self", -5), ("asym", -6)])
+def test_validate_errors(tc, mutate, code):
+    off = np.array([0, 2, 4, 6], dtype=np.int64)
+    cols = np.array([1, 2, 0, 2, 0, 1], dtype=np.int32)
+    n = 3
+    if mutate == "offsets":
+        off = np.array([0, 4, 2, 6], dtype=np.int64)
+    elif mutate == "range":
+        cols[0] = 7
+    elif mutate == "unsorted":
+        cols[0], cols[1] = 2, 1
+    elif mutate == "dup":
+        cols[1] = 1
+    elif mutate == "self":
+        cols[0] = 0
+    elif mutate == "asym":
+        off = np.array([0, 1, 1, 1], np.int64)
+        cols = np.array([1], np.int32)
+    say(f"[validate] {mutate}")
+    G = tc.from_host_csr(n, off, cols)
+    assert tc.validate(G) == code
+    with pytest.raises(tc.TcError) as e:
+        tc.count(G, validate=True)
+    assert e.value.status == code
+    ok = tc.from_host_csr(3, np.array([0, 2, 4, 6], np.int64), np.array([1, 2, 0, 2, 0, 1], np.int32))
+    assert tc.validate(ok) == 0
+    assert tc.count(ok, validate=True).T == 1
+
+
+# ------------------------------------------------- closed forms
+@pytest.mark.parametrize("n", [3, 4, 5, 17, 64, 65, 300])
+def test_complete(tc, n):
+    check_graph(tc, graphgen.complete(n), f"K{n}", baseline=True, per_vertex=n <= 64)
+
+
+@pytest.mark.parametrize("n", [5, 6, 50, 3000])
+def test_wheel(tc, n):
+    check_graph(tc, graphgen.wheel(n), f"W{n}")
+
+
+@pytest.mark.parametrize("g", [graphgen.cycle(3), graphgen.cycle(4), graphgen.cycle(101), graphgen.cycle(1000),
+                               graphgen.path(2), graphgen.path(500), graphgen.star(20000),
+                               graphgen.complete_bipartite(40, 70), graphgen.grid(30, 40),
+                               graphgen.random_bipartite(50, 60, 0.2, 3)],
+                         ids=lambda g: g.name)
+def test_sparse_families(tc, g):
+    check_graph(tc, g, g.name)
+
+
+def test_complete_large_closed_form(tc):
+    """K_4200: the probe set of vertex 1 (4198 forward cover edges) exceeds
+    the on-chip table; closed forms C(n,3), C(n-1,2), C(n-1,2) per vertex."""
+    n = 4200
+    say(f"[closed form] K{n}")
+    g = graphgen.complete(n)
+    G = to_gpu(tc, g)
+    res = tc.count(G, per_vertex=True)
+    assert res.T == math.comb(n, 3)
+    assert res.h == math.comb(n - 1, 2)
+    pv = res.per_vertex.cpu().numpy()
+    assert (pv == math.comb(n - 1, 2)).all()
+    assert int(tc.count_edge_baseline(G).item()) == math.comb(n, 3)
+
+
+def test_friendship_and_big_star(tc):
+    """Windmill graph (k triangles through one hub) and a large wheel: long
+    hub rows split into many segments, bottom-up BFS steps."""
+    k = 60000
+    hub = np.zeros(2 * k, np.int32)
+    leaves = np.arange(1, 2 * k + 1, dtype=np.int32)
+    s = np.concatenate([hub, leaves[0::2]])
+    d = np.concatenate([leaves, leaves[1::2]])
+    say("[closed form] windmill")
+    G = tc.from_host_pairs(2 * k + 1, s, d)
+    res = tc.count(G, per_vertex=True)
+    assert res.T == k and res.h == k
+    pv = res.per_vertex.cpu().numpy()
+    assert pv[0] == k and (pv[1:] == 1).all()
+    assert int(tc.count_edge_baseline(G).item()) == k
+    n = 200001
+    say("[closed form] W200001")
+    Gw = to_gpu(tc, graphgen.wheel(n))
+    res = tc.count(Gw)
+    assert res.T == n - 1 and res.h == n - 1
+
+
+def test_empty_and_edgeless(tc):
+    import torch
+    G = tc.from_host_pairs(0, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert tc.count(G).T == 0
+    G = tc.from_host_pairs(9, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    res = tc.count(G, return_levels=True)
+    assert res.T == 0 and res.h == 0 and (res.levels.cpu().numpy() == 0).all()
+    L, nl = tc.bfs_levels(G)
+    assert nl == 1 and (L.cpu().numpy() == 0).all()
+    assert int(tc.count_edge_baseline(G).item()) == 0
+    torch.cuda.synchronize()
+
+
+# ------------------------------------------------- random graphs
+@pytest.mark.parametrize("block", range(5))
+def test_random_graphs(tc, block):
+    rng = np.random.default_rng(1000 + block)
+    for k in range(40):
+        kind = rng.integers(0, 5)
+        seed = int(rng.integers(0, 10**6))
+        n = int(rng.integers(2, 400))
+        if kind == 0:
+            g = graphgen.erdos_renyi(n, float(rng.uniform(0.005, 0.3)), seed)
+        elif kind == 1:
+            g = graphgen.barabasi_albert(n, int(rng.integers(1, 8)), seed)
+        elif kind == 2:
+            g = graphgen.rmat(int(rng.integers(3, 10)), int(rng.integers(2, 20)), seed=seed)
+        elif kind == 3:
+            g = graphgen.chung_lu(max(n, 50), 2.1, float(rng.uniform(2, 12)), seed)
+        else:
+            g = graphgen.disjoint_union([graphgen.erdos_renyi(n, 0.05, seed), graphgen.complete(5),
+                                         graphgen.cycle(7), graphgen.barabasi_albert(n // 2 + 2, 2, seed)])
+        root = -1 if k % 3 else int(rng.integers(0, g.n))
+        check_graph(tc, g, f"block{block}/{k} {g.name}", root=root)
+
+
+def test_rmat_medium_full_parity(tc):
+    """Scales 12-16: several tiles, hub rows over the short-row limit, heavy
+    anchors with emitted tasks, bottom-up BFS."""
+    for scale, seed in [(12, 1), (14, 7), (16, 1)]:
+        check_graph(tc, graphgen.rmat(scale, 16, seed=seed), f"rmat{scale}", per_vertex=scale <= 14)
+
+
+def test_golden_rmat_s10(tc):
+    gold = json.load(open(os.path.join(GOLDEN, "rmat_s10.json")))
+    G = to_gpu(tc, graphgen.rmat(10, 16, seed=1))
+    res = tc.count(G, return_levels=True)
+    digest = hashlib.sha256(res.levels.cpu().numpy().astype("<i4").tobytes()).hexdigest()
+    assert (res.T, res.h, digest) == (gold["triangles"], gold["h"], gold["levels_sha256"])
+
+
+def test_determinism(tc):
+    G = to_gpu(tc, graphgen.rmat(14, 16, seed=3))
+    outs = set()
+    for _ in range(5):
+        r = tc.count(G, return_levels=True)
+        outs.add((r.T, r.h, hashlib.sha256(r.levels.cpu().numpy().tobytes()).hexdigest(),
+                  int(tc.count_edge_baseline(G).item())))
+    assert len(outs) == 1
