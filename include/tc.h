@@ -225,7 +225,10 @@ typedef struct tc_stats {
   int64_t light_tasks;     /* tasks on the per-task merge path */
   int64_t heavy_items;     /* work items of the anchored (LDS hash) path */
   int64_t heavy_desc;      /* descriptors processed on the anchored path */
-  int64_t reserved[8];
+  int64_t heavy_elems;     /* list elements streamed by the anchored kernel */
+  int64_t heavy_builds;    /* probe-set elements inserted into on-chip tables */
+  int64_t light_elems;     /* list elements streamed by the per-task merges */
+  int64_t reserved[5];
 } tc_stats;
 
 int tc_read_stats(const void* ws, tc_stats* out, tc_stream_t stream);

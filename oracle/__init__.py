@@ -96,6 +96,8 @@ def _bind(lib):
     lib.oracle_edge_support.restype = i64
     lib.oracle_edge_count.argtypes = [i64, p, p]
     lib.oracle_edge_count.restype = i64
+    lib.oracle_count_rows.argtypes = [i64, p, p, p, c_int, i64, i64, p]
+    lib.oracle_count_rows.restype = c_int
     return lib
 
 
@@ -219,6 +221,18 @@ def count(csr: CSR, levels: np.ndarray, mode: int = 0, per_edge: bool = False,
     if per_vertex:
         pv = pv[: csr.n].copy()
     return Count(int(T[0]), pe, pv)
+
+
+def count_rows(csr: CSR, levels: np.ndarray, u_begin: int, u_end: int, mode: int = 0) -> int:
+    """Alg. 1 count restricted to cover edges (u, v) with u in [u_begin, u_end)."""
+    cols = csr.cols if csr.cols.size else np.zeros(1, dtype=np.int32)
+    L = np.ascontiguousarray(levels, dtype=np.int32)
+    if L.size == 0:
+        L = np.zeros(1, dtype=np.int32)
+    T = np.zeros(1, dtype=np.int64)
+    _check(_load().oracle_count_rows(csr.n, _p(csr.row_offsets), _p(cols), _p(L), mode, u_begin, u_end,
+                                     _p(T)))
+    return int(T[0])
 
 
 def edge_support(csr: CSR, levels: np.ndarray, u: int, v: int) -> int:

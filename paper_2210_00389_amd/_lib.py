@@ -63,7 +63,9 @@ class TcStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("h", ctypes.c_int64),
                 ("num_levels", ctypes.c_int64), ("stream_elems", ctypes.c_int64),
                 ("light_tasks", ctypes.c_int64), ("heavy_items", ctypes.c_int64),
-                ("heavy_desc", ctypes.c_int64), ("reserved", ctypes.c_int64 * 8)]
+                ("heavy_desc", ctypes.c_int64), ("heavy_elems", ctypes.c_int64),
+                ("heavy_builds", ctypes.c_int64), ("light_elems", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 5)]
 
 
 _lib = None

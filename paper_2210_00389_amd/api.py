@@ -218,7 +218,8 @@ def read_stats(ws: Workspace | None = None, device=None, stream=None) -> dict:
     st = L.TcStats()
     _check(lib.tc_read_stats(_ptr(w.buf), ctypes.byref(st), _stream(stream)), "tc_read_stats")
     return {k: int(getattr(st, k)) for k in ("n", "nnz", "h", "num_levels", "stream_elems", "light_tasks",
-                                              "heavy_items", "heavy_desc")}
+                                              "heavy_items", "heavy_desc", "heavy_elems", "heavy_builds",
+                                              "light_elems")}
 
 
 def profile_enable(on: bool = True):

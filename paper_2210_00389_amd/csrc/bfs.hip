@@ -37,8 +37,14 @@ __global__ void root_key_kernel(const int64_t* off, int64_t n, unsigned long lon
     unsigned long long k = (d << 32) | (0xFFFFFFFFull - static_cast<unsigned long long>(v));
     best = k > best ? k : best;
   }
+  __shared__ unsigned long long sm[kThreads / kWave];
   best = wave_max(best);
-  if (lane() == 0 && best) atomicMax(key, best);
+  if (lane() == 0) sm[threadIdx.x / kWave] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kThreads / kWave; ++i) best = sm[i] > best ? sm[i] : best;
+    if (best) atomicMax(key, best);
+  }
 }
 
 // Starts the BFS from one root (either the argmax key or a given root):
@@ -65,21 +71,42 @@ __global__ void frontier_deg_kernel(const int64_t* off, const int32_t* q, int64_
     fdeg[i] = row_deg(off, q[i]);
 }
 
-// Wave-aggregated append of the lanes with `take` set; returns nothing, adds
-// `edges` of the appended vertices to ctr[1].
-__device__ __forceinline__ void append(bool take, int32_t w, int64_t dw, int32_t* qn, int64_t* ctr) {
-  uint64_t m = __ballot(take);
-  if (!m) return;
-  int leader = __ffsll(static_cast<long long>(m)) - 1;
-  int cnt = __popcll(m);
-  int64_t e = wave_sum(take ? dw : 0);
-  int64_t base = 0;
-  if (lane() == leader) {
-    base = atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[0]), static_cast<unsigned long long>(cnt));
-    atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[1]), static_cast<unsigned long long>(e));
+// Block-aggregated append: the lanes with `take` set write `item` to the
+// queue q at consecutive slots reserved with one atomic per block on
+// ctr[slot]; ctr[1] accumulates their `weight` (edge counts).  Every thread
+// of the block must call it (it synchronises).
+struct AppendLds {
+  int64_t cnt[kThreads / kWave];
+  int64_t edg[kThreads / kWave];
+  int64_t base;
+};
+
+__device__ __forceinline__ void block_append(bool take, int32_t item, int64_t weight, int32_t* q, int64_t* ctr,
+                                             int slot, AppendLds& L) {
+  const int w = threadIdx.x / kWave;
+  const uint64_t m = __ballot(take);
+  const int64_t we = wave_sum(take ? weight : int64_t(0));
+  if (lane() == 0) {
+    L.cnt[w] = __popcll(m);
+    L.edg[w] = we;
   }
-  base = __shfl(base, leader, kWave);
-  if (take) qn[base + __popcll(m & lanemask_lt())] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t tc = 0, te = 0;
+    for (int i = 0; i < kThreads / kWave; ++i) {
+      const int64_t c = L.cnt[i];
+      L.cnt[i] = tc;
+      tc += c;
+      te += L.edg[i];
+    }
+    L.base = tc ? static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[slot]),
+                                                 static_cast<unsigned long long>(tc)))
+                : 0;
+    if (te) atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[1]), static_cast<unsigned long long>(te));
+  }
+  __syncthreads();
+  if (take && q) q[L.base + L.cnt[w] + __popcll(m & lanemask_lt())] = item;
+  __syncthreads();
 }
 
 // Top-down: flat edge index k in [0, ef) -> frontier slot i with
@@ -89,6 +116,7 @@ __global__ __launch_bounds__(kThreads) void topdown_kernel(const int64_t* off, c
                                                            const int64_t* pre, int64_t ef,
                                                            int32_t next_level, int32_t* L,
                                                            uint32_t* vis, int32_t* qn, int64_t* ctr) {
+  __shared__ AppendLds lds;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k0 = blockIdx.x * (int64_t)blockDim.x; k0 < ef; k0 += stride) {
     const int64_t k = k0 + threadIdx.x;
@@ -109,7 +137,7 @@ __global__ __launch_bounds__(kThreads) void topdown_kernel(const int64_t* off, c
         }
       }
     }
-    append(take, w, dw, qn, ctr);
+    block_append(take, w, dw, qn, ctr, 0, lds);
   }
 }
 
@@ -128,6 +156,7 @@ __global__ __launch_bounds__(kThreads) void bottomup_kernel(const int64_t* off, 
                                                             int32_t next_level, int32_t* L,
                                                             uint32_t* vis, uint32_t* nbits,
                                                             int64_t* ctr) {
+  __shared__ AppendLds lds;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += stride) {
     const int64_t v = v0 + threadIdx.x;
@@ -149,33 +178,18 @@ __global__ __launch_bounds__(kThreads) void bottomup_kernel(const int64_t* off, 
         atomicOr(&vis[v >> 5], 1u << (v & 31));
       }
     }
-    uint64_t m = __ballot(take);
-    if (m) {
-      int64_t cnt = __popcll(m);
-      int64_t e = wave_sum(dv);
-      if (lane() == 0) {
-        atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[0]), static_cast<unsigned long long>(cnt));
-        atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[1]), static_cast<unsigned long long>(e));
-      }
-    }
+    block_append(take, 0, dv, nullptr, ctr, 0, lds);
   }
 }
 
 // Bitmap -> queue (order within the queue is irrelevant).
 __global__ void bits_to_queue_kernel(const uint32_t* bits, int64_t n, int32_t* q, int64_t* ctr) {
+  __shared__ AppendLds lds;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += stride) {
     const int64_t v = v0 + threadIdx.x;
-    bool take = v < n && (bits[v >> 5] & (1u << (v & 31)));
-    uint64_t m = __ballot(take);
-    if (!m) continue;
-    int leader = __ffsll(static_cast<long long>(m)) - 1;
-    int64_t base = 0;
-    if (lane() == leader)
-      base = atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[2]),
-                       static_cast<unsigned long long>(__popcll(m)));
-    base = __shfl(base, leader, kWave);
-    if (take) q[base + __popcll(m & lanemask_lt())] = static_cast<int32_t>(v);
+    const bool take = v < n && (bits[v >> 5] & (1u << (v & 31)));
+    block_append(take, static_cast<int32_t>(v), 0, q, ctr, 2, lds);
   }
 }
 
@@ -230,6 +244,7 @@ __global__ void uf_hook_kernel(const int64_t* off, const int32_t* cols, int64_t 
 // isolated vertices get level 0 and need no expansion.
 __global__ void uf_roots_kernel(const int64_t* off, int64_t n, int32_t* parent, int32_t* L,
                                 uint32_t* vis, int32_t* q, int64_t* ctr) {
+  __shared__ AppendLds lds;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += stride) {
     const int64_t v = v0 + threadIdx.x;
@@ -243,7 +258,7 @@ __global__ void uf_roots_kernel(const int64_t* off, int64_t n, int32_t* parent, 
         take = dv > 0;
       }
     }
-    append(take, static_cast<int32_t>(v), dv, q, ctr);
+    block_append(take, static_cast<int32_t>(v), dv, q, ctr, 0, lds);
   }
 }
 

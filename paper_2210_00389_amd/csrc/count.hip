@@ -10,9 +10,9 @@
 // The down class is summed from the apex side: for every edge x -> w with
 // w in Down(x), count the t in Up(w) with t > x and t in Hfwd(x); each
 // (u, v, w) with u < v is met once, at x = u, t = v.  This is the same set of
-// (edge, apex) pairs, enumerated the way the paper's distributed variant
-// enumerates apexes per owner; it streams the short up-lists of the apexes
-// instead of the long down-lists of the hub pairs.
+// (edge, apex) pairs, enumerated per apex the way the paper's distributed
+// variant enumerates the apexes a processor owns; it streams the short
+// up-lists of the apexes instead of the long down-lists of hub pairs.
 //
 // Every intersection is a "task": stream one sorted list S, test each element
 // for membership in a probe list P of an anchor vertex.  Ownership rules pick
@@ -21,13 +21,15 @@
 //   same   a = |Hfwd(u) ∩ (v,inf)|, b = |Hfwd(v)|; if b < a anchor u streams
 //          Hfwd(v), else anchor v streams Hfwd(u) ∩ (v,inf)
 //   down   anchor x streams Up(w) ∩ (x,inf)
-// Anchors whose probe set Up(x) ∪ Hfwd(x) is short ("light") have their
-// tasks merged right away by the thread that discovers them.  Heavy anchors
-// get work items: a block builds an LDS hash of the anchor's probe set once
-// per item and streams all of the item's lists through it, flattened across
-// the block (a block-wide prefix over list lengths; every lane takes one
-// element), so loads are coalesced and lanes stay busy whatever the list
-// lengths.  Per-lane counts are reduced wave -> block -> one 64-bit atomic.
+// Light anchors (short probe set, few down-neighbours) have their tasks
+// merged by the thread that discovers them.  Heavy anchors become work items
+// of at most D descriptors, binned by probe-set size: a block builds an LDS
+// hash of the anchor's probe set Up(x) ∪ Hfwd(x) (2 KB .. 128 KB of the
+// 160 KB LDS), resolves all descriptors of the item with independent loads,
+// then every lane takes K consecutive elements of the flattened streams (one
+// LDS search, K independent global loads in flight, K probes).  Probe sets
+// beyond the largest table are searched in their sorted rows instead.
+// Per-lane counts are reduced wave -> block -> one 64-bit atomic.
 //
 // The comparator (plain direction-oriented edge iterator) runs through the
 // same kernels with up = 0, Hfwd = forward list N+(x), no down class.
@@ -38,11 +40,18 @@ namespace tc {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kHeavyThreads = 256;
-constexpr int kTabMax = 8192;  // LDS hash slots (32 KB)
+constexpr int kDnLight = 16;  // light anchors have at most this many down-neighbours
+constexpr int kK = 8;         // elements per lane per round
+constexpr int kBins = 4;
 
-enum Acc { kAccT = 0, kAccElems = 1, kAccLight = 2, kAccItems = 3, kAccDesc = 4, kAccItemCtr = 5,
-           kAccItemNext = 6 };
+// bin limits on the probe-set size P
+constexpr int kBinP0 = 256, kBinP1 = 2048, kBinP2 = 16384;
+
+enum Acc {
+  kAccT = 0, kAccElems = 1, kAccLight = 2, kAccBuild = 3, kAccDesc = 4, kAccItems = 5,
+  kAccHeavyElems = 6, kAccBinCount = 8, kAccBinOff = 12, kAccBinCur = 16, kAccBinNext = 20
+};
+constexpr int kAccSlots = 24;
 
 __device__ __forceinline__ void add_pv(int64_t* pv, int32_t a, int32_t b, int32_t c) {
   atomicAdd(reinterpret_cast<unsigned long long*>(&pv[a]), 1ull);
@@ -71,8 +80,13 @@ __device__ __forceinline__ int64_t merge_count(const int32_t* S, int ns, const i
   return c;
 }
 
-__device__ __forceinline__ bool is_light(const VMeta& m, int light_max) {
-  return (m.up + (m.sfe - m.hfb)) <= light_max;
+__device__ __forceinline__ int probe_size(const VMeta& m) { return m.up + (m.sfe - m.hfb); }
+
+// Heavy anchors get work items; every task of a light anchor is merged by
+// the planning kernels.  Must be the same predicate everywhere.
+__device__ __forceinline__ bool is_heavy(const VMeta& m, bool cover, int light_max) {
+  if (probe_size(m) > light_max) return true;
+  return cover && (m.sfe - m.hfb) > 0 && (m.deg - m.sfe) > kDnLight;
 }
 
 __device__ __forceinline__ void block_acc(unsigned long long* acc, int slot, int64_t v, int64_t* sh) {
@@ -82,14 +96,13 @@ __device__ __forceinline__ void block_acc(unsigned long long* acc, int slot, int
 
 // ------------------------------------------------------------ planning
 // One thread per cover edge e = (u, v), v the i-th entry of Hfwd(u).
-// kFill = false: light tasks are merged and counted, heavy "same" tasks whose
+// kFill = false: light tasks are merged and counted; heavy "same" tasks whose
 // anchor is v are counted per anchor.  kFill = true: those tasks are written.
 template <bool kCover, bool kPV, bool kFill>
 __global__ __launch_bounds__(kThreads) void plan_kernel(
-    const int64_t* off, const int32_t* lc, const VMeta* meta, int64_t n, const int64_t* h_off,
-    const int32_t* h_u, const int32_t* h_v, int light_max, int32_t* ecnt, const int64_t* task_off,
-    int32_t* ecur, int64_t* task_begin, int32_t* task_len, int32_t* task_owner,
-    unsigned long long* acc, int64_t* pv) {
+    const int32_t* lc, const VMeta* meta, int64_t n, const int64_t* h_off, const int32_t* h_u,
+    const int32_t* h_v, int light_max, int32_t* ecnt, const int64_t* task_off, int32_t* ecur,
+    int64_t* task_begin, int32_t* task_len, int32_t* task_owner, unsigned long long* acc, int64_t* pv) {
   __shared__ int64_t sh[kThreads / kWave + 1];
   const int64_t H = h_off[n];
   int64_t cnt = 0, light = 0, elems = 0;
@@ -97,15 +110,13 @@ __global__ __launch_bounds__(kThreads) void plan_kernel(
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < H; e += stride) {
     const int32_t u = h_u[e], v = h_v[e];
     const VMeta mu = meta[u], mv = meta[v];
-    const int64_t bu = off[u], bv = off[v];
     const int i = static_cast<int>(e - h_off[u]);
     if (kCover && !kFill) {
       const bool anchor_u = mv.up <= mu.up;
       const VMeta& ma = anchor_u ? mu : mv;
       const VMeta& mo = anchor_u ? mv : mu;
-      if (mo.up > 0 && is_light(ma, light_max)) {
-        const int64_t ba = anchor_u ? bu : bv, bo = anchor_u ? bv : bu;
-        cnt += merge_count<kPV>(lc + bo, mo.up, lc + ba, ma.up, -1, pv, u, v);
+      if (mo.up > 0 && !is_heavy(ma, kCover, light_max)) {
+        cnt += merge_count<kPV>(lc + mo.begin, mo.up, lc + ma.begin, ma.up, -1, pv, u, v);
         ++light;
         elems += mo.up;
       }
@@ -113,16 +124,16 @@ __global__ __launch_bounds__(kThreads) void plan_kernel(
     const int a = (mu.sfe - mu.hfb) - i - 1;
     const int b = mv.sfe - mv.hfb;
     if (a > 0 && b > 0) {
-      const int32_t* Su = lc + bu + mu.hfb + i + 1;  // Hfwd(u) above v
-      const int32_t* Sv = lc + bv + mv.hfb;          // Hfwd(v)
+      const int32_t* Su = lc + mu.begin + mu.hfb + i + 1;  // Hfwd(u) above v
+      const int32_t* Sv = lc + mv.begin + mv.hfb;          // Hfwd(v)
       if (b < a) {  // anchor u
-        if (!kFill && is_light(mu, light_max)) {
+        if (!kFill && !is_heavy(mu, kCover, light_max)) {
           cnt += merge_count<kPV>(Sv, b, Su, a, -1, pv, u, v);
           ++light;
           elems += b;
         }
       } else {  // anchor v
-        if (is_light(mv, light_max)) {
+        if (!is_heavy(mv, kCover, light_max)) {
           if (!kFill) {
             cnt += merge_count<kPV>(Su, a, Sv, b, -1, pv, u, v);
             ++light;
@@ -132,7 +143,7 @@ __global__ __launch_bounds__(kThreads) void plan_kernel(
           atomicAdd(&ecnt[v], 1);
         } else {
           const int64_t pos = task_off[v] + atomicAdd(&ecur[v], 1);
-          task_begin[pos] = bu + mu.hfb + i + 1;
+          task_begin[pos] = mu.begin + mu.hfb + i + 1;
           task_len[pos] = a;
           task_owner[pos] = u;
         }
@@ -146,43 +157,25 @@ __global__ __launch_bounds__(kThreads) void plan_kernel(
   }
 }
 
-// Down class for light anchors: x -> w with w in Down(x); t in Up(w), t > x,
-// t in Hfwd(x).  Short down-lists by one thread, long ones by one wave.
+// Down class of light anchors (at most kDnLight down-neighbours): x -> w,
+// t in Up(w), t > x, t in Hfwd(x).
 template <bool kPV>
-__global__ __launch_bounds__(kThreads) void light_down_kernel(const int64_t* off, const int32_t* lc,
-                                                              const VMeta* meta, int64_t n, int light_max,
-                                                              unsigned long long* acc, int64_t* pv) {
+__global__ __launch_bounds__(kThreads) void light_down_kernel(const int32_t* lc, const VMeta* meta, int64_t n,
+                                                              int light_max, unsigned long long* acc,
+                                                              int64_t* pv) {
   __shared__ int64_t sh[kThreads / kWave + 1];
   int64_t cnt = 0, elems = 0, light = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  constexpr int kShortDown = 16;
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += stride) {
     const VMeta m = meta[x];
     const int hf = m.sfe - m.hfb, nd = m.deg - m.sfe;
-    if (hf == 0 || nd == 0 || nd > kShortDown || !is_light(m, light_max)) continue;
-    const int64_t bx = off[x];
+    if (hf == 0 || nd == 0 || is_heavy(m, true, light_max)) continue;
     for (int k = 0; k < nd; ++k) {
-      const int32_t w = lc[bx + m.sfe + k];
-      const int upw = meta[w].up;
-      cnt += merge_count<kPV>(lc + off[w], upw, lc + bx + m.hfb, hf, static_cast<int32_t>(x), pv,
+      const int32_t w = lc[m.begin + m.sfe + k];
+      const VMeta mw = meta[w];
+      cnt += merge_count<kPV>(lc + mw.begin, mw.up, lc + m.begin + m.hfb, hf, static_cast<int32_t>(x), pv,
                               static_cast<int32_t>(x), w);
-      elems += upw;
-      ++light;
-    }
-  }
-  const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
-  const int64_t nw = stride / kWave;
-  for (int64_t x = wid; x < n; x += nw) {
-    const VMeta m = meta[x];
-    const int hf = m.sfe - m.hfb, nd = m.deg - m.sfe;
-    if (hf == 0 || nd <= kShortDown || !is_light(m, light_max)) continue;
-    const int64_t bx = off[x];
-    for (int k = lane(); k < nd; k += kWave) {
-      const int32_t w = lc[bx + m.sfe + k];
-      const int upw = meta[w].up;
-      cnt += merge_count<kPV>(lc + off[w], upw, lc + bx + m.hfb, hf, static_cast<int32_t>(x), pv,
-                              static_cast<int32_t>(x), w);
-      elems += upw;
+      elems += mw.up;
       ++light;
     }
   }
@@ -192,215 +185,283 @@ __global__ __launch_bounds__(kThreads) void light_down_kernel(const int64_t* off
 }
 
 // ---------------------------------------------------------- heavy items
+// Descriptor index space of an anchor: [down | fwd-up | fwd-same | bwd-up | tasks].
 struct Desc {
-  int nB, nC, nD, nE;
-  __device__ __forceinline__ int total() const { return nB + nC + nD + nE; }
+  int nB, nCu, nCs, nD, nE;
+  __device__ __forceinline__ int total() const { return nB + nCu + nCs + nD + nE; }
 };
 
 __device__ __forceinline__ Desc desc_of(const VMeta& m, bool cover, int nE) {
   Desc d;
   const int hf = m.sfe - m.hfb;
   d.nB = (cover && hf > 0) ? m.deg - m.sfe : 0;
-  d.nC = hf;
+  d.nCu = (cover && m.up > 0) ? hf : 0;
+  d.nCs = hf;
   d.nD = (cover && m.up > 0) ? m.hfb - m.up : 0;
   d.nE = nE;
   return d;
 }
 
-__global__ void items_kernel(const VMeta* meta, int64_t n, const int64_t* task_off, bool cover,
-                             int light_max, int chunk, int2* items, unsigned long long* acc) {
+__device__ __forceinline__ int bin_of(int P) {
+  return P <= kBinP0 ? 0 : (P <= kBinP1 ? 1 : (P <= kBinP2 ? 2 : 3));
+}
+
+__host__ __device__ constexpr int bin_chunk(int b) { return b == 0 ? 256 : 1024; }
+
+// kFill = false: count items per bin.  kFill = true: write them.
+template <bool kFill>
+__global__ __launch_bounds__(kThreads) void items_kernel(const VMeta* meta, int64_t n, const int64_t* task_off,
+                                                         bool cover, int light_max, int2* items,
+                                                         unsigned long long* acc) {
+  __shared__ int s_cnt[kBins];
+  __shared__ unsigned long long s_base[kBins];
   for (int64_t x0 = blockIdx.x * (int64_t)blockDim.x; x0 < n; x0 += (int64_t)gridDim.x * blockDim.x) {
+    if (threadIdx.x < kBins) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
     const int64_t x = x0 + threadIdx.x;
-    int k = 0;
+    int k = 0, b = 0, mine = 0;
     if (x < n) {
       const VMeta m = meta[x];
-      if (!is_light(m, light_max)) {
+      if (is_heavy(m, cover, light_max)) {
         const Desc d = desc_of(m, cover, static_cast<int>(task_off[x + 1] - task_off[x]));
-        k = (d.total() + chunk - 1) / chunk;
+        b = bin_of(probe_size(m));
+        const int ch = bin_chunk(b);
+        k = (d.total() + ch - 1) / ch;
+        if (k) mine = atomicAdd(&s_cnt[b], k);
       }
     }
-    const int incl = wave_incl_scan(k);
-    const int tot = __shfl(incl, kWave - 1, kWave);
-    unsigned long long base = 0;
-    if (lane() == kWave - 1 && tot) base = atomicAdd(&acc[kAccItemCtr], static_cast<unsigned long long>(tot));
-    base = __shfl(base, kWave - 1, kWave);
-    for (int j = 0; j < k; ++j) items[base + incl - k + j] = make_int2(static_cast<int>(x), j);
+    __syncthreads();
+    if (threadIdx.x < kBins && s_cnt[threadIdx.x]) {
+      const unsigned long long c = static_cast<unsigned long long>(s_cnt[threadIdx.x]);
+      if (!kFill) atomicAdd(&acc[kAccBinCount + threadIdx.x], c);
+      else s_base[threadIdx.x] = acc[kAccBinOff + threadIdx.x] + atomicAdd(&acc[kAccBinCur + threadIdx.x], c);
+    }
+    __syncthreads();
+    if (kFill && k) {
+      const unsigned long long base = s_base[b] + mine;
+      for (int j = 0; j < k; ++j) items[base + j] = make_int2(static_cast<int>(x), j);
+    }
+    __syncthreads();
   }
+}
+
+__global__ void bin_offsets_kernel(unsigned long long* acc) {
+  unsigned long long run = 0;
+  for (int b = 0; b < kBins; ++b) {
+    acc[kAccBinOff + b] = run;
+    run += acc[kAccBinCount + b];
+  }
+  acc[kAccItems] = run;
 }
 
 __device__ __forceinline__ uint32_t hslot(int32_t key, int shift) {
   return (static_cast<uint32_t>(key) * 0x9E3779B1u) >> shift;
 }
 
-// Membership of t in a sorted global list [p, p + len).
+// Membership of t in a sorted list [p, p + len) in global memory.
 __device__ __forceinline__ bool gsearch(const int32_t* p, int len, int32_t t) {
   int lo = 0, hi = len;
   while (lo < hi) {
     int mid = (lo + hi) >> 1;
-    int32_t v = p[mid];
-    if (v < t) lo = mid + 1;
+    if (p[mid] < t) lo = mid + 1;
     else hi = mid;
   }
   return lo < len && p[lo] == t;
 }
 
-template <bool kCover, bool kPV>
-__global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(
-    const int64_t* off, const int32_t* lc, const VMeta* meta, const int2* items, const int64_t* task_off,
-    const int64_t* task_begin, const int32_t* task_len, const int32_t* task_owner, int chunk,
-    unsigned long long* acc, int64_t* pv) {
-  __shared__ int32_t tab[kTabMax];
-  __shared__ int64_t s_pre[kHeavyThreads + 1];
-  __shared__ int64_t s_beg1[kHeavyThreads];
-  __shared__ int64_t s_beg2[kHeavyThreads];
-  __shared__ int32_t s_len1[kHeavyThreads];
-  __shared__ int32_t s_flt[kHeavyThreads];
-  __shared__ int32_t s_oth[kHeavyThreads];
-  __shared__ uint8_t s_kind[kHeavyThreads];
-  __shared__ int64_t sh[kHeavyThreads / kWave + 1];
-  __shared__ int s_item;
+// One block per work item (anchor x, descriptor chunk).  TAB = hash slots of
+// the LDS table (0: probe the sorted rows instead), D = descriptors per item.
+template <int TAB, int THREADS, int D, bool kCover, bool kPV>
+__global__ __launch_bounds__(THREADS) void heavy_kernel(const int32_t* lc, const VMeta* meta, int bin,
+                                                        const int2* items, const int64_t* task_off,
+                                                        const int64_t* task_begin, const int32_t* task_len,
+                                                        const int32_t* task_owner, unsigned long long* acc,
+                                                        int64_t* pv) {
+  constexpr int R = D / THREADS;  // descriptors resolved per thread
+  static_assert(R * THREADS == D, "D must be a multiple of THREADS");
+  __shared__ int32_t tab[TAB > 0 ? TAB : 1];
+  __shared__ int64_t s_beg[D];
+  __shared__ int64_t s_pre[D + 1];
+  __shared__ int32_t s_flt[D];
+  __shared__ int32_t s_oth[kPV ? D : 1];
+  __shared__ uint8_t s_up[TAB > 0 ? 1 : D];
+  __shared__ int64_t sh[THREADS / kWave + 1];
+  __shared__ unsigned long long s_item;
 
-  const int64_t num_items = static_cast<int64_t>(acc[kAccItemCtr]);
+  const unsigned long long first = acc[kAccBinOff + bin];
+  const unsigned long long count = acc[kAccBinCount + bin];
   const int tid = threadIdx.x;
-  int64_t cnt = 0, elems = 0, descs = 0;
+  int64_t cnt = 0, elems = 0, descs = 0, builds = 0;
   int32_t cur_x = -1;
   for (;;) {
-    if (tid == 0) s_item = static_cast<int>(atomicAdd(&acc[kAccItemNext], 1ull));
+    if (tid == 0) s_item = atomicAdd(&acc[kAccBinNext + bin], 1ull);
     __syncthreads();
-    const int64_t it = s_item;
+    const unsigned long long it = s_item;
     __syncthreads();
-    if (it >= num_items) break;
-    const int2 item = items[it];
+    if (it >= count) break;
+    const int2 item = items[first + it];
     const int32_t x = item.x;
     const VMeta mx = meta[x];
-    const int64_t bx = off[x];
     const int hf = mx.sfe - mx.hfb;
     const int P = mx.up + hf;
     const int64_t toff = task_off[x];
-    const Desc D = desc_of(mx, kCover, static_cast<int>(task_off[x + 1] - toff));
-    const int d0 = item.y * chunk;
-    const int d1 = min(D.total(), d0 + chunk);
-    const bool use_tab = P <= kTabMax / 2;
-    int cap = 64, lg = 6;
-    while (cap < 2 * P) { cap <<= 1; ++lg; }
-    const int shift = 32 - lg;
-    if (use_tab && x != cur_x) {
-      for (int i = tid; i < cap; i += kHeavyThreads) tab[i] = -1;
-      __syncthreads();
-      for (int i = tid; i < P; i += kHeavyThreads) {
-        const int32_t key = i < mx.up ? lc[bx + i] : lc[bx + mx.hfb + (i - mx.up)];
-        uint32_t h = hslot(key, shift);
-        while (atomicCAS(&tab[h], -1, key) != -1) h = (h + 1) & (cap - 1);
+    const Desc Dx = desc_of(mx, kCover, static_cast<int>(task_off[x + 1] - toff));
+    const int d0 = item.y * D;
+    const int nd = min(Dx.total() - d0, D);
+    int cap = 64, shift = 26;
+    if (TAB > 0) {
+      while (cap < 2 * P) {
+        cap <<= 1;
+        --shift;
       }
-      __syncthreads();
-      cur_x = x;
-    } else if (!use_tab) {
-      cur_x = -1;
+      if (x != cur_x) {
+        for (int i = tid; i < cap; i += THREADS) tab[i] = -1;
+        __syncthreads();
+        for (int i = tid; i < P; i += THREADS) {
+          const int32_t key = i < mx.up ? lc[mx.begin + i] : lc[mx.begin + mx.hfb + (i - mx.up)];
+          uint32_t h = hslot(key, shift);
+          while (atomicCAS(&tab[h], -1, key) != -1) h = (h + 1) & (cap - 1);
+        }
+        __syncthreads();
+        cur_x = x;
+        builds += tid == 0 ? P : 0;
+      }
     }
-    descs += d1 - d0;
-    for (int db = d0; db < d1; db += kHeavyThreads) {
-      const int d = db + tid;
-      int len1 = 0, len2 = 0, flt = -1, oth = x;
-      int64_t beg1 = 0, beg2 = 0;
-      uint8_t kind = 0;  // bit0: stream 1 probes Up(x); bit1: stream 2 probes Up(x)
-      if (d < d1) {
-        if (d < D.nB) {  // down class: Up(w) above x
-          const int32_t w = lc[bx + mx.sfe + d];
-          len1 = meta[w].up;
-          beg1 = off[w];
-          flt = x;
-          oth = w;
-        } else if (d < D.nB + D.nC) {  // forward cover edges (x, v)
-          const int i = d - D.nB;
-          const int32_t v = lc[bx + mx.hfb + i];
+    // ---- resolve this item's descriptors (R per thread, independent loads)
+    int64_t lbeg[R];
+    int32_t llen[R], lflt[R], loth[R];
+    bool lup[R];
+    int64_t mysum = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int dl = tid * R + r;
+      const int d = d0 + dl;
+      lbeg[r] = 0;
+      llen[r] = 0;
+      lflt[r] = -1;
+      loth[r] = x;
+      lup[r] = false;
+      if (dl < nd) {
+        int k = d;
+        if (k < Dx.nB) {  // down class: Up(w) above x
+          const int32_t w = lc[mx.begin + mx.sfe + k];
+          const VMeta mw = meta[w];
+          lbeg[r] = mw.begin;
+          llen[r] = mw.up;
+          lflt[r] = x;
+          loth[r] = w;
+        } else if ((k -= Dx.nB) < Dx.nCu) {  // forward cover edge, up class
+          const int32_t v = lc[mx.begin + mx.hfb + k];
           const VMeta mv = meta[v];
-          const int64_t bv = off[v];
-          oth = v;
-          if (kCover && mv.up > 0 && mv.up <= mx.up) {
-            len1 = mv.up;
-            beg1 = bv;
-            kind |= 1;
+          loth[r] = v;
+          if (mv.up > 0 && mv.up <= mx.up) {
+            lbeg[r] = mv.begin;
+            llen[r] = mv.up;
+            lup[r] = true;
           }
-          const int a = hf - i - 1, b = mv.sfe - mv.hfb;
+        } else if ((k -= Dx.nCu) < Dx.nCs) {  // forward cover edge, same class
+          const int32_t v = lc[mx.begin + mx.hfb + k];
+          const VMeta mv = meta[v];
+          loth[r] = v;
+          const int a = hf - k - 1, b = mv.sfe - mv.hfb;
           if (a > 0 && b > 0 && b < a) {
-            len2 = b;
-            beg2 = bv + mv.hfb;
+            lbeg[r] = mv.begin + mv.hfb;
+            llen[r] = b;
           }
-        } else if (d < D.nB + D.nC + D.nD) {  // backward cover edges (u, x), up class
-          const int j = d - D.nB - D.nC;
-          const int32_t u = lc[bx + mx.up + j];
+        } else if ((k -= Dx.nCs) < Dx.nD) {  // backward cover edge, up class
+          const int32_t u = lc[mx.begin + mx.up + k];
           const VMeta mu = meta[u];
-          oth = u;
+          loth[r] = u;
           if (mu.up > 0 && mu.up < mx.up) {
-            len1 = mu.up;
-            beg1 = off[u];
-            kind |= 1;
+            lbeg[r] = mu.begin;
+            llen[r] = mu.up;
+            lup[r] = true;
           }
-        } else {  // emitted same-class tasks: Hfwd(u) above x
-          const int64_t q = toff + (d - D.nB - D.nC - D.nD);
-          len1 = task_len[q];
-          beg1 = task_begin[q];
-          oth = task_owner[q];
+        } else {  // emitted same-class task: Hfwd(u) above x
+          const int64_t q = toff + (k - Dx.nD);
+          lbeg[r] = task_begin[q];
+          llen[r] = task_len[q];
+          loth[r] = task_owner[q];
         }
       }
-      int64_t tot;
-      const int64_t ex = block_excl_scan(static_cast<int64_t>(len1 + len2), sh, &tot);
-      s_pre[tid] = ex;
-      s_beg1[tid] = beg1;
-      s_beg2[tid] = beg2;
-      s_len1[tid] = len1;
-      s_flt[tid] = flt;
-      s_oth[tid] = oth;
-      s_kind[tid] = kind;
-      if (tid == 0) s_pre[kHeavyThreads] = tot;
-      __syncthreads();
-      elems += (tid == 0) ? tot : 0;
-      for (int64_t e = tid; e < tot; e += kHeavyThreads) {
-        // owner thread j: s_pre[j] <= e < s_pre[j + 1]
-        int lo = 0, hi = kHeavyThreads;
+      mysum += llen[r];
+    }
+    int64_t tot;
+    int64_t run = block_excl_scan(mysum, sh, &tot);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int dl = tid * R + r;
+      s_pre[dl] = run;
+      s_beg[dl] = lbeg[r];
+      s_flt[dl] = lflt[r];
+      if (kPV) s_oth[dl] = loth[r];
+      if (TAB == 0) s_up[dl] = lup[r];
+      run += llen[r];
+    }
+    if (tid == 0) s_pre[D] = tot;
+    __syncthreads();
+    if (tid == 0) {
+      elems += tot;
+      descs += nd;
+    }
+    // ---- stream the elements: K consecutive per lane
+    for (int64_t base = 0; base < tot; base += (int64_t)THREADS * kK) {
+      const int64_t e0 = base + (int64_t)tid * kK;
+      if (e0 < tot) {
+        int lo = 0, hi = D;  // largest j with s_pre[j] <= e0
         while (hi - lo > 1) {
           const int mid = (lo + hi) >> 1;
-          if (s_pre[mid] <= e) lo = mid;
+          if (s_pre[mid] <= e0) lo = mid;
           else hi = mid;
         }
-        const int j = lo;
-        const int64_t r = e - s_pre[j];
-        const int l1 = s_len1[j];
-        int64_t addr;
-        int32_t fl;
-        bool up_probe;
-        if (r < l1) {
-          addr = s_beg1[j] + r;
-          fl = s_flt[j];
-          up_probe = s_kind[j] & 1;
-        } else {
-          addr = s_beg2[j] + (r - l1);
-          fl = -1;
-          up_probe = (s_kind[j] >> 1) & 1;
-        }
-        const int32_t t = lc[addr];
-        if (t > fl) {
-          bool hit;
-          if (use_tab) {
-            uint32_t h = hslot(t, shift);
-            int32_t k;
-            while ((k = tab[h]) != t && k != -1) h = (h + 1) & (cap - 1);
-            hit = k == t;
+        int j = lo;
+        int64_t addr[kK];
+        int32_t flt[kK];
+        int jj[kK];
+#pragma unroll
+        for (int q = 0; q < kK; ++q) {
+          const int64_t e = e0 + q;
+          if (e < tot) {
+            while (s_pre[j + 1] <= e) ++j;
+            addr[q] = s_beg[j] + (e - s_pre[j]);
+            flt[q] = s_flt[j];
+            jj[q] = j;
           } else {
-            hit = up_probe ? gsearch(lc + bx, mx.up, t) : gsearch(lc + bx + mx.hfb, hf, t);
+            addr[q] = -1;
+            flt[q] = 0x7FFFFFFF;
+            jj[q] = j;
           }
-          if (hit) {
-            ++cnt;
-            if (kPV) add_pv(pv, x, s_oth[j], t);
+        }
+        int32_t val[kK];
+#pragma unroll
+        for (int q = 0; q < kK; ++q) val[q] = addr[q] >= 0 ? lc[addr[q]] : -1;
+#pragma unroll
+        for (int q = 0; q < kK; ++q) {
+          const int32_t t = val[q];
+          if (t > flt[q]) {
+            bool hit;
+            if (TAB > 0) {
+              uint32_t h = hslot(t, shift);
+              int32_t k;
+              while ((k = tab[h]) != t && k != -1) h = (h + 1) & (cap - 1);
+              hit = k == t;
+            } else {
+              hit = s_up[jj[q]] ? gsearch(lc + mx.begin, mx.up, t) : gsearch(lc + mx.begin + mx.hfb, hf, t);
+            }
+            if (hit) {
+              ++cnt;
+              if (kPV) add_pv(pv, x, s_oth[jj[q]], t);
+            }
           }
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
   block_acc(acc, kAccT, cnt, sh);
-  block_acc(acc, kAccElems, elems, sh);
+  block_acc(acc, kAccHeavyElems, elems, sh);
   block_acc(acc, kAccDesc, descs, sh);
+  block_acc(acc, kAccBuild, builds, sh);
 }
 
 __global__ void finish_kernel(const unsigned long long* acc, const int64_t* h_off, int64_t n,
@@ -408,10 +469,13 @@ __global__ void finish_kernel(const unsigned long long* acc, const int64_t* h_of
   *triangles = static_cast<int64_t>(acc[kAccT]);
   if (h_count) *h_count = h_off[n];
   stats[2] = h_off[n];
-  stats[4] = static_cast<int64_t>(acc[kAccElems]);
+  stats[4] = static_cast<int64_t>(acc[kAccElems] + acc[kAccHeavyElems]);
   stats[5] = static_cast<int64_t>(acc[kAccLight]);
-  stats[6] = static_cast<int64_t>(acc[kAccItemCtr]);
+  stats[6] = static_cast<int64_t>(acc[kAccItems]);
   stats[7] = static_cast<int64_t>(acc[kAccDesc]);
+  stats[8] = static_cast<int64_t>(acc[kAccHeavyElems]);
+  stats[9] = static_cast<int64_t>(acc[kAccBuild]);
+  stats[10] = static_cast<int64_t>(acc[kAccElems]);
 }
 
 __global__ void forward_meta_kernel(const int64_t* off, const int32_t* cols, int64_t n, VMeta* meta) {
@@ -420,8 +484,16 @@ __global__ void forward_meta_kernel(const int64_t* off, const int32_t* cols, int
     const int64_t b = off[x], e = off[x + 1];
     const int64_t fb = upper_bound_dev(cols, b, e, static_cast<int32_t>(x));
     const int32_t deg = static_cast<int32_t>(e - b);
-    meta[x] = VMeta{0, static_cast<int32_t>(fb - b), deg, deg};
+    meta[x] = VMeta{b, 0, static_cast<int32_t>(fb - b), deg, deg, {0, 0}};
   }
+}
+
+template <int TAB, int THREADS, int D, bool kCover, bool kPV>
+int launch_heavy(const CountArgs& a, CountWs& w, int bin, int blocks_per_cu, hipStream_t s) {
+  heavy_kernel<TAB, THREADS, D, kCover, kPV><<<static_cast<unsigned>(num_cus() * blocks_per_cu), THREADS, 0, s>>>(
+      a.cols, a.meta, bin, w.items, w.task_off, w.task_begin, w.task_len, w.task_owner, w.acc, a.per_vertex_out);
+  TC_HIP(hipGetLastError());
+  return TC_OK;
 }
 
 template <bool kCover, bool kPV>
@@ -430,29 +502,32 @@ int launch_all(const CountArgs& a, CountWs& w, hipStream_t s) {
   const int64_t n = g->n;
   const unsigned gedge = static_cast<unsigned>(num_cus() * 16);
   plan_kernel<kCover, kPV, false><<<gedge, kThreads, 0, s>>>(
-      g->row_offsets, a.cols, a.meta, n, w.h_off, w.h_u, w.h_v, a.light_max, w.ecnt, w.task_off,
-      w.ecur, w.task_begin, w.task_len, w.task_owner, w.acc, a.per_vertex_out);
+      a.cols, a.meta, n, w.h_off, w.h_u, w.h_v, a.light_max, w.ecnt, w.task_off, w.ecur, w.task_begin,
+      w.task_len, w.task_owner, w.acc, a.per_vertex_out);
   TC_HIP(hipGetLastError());
   prof_stage("light_down");
   if (kCover) {
-    light_down_kernel<kPV><<<gedge, kThreads, 0, s>>>(g->row_offsets, a.cols, a.meta, n, a.light_max, w.acc,
-                                                      a.per_vertex_out);
+    light_down_kernel<kPV><<<grid_for(n, kThreads, 16384), kThreads, 0, s>>>(a.cols, a.meta, n, a.light_max,
+                                                                             w.acc, a.per_vertex_out);
     TC_HIP(hipGetLastError());
   }
   prof_stage("plan_tasks");
   Carver sc(w.scratch);
   TC_TRY(scan_exclusive<int32_t>(w.ecnt, w.task_off, n, sc, s));
   plan_kernel<kCover, kPV, true><<<gedge, kThreads, 0, s>>>(
-      g->row_offsets, a.cols, a.meta, n, w.h_off, w.h_u, w.h_v, a.light_max, w.ecnt, w.task_off,
-      w.ecur, w.task_begin, w.task_len, w.task_owner, w.acc, a.per_vertex_out);
-  items_kernel<<<grid_for(n, kThreads, 16384), kThreads, 0, s>>>(a.meta, n, w.task_off, kCover, a.light_max,
-                                                                 a.heavy_chunk, w.items, w.acc);
+      a.cols, a.meta, n, w.h_off, w.h_u, w.h_v, a.light_max, w.ecnt, w.task_off, w.ecur, w.task_begin,
+      w.task_len, w.task_owner, w.acc, a.per_vertex_out);
+  const unsigned gv = grid_for(n, kThreads, 16384);
+  items_kernel<false><<<gv, kThreads, 0, s>>>(a.meta, n, w.task_off, kCover, a.light_max, w.items, w.acc);
+  bin_offsets_kernel<<<1, 1, 0, s>>>(w.acc);
+  items_kernel<true><<<gv, kThreads, 0, s>>>(a.meta, n, w.task_off, kCover, a.light_max, w.items, w.acc);
   TC_HIP(hipGetLastError());
   prof_stage("heavy");
-  heavy_kernel<kCover, kPV><<<static_cast<unsigned>(num_cus() * 8), kHeavyThreads, 0, s>>>(
-      g->row_offsets, a.cols, a.meta, w.items, w.task_off, w.task_begin, w.task_len, w.task_owner,
-      a.heavy_chunk, w.acc, a.per_vertex_out);
-  TC_HIP(hipGetLastError());
+  TC_TRY((launch_heavy<32768, 1024, 1024, kCover, kPV>(a, w, 2, 1, s)));
+  TC_TRY((launch_heavy<4096, 512, 1024, kCover, kPV>(a, w, 1, 4, s)));
+  TC_TRY((launch_heavy<512, 256, 256, kCover, kPV>(a, w, 0, 8, s)));
+  TC_TRY((launch_heavy<0, 512, 1024, kCover, kPV>(a, w, 3, 4, s)));
+  prof_stage("finish");
   return TC_OK;
 }
 
@@ -471,8 +546,10 @@ CountWs count_reserve(Carver& c, int64_t n, int64_t nnz) {
   w.task_begin = c.take<int64_t>(hmax);
   w.task_len = c.take<int32_t>(hmax);
   w.task_owner = c.take<int32_t>(hmax);
-  w.items = c.take<int2>(n + nnz + 2);
-  w.acc = c.take<unsigned long long>(16);
+  // items: one per heavy anchor plus one per started chunk of >= 256
+  // descriptors; descriptors per anchor <= 2 deg + emitted tasks
+  w.items = c.take<int2>(n + (3 * nnz) / 256 + 8);
+  w.acc = c.take<unsigned long long>(kAccSlots);
   w.stats = c.take<int64_t>(16);
   w.scratch = c.take<char>(scan_ws_bytes(n + 1) + (n + 1) * sizeof(int32_t) + 256);
   return w;
@@ -480,8 +557,7 @@ CountWs count_reserve(Carver& c, int64_t n, int64_t nnz) {
 
 int forward_meta_run(const tc_csr* g, VMeta* meta, hipStream_t s) {
   if (g->n == 0) return TC_OK;
-  forward_meta_kernel<<<grid_for(g->n, kThreads, 16384), kThreads, 0, s>>>(g->row_offsets, g->cols, g->n,
-                                                                          meta);
+  forward_meta_kernel<<<grid_for(g->n, kThreads, 16384), kThreads, 0, s>>>(g->row_offsets, g->cols, g->n, meta);
   TC_HIP(hipGetLastError());
   return TC_OK;
 }
@@ -489,7 +565,7 @@ int forward_meta_run(const tc_csr* g, VMeta* meta, hipStream_t s) {
 int count_run(const CountArgs& a, CountWs& w, int64_t* triangles, int64_t* h_count, hipStream_t s) {
   const tc_csr* g = a.g;
   const int64_t n = g->n;
-  TC_TRY(fill_i64(reinterpret_cast<int64_t*>(w.acc), 0, 16, s));
+  TC_TRY(fill_i64(reinterpret_cast<int64_t*>(w.acc), 0, kAccSlots, s));
   TC_TRY(fill_i64(w.stats, 0, 16, s));
   if (n == 0) {
     TC_TRY(fill_i64(triangles, 0, 1, s));

@@ -33,55 +33,58 @@ static std::atomic<int> g_prof_on{0};
 struct ProfCall {
   hipStream_t stream = nullptr;
   std::vector<std::string> names;
-  std::vector<hipEvent_t> marks;  // marks[i] opens stage i, marks[i+1] closes it
+  std::vector<hipEvent_t> pool;  // reused across calls
+  int used = 0;                  // marks[i] = pool[i] opens stage i, pool[i+1] closes it
   bool open = false;
 };
 static thread_local ProfCall g_prof;
 
-static void prof_reset() {
-  for (hipEvent_t e : g_prof.marks) (void)hipEventDestroy(e);
-  g_prof.marks.clear();
-  g_prof.names.clear();
-  g_prof.open = false;
+static hipEvent_t prof_next_event() {
+  if (g_prof.used == static_cast<int>(g_prof.pool.size())) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_prof.pool.push_back(e);
+  }
+  return g_prof.pool[g_prof.used++];
 }
 
 void prof_begin_call(hipStream_t s) {
   if (!g_prof_on.load()) return;
-  prof_reset();
+  g_prof.used = 0;
+  g_prof.names.clear();
+  g_prof.open = false;
   g_prof.stream = s;
 }
 
 void prof_stage(const char* name) {
   if (!g_prof_on.load()) return;
   if (g_prof.names.size() >= TC_PROFILE_MAX_STAGES) return;
-  hipEvent_t e;
-  if (hipEventCreate(&e) != hipSuccess) return;
+  hipEvent_t e = prof_next_event();
+  if (!e) return;
   (void)hipEventRecord(e, g_prof.stream);
-  g_prof.marks.push_back(e);
   g_prof.names.push_back(name);
   g_prof.open = true;
 }
 
 void prof_end_call() {
   if (!g_prof_on.load() || !g_prof.open) return;
-  hipEvent_t e;
-  if (hipEventCreate(&e) != hipSuccess) return;
+  hipEvent_t e = prof_next_event();
+  if (!e) return;
   (void)hipEventRecord(e, g_prof.stream);
-  g_prof.marks.push_back(e);
   g_prof.open = false;
 }
 
 int prof_read(tc_profile* out) {
   memset(out, 0, sizeof *out);
-  if (g_prof.marks.size() < 2) return TC_OK;
-  TC_HIP(hipEventSynchronize(g_prof.marks.back()));
-  int ns = static_cast<int>(g_prof.marks.size()) - 1;
+  if (g_prof.used < 2 || g_prof.open) return TC_OK;
+  TC_HIP(hipEventSynchronize(g_prof.pool[g_prof.used - 1]));
+  int ns = g_prof.used - 1;
   if (ns > TC_PROFILE_MAX_STAGES) ns = TC_PROFILE_MAX_STAGES;
   out->num_stages = ns;
   for (int i = 0; i < ns; ++i) {
     strncpy(out->names[i], g_prof.names[i].c_str(), sizeof out->names[i] - 1);
     float ms = 0.f;
-    TC_HIP(hipEventElapsedTime(&ms, g_prof.marks[i], g_prof.marks[i + 1]));
+    TC_HIP(hipEventElapsedTime(&ms, g_prof.pool[i], g_prof.pool[i + 1]));
     out->ms[i] = ms;
   }
   return TC_OK;

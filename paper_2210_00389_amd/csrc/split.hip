@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kThreads) void split_short_kernel(const int64_t* of
       int pos = c == 0 ? pu++ : (c == 1 ? ps++ : pd++);
       scols[b + pos] = w;
     }
-    meta[x] = VMeta{up, up + slt, up + same, deg};
+    meta[x] = VMeta{b, up, up + slt, up + same, deg, {0, 0}};
   }
 }
 
@@ -155,7 +155,7 @@ __global__ void seg_prefix_kernel(const int64_t* off, int64_t n, const int32_t* 
       slt += seg_cnt[3 * sg + 2];
     }
     const int32_t deg = static_cast<int32_t>(off[x + 1] - off[x]);
-    meta[x] = VMeta{up, up + slt, up + same, deg};
+    meta[x] = VMeta{off[x], up, up + slt, up + same, deg, {0, 0}};
   }
 }
 

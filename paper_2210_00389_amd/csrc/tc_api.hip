@@ -295,7 +295,7 @@ int tc_read_stats(const void* ws, tc_stats* out, tc_stream_t stream) {
   if (!ws || !out) return fail(TC_ERR_INVALID_ARG, "tc_read_stats: NULL");
   memset(out, 0, sizeof *out);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  TC_HIP(hipMemcpyAsync(out, ws, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipMemcpyAsync(out, ws, 16 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
   return TC_OK;
 }

@@ -38,8 +38,11 @@ int bfs_run(const tc_csr* g, int64_t root, int32_t* L, int32_t* num_levels, BfsW
 //   Down  = [sfe, deg) neighbours one level further
 // Each class is ascending.  For the comparator the same record describes the
 // plain forward lists: up = 0, hfb = first neighbour > x, sfe = deg.
-struct VMeta {
+// `begin` repeats row_offsets[x] so that one 32-byte read resolves a vertex.
+struct alignas(32) VMeta {
+  int64_t begin;
   int32_t up, hfb, sfe, deg;
+  int32_t pad[2];
 };
 
 struct SplitWs {

@@ -296,3 +296,13 @@ def test_golden_rmat_s10_reproduces():
     assert (c.n, c.m) == (gold["n"], gold["m"])
     assert hashlib.sha256(lv.levels.astype("<i4").tobytes()).hexdigest() == gold["levels_sha256"]
     assert oracle.count(c, lv.levels).triangles == gold["triangles"] == gold["edge_iterator_triangles"]
+
+
+def test_count_rows_partition_sums_to_T():
+    c = csr_of(graphgen.rmat(11, 16, seed=4))
+    L = oracle.bfs_levels(c).levels
+    T = oracle.count(c, L).triangles
+    cuts = [0, 100, 700, 1500, c.n]
+    parts = [oracle.count_rows(c, L, a, b) for a, b in zip(cuts, cuts[1:])]
+    assert sum(parts) == T
+    assert oracle.count_rows(c, L, 0, c.n, mode=1) == T
