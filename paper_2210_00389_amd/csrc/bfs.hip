@@ -280,6 +280,7 @@ BfsWs bfs_reserve(Carver& c, int64_t n) {
   w.root = c.take<int64_t>(1);
   w.scratch = c.take<char>(scan_ws_bytes(n + 1));
   w.scratch_bytes = scan_ws_bytes(n + 1);
+  w.comp0 = nullptr;
   return w;
 }
 
@@ -353,11 +354,18 @@ static int bfs_loop(const tc_csr* g, int32_t* L, BfsWs& w, int64_t f, int64_t ef
   return TC_OK;
 }
 
+__global__ void copy_words_kernel(const uint32_t* src, uint32_t* dst, int64_t words) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 int bfs_run(const tc_csr* g, int64_t root, int32_t* L, int32_t* num_levels, BfsWs& w,
-            hipStream_t s) {
+            hipStream_t s, int32_t* first_levels) {
   const int64_t n = g->n;
   if (n == 0) {
     if (num_levels) *num_levels = 0;
+    if (first_levels) *first_levels = 0;
     return TC_OK;
   }
   const int64_t words = (n + 31) / 32 + 1;
@@ -377,6 +385,11 @@ int bfs_run(const tc_csr* g, int64_t root, int32_t* L, int32_t* num_levels, BfsW
   int32_t lv0 = 0;
   int64_t unexplored = g->nnz;
   TC_TRY(bfs_loop(g, L, w, host[0], host[1], unexplored, &lv0, s));
+  if (first_levels) *first_levels = lv0;
+  if (w.comp0) {
+    copy_words_kernel<<<grid_for(words, kThreads, 16384), kThreads, 0, s>>>(w.vis, w.comp0, words);
+    TC_HIP(hipGetLastError());
+  }
   // Remaining components (Alg. 1 rescans for unvisited vertices): one
   // union-find pass over the unreached vertices gives each component its
   // smallest id as root.

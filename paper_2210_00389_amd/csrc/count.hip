@@ -44,14 +44,29 @@ constexpr int kDnLight = 16;  // light anchors have at most this many down-neigh
 constexpr int kK = 8;         // elements per lane per round
 constexpr int kBins = 4;
 
-// bin limits on the probe-set size P
-constexpr int kBinP0 = 256, kBinP1 = 2048, kBinP2 = 16384;
+// Bins of heavy anchors by the LDS table they need: 2 KB, 16 KB, 128 KB, or
+// none (bin 3: search the sorted rows).  The probe set P(x) = Up(x) ∪ Hfwd(x)
+// lies in the id window [min P, max P] of R ids; it is held as a bitmap of R
+// bits when that is at most about four words per member (so setting it up
+// costs O(|P|)), else as a hash table of 2|P| (rounded up) slots.
+constexpr int kBinWords0 = 512, kBinWords1 = 4096, kBinWords2 = 32768;
+
+__host__ __device__ constexpr int bin_words(int b) {
+  return b == 0 ? kBinWords0 : (b == 1 ? kBinWords1 : (b == 2 ? kBinWords2 : 0));
+}
+
+__device__ __forceinline__ bool bitmap_fits(int64_t R, int P, int words) {
+  const int64_t need = (R + 31) >> 5;
+  return need <= words && need <= 4 * static_cast<int64_t>(P) + 64;
+}
+
+__device__ __forceinline__ bool hash_fits(int P, int words) { return 2 * P <= words; }
 
 enum Acc {
   kAccT = 0, kAccElems = 1, kAccLight = 2, kAccBuild = 3, kAccDesc = 4, kAccItems = 5,
-  kAccHeavyElems = 6, kAccBinCount = 8, kAccBinOff = 12, kAccBinCur = 16, kAccBinNext = 20
+  kAccHeavyElems = 6, kAccBinCount = 8, kAccBinOff = 13, kAccBinCur = 18, kAccBinNext = 23
 };
-constexpr int kAccSlots = 24;
+constexpr int kAccSlots = 28;
 
 __device__ __forceinline__ void add_pv(int64_t* pv, int32_t a, int32_t b, int32_t c) {
   atomicAdd(reinterpret_cast<unsigned long long*>(&pv[a]), 1ull);
@@ -78,6 +93,17 @@ __device__ __forceinline__ int64_t merge_count(const int32_t* S, int ns, const i
     }
   }
   return c;
+}
+
+// Membership of t in a sorted list [p, p + len) in global memory.
+__device__ __forceinline__ bool gsearch(const int32_t* p, int len, int32_t t) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (p[mid] < t) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo < len && p[lo] == t;
 }
 
 __device__ __forceinline__ int probe_size(const VMeta& m) { return m.up + (m.sfe - m.hfb); }
@@ -157,8 +183,10 @@ __global__ __launch_bounds__(kThreads) void plan_kernel(
   }
 }
 
-// Down class of light anchors (at most kDnLight down-neighbours): x -> w,
-// t in Up(w), t > x, t in Hfwd(x).
+// Down class of light anchors (at most kDnLight down-neighbours): one
+// thread per pair (x, k-th down-neighbour w) counts |Up(w) ∩ Hfwd(x)| (every
+// element of Hfwd(x) lies above x, so no filter is needed), by a merge, or
+// by searching the short list in the long one when Up(w) is long.
 template <bool kPV>
 __global__ __launch_bounds__(kThreads) void light_down_kernel(const int32_t* lc, const VMeta* meta, int64_t n,
                                                               int light_max, unsigned long long* acc,
@@ -166,18 +194,31 @@ __global__ __launch_bounds__(kThreads) void light_down_kernel(const int32_t* lc,
   __shared__ int64_t sh[kThreads / kWave + 1];
   int64_t cnt = 0, elems = 0, light = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += stride) {
+  const int64_t total = n * kDnLight;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total; idx += stride) {
+    const int64_t x = idx / kDnLight;
+    const int k = static_cast<int>(idx % kDnLight);
     const VMeta m = meta[x];
     const int hf = m.sfe - m.hfb, nd = m.deg - m.sfe;
-    if (hf == 0 || nd == 0 || is_heavy(m, true, light_max)) continue;
-    for (int k = 0; k < nd; ++k) {
-      const int32_t w = lc[m.begin + m.sfe + k];
-      const VMeta mw = meta[w];
-      cnt += merge_count<kPV>(lc + mw.begin, mw.up, lc + m.begin + m.hfb, hf, static_cast<int32_t>(x), pv,
-                              static_cast<int32_t>(x), w);
+    if (hf == 0 || k >= nd || is_heavy(m, true, light_max)) continue;
+    const int32_t w = lc[m.begin + m.sfe + k];
+    const VMeta mw = meta[w];
+    const int32_t* S = lc + mw.begin;
+    const int32_t* P = lc + m.begin + m.hfb;
+    if (mw.up > 4 * hf) {
+      for (int i = 0; i < hf; ++i) {
+        const int32_t t = P[i];
+        if (gsearch(S, mw.up, t)) {
+          ++cnt;
+          if (kPV) add_pv(pv, static_cast<int32_t>(x), w, t);
+        }
+      }
+      elems += hf;
+    } else {
+      cnt += merge_count<kPV>(S, mw.up, P, hf, -1, pv, static_cast<int32_t>(x), w);
       elems += mw.up;
-      ++light;
     }
+    ++light;
   }
   block_acc(acc, kAccT, cnt, sh);
   block_acc(acc, kAccElems, elems, sh);
@@ -202,15 +243,34 @@ __device__ __forceinline__ Desc desc_of(const VMeta& m, bool cover, int nE) {
   return d;
 }
 
-__device__ __forceinline__ int bin_of(int P) {
-  return P <= kBinP0 ? 0 : (P <= kBinP1 ? 1 : (P <= kBinP2 ? 2 : 3));
+// Id window [lo, lo + R) of the probe set (R = 0 when it is empty).
+__device__ __forceinline__ void probe_window(const int32_t* lc, const VMeta& m, int32_t& lo, int64_t& R) {
+  const int hf = m.sfe - m.hfb;
+  int32_t mn = 0x7FFFFFFF, mx = -1;
+  if (m.up > 0) {
+    mn = lc[m.begin];
+    mx = lc[m.begin + m.up - 1];
+  }
+  if (hf > 0) {
+    mn = min(mn, lc[m.begin + m.hfb]);
+    mx = max(mx, lc[m.begin + m.sfe - 1]);
+  }
+  lo = mn;
+  R = mx >= mn ? static_cast<int64_t>(mx) - mn + 1 : 0;
+}
+
+__device__ __forceinline__ int bin_of(int64_t R, int P) {
+  for (int b = 0; b < 3; ++b)
+    if (bitmap_fits(R, P, bin_words(b)) || hash_fits(P, bin_words(b))) return b;
+  return 3;
 }
 
 __host__ __device__ constexpr int bin_chunk(int b) { return b == 0 ? 256 : 1024; }
 
 // kFill = false: count items per bin.  kFill = true: write them.
 template <bool kFill>
-__global__ __launch_bounds__(kThreads) void items_kernel(const VMeta* meta, int64_t n, const int64_t* task_off,
+__global__ __launch_bounds__(kThreads) void items_kernel(const int32_t* lc, const VMeta* meta, int64_t n,
+                                                         const int64_t* task_off,
                                                          bool cover, int light_max, int2* items,
                                                          unsigned long long* acc) {
   __shared__ int s_cnt[kBins];
@@ -224,7 +284,10 @@ __global__ __launch_bounds__(kThreads) void items_kernel(const VMeta* meta, int6
       const VMeta m = meta[x];
       if (is_heavy(m, cover, light_max)) {
         const Desc d = desc_of(m, cover, static_cast<int>(task_off[x + 1] - task_off[x]));
-        b = bin_of(probe_size(m));
+        int32_t lo;
+        int64_t R;
+        probe_window(lc, m, lo, R);
+        b = bin_of(R, probe_size(m));
         const int ch = bin_chunk(b);
         k = (d.total() + ch - 1) / ch;
         if (k) mine = atomicAdd(&s_cnt[b], k);
@@ -258,20 +321,45 @@ __device__ __forceinline__ uint32_t hslot(int32_t key, int shift) {
   return (static_cast<uint32_t>(key) * 0x9E3779B1u) >> shift;
 }
 
-// Membership of t in a sorted list [p, p + len) in global memory.
-__device__ __forceinline__ bool gsearch(const int32_t* p, int len, int32_t t) {
-  int lo = 0, hi = len;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (p[mid] < t) lo = mid + 1;
-    else hi = mid;
+
+enum ProbeMode { kBitmap = 0, kHash = 1, kSearch = 2 };
+
+// Membership of t in the anchor's probe set: LDS bitmap over the id window
+// [lo, lo + R), LDS hash table, or binary search in the sorted Up / Hfwd
+// segments of the anchor's row.
+template <int MODE>
+__device__ __forceinline__ bool probe(const uint32_t* tab, int cap, int shift, int32_t lo, uint32_t R,
+                                      const int32_t* lc, const VMeta& mx, bool up_side, int32_t t) {
+  if (MODE == kBitmap) {
+    const uint32_t d = static_cast<uint32_t>(t - lo);
+    const bool in = d < R;
+    const uint32_t word = tab[in ? (d >> 5) : 0];
+    return in && ((word >> (d & 31)) & 1u);
+  } else if (MODE == kHash) {
+    uint32_t h = hslot(t, shift);
+    int32_t k;
+    while ((k = static_cast<int32_t>(tab[h])) != t && k != -1) h = (h + 1) & (cap - 1);
+    return k == t;
   }
-  return lo < len && p[lo] == t;
+  return up_side ? gsearch(lc + mx.begin, mx.up, t) : gsearch(lc + mx.begin + mx.hfb, mx.sfe - mx.hfb, t);
 }
 
-// One block per work item (anchor x, descriptor chunk).  TAB = hash slots of
-// the LDS table (0: probe the sorted rows instead), D = descriptors per item.
-template <int TAB, int THREADS, int D, bool kCover, bool kPV>
+// `mode` is the same for the whole block (one item at a time).
+__device__ __forceinline__ bool probe_any(int mode, const uint32_t* tab, int cap, int shift, int32_t lo, uint32_t R,
+                                          const int32_t* lc, const VMeta& mx, bool up_side, int32_t t) {
+  if (mode == kBitmap) return probe<kBitmap>(tab, cap, shift, lo, R, lc, mx, up_side, t);
+  if (mode == kHash) return probe<kHash>(tab, cap, shift, lo, R, lc, mx, up_side, t);
+  return probe<kSearch>(tab, cap, shift, lo, R, lc, mx, up_side, t);
+}
+
+// One block per work item (anchor x, descriptor chunk).  WORDS is the LDS
+// table size in 32-bit words (0: search the sorted rows); each item picks a
+// bitmap or a hash table (see bitmap_fits); D = descriptors per item.  Short streams (<= kShortStream elements) are handled by the lane
+// that resolved them, with all loads issued before the probes; longer
+// streams are flattened across the block, K consecutive elements per lane.
+constexpr int kShortStream = 16;
+
+template <int WORDS, int THREADS, int D, bool kCover, bool kPV>
 __global__ __launch_bounds__(THREADS) void heavy_kernel(const int32_t* lc, const VMeta* meta, int bin,
                                                         const int2* items, const int64_t* task_off,
                                                         const int64_t* task_begin, const int32_t* task_len,
@@ -279,13 +367,14 @@ __global__ __launch_bounds__(THREADS) void heavy_kernel(const int32_t* lc, const
                                                         int64_t* pv) {
   constexpr int R = D / THREADS;  // descriptors resolved per thread
   static_assert(R * THREADS == D, "D must be a multiple of THREADS");
-  __shared__ int32_t tab[TAB > 0 ? TAB : 1];
+  __shared__ uint32_t tab[WORDS > 0 ? WORDS : 1];
   __shared__ int64_t s_beg[D];
   __shared__ int64_t s_pre[D + 1];
   __shared__ int32_t s_flt[D];
   __shared__ int32_t s_oth[kPV ? D : 1];
-  __shared__ uint8_t s_up[TAB > 0 ? 1 : D];
+  __shared__ uint8_t s_up[WORDS == 0 ? D : 1];
   __shared__ int64_t sh[THREADS / kWave + 1];
+  __shared__ int32_t shi[THREADS / kWave + 1];
   __shared__ unsigned long long s_item;
 
   const unsigned long long first = acc[kAccBinOff + bin];
@@ -309,40 +398,62 @@ __global__ __launch_bounds__(THREADS) void heavy_kernel(const int32_t* lc, const
     const int d0 = item.y * D;
     const int nd = min(Dx.total() - d0, D);
     int cap = 64, shift = 26;
-    if (TAB > 0) {
-      while (cap < 2 * P) {
-        cap <<= 1;
-        --shift;
-      }
+    int32_t wlo = 0;
+    uint32_t wR = 0;
+    int mode = kSearch;
+    if (WORDS > 0) {
+      int64_t R64;
+      probe_window(lc, mx, wlo, R64);
+      wR = static_cast<uint32_t>(R64);
+      mode = bitmap_fits(R64, P, WORDS) ? kBitmap : kHash;
       if (x != cur_x) {
-        for (int i = tid; i < cap; i += THREADS) tab[i] = -1;
-        __syncthreads();
-        for (int i = tid; i < P; i += THREADS) {
-          const int32_t key = i < mx.up ? lc[mx.begin + i] : lc[mx.begin + mx.hfb + (i - mx.up)];
-          uint32_t h = hslot(key, shift);
-          while (atomicCAS(&tab[h], -1, key) != -1) h = (h + 1) & (cap - 1);
+        if (mode == kBitmap) {
+          const int words = static_cast<int>((R64 + 31) >> 5);
+          for (int i = tid; i < words; i += THREADS) tab[i] = 0u;
+          __syncthreads();
+          for (int i = tid; i < P; i += THREADS) {
+            const int32_t key = i < mx.up ? lc[mx.begin + i] : lc[mx.begin + mx.hfb + (i - mx.up)];
+            const uint32_t d = static_cast<uint32_t>(key - wlo);
+            atomicOr(&tab[d >> 5], 1u << (d & 31));
+          }
+        } else {
+          while (cap < 2 * P) {
+            cap <<= 1;
+            --shift;
+          }
+          for (int i = tid; i < cap; i += THREADS) tab[i] = 0xFFFFFFFFu;
+          __syncthreads();
+          for (int i = tid; i < P; i += THREADS) {
+            const int32_t key = i < mx.up ? lc[mx.begin + i] : lc[mx.begin + mx.hfb + (i - mx.up)];
+            uint32_t h = hslot(key, shift);
+            while (atomicCAS(&tab[h], 0xFFFFFFFFu, static_cast<uint32_t>(key)) != 0xFFFFFFFFu)
+              h = (h + 1) & (cap - 1);
+          }
         }
         __syncthreads();
         cur_x = x;
         builds += tid == 0 ? P : 0;
+      } else if (mode == kHash) {
+        while (cap < 2 * P) {
+          cap <<= 1;
+          --shift;
+        }
       }
     }
     // ---- resolve this item's descriptors (R per thread, independent loads)
     int64_t lbeg[R];
     int32_t llen[R], lflt[R], loth[R];
     bool lup[R];
-    int64_t mysum = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int dl = tid * R + r;
-      const int d = d0 + dl;
       lbeg[r] = 0;
       llen[r] = 0;
       lflt[r] = -1;
       loth[r] = x;
       lup[r] = false;
       if (dl < nd) {
-        int k = d;
+        int k = d0 + dl;
         if (k < Dx.nB) {  // down class: Up(w) above x
           const int32_t w = lc[mx.begin + mx.sfe + k];
           const VMeta mw = meta[w];
@@ -384,37 +495,69 @@ __global__ __launch_bounds__(THREADS) void heavy_kernel(const int32_t* lc, const
           loth[r] = task_owner[q];
         }
       }
-      mysum += llen[r];
     }
-    int64_t tot;
-    int64_t run = block_excl_scan(mysum, sh, &tot);
+    // ---- short streams: by the resolving lane, all loads before the probes
+    int64_t longsum = 0;
+    int nlong = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int dl = tid * R + r;
-      s_pre[dl] = run;
-      s_beg[dl] = lbeg[r];
-      s_flt[dl] = lflt[r];
-      if (kPV) s_oth[dl] = loth[r];
-      if (TAB == 0) s_up[dl] = lup[r];
-      run += llen[r];
+      const int len = llen[r];
+      if (len > kShortStream) {
+        longsum += len;
+        ++nlong;
+        continue;
+      }
+      if (len == 0) continue;
+      int32_t val[kShortStream];
+#pragma unroll
+      for (int q = 0; q < kShortStream; ++q) val[q] = q < len ? lc[lbeg[r] + q] : -1;
+#pragma unroll
+      for (int q = 0; q < kShortStream; ++q) {
+        const int32_t t = val[q];
+        if (q < len && t > lflt[r] && probe_any(mode, tab, cap, shift, wlo, wR, lc, mx, lup[r], t)) {
+          ++cnt;
+          if (kPV) add_pv(pv, x, loth[r], t);
+        }
+      }
+      elems += len;
     }
-    if (tid == 0) s_pre[D] = tot;
+    // ---- long streams: compact them, then flatten across the block
+    int32_t ltot;
+    const int32_t lfirst = block_excl_scan(nlong, shi, &ltot);
+    int64_t tot;
+    int64_t run = block_excl_scan(longsum, sh, &tot);
+    {
+      int slot = lfirst;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (llen[r] <= kShortStream) continue;
+        s_pre[slot] = run;
+        s_beg[slot] = lbeg[r];
+        s_flt[slot] = lflt[r];
+        if (kPV) s_oth[slot] = loth[r];
+        if (WORDS == 0) s_up[slot] = lup[r];
+        run += llen[r];
+        ++slot;
+      }
+    }
+    if (tid == 0) s_pre[ltot] = tot;
     __syncthreads();
     if (tid == 0) {
       elems += tot;
       descs += nd;
     }
-    // ---- stream the elements: K consecutive per lane
     for (int64_t base = 0; base < tot; base += (int64_t)THREADS * kK) {
       const int64_t e0 = base + (int64_t)tid * kK;
       if (e0 < tot) {
-        int lo = 0, hi = D;  // largest j with s_pre[j] <= e0
+        int lo = 0, hi = ltot;  // largest j with s_pre[j] <= e0
         while (hi - lo > 1) {
           const int mid = (lo + hi) >> 1;
           if (s_pre[mid] <= e0) lo = mid;
           else hi = mid;
         }
         int j = lo;
+        int64_t cb = s_beg[j], cp = s_pre[j], ce = s_pre[j + 1];
+        int32_t cf = s_flt[j];
         int64_t addr[kK];
         int32_t flt[kK];
         int jj[kK];
@@ -422,15 +565,20 @@ __global__ __launch_bounds__(THREADS) void heavy_kernel(const int32_t* lc, const
         for (int q = 0; q < kK; ++q) {
           const int64_t e = e0 + q;
           if (e < tot) {
-            while (s_pre[j + 1] <= e) ++j;
-            addr[q] = s_beg[j] + (e - s_pre[j]);
-            flt[q] = s_flt[j];
-            jj[q] = j;
+            while (e >= ce) {
+              ++j;
+              cb = s_beg[j];
+              cp = ce;
+              ce = s_pre[j + 1];
+              cf = s_flt[j];
+            }
+            addr[q] = cb + (e - cp);
+            flt[q] = cf;
           } else {
             addr[q] = -1;
             flt[q] = 0x7FFFFFFF;
-            jj[q] = j;
           }
+          jj[q] = j;
         }
         int32_t val[kK];
 #pragma unroll
@@ -438,20 +586,9 @@ __global__ __launch_bounds__(THREADS) void heavy_kernel(const int32_t* lc, const
 #pragma unroll
         for (int q = 0; q < kK; ++q) {
           const int32_t t = val[q];
-          if (t > flt[q]) {
-            bool hit;
-            if (TAB > 0) {
-              uint32_t h = hslot(t, shift);
-              int32_t k;
-              while ((k = tab[h]) != t && k != -1) h = (h + 1) & (cap - 1);
-              hit = k == t;
-            } else {
-              hit = s_up[jj[q]] ? gsearch(lc + mx.begin, mx.up, t) : gsearch(lc + mx.begin + mx.hfb, hf, t);
-            }
-            if (hit) {
-              ++cnt;
-              if (kPV) add_pv(pv, x, s_oth[jj[q]], t);
-            }
+          if (t > flt[q] && probe_any(mode, tab, cap, shift, wlo, wR, lc, mx, WORDS == 0 && s_up[jj[q]], t)) {
+            ++cnt;
+            if (kPV) add_pv(pv, x, s_oth[jj[q]], t);
           }
         }
       }
@@ -488,10 +625,12 @@ __global__ void forward_meta_kernel(const int64_t* off, const int32_t* cols, int
   }
 }
 
-template <int TAB, int THREADS, int D, bool kCover, bool kPV>
+template <int WORDS, int THREADS, int D, bool kCover, bool kPV>
 int launch_heavy(const CountArgs& a, CountWs& w, int bin, int blocks_per_cu, hipStream_t s) {
-  heavy_kernel<TAB, THREADS, D, kCover, kPV><<<static_cast<unsigned>(num_cus() * blocks_per_cu), THREADS, 0, s>>>(
-      a.cols, a.meta, bin, w.items, w.task_off, w.task_begin, w.task_len, w.task_owner, w.acc, a.per_vertex_out);
+  heavy_kernel<WORDS, THREADS, D, kCover, kPV>
+      <<<static_cast<unsigned>(num_cus() * blocks_per_cu), THREADS, 0, s>>>(
+          a.cols, a.meta, bin, w.items, w.task_off, w.task_begin, w.task_len, w.task_owner, w.acc,
+          a.per_vertex_out);
   TC_HIP(hipGetLastError());
   return TC_OK;
 }
@@ -507,8 +646,8 @@ int launch_all(const CountArgs& a, CountWs& w, hipStream_t s) {
   TC_HIP(hipGetLastError());
   prof_stage("light_down");
   if (kCover) {
-    light_down_kernel<kPV><<<grid_for(n, kThreads, 16384), kThreads, 0, s>>>(a.cols, a.meta, n, a.light_max,
-                                                                             w.acc, a.per_vertex_out);
+    light_down_kernel<kPV><<<grid_for(n * kDnLight, kThreads, 32768), kThreads, 0, s>>>(
+        a.cols, a.meta, n, a.light_max, w.acc, a.per_vertex_out);
     TC_HIP(hipGetLastError());
   }
   prof_stage("plan_tasks");
@@ -518,15 +657,20 @@ int launch_all(const CountArgs& a, CountWs& w, hipStream_t s) {
       a.cols, a.meta, n, w.h_off, w.h_u, w.h_v, a.light_max, w.ecnt, w.task_off, w.ecur, w.task_begin,
       w.task_len, w.task_owner, w.acc, a.per_vertex_out);
   const unsigned gv = grid_for(n, kThreads, 16384);
-  items_kernel<false><<<gv, kThreads, 0, s>>>(a.meta, n, w.task_off, kCover, a.light_max, w.items, w.acc);
+  items_kernel<false><<<gv, kThreads, 0, s>>>(a.cols, a.meta, n, w.task_off, kCover, a.light_max, w.items, w.acc);
   bin_offsets_kernel<<<1, 1, 0, s>>>(w.acc);
-  items_kernel<true><<<gv, kThreads, 0, s>>>(a.meta, n, w.task_off, kCover, a.light_max, w.items, w.acc);
+  items_kernel<true><<<gv, kThreads, 0, s>>>(a.cols, a.meta, n, w.task_off, kCover, a.light_max, w.items, w.acc);
   TC_HIP(hipGetLastError());
   prof_stage("heavy");
-  TC_TRY((launch_heavy<32768, 1024, 1024, kCover, kPV>(a, w, 2, 1, s)));
-  TC_TRY((launch_heavy<4096, 512, 1024, kCover, kPV>(a, w, 1, 4, s)));
-  TC_TRY((launch_heavy<512, 256, 256, kCover, kPV>(a, w, 0, 8, s)));
-  TC_TRY((launch_heavy<0, 512, 1024, kCover, kPV>(a, w, 3, 4, s)));
+  // the four bins are independent: run them side by side
+  Fork* f = fork_for_device();
+  if (!f) return TC_ERR_HIP;
+  TC_TRY(fork_begin(f, s));
+  TC_TRY((launch_heavy<kBinWords2, 1024, 1024, kCover, kPV>(a, w, 2, 1, s)));
+  TC_TRY((launch_heavy<kBinWords1, 512, 1024, kCover, kPV>(a, w, 1, 3, f->aux[0])));
+  TC_TRY((launch_heavy<kBinWords0, 256, 256, kCover, kPV>(a, w, 0, 8, f->aux[1])));
+  TC_TRY((launch_heavy<0, 512, 1024, kCover, kPV>(a, w, 3, 4, f->aux[2])));
+  TC_TRY(fork_end(f, s));
   prof_stage("finish");
   return TC_OK;
 }

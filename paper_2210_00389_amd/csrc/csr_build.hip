@@ -120,6 +120,40 @@ __global__ void compact_kernel(const uint64_t* keys, int64_t N, const int32_t* f
 
 }  // namespace
 
+size_t radix_ws_bytes(int64_t N) {
+  Carver c(nullptr);
+  const int64_t nblocks = (N + kTile - 1) / kTile;
+  c.take<int64_t>(kRadix * nblocks + 1);
+  c.take<int64_t>(kRadix * nblocks + 2);
+  c.take<char>(scan_ws_bytes(kRadix * nblocks + 1));
+  return c.used();
+}
+
+int radix_sort_u64(uint64_t* keys, uint64_t* tmp, int64_t N, int bit_lo, int bit_hi, char* scratch,
+                   hipStream_t s, uint64_t** result) {
+  *result = keys;
+  if (N <= 0 || bit_hi <= bit_lo) return TC_OK;
+  const int64_t nblocks = (N + kTile - 1) / kTile;
+  Carver c(scratch);
+  int64_t* ghist = c.take<int64_t>(kRadix * nblocks + 1);
+  int64_t* gpos = c.take<int64_t>(kRadix * nblocks + 2);
+  char* sc_base = c.take<char>(0);
+  uint64_t* a = keys;
+  uint64_t* b = tmp;
+  for (int shift = bit_lo; shift < bit_hi; shift += 8) {
+    hist_kernel<<<(unsigned)nblocks, kThreads, 0, s>>>(a, N, shift, nblocks, ghist);
+    Carver sc(sc_base);
+    TC_TRY(scan_exclusive<int64_t>(ghist, gpos, kRadix * nblocks, sc, s));
+    scatter_kernel<<<(unsigned)nblocks, kThreads, 0, s>>>(a, N, shift, nblocks, gpos, b);
+    TC_HIP(hipGetLastError());
+    uint64_t* t = a;
+    a = b;
+    b = t;
+  }
+  *result = a;
+  return TC_OK;
+}
+
 static int bits_for(int64_t n) {
   int B = 1;
   while (B < 31 && (int64_t(1) << B) < n) ++B;
@@ -130,16 +164,15 @@ size_t build_ws_bytes(int64_t n, int64_t num_pairs) {
   Carver c(nullptr);
   const int64_t N = 2 * num_pairs;
   const int64_t nblocks = (N + kTile - 1) / kTile;
+  (void)nblocks;
   c.take<uint64_t>(N + 1);
   c.take<uint64_t>(N + 1);
-  c.take<int64_t>(kRadix * nblocks + 1);
-  c.take<int64_t>(kRadix * nblocks + 2);
   c.take<int32_t>(N + 1);
   c.take<int64_t>(N + 2);
   c.take<int32_t>(n + 1);
   c.take<int32_t>(4);
   size_t sc = scan_ws_bytes(N + 1);
-  size_t sc2 = scan_ws_bytes(kRadix * nblocks + 1);
+  size_t sc2 = radix_ws_bytes(N);
   c.take<char>(sc > sc2 ? sc : sc2);
   return c.used();
 }
@@ -149,12 +182,9 @@ int build_run(int64_t n, int64_t P, const int32_t* src, const int32_t* dst, int6
   if (ws_bytes < build_ws_bytes(n, P))
     return fail(TC_ERR_WORKSPACE, "tc_build_csr: workspace %zu < %zu bytes", ws_bytes, build_ws_bytes(n, P));
   const int64_t N = 2 * P;
-  const int64_t nblocks = (N + kTile - 1) / kTile;
   Carver c(ws);
   uint64_t* ka = c.take<uint64_t>(N + 1);
   uint64_t* kb = c.take<uint64_t>(N + 1);
-  int64_t* ghist = c.take<int64_t>(kRadix * nblocks + 1);
-  int64_t* gpos = c.take<int64_t>(kRadix * nblocks + 2);
   int32_t* flag = c.take<int32_t>(N + 1);
   int64_t* pos = c.take<int64_t>(N + 2);
   int32_t* deg = c.take<int32_t>(n + 1);
@@ -171,18 +201,9 @@ int build_run(int64_t n, int64_t P, const int32_t* src, const int32_t* dst, int6
     if (hbad) return fail(TC_ERR_OUT_OF_RANGE, "tc_build_csr: a pair has an id outside [0, %lld)", (long long)n);
     const int B = bits_for(n);
     make_keys_kernel<<<grid_for(P, kThreads, 16384), kThreads, 0, s>>>(src, dst, P, B, ka);
-    const int passes = (2 * B + 7) / 8;
-    for (int p = 0; p < passes; ++p) {
-      const int shift = 8 * p;
-      hist_kernel<<<(unsigned)nblocks, kThreads, 0, s>>>(ka, N, shift, nblocks, ghist);
-      Carver sc(scratch);
-      TC_TRY(scan_exclusive<int64_t>(ghist, gpos, kRadix * nblocks, sc, s));
-      scatter_kernel<<<(unsigned)nblocks, kThreads, 0, s>>>(ka, N, shift, nblocks, gpos, kb);
-      TC_HIP(hipGetLastError());
-      uint64_t* t = ka;
-      ka = kb;
-      kb = t;
-    }
+    uint64_t* sorted = nullptr;
+    TC_TRY(radix_sort_u64(ka, kb, N, 0, 2 * B, scratch, s, &sorted));
+    ka = sorted;
     unique_flags_kernel<<<grid_for(N, kThreads, 16384), kThreads, 0, s>>>(ka, N, flag);
     Carver sc(scratch);
     TC_TRY(scan_exclusive<int32_t>(flag, pos, N, sc, s));

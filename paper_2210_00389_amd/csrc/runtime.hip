@@ -105,6 +105,48 @@ int num_cus() {
   return cached;
 }
 
+// --------------------------------------------------------------- fork
+static thread_local Fork g_forks[16];
+static thread_local bool g_fork_ok[16];
+
+Fork* fork_for_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) {
+    fail(TC_ERR_HIP, "fork_for_device: no current device");
+    return nullptr;
+  }
+  Fork& f = g_forks[dev];
+  if (!g_fork_ok[dev]) {
+    for (int i = 0; i < kForkWays; ++i) {
+      if (hipStreamCreateWithFlags(&f.aux[i], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&f.join[i], hipEventDisableTiming) != hipSuccess) {
+        fail(TC_ERR_HIP, "fork_for_device: cannot create auxiliary streams");
+        return nullptr;
+      }
+    }
+    if (hipEventCreateWithFlags(&f.fork, hipEventDisableTiming) != hipSuccess) {
+      fail(TC_ERR_HIP, "fork_for_device: cannot create events");
+      return nullptr;
+    }
+    g_fork_ok[dev] = true;
+  }
+  return &f;
+}
+
+int fork_begin(Fork* f, hipStream_t s) {
+  TC_HIP(hipEventRecord(f->fork, s));
+  for (int i = 0; i < kForkWays; ++i) TC_HIP(hipStreamWaitEvent(f->aux[i], f->fork, 0));
+  return TC_OK;
+}
+
+int fork_end(Fork* f, hipStream_t s) {
+  for (int i = 0; i < kForkWays; ++i) {
+    TC_HIP(hipEventRecord(f->join[i], f->aux[i]));
+    TC_HIP(hipStreamWaitEvent(s, f->join[i], 0));
+  }
+  return TC_OK;
+}
+
 // --------------------------------------------------------------- fill
 template <class T>
 __global__ void fill_kernel(T* p, T v, int64_t count) {

@@ -1,18 +1,26 @@
 // split.hip -- level-class layout of the adjacency and the cover-edge list.
 //
 // Alg. 1 selects the horizontal edges (L(u) = L(v), u < v) and tests every
-// common neighbour w of a cover edge against L(w) = L(u).  Because BFS levels
-// of adjacent vertices differ by at most one (the parity argument of
-// Lemma 1), the level of a neighbour relative to its row is one of three
-// classes -- one up, same, one down -- and L mod 4 (2 bits per vertex, 4 MB
-// for 16.7 M vertices, so it stays in L2) is enough to tell them apart.
+// common neighbour w of a cover edge against L(w) = L(u).  BFS levels of
+// adjacent vertices differ by at most one (the parity argument of Lemma 1),
+// so relative to its row a neighbour is in one of three classes -- one level
+// up, same level, one level down.
 //
-// This pass rewrites every row as [Up | Same | Down], each part still
-// ascending (a stable partition), and records per vertex the class bounds and
-// the start of Hfwd(x) = {v in Same(x) : v > x}, the cover edges leaving x.
-// The counting kernels then evaluate the test structurally: a common
-// neighbour found in two Up lists or two Down lists is on another level, and
-// one found in two Same lists is counted only when it lies above v.
+// This pass rewrites every row as [Up | Same | Down], each part ascending (a
+// stable partition of the sorted row), and records per vertex the class
+// bounds and the start of Hfwd(x) = {v in Same(x) : v > x}, the cover edges
+// leaving x.  The counting kernels then evaluate the paper's test
+// structurally (see count.hip).
+//
+// Two layouts share the row engine:
+//   * identity: same vertex ids, classes from the given int32 levels (any
+//     level function; used for the explicit cover-edge list);
+//   * relabelled (for counting): vertices renumbered by (virtual level, id),
+//     columns rewritten to the new ids, classes read off the new id ranges.
+//     Within one (component, level) class the new order is the old order,
+//     and the method only compares ids inside such a class, so H and every
+//     count are unchanged; each level becomes a contiguous id range, which
+//     keeps the probe sets of the counting kernels inside a small id window.
 //
 // Rows of up to kShort entries are handled by one thread each; longer rows
 // are cut into segments of kSeg entries handled by one wave each (counts,
@@ -27,108 +35,128 @@ constexpr int kThreads = 256;
 constexpr int kShort = 32;
 constexpr int kSeg = 2048;
 
-// class of neighbour w of row x: 0 = up, 1 = same, 2 = down
-struct FullLevels {
+// ---------------------------------------------------------- layouts
+// A layout maps output row i to an input row and classifies its entries:
+//   ctx(i)          per-row context
+//   cls(c, w, v)    class of input entry w (0 up, 1 same, 2 down); v gets
+//                   the value written to the output row
+struct RowCtx {
+  int64_t ib, ie, ob;  // input range, output begin
+  int32_t self;        // the row's own id in the output numbering
+  int32_t key;         // the row's (virtual) level
+  int64_t lo, hi;      // same-level id window (relabelled layout)
+};
+
+struct IdentityLayout {
+  const int64_t* off;
   const int32_t* L;
-  __device__ __forceinline__ int row(int64_t x) const { return L[x]; }
-  __device__ __forceinline__ int cls(int rowkey, int32_t w) const {
-    int lw = L[w];
-    return lw < rowkey ? 0 : (lw == rowkey ? 1 : 2);
+  __device__ __forceinline__ RowCtx ctx(int64_t i) const {
+    RowCtx c;
+    c.ib = off[i];
+    c.ie = off[i + 1];
+    c.ob = c.ib;
+    c.self = static_cast<int32_t>(i);
+    c.key = L[i];
+    c.lo = c.hi = 0;
+    return c;
+  }
+  __device__ __forceinline__ int cls(const RowCtx& c, int32_t w, int32_t& v) const {
+    v = w;
+    const int lw = L[w];
+    return lw < c.key ? 0 : (lw == c.key ? 1 : 2);
   }
 };
 
-struct Residues {
-  const uint32_t* res;
-  __device__ __forceinline__ int get(int64_t v) const {
-    return static_cast<int>((res[v >> 4] >> ((v & 15) * 2)) & 3u);
+struct RelabelLayout {
+  const int64_t* off;    // input row offsets
+  const int64_t* noff;   // output row offsets
+  const int32_t* order;  // new id -> old id
+  const int32_t* perm;   // old id -> new id
+  const int32_t* L;
+  const uint32_t* comp0;
+  int32_t d0;
+  const int64_t* lstart;
+  __device__ __forceinline__ RowCtx ctx(int64_t i) const {
+    RowCtx c;
+    const int32_t x = order[i];
+    c.ib = off[x];
+    c.ie = off[x + 1];
+    c.ob = noff[i];
+    c.self = static_cast<int32_t>(i);
+    const int vl = L[x] + (((comp0[x >> 5] >> (x & 31)) & 1u) ? 0 : d0);
+    c.key = vl;
+    c.lo = lstart[vl];
+    c.hi = lstart[vl + 1];
+    return c;
   }
-  __device__ __forceinline__ int row(int64_t x) const { return get(x); }
-  __device__ __forceinline__ int cls(int rowkey, int32_t w) const {
-    int d = (get(w) - rowkey) & 3;  // 0 same, 1 down, 3 up
-    return d == 0 ? 1 : (d == 3 ? 0 : 2);
+  __device__ __forceinline__ int cls(const RowCtx& c, int32_t w, int32_t& v) const {
+    v = perm[w];
+    return v < c.lo ? 0 : (v < c.hi ? 1 : 2);
   }
 };
 
-__global__ void pack_res_kernel(const int32_t* L, int64_t n, uint32_t* res) {
-  const int64_t words = (n + 15) / 16;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t r = 0;
-    const int64_t v0 = i * 16;
-#pragma unroll
-    for (int j = 0; j < 16; ++j)
-      if (v0 + j < n) r |= (static_cast<uint32_t>(L[v0 + j]) & 3u) << (2 * j);
-    res[i] = r;
-  }
-}
-
-template <class C>
-__global__ __launch_bounds__(kThreads) void split_short_kernel(const int64_t* off, const int32_t* cols,
-                                                               int64_t n, C cl, int32_t* scols,
-                                                               VMeta* meta, int32_t* nseg) {
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
-       x += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t b = off[x], e = off[x + 1];
-    const int32_t deg = static_cast<int32_t>(e - b);
+// Rows of at most kShort entries: one thread, two passes (count, scatter).
+template <class Lay>
+__global__ __launch_bounds__(kThreads) void lay_short_kernel(Lay lay, const int32_t* cols, int64_t n, int32_t* out,
+                                                             VMeta* meta, int32_t* nseg) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const RowCtx c = lay.ctx(i);
+    const int32_t deg = static_cast<int32_t>(c.ie - c.ib);
     if (deg > kShort) {
-      nseg[x] = (deg + kSeg - 1) / kSeg;
+      nseg[i] = (deg + kSeg - 1) / kSeg;
       continue;
     }
-    nseg[x] = 0;
-    const int rk = deg ? cl.row(x) : 0;
+    nseg[i] = 0;
     int up = 0, same = 0, slt = 0;
-    for (int64_t j = b; j < e; ++j) {
-      int32_t w = cols[j];
-      int c = cl.cls(rk, w);
-      up += c == 0;
-      same += c == 1;
-      slt += (c == 1) & (w < x);
+    for (int64_t j = c.ib; j < c.ie; ++j) {
+      int32_t v;
+      const int k = lay.cls(c, cols[j], v);
+      up += k == 0;
+      same += k == 1;
+      slt += (k == 1) & (v < c.self);
     }
     int pu = 0, ps = up, pd = up + same;
-    for (int64_t j = b; j < e; ++j) {
-      int32_t w = cols[j];
-      int c = cl.cls(rk, w);
-      int pos = c == 0 ? pu++ : (c == 1 ? ps++ : pd++);
-      scols[b + pos] = w;
+    for (int64_t j = c.ib; j < c.ie; ++j) {
+      int32_t v;
+      const int k = lay.cls(c, cols[j], v);
+      const int pos = k == 0 ? pu++ : (k == 1 ? ps++ : pd++);
+      out[c.ob + pos] = v;
     }
-    meta[x] = VMeta{b, up, up + slt, up + same, deg, {0, 0}};
+    meta[i] = VMeta{c.ob, up, up + slt, up + same, deg, {c.key, 0}};
   }
 }
 
 __global__ void seg_vtx_kernel(const int32_t* nseg, const int64_t* seg_off, int64_t n, int32_t* seg_vtx) {
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
-       x += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
     const int k = nseg[x];
     const int64_t s0 = seg_off[x];
     for (int i = 0; i < k; ++i) seg_vtx[s0 + i] = static_cast<int32_t>(x);
   }
 }
 
-template <class C>
-__global__ __launch_bounds__(kThreads) void seg_count_kernel(const int64_t* off, const int32_t* cols,
-                                                             int64_t n, C cl, const int64_t* seg_off,
-                                                             const int32_t* seg_vtx, int32_t* seg_cnt) {
+// One wave per segment of a long row: class counts of the segment.
+template <class Lay>
+__global__ __launch_bounds__(kThreads) void lay_seg_count_kernel(Lay lay, const int32_t* cols, int64_t n,
+                                                                 const int64_t* seg_off, const int32_t* seg_vtx,
+                                                                 int32_t* seg_cnt) {
   const int64_t nsegs = seg_off[n];
   const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   for (int64_t sg = wid; sg < nsegs; sg += nw) {
-    const int32_t x = seg_vtx[sg];
-    const int64_t s = sg - seg_off[x];
-    const int64_t b = off[x] + s * kSeg;
-    const int64_t e = min(off[x + 1], b + kSeg);
-    const int rk = cl.row(x);
+    const int32_t i = seg_vtx[sg];
+    const RowCtx c = lay.ctx(i);
+    const int64_t s = sg - seg_off[i];
+    const int64_t b = c.ib + s * kSeg;
+    const int64_t e = min(c.ie, b + kSeg);
     int up = 0, same = 0, slt = 0;
     for (int64_t j0 = b; j0 < e; j0 += kWave) {
       const int64_t j = j0 + lane();
-      int c = 3;
-      int32_t w = 0;
-      if (j < e) {
-        w = cols[j];
-        c = cl.cls(rk, w);
-      }
-      up += __popcll(__ballot(c == 0));
-      same += __popcll(__ballot(c == 1));
-      slt += __popcll(__ballot((c == 1) & (w < x)));
+      int k = 3;
+      int32_t v = 0;
+      if (j < e) k = lay.cls(c, cols[j], v);
+      up += __popcll(__ballot(k == 0));
+      same += __popcll(__ballot(k == 1));
+      slt += __popcll(__ballot((k == 1) & (v < c.self)));
     }
     if (lane() == 0) {
       seg_cnt[3 * sg + 0] = up;
@@ -138,59 +166,57 @@ __global__ __launch_bounds__(kThreads) void seg_count_kernel(const int64_t* off,
   }
 }
 
-__global__ void seg_prefix_kernel(const int64_t* off, int64_t n, const int32_t* nseg, const int64_t* seg_off,
-                                  const int32_t* seg_cnt, int32_t* seg_pre, VMeta* meta) {
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
-       x += (int64_t)gridDim.x * blockDim.x) {
-    const int k = nseg[x];
+// Per long row: prefix of its segments' counts, and the row record.
+template <class Lay>
+__global__ void lay_seg_prefix_kernel(Lay lay, int64_t n, const int32_t* nseg, const int64_t* seg_off,
+                                      const int32_t* seg_cnt, int32_t* seg_pre, VMeta* meta) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = nseg[i];
     if (k == 0) continue;
-    const int64_t s0 = seg_off[x];
+    const int64_t s0 = seg_off[i];
     int up = 0, same = 0, slt = 0;
-    for (int i = 0; i < k; ++i) {
-      const int64_t sg = s0 + i;
+    for (int j = 0; j < k; ++j) {
+      const int64_t sg = s0 + j;
       seg_pre[3 * sg + 0] = up;
       seg_pre[3 * sg + 1] = same;
       up += seg_cnt[3 * sg + 0];
       same += seg_cnt[3 * sg + 1];
       slt += seg_cnt[3 * sg + 2];
     }
-    const int32_t deg = static_cast<int32_t>(off[x + 1] - off[x]);
-    meta[x] = VMeta{off[x], up, up + slt, up + same, deg, {0, 0}};
+    const RowCtx c = lay.ctx(i);
+    meta[i] = VMeta{c.ob, up, up + slt, up + same, static_cast<int32_t>(c.ie - c.ib), {c.key, 0}};
   }
 }
 
-template <class C>
-__global__ __launch_bounds__(kThreads) void seg_write_kernel(const int64_t* off, const int32_t* cols,
-                                                             int64_t n, C cl, const int64_t* seg_off,
-                                                             const int32_t* seg_vtx, const int32_t* seg_pre,
-                                                             const VMeta* meta, int32_t* scols) {
+// One wave per segment: stable scatter of the segment's entries.
+template <class Lay>
+__global__ __launch_bounds__(kThreads) void lay_seg_write_kernel(Lay lay, const int32_t* cols, int64_t n,
+                                                                 const int64_t* seg_off, const int32_t* seg_vtx,
+                                                                 const int32_t* seg_pre, const VMeta* meta,
+                                                                 int32_t* out) {
   const int64_t nsegs = seg_off[n];
   const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const uint64_t lt = lanemask_lt();
   for (int64_t sg = wid; sg < nsegs; sg += nw) {
-    const int32_t x = seg_vtx[sg];
-    const int64_t s = sg - seg_off[x];
-    const int64_t rb = off[x];
-    const int64_t b = rb + s * kSeg;
-    const int64_t e = min(off[x + 1], b + kSeg);
-    const VMeta mx = meta[x];
-    const int rk = cl.row(x);
+    const int32_t i = seg_vtx[sg];
+    const RowCtx c = lay.ctx(i);
+    const int64_t s = sg - seg_off[i];
+    const int64_t b = c.ib + s * kSeg;
+    const int64_t e = min(c.ie, b + kSeg);
+    const VMeta m = meta[i];
     int64_t pu = seg_pre[3 * sg + 0];
-    int64_t ps = mx.up + seg_pre[3 * sg + 1];
-    int64_t pd = mx.sfe + (s * kSeg - seg_pre[3 * sg + 0] - seg_pre[3 * sg + 1]);
-    const uint64_t lt = lanemask_lt();
+    int64_t ps = m.up + seg_pre[3 * sg + 1];
+    int64_t pd = m.sfe + (s * kSeg - seg_pre[3 * sg + 0] - seg_pre[3 * sg + 1]);
     for (int64_t j0 = b; j0 < e; j0 += kWave) {
       const int64_t j = j0 + lane();
-      int c = 3;
-      int32_t w = 0;
-      if (j < e) {
-        w = cols[j];
-        c = cl.cls(rk, w);
-      }
-      const uint64_t mu = __ballot(c == 0), ms = __ballot(c == 1), md = __ballot(c == 2);
-      if (c == 0) scols[rb + pu + __popcll(mu & lt)] = w;
-      else if (c == 1) scols[rb + ps + __popcll(ms & lt)] = w;
-      else if (c == 2) scols[rb + pd + __popcll(md & lt)] = w;
+      int k = 3;
+      int32_t v = 0;
+      if (j < e) k = lay.cls(c, cols[j], v);
+      const uint64_t mu = __ballot(k == 0), ms = __ballot(k == 1), md = __ballot(k == 2);
+      if (k == 0) out[c.ob + pu + __popcll(mu & lt)] = v;
+      else if (k == 1) out[c.ob + ps + __popcll(ms & lt)] = v;
+      else if (k == 2) out[c.ob + pd + __popcll(md & lt)] = v;
       pu += __popcll(mu);
       ps += __popcll(ms);
       pd += __popcll(md);
@@ -198,16 +224,71 @@ __global__ __launch_bounds__(kThreads) void seg_write_kernel(const int64_t* off,
   }
 }
 
+template <class Lay>
+int layout_run(const Lay& lay, const int32_t* cols, int64_t n, SplitWs& w, hipStream_t s) {
+  const unsigned gv = grid_for(n, kThreads, 16384);
+  const unsigned gw = static_cast<unsigned>(num_cus() * 8);
+  lay_short_kernel<Lay><<<gv, kThreads, 0, s>>>(lay, cols, n, w.scols, w.meta, w.nseg);
+  TC_HIP(hipGetLastError());
+  Carver sc(w.scratch);
+  TC_TRY(scan_exclusive<int32_t>(w.nseg, w.seg_off, n, sc, s));
+  seg_vtx_kernel<<<gv, kThreads, 0, s>>>(w.nseg, w.seg_off, n, w.seg_vtx);
+  lay_seg_count_kernel<Lay><<<gw, kThreads, 0, s>>>(lay, cols, n, w.seg_off, w.seg_vtx, w.seg_cnt);
+  lay_seg_prefix_kernel<Lay><<<gv, kThreads, 0, s>>>(lay, n, w.nseg, w.seg_off, w.seg_cnt, w.seg_pre, w.meta);
+  lay_seg_write_kernel<Lay><<<gw, kThreads, 0, s>>>(lay, cols, n, w.seg_off, w.seg_vtx, w.seg_pre, w.meta,
+                                                    w.scols);
+  TC_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+// ------------------------------------------------------- relabelling
+// Virtual level: L(v) in r0's component, L(v) + d0 elsewhere.
+__device__ __forceinline__ int vlevel(const int32_t* L, const uint32_t* comp0, int32_t d0, int64_t v) {
+  return L[v] + (((comp0[v >> 5] >> (v & 31)) & 1u) ? 0 : d0);
+}
+
+__global__ __launch_bounds__(kThreads) void vl_hist_kernel(const int32_t* L, const uint32_t* comp0, int32_t d0,
+                                                           int64_t n, int32_t nvl, int32_t* cnt) {
+  constexpr int kLds = 1024;
+  __shared__ int32_t h[kLds];
+  const bool local = nvl <= kLds;
+  if (local)
+    for (int i = threadIdx.x; i < nvl; i += kThreads) h[i] = 0;
+  __syncthreads();
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int vl = vlevel(L, comp0, d0, v);
+    if (local) atomicAdd(&h[vl], 1);
+    else atomicAdd(&cnt[vl], 1);
+  }
+  __syncthreads();
+  if (local)
+    for (int i = threadIdx.x; i < nvl; i += kThreads)
+      if (h[i]) atomicAdd(&cnt[i], h[i]);
+}
+
+__global__ void vl_keys_kernel(const int32_t* L, const uint32_t* comp0, int32_t d0, int64_t n, uint64_t* keys) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    keys[v] = (static_cast<uint64_t>(vlevel(L, comp0, d0, v)) << 32) | static_cast<uint64_t>(v);
+}
+
+__global__ void order_kernel(const uint64_t* sorted, int64_t n, const int64_t* off, int32_t* order, int32_t* perm,
+                             int32_t* ndeg) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t x = static_cast<int32_t>(sorted[i] & 0xFFFFFFFFull);
+    order[i] = x;
+    perm[x] = static_cast<int32_t>(i);
+    ndeg[i] = static_cast<int32_t>(off[x + 1] - off[x]);
+  }
+}
+
 // ------------------------------------------------------- H list
 __global__ void hcount_kernel(const VMeta* meta, int64_t n, int32_t* hc) {
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
-       x += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
     hc[x] = meta[x].sfe - meta[x].hfb;
 }
 
-// Rows with at most 32 cover edges: one thread; longer: one wave.
-__global__ __launch_bounds__(kThreads) void hlist_kernel(const int64_t* off, const VMeta* meta,
-                                                         const int32_t* cols, int64_t n,
+// Rows with at most kShort cover edges: one thread; longer: one wave.
+__global__ __launch_bounds__(kThreads) void hlist_kernel(const VMeta* meta, const int32_t* cols, int64_t n,
                                                          const int64_t* h_off, int64_t cap, int32_t* h_u,
                                                          int32_t* h_v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -215,20 +296,19 @@ __global__ __launch_bounds__(kThreads) void hlist_kernel(const int64_t* off, con
     const VMeta m = meta[x];
     const int hf = m.sfe - m.hfb;
     if (hf == 0 || hf > kShort) continue;
-    const int64_t src = off[x] + m.hfb, dst = h_off[x];
+    const int64_t src = m.begin + m.hfb, dst = h_off[x];
     for (int i = 0; i < hf && dst + i < cap; ++i) {
       h_u[dst + i] = static_cast<int32_t>(x);
       h_v[dst + i] = cols[src + i];
     }
   }
-  // long rows, one wave each
   const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = stride / kWave;
   for (int64_t x = wid; x < n; x += nw) {
     const VMeta m = meta[x];
     const int hf = m.sfe - m.hfb;
     if (hf <= kShort) continue;
-    const int64_t src = off[x] + m.hfb, dst = h_off[x];
+    const int64_t src = m.begin + m.hfb, dst = h_off[x];
     for (int i = lane(); i < hf && dst + i < cap; i += kWave) {
       h_u[dst + i] = static_cast<int32_t>(x);
       h_v[dst + i] = cols[src + i];
@@ -244,7 +324,7 @@ SplitWs split_reserve(Carver& c, int64_t n, int64_t nnz) {
   SplitWs w;
   w.meta = c.take<VMeta>(n + 1);
   w.scols = c.take<int32_t>(nnz + 1);
-  w.res = c.take<uint32_t>((n + 15) / 16 + 1);
+  w.res = c.take<uint32_t>(1);
   w.nseg = c.take<int32_t>(n + 1);
   w.seg_off = c.take<int64_t>(n + 2);
   const int64_t max_segs = nnz / (kShort + 1) + 1;  // every long row has > kShort entries
@@ -257,46 +337,56 @@ SplitWs split_reserve(Carver& c, int64_t n, int64_t nnz) {
 }
 
 int split_run(const tc_csr* g, const int32_t* L, bool full_levels, SplitWs& w, hipStream_t s) {
+  (void)full_levels;
+  if (g->n == 0) return TC_OK;
+  IdentityLayout lay{g->row_offsets, L};
+  return layout_run(lay, g->cols, g->n, w, s);
+}
+
+RelabelWs relabel_reserve(Carver& c, int64_t n, int64_t max_vlevels) {
+  RelabelWs w;
+  w.order = c.take<int32_t>(n + 1);
+  w.perm = c.take<int32_t>(n + 1);
+  w.off = c.take<int64_t>(n + 2);
+  w.lstart_cnt = c.take<int32_t>(max_vlevels + 2);
+  w.lstart = c.take<int64_t>(max_vlevels + 3);
+  w.keys = c.take<uint64_t>(n + 1);
+  w.keys_tmp = c.take<uint64_t>(n + 1);
+  w.deg = c.take<int32_t>(n + 1);
+  const size_t a = radix_ws_bytes(n), b = scan_ws_bytes(n + 2);
+  w.scratch = c.take<char>(a > b ? a : b);
+  return w;
+}
+
+int relabel_run(const tc_csr* g, const int32_t* L, const uint32_t* comp0, int32_t d0, int32_t nvl, RelabelWs& w,
+                SplitWs& sp, hipStream_t s) {
   const int64_t n = g->n;
   if (n == 0) return TC_OK;
   const unsigned gv = grid_for(n, kThreads, 16384);
-  const unsigned gw = static_cast<unsigned>(num_cus() * 8);
-  if (full_levels) {
-    FullLevels cl{L};
-    split_short_kernel<<<gv, kThreads, 0, s>>>(g->row_offsets, g->cols, n, cl, w.scols, w.meta, w.nseg);
-  } else {
-    pack_res_kernel<<<grid_for((n + 15) / 16, kThreads, 16384), kThreads, 0, s>>>(L, n, w.res);
-    Residues cl{w.res};
-    split_short_kernel<<<gv, kThreads, 0, s>>>(g->row_offsets, g->cols, n, cl, w.scols, w.meta, w.nseg);
-  }
+  TC_TRY(fill_i32(w.lstart_cnt, 0, nvl + 1, s));
+  vl_hist_kernel<<<gv, kThreads, 0, s>>>(L, comp0, d0, n, nvl, w.lstart_cnt);
   TC_HIP(hipGetLastError());
-  Carver sc(w.scratch);
-  TC_TRY(scan_exclusive<int32_t>(w.nseg, w.seg_off, n, sc, s));
-  seg_vtx_kernel<<<gv, kThreads, 0, s>>>(w.nseg, w.seg_off, n, w.seg_vtx);
-  if (full_levels) {
-    FullLevels cl{L};
-    seg_count_kernel<<<gw, kThreads, 0, s>>>(g->row_offsets, g->cols, n, cl, w.seg_off, w.seg_vtx, w.seg_cnt);
-  } else {
-    Residues cl{w.res};
-    seg_count_kernel<<<gw, kThreads, 0, s>>>(g->row_offsets, g->cols, n, cl, w.seg_off, w.seg_vtx, w.seg_cnt);
+  {
+    Carver sc(w.scratch);
+    TC_TRY(scan_exclusive<int32_t>(w.lstart_cnt, w.lstart, nvl, sc, s));
   }
-  seg_prefix_kernel<<<gv, kThreads, 0, s>>>(g->row_offsets, n, w.nseg, w.seg_off, w.seg_cnt, w.seg_pre,
-                                            w.meta);
-  if (full_levels) {
-    FullLevels cl{L};
-    seg_write_kernel<<<gw, kThreads, 0, s>>>(g->row_offsets, g->cols, n, cl, w.seg_off, w.seg_vtx,
-                                             w.seg_pre, w.meta, w.scols);
-  } else {
-    Residues cl{w.res};
-    seg_write_kernel<<<gw, kThreads, 0, s>>>(g->row_offsets, g->cols, n, cl, w.seg_off, w.seg_vtx,
-                                             w.seg_pre, w.meta, w.scols);
-  }
+  vl_keys_kernel<<<gv, kThreads, 0, s>>>(L, comp0, d0, n, w.keys);
+  int bits = 0;
+  while ((int64_t(1) << bits) < nvl) ++bits;
+  uint64_t* sorted = w.keys;
+  TC_TRY(radix_sort_u64(w.keys, w.keys_tmp, n, 32, 32 + bits, w.scratch, s, &sorted));
+  order_kernel<<<gv, kThreads, 0, s>>>(sorted, n, g->row_offsets, w.order, w.perm, w.deg);
   TC_HIP(hipGetLastError());
-  return TC_OK;
+  {
+    Carver sc(w.scratch);
+    TC_TRY(scan_exclusive<int32_t>(w.deg, w.off, n, sc, s));
+  }
+  RelabelLayout lay{g->row_offsets, w.off, w.order, w.perm, L, comp0, d0, w.lstart};
+  return layout_run(lay, g->cols, n, sp, s);
 }
 
-int hlist_run(const tc_csr* g, const VMeta* meta, const int32_t* cols, int64_t* h_off, int32_t* h_u,
-              int32_t* h_v, int64_t cap, int64_t* h_count, char* scratch, hipStream_t s) {
+int hlist_run(const tc_csr* g, const VMeta* meta, const int32_t* cols, int64_t* h_off, int32_t* h_u, int32_t* h_v,
+              int64_t cap, int64_t* h_count, char* scratch, hipStream_t s) {
   const int64_t n = g->n;
   if (n == 0) {
     TC_TRY(fill_i64(h_off, 0, 1, s));
@@ -308,8 +398,7 @@ int hlist_run(const tc_csr* g, const VMeta* meta, const int32_t* cols, int64_t* 
   hcount_kernel<<<grid_for(n, kThreads, 16384), kThreads, 0, s>>>(meta, n, hc);
   TC_TRY(scan_exclusive<int32_t>(hc, h_off, n, sc, s));
   if (h_u)
-    hlist_kernel<<<static_cast<unsigned>(num_cus() * 8), kThreads, 0, s>>>(g->row_offsets, meta, cols, n,
-                                                                          h_off, cap, h_u, h_v);
+    hlist_kernel<<<static_cast<unsigned>(num_cus() * 8), kThreads, 0, s>>>(meta, cols, n, h_off, cap, h_u, h_v);
   if (h_count) copy_total_kernel<<<1, 1, 0, s>>>(h_off, n, h_count);
   TC_HIP(hipGetLastError());
   return TC_OK;

@@ -33,10 +33,13 @@ int check_ws(void* ws, size_t ws_bytes, size_t need, const char* fn) {
 struct CountPlan {
   int64_t* stats;
   int32_t* L;
-  char* region;  // BFS first, then layout + count
+  uint32_t* comp0;  // r0's component (kept from the BFS for the relabelling)
+  char* region;     // BFS first, then relabelled layout + count
   BfsWs bfs;
+  RelabelWs relabel;
   SplitWs split;
   CountWs count;
+  int64_t* pv_new;  // per-vertex counts in relabelled ids
   size_t bytes;
 };
 
@@ -45,16 +48,25 @@ CountPlan plan_count(void* base, int64_t n, int64_t nnz) {
   Carver c(base);
   p.stats = c.take<int64_t>(16);
   p.L = c.take<int32_t>(n + 1);
+  p.comp0 = c.take<uint32_t>((n + 31) / 32 + 1);
   p.region = c.take<char>(0);
   const size_t head = c.used();
   Carver a(p.region);
   p.bfs = bfs_reserve(a, n);
+  p.bfs.comp0 = p.comp0;
   Carver b(p.region);
+  p.relabel = relabel_reserve(b, n, 2 * n + 2);
   p.split = split_reserve(b, n, nnz);
   p.count = count_reserve(b, n, nnz);
   p.count.stats = p.stats;
+  p.pv_new = b.take<int64_t>(n + 1);
   p.bytes = head + (a.used() > b.used() ? a.used() : b.used());
   return p;
+}
+
+__global__ void pv_back_kernel(const int64_t* pv_new, const int32_t* order, int64_t n, int64_t* pv) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    pv[order[i]] = pv_new[i];
 }
 
 struct BaselinePlan {
@@ -199,24 +211,31 @@ int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles, 
   TC_TRY(maybe_validate(g, flags, ws, s));
   CountPlan p = plan_count(ws, g->n, g->nnz);
   int32_t* L = levels ? levels : p.L;
-  int32_t nl = 0;
+  int32_t nl = 0, d0 = 0;
   prof_stage("bfs");
-  TC_TRY(bfs_run(g, root, L, &nl, p.bfs, s));
-  if (pv) TC_TRY(fill_i64(per_vertex, 0, g->n, s));
+  TC_TRY(bfs_run(g, root, L, &nl, p.bfs, s, &d0));
+  tc_csr rg = *g;  // the relabelled graph
   if (g->n > 0) {
-    prof_stage("split");
-    TC_TRY(split_run(g, L, false, p.split, s));
+    prof_stage("relabel");
+    TC_TRY(relabel_run(g, L, p.comp0, d0, d0 + nl + 1, p.relabel, p.split, s));
+    rg.row_offsets = p.relabel.off;
+    rg.cols = p.split.scols;
   }
+  if (pv) TC_TRY(fill_i64(p.pv_new, 0, g->n, s));
   CountArgs a;
-  a.g = g;
+  a.g = &rg;
   a.cols = p.split.scols;
   a.meta = p.split.meta;
   a.cover = true;
   a.per_vertex = pv;
-  a.per_vertex_out = per_vertex;
+  a.per_vertex_out = p.pv_new;
   a.light_max = 32;
   a.heavy_chunk = 1024;
   TC_TRY(count_run(a, p.count, triangles, h_count, s));
+  if (pv && g->n > 0) {
+    pv_back_kernel<<<grid_for(g->n, 256, 16384), 256, 0, s>>>(p.pv_new, p.relabel.order, g->n, per_vertex);
+    TC_HIP(hipGetLastError());
+  }
   stats_kernel<<<1, 1, 0, s>>>(p.stats, g->n, g->nnz, nl);
   TC_HIP(hipGetLastError());
   return TC_OK;

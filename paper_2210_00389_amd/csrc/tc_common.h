@@ -66,6 +66,19 @@ inline unsigned grid_for(int64_t work, int per_block, unsigned cap = 1u << 20) {
 
 int num_cus();
 
+// Auxiliary streams (default priority) for fork/join concurrency inside one
+// call, created once per host thread and device.
+constexpr int kForkWays = 3;
+struct Fork {
+  hipStream_t aux[kForkWays];
+  hipEvent_t fork;
+  hipEvent_t join[kForkWays];
+};
+// Returns nullptr (and records the error) if streams/events cannot be made.
+Fork* fork_for_device();
+int fork_begin(Fork* f, hipStream_t s);  // aux streams wait for s
+int fork_end(Fork* f, hipStream_t s);    // s waits for the aux streams
+
 // ------------------------------------------------------ device helpers
 __device__ __forceinline__ int lane() { return static_cast<int>(__lane_id()); }
 __device__ __forceinline__ uint64_t lanemask_lt() { return __lanemask_lt(); }

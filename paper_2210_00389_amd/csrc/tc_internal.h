@@ -25,10 +25,19 @@ struct BfsWs {
   int64_t* root;
   char* scratch;
   size_t scratch_bytes;
+  uint32_t* comp0;  // optional (caller-owned, n/32+1 words): r0's component
 };
 BfsWs bfs_reserve(Carver& c, int64_t n);
+// *first_levels (nullable) receives the level count of the BFS from r0.
 int bfs_run(const tc_csr* g, int64_t root, int32_t* L, int32_t* num_levels, BfsWs& w,
-            hipStream_t s);
+            hipStream_t s, int32_t* first_levels = nullptr);
+
+// ------------------------------------------------------ radix sort
+// LSD radix sort of 64-bit keys on bits [bit_lo, bit_hi), 8 bits per pass,
+// stable.  Returns the buffer holding the result (keys or tmp).
+size_t radix_ws_bytes(int64_t N);
+int radix_sort_u64(uint64_t* keys, uint64_t* tmp, int64_t N, int bit_lo, int bit_hi, char* scratch,
+                   hipStream_t s, uint64_t** result);
 
 // ------------------------------------------------ level-class layout
 // Per vertex x, relative to row_offsets[x] in the re-laid-out columns:
@@ -61,6 +70,29 @@ SplitWs split_reserve(Carver& c, int64_t n, int64_t nnz);
 // full_levels: classify by comparing int32 levels (any level function);
 // otherwise use packed residues (requires |L(u) - L(v)| <= 1 on edges).
 int split_run(const tc_csr* g, const int32_t* L, bool full_levels, SplitWs& w, hipStream_t s);
+
+// Relabelled layout for counting: vertices renumbered by (virtual level, id)
+// where the virtual level is L(v) in r0's component and L(v) + D0 elsewhere
+// (D0 = level count from r0).  The order is monotone within every
+// (component, level) class, and the method only ever compares ids of one
+// class, so cover edges, the counting test and every per-edge count are
+// unchanged.  Each level becomes a contiguous id range.
+struct RelabelWs {
+  int32_t* order;     // new id -> old id
+  int32_t* perm;      // old id -> new id
+  int64_t* off;       // relabelled row offsets [n + 1]
+  int32_t* lstart_cnt;  // virtual-level histogram
+  int64_t* lstart;    // virtual-level starts
+  uint64_t* keys;
+  uint64_t* keys_tmp;
+  int32_t* deg;
+  char* scratch;
+};
+RelabelWs relabel_reserve(Carver& c, int64_t n, int64_t max_vlevels);
+// Writes the relabelled rows into split.scols and records into split.meta
+// (indexed by new ids); fills w.off, w.order, w.perm.
+int relabel_run(const tc_csr* g, const int32_t* L, const uint32_t* comp0, int32_t d0, int32_t max_vl,
+                RelabelWs& w, SplitWs& sp, hipStream_t s);
 
 // Explicit horizontal-edge list from the layout: h_off = scan of
 // (sfe - hfb), then (x, scols[..]) for every cover edge, lexicographic.
