@@ -228,7 +228,10 @@ typedef struct tc_stats {
   int64_t heavy_elems;     /* list elements streamed by the anchored kernel */
   int64_t heavy_builds;    /* probe-set elements inserted into on-chip tables */
   int64_t light_elems;     /* list elements streamed by the per-task merges */
-  int64_t reserved[5];
+  int64_t bin_elems[4];    /* anchored-kernel elements per table bin (2 KB,
+                              16 KB, 128 KB, row search) */
+  int64_t bin_items[4];    /* work items per table bin */
+  int64_t reserved[1];
 } tc_stats;
 
 int tc_read_stats(const void* ws, tc_stats* out, tc_stream_t stream);

@@ -65,7 +65,8 @@ class TcStats(ctypes.Structure):
                 ("light_tasks", ctypes.c_int64), ("heavy_items", ctypes.c_int64),
                 ("heavy_desc", ctypes.c_int64), ("heavy_elems", ctypes.c_int64),
                 ("heavy_builds", ctypes.c_int64), ("light_elems", ctypes.c_int64),
-                ("reserved", ctypes.c_int64 * 5)]
+                ("bin_elems", ctypes.c_int64 * 4), ("bin_items", ctypes.c_int64 * 4),
+                ("reserved", ctypes.c_int64 * 1)]
 
 
 _lib = None

@@ -22,13 +22,14 @@
 //          Hfwd(v), else anchor v streams Hfwd(u) ∩ (v,inf)
 //   down   anchor x streams Up(w) ∩ (x,inf)
 // Light anchors (short probe set, few down-neighbours) have their tasks
-// merged by the thread that discovers them.  Heavy anchors become work items
-// of at most D descriptors, binned by probe-set size: a block builds an LDS
-// hash of the anchor's probe set Up(x) ∪ Hfwd(x) (2 KB .. 128 KB of the
-// 160 KB LDS), resolves all descriptors of the item with independent loads,
-// then every lane takes K consecutive elements of the flattened streams (one
-// LDS search, K independent global loads in flight, K probes).  Probe sets
-// beyond the largest table are searched in their sorted rows instead.
+// merged by the thread that discovers them.  For heavy anchors every task
+// descriptor is resolved into a stream record (begin, length, flags) by a
+// separate pass; the records of an anchor are cut into work items of about
+// kElemChunk elements, binned by the on-chip table the anchor's probe set
+// Up(x) ∪ Hfwd(x) needs (2 KB .. 128 KB of the 160 KB LDS; bitmap over the
+// id window or hash table).  A block builds the table once per anchor and
+// streams the item's records in chunks of 8 elements of one stream per lane;
+// probe sets beyond the largest table are searched in their sorted rows.
 // Per-lane counts are reduced wave -> block -> one 64-bit atomic.
 //
 // The comparator (plain direction-oriented edge iterator) runs through the
@@ -41,32 +42,54 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kDnLight = 16;  // light anchors have at most this many down-neighbours
-constexpr int kK = 8;         // elements per lane per round
 constexpr int kBins = 4;
 
-// Bins of heavy anchors by the LDS table they need: 2 KB, 16 KB, 128 KB, or
+// Bins of heavy anchors by the LDS table they need: 2 KB, 32 KB, 128 KB, or
 // none (bin 3: search the sorted rows).  The probe set P(x) = Up(x) ∪ Hfwd(x)
-// lies in the id window [min P, max P] of R ids; it is held as a bitmap of R
-// bits when that is at most about four words per member (so setting it up
-// costs O(|P|)), else as a hash table of 2|P| (rounded up) slots.
-constexpr int kBinWords0 = 512, kBinWords1 = 4096, kBinWords2 = 32768;
+// lies in the id window [min P, max P] of R ids.  It is held as a bitmap of
+// R + 1 bits (bit R stays clear and absorbs every id outside the window)
+// when clearing that bitmap costs little next to the anchor's work (at most
+// four words per member, or per four streamed elements), else as a hash
+// table filling the bin's whole table (at most half full).
+constexpr int kBinWords0 = 512, kBinWords1 = 8192, kBinWords2 = 32768;
 
 __host__ __device__ constexpr int bin_words(int b) {
   return b == 0 ? kBinWords0 : (b == 1 ? kBinWords1 : (b == 2 ? kBinWords2 : 0));
 }
 
-__device__ __forceinline__ bool bitmap_fits(int64_t R, int P, int words) {
-  const int64_t need = (R + 31) >> 5;
-  return need <= words && need <= 4 * static_cast<int64_t>(P) + 64;
-}
+__device__ __forceinline__ int64_t bitmap_words(int64_t R) { return (R + 32) >> 5; }
 
-__device__ __forceinline__ bool hash_fits(int P, int words) { return 2 * P <= words; }
+// Bin of an anchor with window R, probe-set size P and E streamed elements;
+// *bitmap tells the table kind.
+__device__ __forceinline__ int choose_bin(int64_t R, int P, int64_t E, bool* bitmap) {
+  const int64_t need = bitmap_words(R);
+  if (need <= 4 * static_cast<int64_t>(P) + 64 || 4 * need <= E) {
+    for (int b = 0; b < 3; ++b)
+      if (need <= bin_words(b)) {
+        *bitmap = true;
+        return b;
+      }
+  }
+  *bitmap = false;
+  for (int b = 0; b < 3; ++b)
+    if (2 * static_cast<int64_t>(P) <= bin_words(b)) return b;
+  return 3;
+}
 
 enum Acc {
   kAccT = 0, kAccElems = 1, kAccLight = 2, kAccBuild = 3, kAccDesc = 4, kAccItems = 5,
-  kAccHeavyElems = 6, kAccBinCount = 8, kAccBinOff = 13, kAccBinCur = 18, kAccBinNext = 23
+  kAccHeavyElems = 6, kAccChunks = 7, kAccBinCount = 8, kAccBinOff = 13, kAccBinCur = 18, kAccBinNext = 23,
+  kAccBinElems = 28
 };
-constexpr int kAccSlots = 28;
+constexpr int kAccSlots = 33;
+constexpr int kResolveChunk = 1024;   // descriptors per resolution chunk
+constexpr int64_t kElemChunk = 65536;  // elements per work item (target)
+// stream record flags (in the length word)
+constexpr int32_t kFlagUp = 1 << 29;     // probe the anchor's Up list (row search)
+// work item flag (in the stream-count word): the anchor's table is a bitmap
+constexpr int32_t kItemBitmap = 1 << 30;
+constexpr int64_t kItemMaxStreams = 1 << 29;
+constexpr int32_t kLenMask = kFlagUp - 1;
 
 __device__ __forceinline__ void add_pv(int64_t* pv, int32_t a, int32_t b, int32_t c) {
   atomicAdd(reinterpret_cast<unsigned long long*>(&pv[a]), 1ull);
@@ -259,20 +282,119 @@ __device__ __forceinline__ void probe_window(const int32_t* lc, const VMeta& m, 
   R = mx >= mn ? static_cast<int64_t>(mx) - mn + 1 : 0;
 }
 
-__device__ __forceinline__ int bin_of(int64_t R, int P) {
-  for (int b = 0; b < 3; ++b)
-    if (bitmap_fits(R, P, bin_words(b)) || hash_fits(P, bin_words(b))) return b;
-  return 3;
+
+// Descriptor counts of heavy anchors and their resolution chunks.
+// kFill = false: ndesc per vertex and the chunk count; kFill = true: chunks.
+template <bool kFill>
+__global__ __launch_bounds__(kThreads) void desc_plan_kernel(const VMeta* meta, int64_t n, const int64_t* task_off,
+                                                             bool cover, int light_max, int32_t* ndesc,
+                                                             int2* rchunks, int64_t rcap, unsigned long long* acc) {
+  __shared__ int s_cnt;
+  __shared__ unsigned long long s_base;
+  for (int64_t x0 = blockIdx.x * (int64_t)blockDim.x; x0 < n; x0 += (int64_t)gridDim.x * blockDim.x) {
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    const int64_t x = x0 + threadIdx.x;
+    int k = 0, mine = 0, total = 0;
+    if (x < n) {
+      const VMeta m = meta[x];
+      if (is_heavy(m, cover, light_max))
+        total = desc_of(m, cover, static_cast<int>(task_off[x + 1] - task_off[x])).total();
+      k = (total + kResolveChunk - 1) / kResolveChunk;
+      if (!kFill) ndesc[x] = total;
+      if (k) mine = atomicAdd(&s_cnt, k);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cnt) {
+      if (!kFill) atomicAdd(&acc[kAccChunks], static_cast<unsigned long long>(s_cnt));
+      else s_base = atomicAdd(&acc[kAccDesc], static_cast<unsigned long long>(s_cnt));
+    }
+    __syncthreads();
+    if (kFill)
+      for (int j = 0; j < k; ++j)
+        if (static_cast<int64_t>(s_base + mine + j) < rcap) rchunks[s_base + mine + j] = make_int2(static_cast<int>(x), j);
+    __syncthreads();
+  }
 }
 
-__host__ __device__ constexpr int bin_chunk(int b) { return b == 0 ? 256 : 1024; }
+// Resolves every descriptor of every heavy anchor into a stream record:
+// begin, length | flags, owner of the streamed list.  One block per chunk of
+// kResolveChunk descriptors; no LDS, so many blocks hide the two dependent
+// loads (descriptor id, vertex record) per descriptor.
+template <bool kCover>
+__global__ __launch_bounds__(kThreads) void resolve_kernel(
+    const int32_t* lc, const VMeta* meta, const int64_t* task_off, const int64_t* task_begin,
+    const int32_t* task_len, const int32_t* task_owner, const int2* rchunks, int64_t rcap,
+    const unsigned long long* acc, const int64_t* so, int64_t scap, int64_t* sbeg, int32_t* slen, int32_t* soth) {
+  const int64_t nchunks = min(static_cast<int64_t>(acc[kAccChunks]), rcap);
+  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const int2 ch = rchunks[c];
+    const int32_t x = ch.x;
+    const VMeta mx = meta[x];
+    const int hf = mx.sfe - mx.hfb;
+    const int64_t toff = task_off[x];
+    const Desc Dx = desc_of(mx, kCover, static_cast<int>(task_off[x + 1] - toff));
+    const int d_end = min(Dx.total(), (ch.y + 1) * kResolveChunk);
+    const int64_t base = so[x];
+    for (int d = ch.y * kResolveChunk + threadIdx.x; d < d_end; d += blockDim.x) {
+      int64_t beg = 0;
+      int32_t len = 0, oth = x;
+      int k = d;
+      if (k < Dx.nB) {  // down class: Up(w); its members in P(x) are in Hfwd(x), so above x
+        const int32_t w = lc[mx.begin + mx.sfe + k];
+        const VMeta mw = meta[w];
+        beg = mw.begin;
+        len = mw.up;
+        oth = w;
+      } else if ((k -= Dx.nB) < Dx.nCu) {  // forward cover edge, up class
+        const int32_t v = lc[mx.begin + mx.hfb + k];
+        const VMeta mv = meta[v];
+        oth = v;
+        if (mv.up > 0 && mv.up <= mx.up) {
+          beg = mv.begin;
+          len = mv.up | kFlagUp;
+        }
+      } else if ((k -= Dx.nCu) < Dx.nCs) {  // forward cover edge, same class
+        const int32_t v = lc[mx.begin + mx.hfb + k];
+        const VMeta mv = meta[v];
+        oth = v;
+        const int a = hf - k - 1, b = mv.sfe - mv.hfb;
+        if (a > 0 && b > 0 && b < a) {
+          beg = mv.begin + mv.hfb;
+          len = b;
+        }
+      } else if ((k -= Dx.nCs) < Dx.nD) {  // backward cover edge, up class
+        const int32_t u = lc[mx.begin + mx.up + k];
+        const VMeta mu = meta[u];
+        oth = u;
+        if (mu.up > 0 && mu.up < mx.up) {
+          beg = mu.begin;
+          len = mu.up | kFlagUp;
+        }
+      } else {  // emitted same-class task: Hfwd(u) above x
+        const int64_t q = toff + (k - Dx.nD);
+        beg = task_begin[q];
+        len = task_len[q];
+        oth = task_owner[q];
+      }
+      const int64_t pos = base + d;
+      if (pos < scap) {
+        sbeg[pos] = beg;
+        slen[pos] = len;
+        soth[pos] = oth;
+      }
+    }
+  }
+}
 
-// kFill = false: count items per bin.  kFill = true: write them.
+// Work items: the streams of anchor x are split into at most
+// ceil(E / kElemChunk) ranges of about equal element count E / nit (cut at
+// stream starts).  kFill = false counts items per bin; kFill = true writes
+// int4 {x, first stream (lo, hi), stream count | kItemBitmap}.
 template <bool kFill>
 __global__ __launch_bounds__(kThreads) void items_kernel(const int32_t* lc, const VMeta* meta, int64_t n,
-                                                         const int64_t* task_off,
-                                                         bool cover, int light_max, int2* items,
-                                                         unsigned long long* acc) {
+                                                         const int32_t* ndesc, const int64_t* so, const int64_t* epre,
+                                                         int64_t scap, int4* items, unsigned long long* acc) {
   __shared__ int s_cnt[kBins];
   __shared__ unsigned long long s_base[kBins];
   for (int64_t x0 = blockIdx.x * (int64_t)blockDim.x; x0 < n; x0 += (int64_t)gridDim.x * blockDim.x) {
@@ -280,17 +402,23 @@ __global__ __launch_bounds__(kThreads) void items_kernel(const int32_t* lc, cons
     __syncthreads();
     const int64_t x = x0 + threadIdx.x;
     int k = 0, b = 0, mine = 0;
-    if (x < n) {
-      const VMeta m = meta[x];
-      if (is_heavy(m, cover, light_max)) {
-        const Desc d = desc_of(m, cover, static_cast<int>(task_off[x + 1] - task_off[x]));
+    bool bm = false;
+    int64_t s0 = 0, s1 = 0, e0 = 0, E = 0;
+    if (x < n && ndesc[x] > 0) {
+      s0 = min(so[x], scap);
+      s1 = min(so[x + 1], scap);
+      e0 = epre[s0];
+      E = epre[s1] - e0;
+      if (E > 0) {
+        const VMeta m = meta[x];
         int32_t lo;
         int64_t R;
         probe_window(lc, m, lo, R);
-        b = bin_of(R, probe_size(m));
-        const int ch = bin_chunk(b);
-        k = (d.total() + ch - 1) / ch;
-        if (k) mine = atomicAdd(&s_cnt[b], k);
+        b = choose_bin(R, probe_size(m), E, &bm);
+        int64_t want = (E + kElemChunk - 1) / kElemChunk;
+        want = max(want, (s1 - s0 + kItemMaxStreams - 1) / kItemMaxStreams);
+        k = static_cast<int>(min(want, s1 - s0));
+        mine = atomicAdd(&s_cnt[b], k);
       }
     }
     __syncthreads();
@@ -302,7 +430,16 @@ __global__ __launch_bounds__(kThreads) void items_kernel(const int32_t* lc, cons
     __syncthreads();
     if (kFill && k) {
       const unsigned long long base = s_base[b] + mine;
-      for (int j = 0; j < k; ++j) items[base + j] = make_int2(static_cast<int>(x), j);
+      int64_t prev = s0;
+      for (int j = 0; j < k; ++j) {
+        // first stream starting at or after e0 + (j+1) E / k
+        const int64_t cut = e0 + (E * (j + 1)) / k;
+        const int64_t nxt = j + 1 == k ? s1 : lower_bound_dev(epre, prev, s1, cut);
+        items[base + j] = make_int4(static_cast<int>(x), static_cast<int>(prev & 0xFFFFFFFF),
+                                    static_cast<int>(prev >> 32),
+                                    static_cast<int>(nxt - prev) | (bm ? kItemBitmap : 0));
+        prev = nxt;
+      }
     }
     __syncthreads();
   }
@@ -321,58 +458,169 @@ __device__ __forceinline__ uint32_t hslot(int32_t key, int shift) {
   return (static_cast<uint32_t>(key) * 0x9E3779B1u) >> shift;
 }
 
-
 enum ProbeMode { kBitmap = 0, kHash = 1, kSearch = 2 };
 
-// Membership of t in the anchor's probe set: LDS bitmap over the id window
-// [lo, lo + R), LDS hash table, or binary search in the sorted Up / Hfwd
-// segments of the anchor's row.
+// Probe set P(x) = Up(x) ∪ Hfwd(x) of the block's current anchor.
+struct ProbeSet {
+  const uint32_t* tab;
+  int32_t lo;      // bitmap: id of bit 0
+  uint32_t R;      // bitmap: window length; bit R is kept clear
+  int cap, shift;  // hash: slot count (power of two) and hslot shift
+  const int32_t* up_row;
+  const int32_t* hf_row;
+  int up_len, hf_len;
+};
+
+// 1 if t is in the probe set, else 0.  t may be any value (the tail of a
+// chunk past the stream end is probed and masked afterwards).
 template <int MODE>
-__device__ __forceinline__ bool probe(const uint32_t* tab, int cap, int shift, int32_t lo, uint32_t R,
-                                      const int32_t* lc, const VMeta& mx, bool up_side, int32_t t) {
+__device__ __forceinline__ uint32_t probe(const ProbeSet& ps, int32_t t, bool up_side) {
   if (MODE == kBitmap) {
-    const uint32_t d = static_cast<uint32_t>(t - lo);
-    const bool in = d < R;
-    const uint32_t word = tab[in ? (d >> 5) : 0];
-    return in && ((word >> (d & 31)) & 1u);
+    const uint32_t d = min(static_cast<uint32_t>(t) - static_cast<uint32_t>(ps.lo), ps.R);
+    return (ps.tab[d >> 5] >> (d & 31)) & 1u;
   } else if (MODE == kHash) {
-    uint32_t h = hslot(t, shift);
+    uint32_t h = hslot(t, ps.shift);
     int32_t k;
-    while ((k = static_cast<int32_t>(tab[h])) != t && k != -1) h = (h + 1) & (cap - 1);
-    return k == t;
+    while ((k = static_cast<int32_t>(ps.tab[h])) != t && k != -1) h = (h + 1) & (ps.cap - 1);
+    return k == t ? 1u : 0u;
   }
-  return up_side ? gsearch(lc + mx.begin, mx.up, t) : gsearch(lc + mx.begin + mx.hfb, mx.sfe - mx.hfb, t);
+  return (up_side ? gsearch(ps.up_row, ps.up_len, t) : gsearch(ps.hf_row, ps.hf_len, t)) ? 1u : 0u;
 }
 
-// `mode` is the same for the whole block (one item at a time).
-__device__ __forceinline__ bool probe_any(int mode, const uint32_t* tab, int cap, int shift, int32_t lo, uint32_t R,
-                                          const int32_t* lc, const VMeta& mx, bool up_side, int32_t t) {
-  if (mode == kBitmap) return probe<kBitmap>(tab, cap, shift, lo, R, lc, mx, up_side, t);
-  if (mode == kHash) return probe<kHash>(tab, cap, shift, lo, R, lc, mx, up_side, t);
-  return probe<kSearch>(tab, cap, shift, lo, R, lc, mx, up_side, t);
+// Streams are cut into chunks of kChunk consecutive elements that never
+// cross a stream end; a lane takes one chunk at a time (kChunk independent
+// loads in flight, one 64-bit address).  The column buffers carry kColPad
+// readable entries past nnz, so the tail of a stream's last chunk is loaded
+// unconditionally and masked.
+constexpr int kChunk = 8;
+constexpr int kWinIters = 8;  // chunk rounds of the block per window
+static_assert(kChunk <= kColPad, "chunk tail must stay inside the padded columns");
+
+template <int MODE, bool kPV>
+__device__ __forceinline__ uint32_t chunk_hits(const int32_t* p, int len, const ProbeSet& ps, bool up_side,
+                                               int32_t x, int32_t oth, int64_t* pv) {
+  int32_t v[kChunk];
+#pragma unroll
+  for (int q = 0; q < kChunk; ++q) v[q] = p[q];
+  const uint32_t lenmask = len >= kChunk ? ((1u << kChunk) - 1u) : ((1u << len) - 1u);
+  uint32_t hits = 0;
+  if (MODE == kHash) {
+    // all first probes in flight together; collision chains (rare at load
+    // factor <= 1/2) are walked afterwards, one slot per round for all
+    uint32_t h[kChunk];
+    uint32_t pend = 0;
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) h[q] = hslot(v[q], ps.shift);
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) {
+      const int32_t k = static_cast<int32_t>(ps.tab[h[q]]);
+      hits |= static_cast<uint32_t>(k == v[q]) << q;
+      pend |= static_cast<uint32_t>(k != v[q] && k != -1) << q;
+    }
+    pend &= lenmask;
+    while (pend) {
+#pragma unroll
+      for (int q = 0; q < kChunk; ++q) {
+        const uint32_t pb = (pend >> q) & 1u;
+        h[q] = (h[q] + pb) & static_cast<uint32_t>(ps.cap - 1);
+        const int32_t k = static_cast<int32_t>(ps.tab[h[q]]);
+        hits |= (pb & static_cast<uint32_t>(k == v[q])) << q;
+        pend &= ~(static_cast<uint32_t>(k == v[q] || k == -1) << q);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) hits |= probe<MODE>(ps, v[q], up_side) << q;
+  }
+  hits &= lenmask;
+  if (kPV && hits) {
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q)
+      if ((hits >> q) & 1u) add_pv(pv, x, oth, v[q]);
+  }
+  return static_cast<uint32_t>(__popc(hits));
 }
 
-// One block per work item (anchor x, descriptor chunk).  WORDS is the LDS
-// table size in 32-bit words (0: search the sorted rows); each item picks a
-// bitmap or a hash table (see bitmap_fits); D = descriptors per item.  Short streams (<= kShortStream elements) are handled by the lane
-// that resolved them, with all loads issued before the probes; longer
-// streams are flattened across the block, K consecutive elements per lane.
-constexpr int kShortStream = 16;
+// All chunks of one batch of streams.  The chunk space [0, C) is walked in
+// windows of THREADS * kWinIters chunks; a window is split into tiles of 64
+// chunks, one per wave and round, and for each tile the block first records
+// the number of streams that start before it (s_tb) and a 64-bit mask of the
+// streams that start inside it (s_M).  Lane i of a wave then finds the
+// stream of its chunk as s_tb + popcount(mask bits <= i) - 1, with no search.
+template <int MODE, int THREADS, bool kPV>
+__device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_cl, const int64_t* s_beg,
+                                               const int32_t* s_oth, const uint8_t* s_up, uint64_t* s_M,
+                                               int32_t* s_tb, const int32_t* lc, const ProbeSet& ps, int32_t x,
+                                               int64_t* pv) {
+  constexpr int kWin = THREADS * kWinIters;
+  constexpr int kTiles = kWin / kWave;
+  static_assert(THREADS % kWave == 0, "block must be whole waves");
+  const int tid = threadIdx.x;
+  const uint32_t ln = static_cast<uint32_t>(lane());
+  uint32_t cnt = 0;
+  for (int w0 = 0; w0 < C; w0 += kWin) {
+    for (int t = tid; t < kTiles; t += THREADS) {
+      const int ct = w0 + t * kWave;
+      if (ct < C) {
+        int lo = 0, hi = nslots;  // first stream starting at or after ct
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (s_cl[mid].x < ct) lo = mid + 1;
+          else hi = mid;
+        }
+        uint64_t M = 0;
+        for (int j = lo; j < nslots; ++j) {
+          const int f = s_cl[j].x;
+          if (f >= ct + kWave) break;
+          M |= 1ull << (f - ct);
+        }
+        s_tb[t] = lo;
+        s_M[t] = M;
+      }
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int i = 0; i < kWinIters; ++i) {
+      const int rel = i * THREADS + tid;
+      const int c = w0 + rel;
+      if (c < C) {
+        const int t = rel >> 6;
+        const uint64_t M = s_M[t];
+        const int below = static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+            static_cast<uint32_t>(M >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(M), 0u)));
+        const int j = s_tb[t] + below + static_cast<int>((M >> ln) & 1ull) - 1;
+        const int2 cl = s_cl[j];
+        const int k = c - cl.x;
+        const int32_t* p = lc + s_beg[j] + static_cast<int64_t>(k) * kChunk;
+        cnt += chunk_hits<MODE, kPV>(p, cl.y - k * kChunk, ps, MODE == kSearch && s_up[j] != 0, x,
+                                     kPV ? s_oth[j] : 0, pv);
+      }
+    }
+    __syncthreads();
+  }
+  return cnt;
+}
 
-template <int WORDS, int THREADS, int D, bool kCover, bool kPV>
+// One block per work item (anchor x, range of resolved streams).  WORDS is
+// the LDS table size in 32-bit words (0: search the sorted rows); the item
+// says whether the anchor's table is a bitmap or a hash table.  Stream records are
+// loaded D at a time (R per thread), the non-empty ones are compacted into
+// LDS with their first chunk, and run_chunks streams them.
+template <int WORDS, int THREADS, int D, bool kPV>
 __global__ __launch_bounds__(THREADS) void heavy_kernel(const int32_t* lc, const VMeta* meta, int bin,
-                                                        const int2* items, const int64_t* task_off,
-                                                        const int64_t* task_begin, const int32_t* task_len,
-                                                        const int32_t* task_owner, unsigned long long* acc,
-                                                        int64_t* pv) {
-  constexpr int R = D / THREADS;  // descriptors resolved per thread
+                                                        const int4* items, const int64_t* sbeg,
+                                                        const int32_t* slen, const int32_t* soth,
+                                                        unsigned long long* acc, int64_t* pv) {
+  constexpr int R = D / THREADS;  // records loaded per thread
   static_assert(R * THREADS == D, "D must be a multiple of THREADS");
+  constexpr int kTiles = THREADS * kWinIters / kWave;
   __shared__ uint32_t tab[WORDS > 0 ? WORDS : 1];
   __shared__ int64_t s_beg[D];
-  __shared__ int64_t s_pre[D + 1];
-  __shared__ int32_t s_flt[D];
+  __shared__ int2 s_cl[D + 1];  // (first chunk, length) of each non-empty stream
   __shared__ int32_t s_oth[kPV ? D : 1];
   __shared__ uint8_t s_up[WORDS == 0 ? D : 1];
+  __shared__ uint64_t s_M[kTiles];
+  __shared__ int32_t s_tb[kTiles];
   __shared__ int64_t sh[THREADS / kWave + 1];
   __shared__ int32_t shi[THREADS / kWave + 1];
   __shared__ unsigned long long s_item;
@@ -380,7 +628,7 @@ __global__ __launch_bounds__(THREADS) void heavy_kernel(const int32_t* lc, const
   const unsigned long long first = acc[kAccBinOff + bin];
   const unsigned long long count = acc[kAccBinCount + bin];
   const int tid = threadIdx.x;
-  int64_t cnt = 0, elems = 0, descs = 0, builds = 0;
+  int64_t cnt = 0, elems = 0, builds = 0;
   int32_t cur_x = -1;
   for (;;) {
     if (tid == 0) s_item = atomicAdd(&acc[kAccBinNext + bin], 1ull);
@@ -388,220 +636,113 @@ __global__ __launch_bounds__(THREADS) void heavy_kernel(const int32_t* lc, const
     const unsigned long long it = s_item;
     __syncthreads();
     if (it >= count) break;
-    const int2 item = items[first + it];
+    const int4 item = items[first + it];
     const int32_t x = item.x;
+    const int64_t sa = static_cast<int64_t>(static_cast<uint32_t>(item.y)) | (static_cast<int64_t>(item.z) << 32);
+    const int64_t sb = sa + (item.w & (kItemBitmap - 1));
     const VMeta mx = meta[x];
-    const int hf = mx.sfe - mx.hfb;
-    const int P = mx.up + hf;
-    const int64_t toff = task_off[x];
-    const Desc Dx = desc_of(mx, kCover, static_cast<int>(task_off[x + 1] - toff));
-    const int d0 = item.y * D;
-    const int nd = min(Dx.total() - d0, D);
-    int cap = 64, shift = 26;
-    int32_t wlo = 0;
-    uint32_t wR = 0;
+    const int P = mx.up + (mx.sfe - mx.hfb);
+    ProbeSet ps;
+    ps.tab = tab;
+    ps.lo = 0;
+    ps.R = 0;
+    ps.cap = 64;
+    ps.shift = 26;
+    ps.up_row = lc + mx.begin;
+    ps.up_len = mx.up;
+    ps.hf_row = lc + mx.begin + mx.hfb;
+    ps.hf_len = mx.sfe - mx.hfb;
     int mode = kSearch;
     if (WORDS > 0) {
       int64_t R64;
-      probe_window(lc, mx, wlo, R64);
-      wR = static_cast<uint32_t>(R64);
-      mode = bitmap_fits(R64, P, WORDS) ? kBitmap : kHash;
+      probe_window(lc, mx, ps.lo, R64);
+      ps.R = static_cast<uint32_t>(R64);
+      mode = (item.w & kItemBitmap) ? kBitmap : kHash;
+      ps.cap = WORDS;
+      ps.shift = 32 - __builtin_ctz(WORDS);
       if (x != cur_x) {
         if (mode == kBitmap) {
-          const int words = static_cast<int>((R64 + 31) >> 5);
+          const int words = static_cast<int>(bitmap_words(R64));
           for (int i = tid; i < words; i += THREADS) tab[i] = 0u;
           __syncthreads();
           for (int i = tid; i < P; i += THREADS) {
             const int32_t key = i < mx.up ? lc[mx.begin + i] : lc[mx.begin + mx.hfb + (i - mx.up)];
-            const uint32_t d = static_cast<uint32_t>(key - wlo);
+            const uint32_t d = static_cast<uint32_t>(key - ps.lo);
             atomicOr(&tab[d >> 5], 1u << (d & 31));
           }
         } else {
-          while (cap < 2 * P) {
-            cap <<= 1;
-            --shift;
-          }
-          for (int i = tid; i < cap; i += THREADS) tab[i] = 0xFFFFFFFFu;
+          for (int i = tid; i < ps.cap; i += THREADS) tab[i] = 0xFFFFFFFFu;
           __syncthreads();
           for (int i = tid; i < P; i += THREADS) {
             const int32_t key = i < mx.up ? lc[mx.begin + i] : lc[mx.begin + mx.hfb + (i - mx.up)];
-            uint32_t h = hslot(key, shift);
+            uint32_t h = hslot(key, ps.shift);
             while (atomicCAS(&tab[h], 0xFFFFFFFFu, static_cast<uint32_t>(key)) != 0xFFFFFFFFu)
-              h = (h + 1) & (cap - 1);
+              h = (h + 1) & (ps.cap - 1);
           }
         }
         __syncthreads();
         cur_x = x;
         builds += tid == 0 ? P : 0;
-      } else if (mode == kHash) {
-        while (cap < 2 * P) {
-          cap <<= 1;
-          --shift;
-        }
       }
     }
-    // ---- resolve this item's descriptors (R per thread, independent loads)
-    int64_t lbeg[R];
-    int32_t llen[R], lflt[R], loth[R];
-    bool lup[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int dl = tid * R + r;
-      lbeg[r] = 0;
-      llen[r] = 0;
-      lflt[r] = -1;
-      loth[r] = x;
-      lup[r] = false;
-      if (dl < nd) {
-        int k = d0 + dl;
-        if (k < Dx.nB) {  // down class: Up(w) above x
-          const int32_t w = lc[mx.begin + mx.sfe + k];
-          const VMeta mw = meta[w];
-          lbeg[r] = mw.begin;
-          llen[r] = mw.up;
-          lflt[r] = x;
-          loth[r] = w;
-        } else if ((k -= Dx.nB) < Dx.nCu) {  // forward cover edge, up class
-          const int32_t v = lc[mx.begin + mx.hfb + k];
-          const VMeta mv = meta[v];
-          loth[r] = v;
-          if (mv.up > 0 && mv.up <= mx.up) {
-            lbeg[r] = mv.begin;
-            llen[r] = mv.up;
-            lup[r] = true;
-          }
-        } else if ((k -= Dx.nCu) < Dx.nCs) {  // forward cover edge, same class
-          const int32_t v = lc[mx.begin + mx.hfb + k];
-          const VMeta mv = meta[v];
-          loth[r] = v;
-          const int a = hf - k - 1, b = mv.sfe - mv.hfb;
-          if (a > 0 && b > 0 && b < a) {
-            lbeg[r] = mv.begin + mv.hfb;
-            llen[r] = b;
-          }
-        } else if ((k -= Dx.nCs) < Dx.nD) {  // backward cover edge, up class
-          const int32_t u = lc[mx.begin + mx.up + k];
-          const VMeta mu = meta[u];
-          loth[r] = u;
-          if (mu.up > 0 && mu.up < mx.up) {
-            lbeg[r] = mu.begin;
-            llen[r] = mu.up;
-            lup[r] = true;
-          }
-        } else {  // emitted same-class task: Hfwd(u) above x
-          const int64_t q = toff + (k - Dx.nD);
-          lbeg[r] = task_begin[q];
-          llen[r] = task_len[q];
-          loth[r] = task_owner[q];
-        }
-      }
-    }
-    // ---- short streams: by the resolving lane, all loads before the probes
-    int64_t longsum = 0;
-    int nlong = 0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int len = llen[r];
-      if (len > kShortStream) {
-        longsum += len;
-        ++nlong;
-        continue;
-      }
-      if (len == 0) continue;
-      int32_t val[kShortStream];
-#pragma unroll
-      for (int q = 0; q < kShortStream; ++q) val[q] = q < len ? lc[lbeg[r] + q] : -1;
-#pragma unroll
-      for (int q = 0; q < kShortStream; ++q) {
-        const int32_t t = val[q];
-        if (q < len && t > lflt[r] && probe_any(mode, tab, cap, shift, wlo, wR, lc, mx, lup[r], t)) {
-          ++cnt;
-          if (kPV) add_pv(pv, x, loth[r], t);
-        }
-      }
-      elems += len;
-    }
-    // ---- long streams: compact them, then flatten across the block
-    int32_t ltot;
-    const int32_t lfirst = block_excl_scan(nlong, shi, &ltot);
-    int64_t tot;
-    int64_t run = block_excl_scan(longsum, sh, &tot);
-    {
-      int slot = lfirst;
+    for (int64_t bs = sa; bs < sb; bs += D) {
+      const int nd = static_cast<int>(min(static_cast<int64_t>(D), sb - bs));
+      int64_t lbeg[R];
+      int32_t llen[R], loth[R];
+      bool lup[R];
+      int nne = 0, nch = 0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if (llen[r] <= kShortStream) continue;
-        s_pre[slot] = run;
+        const int dl = tid * R + r;
+        lbeg[r] = 0;
+        llen[r] = 0;
+        loth[r] = x;
+        lup[r] = false;
+        if (dl < nd) {
+          const int64_t k = bs + dl;
+          const int32_t lf = slen[k];
+          lbeg[r] = sbeg[k];
+          llen[r] = lf & kLenMask;
+          lup[r] = (lf & kFlagUp) != 0;
+          if (kPV) loth[r] = soth[k];
+        }
+        if (llen[r] > 0) {
+          ++nne;
+          nch += (llen[r] + kChunk - 1) / kChunk;
+          elems += llen[r];
+        }
+      }
+      int32_t nslots, C;
+      int slot = block_excl_scan(nne, shi, &nslots);
+      int cb = block_excl_scan(nch, shi, &C);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (llen[r] <= 0) continue;
+        s_cl[slot] = make_int2(cb, llen[r]);
         s_beg[slot] = lbeg[r];
-        s_flt[slot] = lflt[r];
         if (kPV) s_oth[slot] = loth[r];
-        if (WORDS == 0) s_up[slot] = lup[r];
-        run += llen[r];
+        if (WORDS == 0) s_up[slot] = lup[r] ? 1 : 0;
+        cb += (llen[r] + kChunk - 1) / kChunk;
         ++slot;
       }
-    }
-    if (tid == 0) s_pre[ltot] = tot;
-    __syncthreads();
-    if (tid == 0) {
-      elems += tot;
-      descs += nd;
-    }
-    for (int64_t base = 0; base < tot; base += (int64_t)THREADS * kK) {
-      const int64_t e0 = base + (int64_t)tid * kK;
-      if (e0 < tot) {
-        int lo = 0, hi = ltot;  // largest j with s_pre[j] <= e0
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (s_pre[mid] <= e0) lo = mid;
-          else hi = mid;
-        }
-        int j = lo;
-        int64_t cb = s_beg[j], cp = s_pre[j], ce = s_pre[j + 1];
-        int32_t cf = s_flt[j];
-        int64_t addr[kK];
-        int32_t flt[kK];
-        int jj[kK];
-#pragma unroll
-        for (int q = 0; q < kK; ++q) {
-          const int64_t e = e0 + q;
-          if (e < tot) {
-            while (e >= ce) {
-              ++j;
-              cb = s_beg[j];
-              cp = ce;
-              ce = s_pre[j + 1];
-              cf = s_flt[j];
-            }
-            addr[q] = cb + (e - cp);
-            flt[q] = cf;
-          } else {
-            addr[q] = -1;
-            flt[q] = 0x7FFFFFFF;
-          }
-          jj[q] = j;
-        }
-        int32_t val[kK];
-#pragma unroll
-        for (int q = 0; q < kK; ++q) val[q] = addr[q] >= 0 ? lc[addr[q]] : -1;
-#pragma unroll
-        for (int q = 0; q < kK; ++q) {
-          const int32_t t = val[q];
-          if (t > flt[q] && probe_any(mode, tab, cap, shift, wlo, wR, lc, mx, WORDS == 0 && s_up[jj[q]], t)) {
-            ++cnt;
-            if (kPV) add_pv(pv, x, s_oth[jj[q]], t);
-          }
-        }
+      if (tid == 0) s_cl[nslots] = make_int2(C, 0);
+      __syncthreads();
+      if (WORDS == 0) {
+        cnt += run_chunks<kSearch, THREADS, kPV>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, pv);
+      } else if (mode == kBitmap) {
+        cnt += run_chunks<kBitmap, THREADS, kPV>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, pv);
+      } else {
+        cnt += run_chunks<kHash, THREADS, kPV>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, pv);
       }
     }
-    __syncthreads();
   }
   block_acc(acc, kAccT, cnt, sh);
   block_acc(acc, kAccHeavyElems, elems, sh);
-  block_acc(acc, kAccDesc, descs, sh);
+  block_acc(acc, kAccBinElems + bin, elems, sh);
   block_acc(acc, kAccBuild, builds, sh);
 }
 
-__global__ void finish_kernel(const unsigned long long* acc, const int64_t* h_off, int64_t n,
+__global__ void finish_kernel(const unsigned long long* acc, const int64_t* h_off, int64_t n, const int64_t* so,
                               int64_t* triangles, int64_t* h_count, int64_t* stats) {
   *triangles = static_cast<int64_t>(acc[kAccT]);
   if (h_count) *h_count = h_off[n];
@@ -609,10 +750,14 @@ __global__ void finish_kernel(const unsigned long long* acc, const int64_t* h_of
   stats[4] = static_cast<int64_t>(acc[kAccElems] + acc[kAccHeavyElems]);
   stats[5] = static_cast<int64_t>(acc[kAccLight]);
   stats[6] = static_cast<int64_t>(acc[kAccItems]);
-  stats[7] = static_cast<int64_t>(acc[kAccDesc]);
+  stats[7] = so[n];
   stats[8] = static_cast<int64_t>(acc[kAccHeavyElems]);
   stats[9] = static_cast<int64_t>(acc[kAccBuild]);
   stats[10] = static_cast<int64_t>(acc[kAccElems]);
+  for (int b = 0; b < kBins; ++b) {
+    stats[11 + b] = static_cast<int64_t>(acc[kAccBinElems + b]);
+    stats[11 + kBins + b] = static_cast<int64_t>(acc[kAccBinCount + b]);
+  }
 }
 
 __global__ void forward_meta_kernel(const int64_t* off, const int32_t* cols, int64_t n, VMeta* meta) {
@@ -625,12 +770,10 @@ __global__ void forward_meta_kernel(const int64_t* off, const int32_t* cols, int
   }
 }
 
-template <int WORDS, int THREADS, int D, bool kCover, bool kPV>
+template <int WORDS, int THREADS, int D, bool kPV>
 int launch_heavy(const CountArgs& a, CountWs& w, int bin, int blocks_per_cu, hipStream_t s) {
-  heavy_kernel<WORDS, THREADS, D, kCover, kPV>
-      <<<static_cast<unsigned>(num_cus() * blocks_per_cu), THREADS, 0, s>>>(
-          a.cols, a.meta, bin, w.items, w.task_off, w.task_begin, w.task_len, w.task_owner, w.acc,
-          a.per_vertex_out);
+  heavy_kernel<WORDS, THREADS, D, kPV><<<static_cast<unsigned>(num_cus() * blocks_per_cu), THREADS, 0, s>>>(
+      a.cols, a.meta, bin, w.items, w.sbeg, w.slen, w.soth, w.acc, a.per_vertex_out);
   TC_HIP(hipGetLastError());
   return TC_OK;
 }
@@ -640,6 +783,7 @@ int launch_all(const CountArgs& a, CountWs& w, hipStream_t s) {
   const tc_csr* g = a.g;
   const int64_t n = g->n;
   const unsigned gedge = static_cast<unsigned>(num_cus() * 16);
+  const unsigned gv = grid_for(n, kThreads, 16384);
   plan_kernel<kCover, kPV, false><<<gedge, kThreads, 0, s>>>(
       a.cols, a.meta, n, w.h_off, w.h_u, w.h_v, a.light_max, w.ecnt, w.task_off, w.ecur, w.task_begin,
       w.task_len, w.task_owner, w.acc, a.per_vertex_out);
@@ -656,20 +800,47 @@ int launch_all(const CountArgs& a, CountWs& w, hipStream_t s) {
   plan_kernel<kCover, kPV, true><<<gedge, kThreads, 0, s>>>(
       a.cols, a.meta, n, w.h_off, w.h_u, w.h_v, a.light_max, w.ecnt, w.task_off, w.ecur, w.task_begin,
       w.task_len, w.task_owner, w.acc, a.per_vertex_out);
-  const unsigned gv = grid_for(n, kThreads, 16384);
-  items_kernel<false><<<gv, kThreads, 0, s>>>(a.cols, a.meta, n, w.task_off, kCover, a.light_max, w.items, w.acc);
+  prof_stage("resolve");
+  TC_TRY(fill_i64(reinterpret_cast<int64_t*>(w.acc) + kAccChunks, 0, 1, s));
+  desc_plan_kernel<false><<<gv, kThreads, 0, s>>>(a.meta, n, w.task_off, kCover, a.light_max, w.ndesc, w.rchunks,
+                                                  w.rcap, w.acc);
+  desc_plan_kernel<true><<<gv, kThreads, 0, s>>>(a.meta, n, w.task_off, kCover, a.light_max, w.ndesc, w.rchunks,
+                                                 w.rcap, w.acc);
+  {
+    Carver sc2(w.scratch);
+    TC_TRY(scan_exclusive<int32_t>(w.ndesc, w.so, n, sc2, s));
+  }
+  resolve_kernel<kCover><<<static_cast<unsigned>(num_cus() * 16), kThreads, 0, s>>>(
+      a.cols, a.meta, w.task_off, w.task_begin, w.task_len, w.task_owner, w.rchunks, w.rcap, w.acc, w.so, w.scap,
+      w.sbeg, w.slen, w.soth);
+  TC_HIP(hipGetLastError());
+  // element prefix over the streams actually written
+  int64_t nstreams = 0;
+  TC_HIP(hipMemcpyAsync(&nstreams, w.so + n, sizeof nstreams, hipMemcpyDeviceToHost, s));
+  TC_HIP(hipStreamSynchronize(s));
+  // a symmetric simple graph has at most 2 nnz descriptors (deg + |Hfwd| +
+  // emitted tasks per anchor); more means an unvalidated asymmetric input
+  if (nstreams > w.scap)
+    return fail(TC_ERR_NOT_SYMMETRIC, "tc_count: %lld intersection descriptors exceed the bound 2 nnz of a "
+                "symmetric graph (validate the input with TC_VALIDATE)", (long long)nstreams);
+  const int64_t sc_n = nstreams;
+  {
+    Carver sc3(w.scratch);
+    TC_TRY(scan_exclusive_masked(w.slen, kLenMask, w.epre, sc_n, sc3, s));
+  }
+  items_kernel<false><<<gv, kThreads, 0, s>>>(a.cols, a.meta, n, w.ndesc, w.so, w.epre, sc_n, w.items, w.acc);
   bin_offsets_kernel<<<1, 1, 0, s>>>(w.acc);
-  items_kernel<true><<<gv, kThreads, 0, s>>>(a.cols, a.meta, n, w.task_off, kCover, a.light_max, w.items, w.acc);
+  items_kernel<true><<<gv, kThreads, 0, s>>>(a.cols, a.meta, n, w.ndesc, w.so, w.epre, sc_n, w.items, w.acc);
   TC_HIP(hipGetLastError());
   prof_stage("heavy");
-  // the four bins are independent: run them side by side
+  // the bins are independent: run them side by side
   Fork* f = fork_for_device();
   if (!f) return TC_ERR_HIP;
   TC_TRY(fork_begin(f, s));
-  TC_TRY((launch_heavy<kBinWords2, 1024, 1024, kCover, kPV>(a, w, 2, 1, s)));
-  TC_TRY((launch_heavy<kBinWords1, 512, 1024, kCover, kPV>(a, w, 1, 3, f->aux[0])));
-  TC_TRY((launch_heavy<kBinWords0, 256, 256, kCover, kPV>(a, w, 0, 8, f->aux[1])));
-  TC_TRY((launch_heavy<0, 512, 1024, kCover, kPV>(a, w, 3, 4, f->aux[2])));
+  TC_TRY((launch_heavy<kBinWords2, 1024, 1024, kPV>(a, w, 2, 1, s)));
+  TC_TRY((launch_heavy<kBinWords1, 512, 1024, kPV>(a, w, 1, 3, f->aux[0])));
+  TC_TRY((launch_heavy<kBinWords0, 64, 256, kPV>(a, w, 0, 24, f->aux[1])));
+  TC_TRY((launch_heavy<0, 512, 1024, kPV>(a, w, 3, 4, f->aux[2])));
   TC_TRY(fork_end(f, s));
   prof_stage("finish");
   return TC_OK;
@@ -690,12 +861,21 @@ CountWs count_reserve(Carver& c, int64_t n, int64_t nnz) {
   w.task_begin = c.take<int64_t>(hmax);
   w.task_len = c.take<int32_t>(hmax);
   w.task_owner = c.take<int32_t>(hmax);
-  // items: one per heavy anchor plus one per started chunk of >= 256
-  // descriptors; descriptors per anchor <= 2 deg + emitted tasks
-  w.items = c.take<int2>(n + (3 * nnz) / 256 + 8);
+  w.ndesc = c.take<int32_t>(n + 1);
+  w.so = c.take<int64_t>(n + 2);
+  // descriptors of a simple graph: at most deg + |Hfwd| + emitted tasks per
+  // anchor, i.e. <= 2 nnz in total; records beyond the capacity are dropped
+  w.scap = 2 * nnz + 2;
+  w.rcap = n + w.scap / kResolveChunk + 8;
+  w.rchunks = c.take<int2>(w.rcap);
+  w.sbeg = c.take<int64_t>(w.scap);
+  w.slen = c.take<int32_t>(w.scap);
+  w.soth = c.take<int32_t>(w.scap);
+  w.epre = c.take<int64_t>(w.scap + 1);
+  w.items = c.take<int4>(w.scap + 8);
   w.acc = c.take<unsigned long long>(kAccSlots);
-  w.stats = c.take<int64_t>(16);
-  w.scratch = c.take<char>(scan_ws_bytes(n + 1) + (n + 1) * sizeof(int32_t) + 256);
+  w.stats = c.take<int64_t>(24);
+  w.scratch = c.take<char>(scan_ws_bytes(w.scap + 1) + (n + 1) * sizeof(int32_t) + 256);
   return w;
 }
 
@@ -710,7 +890,7 @@ int count_run(const CountArgs& a, CountWs& w, int64_t* triangles, int64_t* h_cou
   const tc_csr* g = a.g;
   const int64_t n = g->n;
   TC_TRY(fill_i64(reinterpret_cast<int64_t*>(w.acc), 0, kAccSlots, s));
-  TC_TRY(fill_i64(w.stats, 0, 16, s));
+  TC_TRY(fill_i64(w.stats, 0, 24, s));
   if (n == 0) {
     TC_TRY(fill_i64(triangles, 0, 1, s));
     if (h_count) TC_TRY(fill_i64(h_count, 0, 1, s));
@@ -728,7 +908,7 @@ int count_run(const CountArgs& a, CountWs& w, int64_t* triangles, int64_t* h_cou
     if (a.per_vertex) TC_TRY((launch_all<false, true>(a, w, s)));
     else TC_TRY((launch_all<false, false>(a, w, s)));
   }
-  finish_kernel<<<1, 1, 0, s>>>(w.acc, w.h_off, n, triangles, h_count, w.stats);
+  finish_kernel<<<1, 1, 0, s>>>(w.acc, w.h_off, n, w.so, triangles, h_count, w.stats);
   TC_HIP(hipGetLastError());
   return TC_OK;
 }

@@ -177,23 +177,33 @@ constexpr int kScanItems = 8;
 constexpr int64_t kScanTile = kScanThreads * kScanItems;
 
 template <class T>
-__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const T* in, int64_t count,
-                                                                    int64_t* partial) {
+struct LoadAll {
+  const T* p;
+  __device__ __forceinline__ int64_t operator()(int64_t i) const { return static_cast<int64_t>(p[i]); }
+};
+
+struct LoadMasked {
+  const int32_t* p;
+  int32_t mask;
+  __device__ __forceinline__ int64_t operator()(int64_t i) const { return static_cast<int64_t>(p[i] & mask); }
+};
+
+template <class F>
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(F in, int64_t count, int64_t* partial) {
   __shared__ int64_t sh[kScanThreads / kWave + 1];
   const int64_t base = blockIdx.x * kScanTile + threadIdx.x * (int64_t)kScanItems;
   int64_t s = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i)
-    if (base + i < count) s += static_cast<int64_t>(in[base + i]);
+    if (base + i < count) s += in(base + i);
   s = block_sum(s, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
 // Scans each tile; adds the scanned tile offset (nullable -> 0); writes
 // out[count] = total when this tile holds the last element.
-template <class T>
-__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const T* in, int64_t count,
-                                                                   const int64_t* tile_off,
+template <class F>
+__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(F in, int64_t count, const int64_t* tile_off,
                                                                    int64_t* out) {
   __shared__ int64_t sh[kScanThreads / kWave + 1];
   const int64_t base = blockIdx.x * kScanTile + threadIdx.x * (int64_t)kScanItems;
@@ -201,7 +211,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const T* in, i
   int64_t s = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    v[i] = (base + i < count) ? static_cast<int64_t>(in[base + i]) : 0;
+    v[i] = (base + i < count) ? in(base + i) : 0;
     s += v[i];
   }
   int64_t tot;
@@ -225,25 +235,34 @@ size_t scan_ws_bytes(int64_t count) {
   return b + 256;
 }
 
-template <class T>
-int scan_exclusive(const T* in, int64_t* out, int64_t count, Carver& ws, hipStream_t s) {
+template <class F>
+static int scan_impl(F in, int64_t* out, int64_t count, Carver& ws, hipStream_t s) {
   if (count <= 0) return fill_i64(out, 0, 1, s);
   const int64_t tiles = (count + kScanTile - 1) / kScanTile;
   if (tiles == 1) {
-    scan_apply_kernel<T><<<1, kScanThreads, 0, s>>>(in, count, nullptr, out);
+    scan_apply_kernel<F><<<1, kScanThreads, 0, s>>>(in, count, nullptr, out);
     TC_HIP(hipGetLastError());
     return TC_OK;
   }
   int64_t* partial = ws.take<int64_t>(tiles + 1);
-  scan_reduce_kernel<T><<<(unsigned)tiles, kScanThreads, 0, s>>>(in, count, partial);
+  scan_reduce_kernel<F><<<(unsigned)tiles, kScanThreads, 0, s>>>(in, count, partial);
   TC_HIP(hipGetLastError());
-  // scan the tile sums in place (out-of-place into the same buffer is not
-  // allowed, so recurse into a fresh buffer)
+  // the tile sums are scanned into a fresh buffer (recursively)
   int64_t* partial_scan = ws.take<int64_t>(tiles + 1);
-  TC_TRY(scan_exclusive<int64_t>(partial, partial_scan, tiles, ws, s));
-  scan_apply_kernel<T><<<(unsigned)tiles, kScanThreads, 0, s>>>(in, count, partial_scan, out);
+  TC_TRY(scan_impl(LoadAll<int64_t>{partial}, partial_scan, tiles, ws, s));
+  scan_apply_kernel<F><<<(unsigned)tiles, kScanThreads, 0, s>>>(in, count, partial_scan, out);
   TC_HIP(hipGetLastError());
   return TC_OK;
+}
+
+template <class T>
+int scan_exclusive(const T* in, int64_t* out, int64_t count, Carver& ws, hipStream_t s) {
+  return scan_impl(LoadAll<T>{in}, out, count, ws, s);
+}
+
+int scan_exclusive_masked(const int32_t* in, int32_t mask, int64_t* out, int64_t count, Carver& ws,
+                          hipStream_t s) {
+  return scan_impl(LoadMasked{in, mask}, out, count, ws, s);
 }
 
 template int scan_exclusive<int32_t>(const int32_t*, int64_t*, int64_t, Carver&, hipStream_t);

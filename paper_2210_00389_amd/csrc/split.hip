@@ -323,7 +323,7 @@ __global__ void copy_total_kernel(const int64_t* h_off, int64_t n, int64_t* out)
 SplitWs split_reserve(Carver& c, int64_t n, int64_t nnz) {
   SplitWs w;
   w.meta = c.take<VMeta>(n + 1);
-  w.scols = c.take<int32_t>(nnz + 1);
+  w.scols = c.take<int32_t>(nnz + kColPad);
   w.res = c.take<uint32_t>(1);
   w.nseg = c.take<int32_t>(n + 1);
   w.seg_off = c.take<int64_t>(n + 2);

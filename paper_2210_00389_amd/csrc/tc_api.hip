@@ -46,7 +46,7 @@ struct CountPlan {
 CountPlan plan_count(void* base, int64_t n, int64_t nnz) {
   CountPlan p;
   Carver c(base);
-  p.stats = c.take<int64_t>(16);
+  p.stats = c.take<int64_t>(24);
   p.L = c.take<int32_t>(n + 1);
   p.comp0 = c.take<uint32_t>((n + 31) / 32 + 1);
   p.region = c.take<char>(0);
@@ -72,6 +72,7 @@ __global__ void pv_back_kernel(const int64_t* pv_new, const int32_t* order, int6
 struct BaselinePlan {
   int64_t* stats;
   VMeta* meta;
+  int32_t* cols;  // padded copy of the caller's columns
   CountWs count;
   size_t bytes;
 };
@@ -79,8 +80,9 @@ struct BaselinePlan {
 BaselinePlan plan_baseline(void* base, int64_t n, int64_t nnz) {
   BaselinePlan p;
   Carver c(base);
-  p.stats = c.take<int64_t>(16);
+  p.stats = c.take<int64_t>(24);
   p.meta = c.take<VMeta>(n + 1);
+  p.cols = c.take<int32_t>(nnz + kColPad);
   p.count = count_reserve(c, n, nnz);
   p.count.stats = p.stats;
   p.bytes = c.used();
@@ -253,9 +255,11 @@ int tc_count_edge_baseline(const tc_csr* g, uint32_t flags, int64_t* triangles, 
   BaselinePlan p = plan_baseline(ws, g->n, g->nnz);
   prof_stage("forward_lists");
   TC_TRY(forward_meta_run(g, p.meta, s));
+  if (g->nnz > 0)
+    TC_HIP(hipMemcpyAsync(p.cols, g->cols, g->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   CountArgs a;
   a.g = g;
-  a.cols = g->cols;
+  a.cols = p.cols;
   a.meta = p.meta;
   a.cover = false;
   a.per_vertex = false;
@@ -314,7 +318,7 @@ int tc_read_stats(const void* ws, tc_stats* out, tc_stream_t stream) {
   if (!ws || !out) return fail(TC_ERR_INVALID_ARG, "tc_read_stats: NULL");
   memset(out, 0, sizeof *out);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  TC_HIP(hipMemcpyAsync(out, ws, 16 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipMemcpyAsync(out, ws, sizeof(tc_stats), hipMemcpyDeviceToHost, s));
   TC_HIP(hipStreamSynchronize(s));
   return TC_OK;
 }

@@ -103,6 +103,10 @@ int hlist_run(const tc_csr* g, const VMeta* meta, const int32_t* cols, int64_t* 
               hipStream_t s);
 
 // ------------------------------------------------------------ count
+// Column buffers handed to count_run hold at least this many readable
+// entries past nnz (the streaming kernel loads whole chunks).
+constexpr int kColPad = 64;
+
 struct CountWs {
   int64_t* h_off;     // [n + 1]
   int32_t* h_u;       // [nnz / 2]
@@ -113,8 +117,19 @@ struct CountWs {
   int64_t* task_begin;
   int32_t* task_len;
   int32_t* task_owner;
-  int2* items;        // heavy work items (anchor, chunk)
-  unsigned long long* acc;  // [8]: T, stream elems, light tasks, items, descs, ...
+  // heavy anchors: descriptors resolved into stream records, then work
+  // items of about kElemChunk elements each
+  int32_t* ndesc;     // per vertex: descriptors of a heavy anchor, else 0
+  int64_t* so;        // exclusive scan of ndesc [n + 2]
+  int2* rchunks;      // resolution chunks (anchor, chunk) [rcap]
+  int64_t rcap;
+  int64_t* sbeg;      // stream records [scap]
+  int32_t* slen;      // length | flags
+  int32_t* soth;      // the vertex the streamed list belongs to
+  int64_t* epre;      // element prefix of the streams [scap + 1]
+  int64_t scap;
+  int4* items;        // (anchor, first stream lo/hi, stream count)
+  unsigned long long* acc;
   int64_t* stats;     // tc_stats mirror
   char* scratch;
 };
@@ -122,7 +137,7 @@ CountWs count_reserve(Carver& c, int64_t n, int64_t nnz);
 
 struct CountArgs {
   const tc_csr* g;
-  const int32_t* cols;  // layout columns (cover: split; comparator: original)
+  const int32_t* cols;  // layout columns [nnz + kColPad] (cover: split; comparator: copy)
   const VMeta* meta;
   bool cover;           // cover edges (three classes) or the comparator
   bool per_vertex;

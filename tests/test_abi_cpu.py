@@ -55,8 +55,10 @@ def test_workspace_sizes(lib):
         assert lib.tc_workspace_bytes(op, 0, 0, 0) > 0
     assert lib.tc_workspace_bytes(99, 10, 10, 0) == 0
     assert lib.tc_workspace_bytes(_lib.OP_COUNT, -1, 10, 0) == 0
-    # R-MAT scale 24 (16.7 M vertices, ~0.52 G entries) fits easily in 288 GB
-    assert lib.tc_workspace_bytes(_lib.OP_COUNT, 1 << 24, 520_000_000, 0) < 40 * 2**30
+    # R-MAT scale 24 (16.7 M vertices, ~0.52 G entries): the workspace (about
+    # 115 B per entry, most of it the stream records of the heavy anchors)
+    # stays well inside one GPU's 288 GB
+    assert lib.tc_workspace_bytes(_lib.OP_COUNT, 1 << 24, 520_000_000, 0) < 64 * 2**30
 
 
 def test_argument_errors_without_gpu(lib):
