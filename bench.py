@@ -51,23 +51,25 @@ def percentile(xs, p):
 
 def stage_bytes(name, st, n, nnz, cover):
     """Algorithmic HBM bytes of one stage (what the method must move)."""
-    h = st["h"]
     if name == "bfs":
-        # offsets + every row once + visited-bit gathers + levels + parity + queues
-        return 8 * (n + 1) + 4 * nnz + nnz / 8 + 4 * n + n / 8 + 8 * n
-    if name == "split":
-        # offsets + rows + 2-bit residue gathers + re-laid-out rows + class bounds
-        return 8 * (n + 1) + 4 * nnz + nnz / 4 + 4 * nnz + 16 * n
+        # offsets + every row once + visited-bit gathers + levels + queues
+        return 8 * (n + 1) + 4 * nnz + nnz / 8 + 4 * n + 8 * n
+    if name == "relabel":
+        # offsets + rows + new-id gathers + re-laid-out rows + offsets + vertex records
+        return 8 * (n + 1) + 4 * nnz + 4 * nnz + 4 * nnz + 8 * (n + 1) + 32 * n
     if name == "forward_lists":
-        return 8 * (n + 1) + 4 * n * max(1, math.log2(max(nnz / max(n, 1), 2))) + 16 * n
-    if name == "hlist":
-        return 16 * n + 8 * n + 4 * h + 8 * h
-    if name == "plan_light":
-        # cover-edge pairs + both endpoints' bounds/offsets + merged list elements
-        return 8 * h + 48 * h + 4 * st["light_elems"] * 2
+        return 8 * (n + 1) + 4 * nnz + 4 * nnz + 32 * n
+    if name == "plan":
+        # vertex records + descriptor counts + plan bytes + scan
+        return 32 * n + 4 * n + n + 12 * n
+    if name == "resolve":
+        # per descriptor: its column entry + the other endpoint's record;
+        # light merges; records written; items written, read and regrouped
+        d = st.get("descriptors", 0)
+        return 36 * d + 4 * st["light_elems"] + 16 * st["heavy_desc"] + 48 * st["heavy_items"]
     if name == "heavy":
-        # streamed list elements + probe-set inserts + descriptor ids/bounds/offsets
-        return 4 * st["heavy_elems"] + 4 * st["heavy_builds"] + 28 * st["heavy_desc"]
+        # streamed list elements + records + probe-set inserts + items
+        return 4 * st["heavy_elems"] + 16 * st["heavy_desc"] + 4 * st["heavy_builds"] + 16 * st["heavy_items"]
     return None
 
 

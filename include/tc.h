@@ -224,14 +224,14 @@ typedef struct tc_stats {
   int64_t stream_elems;    /* list elements streamed by the intersections */
   int64_t light_tasks;     /* tasks on the per-task merge path */
   int64_t heavy_items;     /* work items of the anchored (LDS hash) path */
-  int64_t heavy_desc;      /* descriptors processed on the anchored path */
+  int64_t heavy_desc;      /* stream records of heavy anchors (anchored path) */
   int64_t heavy_elems;     /* list elements streamed by the anchored kernel */
   int64_t heavy_builds;    /* probe-set elements inserted into on-chip tables */
   int64_t light_elems;     /* list elements streamed by the per-task merges */
   int64_t bin_elems[4];    /* anchored-kernel elements per table bin (2 KB,
                               16 KB, 128 KB, row search) */
   int64_t bin_items[4];    /* work items per table bin */
-  int64_t reserved[1];
+  int64_t descriptors;     /* per-vertex task descriptors examined */
 } tc_stats;
 
 int tc_read_stats(const void* ws, tc_stats* out, tc_stream_t stream);

@@ -66,7 +66,7 @@ class TcStats(ctypes.Structure):
                 ("heavy_desc", ctypes.c_int64), ("heavy_elems", ctypes.c_int64),
                 ("heavy_builds", ctypes.c_int64), ("light_elems", ctypes.c_int64),
                 ("bin_elems", ctypes.c_int64 * 4), ("bin_items", ctypes.c_int64 * 4),
-                ("reserved", ctypes.c_int64 * 1)]
+                ("descriptors", ctypes.c_int64)]
 
 
 _lib = None

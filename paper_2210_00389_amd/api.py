@@ -219,7 +219,7 @@ def read_stats(ws: Workspace | None = None, device=None, stream=None) -> dict:
     _check(lib.tc_read_stats(_ptr(w.buf), ctypes.byref(st), _stream(stream)), "tc_read_stats")
     out = {k: int(getattr(st, k)) for k in ("n", "nnz", "h", "num_levels", "stream_elems", "light_tasks",
                                              "heavy_items", "heavy_desc", "heavy_elems", "heavy_builds",
-                                             "light_elems")}
+                                             "light_elems", "descriptors")}
     out["bin_elems"] = [int(x) for x in st.bin_elems]
     out["bin_items"] = [int(x) for x in st.bin_items]
     return out

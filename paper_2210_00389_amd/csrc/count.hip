@@ -8,29 +8,34 @@
 //                          holds exactly the same-level neighbours above v)
 //   down  w on level l+1:  w in Down(u) ∩ Down(v)   (always counted)
 // The down class is summed from the apex side: for every edge x -> w with
-// w in Down(x), count the t in Up(w) with t > x and t in Hfwd(x); each
-// (u, v, w) with u < v is met once, at x = u, t = v.  This is the same set of
-// (edge, apex) pairs, enumerated per apex the way the paper's distributed
-// variant enumerates the apexes a processor owns; it streams the short
-// up-lists of the apexes instead of the long down-lists of hub pairs.
+// w in Down(x), count the t in Up(w) that lie in Hfwd(x); each (u, v, w)
+// with u < v is met once, at x = u, t = v.  This is the same set of (edge,
+// apex) pairs, enumerated per apex the way the paper's distributed variant
+// enumerates the apexes a processor owns; it streams the short up-lists of
+// the apexes instead of the long down-lists of hub pairs.
 //
-// Every intersection is a "task": stream one sorted list S, test each element
-// for membership in a probe list P of an anchor vertex.  Ownership rules pick
-// the cheaper side per task:
+// Every intersection is a task: stream one sorted list S and test each
+// element for membership in the probe set P(x) = Up(x) ∪ Hfwd(x) of an
+// anchor x.  Ownership rules pick the cheaper side per task:
 //   up     anchor = u if |Up(v)| <= |Up(u)| else v; stream Up(other)
 //   same   a = |Hfwd(u) ∩ (v,inf)|, b = |Hfwd(v)|; if b < a anchor u streams
 //          Hfwd(v), else anchor v streams Hfwd(u) ∩ (v,inf)
-//   down   anchor x streams Up(w) ∩ (x,inf)
-// Light anchors (short probe set, few down-neighbours) have their tasks
-// merged by the thread that discovers them.  For heavy anchors every task
-// descriptor is resolved into a stream record (begin, length, flags) by a
-// separate pass; the records of an anchor are cut into work items of about
-// kElemChunk elements, binned by the on-chip table the anchor's probe set
-// Up(x) ∪ Hfwd(x) needs (2 KB .. 128 KB of the 160 KB LDS; bitmap over the
-// id window or hash table).  A block builds the table once per anchor and
-// streams the item's records in chunks of 8 elements of one stream per lane;
-// probe sets beyond the largest table are searched in their sorted rows.
-// Per-lane counts are reduced wave -> block -> one 64-bit atomic.
+//   down   anchor x streams Up(w)
+// A streamed list lies on one level, so the members of P(x) it can meet are
+// in one segment: Up(x) for the up class, Hfwd(x) for the others.
+//
+// Every vertex x owns the descriptors [down | forward cover edges | backward
+// cover edges]: deg(x) - sfe (when Hfwd(x) is not empty), |Hfwd(x)|, and
+// its same-level neighbours below x.  One pass over all descriptors applies
+// the ownership rules from x's side.  Light anchors (short probe set, few
+// down-neighbours) merge their tasks at once.  Heavy anchors emit stream
+// records, compacted per block, and the block cuts its records into work
+// items of about kElemChunk elements of one anchor, tagged with the on-chip
+// table the anchor needs (2 KB .. 128 KB of the 160 KB LDS: a bitmap over the
+// probe set's id window, or a hash table) or row search beyond that.  The
+// streaming kernel builds the table once per item and hands each lane chunks
+// of 8 elements of one stream.  Per-lane counts are reduced wave -> block ->
+// one 64-bit atomic; the count runs without a host synchronisation.
 //
 // The comparator (plain direction-oriented edge iterator) runs through the
 // same kernels with up = 0, Hfwd = forward list N+(x), no down class.
@@ -42,15 +47,16 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kDnLight = 16;  // light anchors have at most this many down-neighbours
+constexpr int kLightMax = 32; // and a probe set of at most this many ids
 constexpr int kBins = 4;
 
 // Bins of heavy anchors by the LDS table they need: 2 KB, 32 KB, 128 KB, or
-// none (bin 3: search the sorted rows).  The probe set P(x) = Up(x) ∪ Hfwd(x)
-// lies in the id window [min P, max P] of R ids.  It is held as a bitmap of
-// R + 1 bits (bit R stays clear and absorbs every id outside the window)
-// when clearing that bitmap costs little next to the anchor's work (at most
-// four words per member, or per four streamed elements), else as a hash
-// table filling the bin's whole table (at most half full).
+// none (bin 3: search the sorted rows).  The probe set P(x) lies in the id
+// window [min P, max P] of R ids.  It is held as a bitmap of R + 1 bits (bit
+// R stays clear and absorbs every id outside the window) when clearing that
+// bitmap costs little next to the anchor's work (at most four words per
+// member plus 64, or 16 words per descriptor), else as a hash table filling
+// the bin's whole table (at most half full).
 constexpr int kBinWords0 = 512, kBinWords1 = 8192, kBinWords2 = 32768;
 
 __host__ __device__ constexpr int bin_words(int b) {
@@ -59,11 +65,11 @@ __host__ __device__ constexpr int bin_words(int b) {
 
 __device__ __forceinline__ int64_t bitmap_words(int64_t R) { return (R + 32) >> 5; }
 
-// Bin of an anchor with window R, probe-set size P and E streamed elements;
+// Bin of an anchor with window R, probe-set size P and D descriptors;
 // *bitmap tells the table kind.
-__device__ __forceinline__ int choose_bin(int64_t R, int P, int64_t E, bool* bitmap) {
+__device__ __forceinline__ int choose_bin(int64_t R, int P, int64_t D, bool* bitmap) {
   const int64_t need = bitmap_words(R);
-  if (need <= 4 * static_cast<int64_t>(P) + 64 || 4 * need <= E) {
+  if (need <= 4 * static_cast<int64_t>(P) + 64 || need <= 16 * D) {
     for (int b = 0; b < 3; ++b)
       if (need <= bin_words(b)) {
         *bitmap = true;
@@ -77,19 +83,23 @@ __device__ __forceinline__ int choose_bin(int64_t R, int P, int64_t E, bool* bit
 }
 
 enum Acc {
-  kAccT = 0, kAccElems = 1, kAccLight = 2, kAccBuild = 3, kAccDesc = 4, kAccItems = 5,
-  kAccHeavyElems = 6, kAccChunks = 7, kAccBinCount = 8, kAccBinOff = 13, kAccBinCur = 18, kAccBinNext = 23,
-  kAccBinElems = 28
+  kAccT = 0, kAccElems = 1, kAccLight = 2, kAccBuild = 3, kAccRecs = 4, kAccItems = 5, kAccHeavyElems = 6,
+  kAccH = 7, kAccBinCount = 8, kAccBinOff = 12, kAccBinCur = 16, kAccBinNext = 20, kAccBinElems = 24,
+  kAccLightRecs = 28
 };
-constexpr int kAccSlots = 33;
-constexpr int kResolveChunk = 1024;   // descriptors per resolution chunk
-constexpr int64_t kElemChunk = 65536;  // elements per work item (target)
-// stream record flags (in the length word)
-constexpr int32_t kFlagUp = 1 << 29;     // probe the anchor's Up list (row search)
-// work item flag (in the stream-count word): the anchor's table is a bitmap
-constexpr int32_t kItemBitmap = 1 << 30;
-constexpr int64_t kItemMaxStreams = 1 << 29;
+constexpr int kAccSlots = 29;
+constexpr int64_t kElemChunk = 65536;  // elements per work item (target; a power of two)
+constexpr int kElemChunkLog = 16;
+static_assert(kElemChunk == (int64_t(1) << kElemChunkLog), "kElemChunk must be 2^kElemChunkLog");
+// stream record flag (in the length word): probe the anchor's Up list
+constexpr int32_t kFlagUp = 1 << 29;
 constexpr int32_t kLenMask = kFlagUp - 1;
+// work item word: stream count | bin << 28 | kItemBitmap
+constexpr int32_t kItemCountMask = (1 << 28) - 1;
+constexpr int32_t kItemBitmap = 1 << 30;
+// per-vertex plan byte: kViHeavy | bitmap << 2 | bin
+constexpr uint8_t kViHeavy = 0x80;
+constexpr uint8_t kViBitmap = 0x04;
 
 __device__ __forceinline__ void add_pv(int64_t* pv, int32_t a, int32_t b, int32_t c) {
   atomicAdd(reinterpret_cast<unsigned long long*>(&pv[a]), 1ull);
@@ -133,8 +143,8 @@ __device__ __forceinline__ int probe_size(const VMeta& m) { return m.up + (m.sfe
 
 // Heavy anchors get work items; every task of a light anchor is merged by
 // the planning kernels.  Must be the same predicate everywhere.
-__device__ __forceinline__ bool is_heavy(const VMeta& m, bool cover, int light_max) {
-  if (probe_size(m) > light_max) return true;
+__device__ __forceinline__ bool is_heavy(const VMeta& m, bool cover) {
+  if (probe_size(m) > kLightMax) return true;
   return cover && (m.sfe - m.hfb) > 0 && (m.deg - m.sfe) > kDnLight;
 }
 
@@ -143,128 +153,6 @@ __device__ __forceinline__ void block_acc(unsigned long long* acc, int slot, int
   if (threadIdx.x == 0 && s) atomicAdd(&acc[slot], static_cast<unsigned long long>(s));
 }
 
-// ------------------------------------------------------------ planning
-// One thread per cover edge e = (u, v), v the i-th entry of Hfwd(u).
-// kFill = false: light tasks are merged and counted; heavy "same" tasks whose
-// anchor is v are counted per anchor.  kFill = true: those tasks are written.
-template <bool kCover, bool kPV, bool kFill>
-__global__ __launch_bounds__(kThreads) void plan_kernel(
-    const int32_t* lc, const VMeta* meta, int64_t n, const int64_t* h_off, const int32_t* h_u,
-    const int32_t* h_v, int light_max, int32_t* ecnt, const int64_t* task_off, int32_t* ecur,
-    int64_t* task_begin, int32_t* task_len, int32_t* task_owner, unsigned long long* acc, int64_t* pv) {
-  __shared__ int64_t sh[kThreads / kWave + 1];
-  const int64_t H = h_off[n];
-  int64_t cnt = 0, light = 0, elems = 0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < H; e += stride) {
-    const int32_t u = h_u[e], v = h_v[e];
-    const VMeta mu = meta[u], mv = meta[v];
-    const int i = static_cast<int>(e - h_off[u]);
-    if (kCover && !kFill) {
-      const bool anchor_u = mv.up <= mu.up;
-      const VMeta& ma = anchor_u ? mu : mv;
-      const VMeta& mo = anchor_u ? mv : mu;
-      if (mo.up > 0 && !is_heavy(ma, kCover, light_max)) {
-        cnt += merge_count<kPV>(lc + mo.begin, mo.up, lc + ma.begin, ma.up, -1, pv, u, v);
-        ++light;
-        elems += mo.up;
-      }
-    }
-    const int a = (mu.sfe - mu.hfb) - i - 1;
-    const int b = mv.sfe - mv.hfb;
-    if (a > 0 && b > 0) {
-      const int32_t* Su = lc + mu.begin + mu.hfb + i + 1;  // Hfwd(u) above v
-      const int32_t* Sv = lc + mv.begin + mv.hfb;          // Hfwd(v)
-      if (b < a) {  // anchor u
-        if (!kFill && !is_heavy(mu, kCover, light_max)) {
-          cnt += merge_count<kPV>(Sv, b, Su, a, -1, pv, u, v);
-          ++light;
-          elems += b;
-        }
-      } else {  // anchor v
-        if (!is_heavy(mv, kCover, light_max)) {
-          if (!kFill) {
-            cnt += merge_count<kPV>(Su, a, Sv, b, -1, pv, u, v);
-            ++light;
-            elems += a;
-          }
-        } else if (!kFill) {
-          atomicAdd(&ecnt[v], 1);
-        } else {
-          const int64_t pos = task_off[v] + atomicAdd(&ecur[v], 1);
-          task_begin[pos] = mu.begin + mu.hfb + i + 1;
-          task_len[pos] = a;
-          task_owner[pos] = u;
-        }
-      }
-    }
-  }
-  if (!kFill) {
-    block_acc(acc, kAccT, cnt, sh);
-    block_acc(acc, kAccLight, light, sh);
-    block_acc(acc, kAccElems, elems, sh);
-  }
-}
-
-// Down class of light anchors (at most kDnLight down-neighbours): one
-// thread per pair (x, k-th down-neighbour w) counts |Up(w) ∩ Hfwd(x)| (every
-// element of Hfwd(x) lies above x, so no filter is needed), by a merge, or
-// by searching the short list in the long one when Up(w) is long.
-template <bool kPV>
-__global__ __launch_bounds__(kThreads) void light_down_kernel(const int32_t* lc, const VMeta* meta, int64_t n,
-                                                              int light_max, unsigned long long* acc,
-                                                              int64_t* pv) {
-  __shared__ int64_t sh[kThreads / kWave + 1];
-  int64_t cnt = 0, elems = 0, light = 0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t total = n * kDnLight;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total; idx += stride) {
-    const int64_t x = idx / kDnLight;
-    const int k = static_cast<int>(idx % kDnLight);
-    const VMeta m = meta[x];
-    const int hf = m.sfe - m.hfb, nd = m.deg - m.sfe;
-    if (hf == 0 || k >= nd || is_heavy(m, true, light_max)) continue;
-    const int32_t w = lc[m.begin + m.sfe + k];
-    const VMeta mw = meta[w];
-    const int32_t* S = lc + mw.begin;
-    const int32_t* P = lc + m.begin + m.hfb;
-    if (mw.up > 4 * hf) {
-      for (int i = 0; i < hf; ++i) {
-        const int32_t t = P[i];
-        if (gsearch(S, mw.up, t)) {
-          ++cnt;
-          if (kPV) add_pv(pv, static_cast<int32_t>(x), w, t);
-        }
-      }
-      elems += hf;
-    } else {
-      cnt += merge_count<kPV>(S, mw.up, P, hf, -1, pv, static_cast<int32_t>(x), w);
-      elems += mw.up;
-    }
-    ++light;
-  }
-  block_acc(acc, kAccT, cnt, sh);
-  block_acc(acc, kAccElems, elems, sh);
-  block_acc(acc, kAccLight, light, sh);
-}
-
-// ---------------------------------------------------------- heavy items
-// Descriptor index space of an anchor: [down | fwd-up | fwd-same | bwd-up | tasks].
-struct Desc {
-  int nB, nCu, nCs, nD, nE;
-  __device__ __forceinline__ int total() const { return nB + nCu + nCs + nD + nE; }
-};
-
-__device__ __forceinline__ Desc desc_of(const VMeta& m, bool cover, int nE) {
-  Desc d;
-  const int hf = m.sfe - m.hfb;
-  d.nB = (cover && hf > 0) ? m.deg - m.sfe : 0;
-  d.nCu = (cover && m.up > 0) ? hf : 0;
-  d.nCs = hf;
-  d.nD = (cover && m.up > 0) ? m.hfb - m.up : 0;
-  d.nE = nE;
-  return d;
-}
 
 // Id window [lo, lo + R) of the probe set (R = 0 when it is empty).
 __device__ __forceinline__ void probe_window(const int32_t* lc, const VMeta& m, int32_t& lo, int64_t& R) {
@@ -283,166 +171,350 @@ __device__ __forceinline__ void probe_window(const int32_t* lc, const VMeta& m, 
 }
 
 
-// Descriptor counts of heavy anchors and their resolution chunks.
-// kFill = false: ndesc per vertex and the chunk count; kFill = true: chunks.
-template <bool kFill>
-__global__ __launch_bounds__(kThreads) void desc_plan_kernel(const VMeta* meta, int64_t n, const int64_t* task_off,
-                                                             bool cover, int light_max, int32_t* ndesc,
-                                                             int2* rchunks, int64_t rcap, unsigned long long* acc) {
-  __shared__ int s_cnt;
-  __shared__ unsigned long long s_base;
-  for (int64_t x0 = blockIdx.x * (int64_t)blockDim.x; x0 < n; x0 += (int64_t)gridDim.x * blockDim.x) {
-    if (threadIdx.x == 0) s_cnt = 0;
-    __syncthreads();
-    const int64_t x = x0 + threadIdx.x;
-    int k = 0, mine = 0, total = 0;
-    if (x < n) {
-      const VMeta m = meta[x];
-      if (is_heavy(m, cover, light_max))
-        total = desc_of(m, cover, static_cast<int>(task_off[x + 1] - task_off[x])).total();
-      k = (total + kResolveChunk - 1) / kResolveChunk;
-      if (!kFill) ndesc[x] = total;
-      if (k) mine = atomicAdd(&s_cnt, k);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && s_cnt) {
-      if (!kFill) atomicAdd(&acc[kAccChunks], static_cast<unsigned long long>(s_cnt));
-      else s_base = atomicAdd(&acc[kAccDesc], static_cast<unsigned long long>(s_cnt));
-    }
-    __syncthreads();
-    if (kFill)
-      for (int j = 0; j < k; ++j)
-        if (static_cast<int64_t>(s_base + mine + j) < rcap) rchunks[s_base + mine + j] = make_int2(static_cast<int>(x), j);
-    __syncthreads();
-  }
-}
-
-// Resolves every descriptor of every heavy anchor into a stream record:
-// begin, length | flags, owner of the streamed list.  One block per chunk of
-// kResolveChunk descriptors; no LDS, so many blocks hide the two dependent
-// loads (descriptor id, vertex record) per descriptor.
+// ------------------------------------------------------------ planning
+// One thread per vertex: descriptor count, |Hfwd| (for |H|), and for heavy
+// anchors the table bin.
 template <bool kCover>
-__global__ __launch_bounds__(kThreads) void resolve_kernel(
-    const int32_t* lc, const VMeta* meta, const int64_t* task_off, const int64_t* task_begin,
-    const int32_t* task_len, const int32_t* task_owner, const int2* rchunks, int64_t rcap,
-    const unsigned long long* acc, const int64_t* so, int64_t scap, int64_t* sbeg, int32_t* slen, int32_t* soth) {
-  const int64_t nchunks = min(static_cast<int64_t>(acc[kAccChunks]), rcap);
-  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    const int2 ch = rchunks[c];
-    const int32_t x = ch.x;
-    const VMeta mx = meta[x];
-    const int hf = mx.sfe - mx.hfb;
-    const int64_t toff = task_off[x];
-    const Desc Dx = desc_of(mx, kCover, static_cast<int>(task_off[x + 1] - toff));
-    const int d_end = min(Dx.total(), (ch.y + 1) * kResolveChunk);
-    const int64_t base = so[x];
-    for (int d = ch.y * kResolveChunk + threadIdx.x; d < d_end; d += blockDim.x) {
-      int64_t beg = 0;
-      int32_t len = 0, oth = x;
-      int k = d;
-      if (k < Dx.nB) {  // down class: Up(w); its members in P(x) are in Hfwd(x), so above x
-        const int32_t w = lc[mx.begin + mx.sfe + k];
-        const VMeta mw = meta[w];
-        beg = mw.begin;
-        len = mw.up;
-        oth = w;
-      } else if ((k -= Dx.nB) < Dx.nCu) {  // forward cover edge, up class
-        const int32_t v = lc[mx.begin + mx.hfb + k];
-        const VMeta mv = meta[v];
-        oth = v;
-        if (mv.up > 0 && mv.up <= mx.up) {
-          beg = mv.begin;
-          len = mv.up | kFlagUp;
-        }
-      } else if ((k -= Dx.nCu) < Dx.nCs) {  // forward cover edge, same class
-        const int32_t v = lc[mx.begin + mx.hfb + k];
-        const VMeta mv = meta[v];
-        oth = v;
-        const int a = hf - k - 1, b = mv.sfe - mv.hfb;
-        if (a > 0 && b > 0 && b < a) {
-          beg = mv.begin + mv.hfb;
-          len = b;
-        }
-      } else if ((k -= Dx.nCs) < Dx.nD) {  // backward cover edge, up class
-        const int32_t u = lc[mx.begin + mx.up + k];
-        const VMeta mu = meta[u];
-        oth = u;
-        if (mu.up > 0 && mu.up < mx.up) {
-          beg = mu.begin;
-          len = mu.up | kFlagUp;
-        }
-      } else {  // emitted same-class task: Hfwd(u) above x
-        const int64_t q = toff + (k - Dx.nD);
-        beg = task_begin[q];
-        len = task_len[q];
-        oth = task_owner[q];
-      }
-      const int64_t pos = base + d;
-      if (pos < scap) {
-        sbeg[pos] = beg;
-        slen[pos] = len;
-        soth[pos] = oth;
-      }
+__global__ __launch_bounds__(kThreads) void plan_kernel(const int32_t* lc, const VMeta* meta, int64_t n,
+                                                        int32_t* ndesc, uint8_t* vinfo,
+                                                        unsigned long long* acc) {
+  __shared__ int64_t sh[kThreads / kWave + 1];
+  int64_t h = 0;
+  for (int64_t x0 = blockIdx.x * (int64_t)blockDim.x; x0 < n; x0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = x0 + threadIdx.x;
+    if (x >= n) continue;
+    const VMeta m = meta[x];
+    const int hf = m.sfe - m.hfb;
+    const int nB = (kCover && hf > 0) ? m.deg - m.sfe : 0;
+    const int D = nB + hf + (m.hfb - m.up);
+    h += hf;
+    uint8_t vi = 0;
+    if (D > 0 && is_heavy(m, kCover)) {
+      int32_t lo;
+      int64_t R;
+      probe_window(lc, m, lo, R);
+      bool bm = false;
+      const int b = choose_bin(R, probe_size(m), D, &bm);
+      vi = static_cast<uint8_t>(kViHeavy | (bm ? kViBitmap : 0) | b);
+    }
+    ndesc[x] = D;
+    vinfo[x] = vi;
+  }
+  block_acc(acc, kAccH, h, sh);
+}
+
+// ------------------------------------------------------------ resolution
+// One thread per descriptor, chunks of kResChunk descriptors per block.  A
+// descriptor yields at most two tasks with its vertex x as anchor (slot 0:
+// up or down class, slot 1: same class).  Tasks of heavy anchors become
+// stream records (from the front of the record arrays), tasks of light
+// anchors go to the light list (from the back), merged by light_kernel.
+constexpr int kResThreads = 256;
+constexpr int kResChunk = kResThreads;
+constexpr int kResRecs = 2 * kResChunk;
+constexpr int kResSpan = 2 * kResChunk;  // vertex offsets staged in LDS
+
+struct Task {
+  int64_t beg;  // stream begin in the columns
+  int32_t len;  // stream length (0: no task) | kFlagUp
+  int32_t oth;  // vertex whose list is streamed
+};
+
+// Tasks of descriptor k of vertex x (x is the anchor of every returned task).
+template <bool kCover>
+__device__ __forceinline__ void describe(const int32_t* lc, const VMeta* meta, int32_t x, const VMeta& mx, int k,
+                                         Task& ta, Task& tb) {
+  ta = Task{0, 0, 0};
+  tb = Task{0, 0, 0};
+  const int hf = mx.sfe - mx.hfb;
+  const int nB = (kCover && hf > 0) ? mx.deg - mx.sfe : 0;
+  if (k < nB) {  // down class: stream Up(w)
+    const int32_t w = lc[mx.begin + mx.sfe + k];
+    const VMeta mw = meta[w];
+    if (mw.up > 0) ta = Task{mw.begin, mw.up, w};
+  } else if ((k -= nB) < hf) {  // forward cover edge (x, v)
+    const int32_t v = lc[mx.begin + mx.hfb + k];
+    const VMeta mv = meta[v];
+    if (kCover && mv.up > 0 && mv.up <= mx.up) ta = Task{mv.begin, mv.up | kFlagUp, v};
+    const int a = hf - k - 1, b = mv.sfe - mv.hfb;
+    if (a > 0 && b > 0 && b < a) tb = Task{mv.begin + mv.hfb, b, v};
+  } else {  // backward cover edge (u, x), u < x
+    k -= hf;
+    const int32_t u = lc[mx.begin + mx.up + k];
+    const VMeta mu = meta[u];
+    if (kCover && mu.up > 0 && mu.up < mx.up) ta = Task{mu.begin, mu.up | kFlagUp, u};
+    const int hu = mu.sfe - mu.hfb;
+    if (hf > 0 && hu > 0) {
+      // a = |Hfwd(u) ∩ (x, inf)|; x itself is in Hfwd(u)
+      const int64_t e = mu.begin + mu.sfe;
+      const int64_t pos = lower_bound_dev(lc, mu.begin + mu.hfb, e, x);
+      const int a = static_cast<int>(e - pos) - 1;
+      if (a > 0 && hf >= a) tb = Task{pos + 1, a, u};
     }
   }
 }
 
-// Work items: the streams of anchor x are split into at most
-// ceil(E / kElemChunk) ranges of about equal element count E / nit (cut at
-// stream starts).  kFill = false counts items per bin; kFill = true writes
-// int4 {x, first stream (lo, hi), stream count | kItemBitmap}.
-template <bool kFill>
-__global__ __launch_bounds__(kThreads) void items_kernel(const int32_t* lc, const VMeta* meta, int64_t n,
-                                                         const int32_t* ndesc, const int64_t* so, const int64_t* epre,
-                                                         int64_t scap, int4* items, unsigned long long* acc) {
-  __shared__ int s_cnt[kBins];
-  __shared__ unsigned long long s_base[kBins];
-  for (int64_t x0 = blockIdx.x * (int64_t)blockDim.x; x0 < n; x0 += (int64_t)gridDim.x * blockDim.x) {
-    if (threadIdx.x < kBins) s_cnt[threadIdx.x] = 0;
+// First vertex of every chunk of kResChunk descriptors: chunk c starts at
+// descriptor c * kResChunk, owned by the vertex x with so[x] <= it < so[x+1].
+// cx0[nchunks] = n - 1 closes the last chunk.
+__global__ void chunk_start_kernel(const int64_t* so, int64_t n, int32_t* cx0) {
+  const int64_t total = so[n];
+  const int64_t nch = (total + kResChunk - 1) / kResChunk;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c0 = (so[x] + kResChunk - 1) / kResChunk, c1 = (so[x + 1] + kResChunk - 1) / kResChunk;
+    for (int64_t c = c0; c < c1; ++c) cx0[c] = static_cast<int32_t>(x);
+    if (x == n - 1) cx0[nch] = static_cast<int32_t>(n - 1);
+  }
+}
+
+// Chunk c owns the record region [2 d0, 2 d1) of its descriptors [d0, d1):
+// records of heavy anchors from the front, tasks of light anchors from the
+// back, its work items at the same offsets of items_raw; ccnt[c] = (heavy
+// records, light tasks, items).  No counter is shared between blocks.
+template <bool kCover>
+__global__ __launch_bounds__(kResThreads) void resolve_kernel(
+    const int32_t* lc, const VMeta* meta, const uint8_t* vinfo, const int64_t* so, const int32_t* cx0, int64_t n,
+    int64_t* sbeg, int32_t* slen, int32_t* soth, int32_t* sx, int4* items_raw, int4* ccnt) {
+  __shared__ int64_t sh[kResThreads / kWave + 1];
+  __shared__ int32_t shi[kResThreads / kWave + 1];
+  __shared__ int64_t s_so[kResSpan];
+  __shared__ int32_t s_x[kResRecs];
+  __shared__ int64_t s_pre[kResRecs];
+  __shared__ int32_t s_first[kResRecs + 1];
+  const int tid = threadIdx.x;
+  const int64_t total = so[n];
+  const int64_t nch = (total + kResChunk - 1) / kResChunk;
+  for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+    const int64_t d0 = c * kResChunk;
+    const int64_t d1 = min(d0 + kResChunk, total);
+    const int64_t xa = cx0[c], xz = cx0[c + 1];  // the vertex of d1 - 1 is in [xa, xz]
+    const int64_t span = xz - xa + 2;            // so[xa .. xz + 1]
+    const bool staged = span <= kResSpan;
+    if (staged)
+      for (int i = tid; i < span; i += kResThreads) s_so[i] = so[xa + i];
     __syncthreads();
-    const int64_t x = x0 + threadIdx.x;
-    int k = 0, b = 0, mine = 0;
-    bool bm = false;
-    int64_t s0 = 0, s1 = 0, e0 = 0, E = 0;
-    if (x < n && ndesc[x] > 0) {
-      s0 = min(so[x], scap);
-      s1 = min(so[x + 1], scap);
-      e0 = epre[s0];
-      E = epre[s1] - e0;
-      if (E > 0) {
-        const VMeta m = meta[x];
-        int32_t lo;
-        int64_t R;
-        probe_window(lc, m, lo, R);
-        b = choose_bin(R, probe_size(m), E, &bm);
-        int64_t want = (E + kElemChunk - 1) / kElemChunk;
-        want = max(want, (s1 - s0 + kItemMaxStreams - 1) / kItemMaxStreams);
-        k = static_cast<int>(min(want, s1 - s0));
-        mine = atomicAdd(&s_cnt[b], k);
+    Task ta{0, 0, 0}, tb{0, 0, 0};
+    int32_t xi = 0;
+    bool heavy = false;
+    const int64_t d = d0 + tid;
+    if (d < d1) {
+      int64_t x, xb;
+      if (staged) {
+        int lo = 0, hi = static_cast<int>(span);  // first index with s_so > d
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (s_so[mid] <= d) lo = mid + 1;
+          else hi = mid;
+        }
+        x = xa + lo - 1;
+        xb = s_so[lo - 1];
+      } else {
+        x = upper_bound_dev(so, xa, xz + 2, d) - 1;
+        xb = so[x];
+      }
+      xi = static_cast<int32_t>(x);
+      const VMeta mx = meta[x];
+      heavy = (vinfo[x] & kViHeavy) != 0;
+      describe<kCover>(lc, meta, xi, mx, static_cast<int>(d - xb), ta, tb);
+    }
+    const int nl = heavy ? 0 : (ta.len != 0) + (tb.len != 0);
+    const int nh = heavy ? (ta.len != 0) + (tb.len != 0) : 0;
+    int32_t ltot, htot;
+    const int lslot = block_excl_scan(nl, shi, &ltot);
+    const int hslot0 = block_excl_scan(nh, shi, &htot);
+    const int64_t he = heavy ? static_cast<int64_t>(ta.len & kLenMask) + (tb.len & kLenMask) : 0;
+    int64_t etot;
+    int64_t epre = block_excl_scan(he, sh, &etot);
+    const int64_t rbase = 2 * d0, rend = 2 * d1;
+    // ---- light tasks to the back of the region
+    if (nl) {
+      int64_t pos = rend - 1 - lslot;
+      if (ta.len) {
+        sbeg[pos] = ta.beg;
+        slen[pos] = ta.len;
+        soth[pos] = ta.oth;
+        sx[pos] = xi;
+        --pos;
+      }
+      if (tb.len) {
+        sbeg[pos] = tb.beg;
+        slen[pos] = tb.len;
+        soth[pos] = tb.oth;
+        sx[pos] = xi;
+      }
+    }
+    // ---- heavy records to the front, in descriptor order
+    if (nh) {
+      int sl = hslot0;
+      if (ta.len) {
+        sbeg[rbase + sl] = ta.beg;
+        slen[rbase + sl] = ta.len;
+        soth[rbase + sl] = ta.oth;
+        s_x[sl] = xi;
+        s_pre[sl] = epre;
+        epre += ta.len & kLenMask;
+        ++sl;
+      }
+      if (tb.len) {
+        sbeg[rbase + sl] = tb.beg;
+        slen[rbase + sl] = tb.len;
+        soth[rbase + sl] = tb.oth;
+        s_x[sl] = xi;
+        s_pre[sl] = epre;
       }
     }
     __syncthreads();
-    if (threadIdx.x < kBins && s_cnt[threadIdx.x]) {
-      const unsigned long long c = static_cast<unsigned long long>(s_cnt[threadIdx.x]);
-      if (!kFill) atomicAdd(&acc[kAccBinCount + threadIdx.x], c);
-      else s_base[threadIdx.x] = acc[kAccBinOff + threadIdx.x] + atomicAdd(&acc[kAccBinCur + threadIdx.x], c);
+    // ---- cut into work items: a new item starts where the anchor changes
+    // or the record's element offset enters the next kElemChunk
+    int ns = 0;
+    for (int q = hslot0; q < hslot0 + nh; ++q)
+      ns += (q == 0 || s_x[q] != s_x[q - 1] || (s_pre[q] >> kElemChunkLog) != (s_pre[q - 1] >> kElemChunkLog));
+    int32_t nitems;
+    int it = block_excl_scan(ns, shi, &nitems);
+    for (int q = hslot0; q < hslot0 + nh; ++q)
+      if (q == 0 || s_x[q] != s_x[q - 1] || (s_pre[q] >> kElemChunkLog) != (s_pre[q - 1] >> kElemChunkLog))
+        s_first[it++] = q;
+    if (tid == 0) {
+      s_first[nitems] = htot;
+      ccnt[c] = make_int4(htot, ltot, nitems, 0);
     }
     __syncthreads();
-    if (kFill && k) {
-      const unsigned long long base = s_base[b] + mine;
-      int64_t prev = s0;
-      for (int j = 0; j < k; ++j) {
-        // first stream starting at or after e0 + (j+1) E / k
-        const int64_t cut = e0 + (E * (j + 1)) / k;
-        const int64_t nxt = j + 1 == k ? s1 : lower_bound_dev(epre, prev, s1, cut);
-        items[base + j] = make_int4(static_cast<int>(x), static_cast<int>(prev & 0xFFFFFFFF),
-                                    static_cast<int>(prev >> 32),
-                                    static_cast<int>(nxt - prev) | (bm ? kItemBitmap : 0));
-        prev = nxt;
+    for (int i = tid; i < nitems; i += kResThreads) {
+      const int32_t x = s_x[s_first[i]];
+      const uint8_t vi = vinfo[x];
+      const int64_t r0 = rbase + s_first[i];
+      const int cntr = s_first[i + 1] - s_first[i];
+      const int32_t w = cntr | ((vi & 3) << 28) | ((vi & kViBitmap) ? kItemBitmap : 0);
+      items_raw[rbase + i] = make_int4(x, static_cast<int>(r0 & 0xFFFFFFFF), static_cast<int>(r0 >> 32), w);
+    }
+    __syncthreads();
+  }
+}
+
+// Tasks of light anchors, read from the back of every chunk's region; one
+// thread per task, found from the scan lpre of the per-chunk task counts.
+// The probe segment (at most kLightMax ids) and a stream of at most
+// kLightMax ids are loaded into registers with independent loads and
+// compared pairwise; a longer stream (down class) is searched for every
+// probe id, all searches advancing together.
+
+template <bool kPV>
+__global__ __launch_bounds__(kThreads) void light_kernel(const int32_t* lc, const VMeta* meta, const int64_t* so,
+                                                         int64_t n, const int64_t* lpre, int64_t nchunk_cap,
+                                                         const int64_t* sbeg, const int32_t* slen,
+                                                         const int32_t* soth, const int32_t* sx,
+                                                         unsigned long long* acc, int64_t* pv) {
+  __shared__ int64_t sh[kThreads / kWave + 1];
+  const int64_t total = so[n];
+  const int64_t nl = lpre[nchunk_cap];
+  int64_t cnt = 0, elems = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nl; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = upper_bound_dev(lpre, 0, nchunk_cap + 1, i) - 1;
+    const int64_t pos = 2 * min((c + 1) * kResChunk, total) - 1 - (i - lpre[c]);
+    const int32_t x = sx[pos];
+    const int32_t lf = slen[pos];
+    const int32_t oth = kPV ? soth[pos] : 0;
+    const VMeta mx = meta[x];
+    const int len = lf & kLenMask;
+    const bool up = (lf & kFlagUp) != 0;
+    const int32_t* P = lc + mx.begin + (up ? 0 : mx.hfb);
+    const int np = up ? mx.up : mx.sfe - mx.hfb;
+    const int32_t* S = lc + sbeg[pos];
+    int32_t pr[kLightMax];
+#pragma unroll
+    for (int q = 0; q < kLightMax; ++q) pr[q] = q < np ? P[q] : -1;
+    if (len <= kLightMax) {
+      int32_t sv[kLightMax];
+#pragma unroll
+      for (int q = 0; q < kLightMax; ++q) sv[q] = q < len ? S[q] : -2;
+#pragma unroll
+      for (int q = 0; q < kLightMax; ++q) {
+        int m = 0;
+#pragma unroll
+        for (int j = 0; j < kLightMax; ++j) m |= sv[q] == pr[j];
+        cnt += m;
+        if (kPV && m) add_pv(pv, x, oth, sv[q]);
+      }
+      elems += len;
+    } else {
+      // lower bound of every probe id in S, all at once
+      int lo[kLightMax];
+#pragma unroll
+      for (int q = 0; q < kLightMax; ++q) lo[q] = 0;
+      for (int step = 1 << (31 - __clz(len)); step > 0; step >>= 1) {
+#pragma unroll
+        for (int q = 0; q < kLightMax; ++q) {
+          // binary lifting over powers of two: lo ends as |{s in S : s < p}|
+          const int probe_at = lo[q] + step - 1;
+          const int32_t v = probe_at < len ? S[probe_at] : 0x7FFFFFFF;
+          if (v < pr[q]) lo[q] += step;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kLightMax; ++q) {
+        const bool m = q < np && lo[q] < len && S[lo[q]] == pr[q];
+        cnt += m;
+        if (kPV && m) add_pv(pv, x, oth, pr[q]);
+      }
+      elems += np;
+    }
+  }
+  block_acc(acc, kAccT, cnt, sh);
+  block_acc(acc, kAccElems, elems, sh);
+}
+
+// Items grouped by bin, in chunk order within each block of chunks (so the
+// consecutive items of one anchor stay adjacent).  One thread per chunk;
+// kFill = false counts per bin, kFill = true scatters.
+template <bool kFill>
+__global__ __launch_bounds__(kThreads) void bin_split_kernel(const int64_t* so, int64_t n, const int4* ccnt,
+                                                             const int4* items_raw, int4* items,
+                                                             unsigned long long* acc) {
+  __shared__ unsigned long long s_base[kBins];
+  __shared__ int64_t sh[kThreads / kWave + 1];
+  const int64_t total = so[n];
+  const int64_t nch = (total + kResChunk - 1) / kResChunk;
+  int64_t recs = 0;
+  for (int64_t c0 = blockIdx.x * (int64_t)blockDim.x; c0 < nch; c0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = c0 + threadIdx.x;
+    int ni = 0;
+    int k[kBins] = {0, 0, 0, 0};
+    if (c < nch) {
+      ni = ccnt[c].z;
+      if (!kFill) recs += ccnt[c].x;
+      for (int i = 0; i < ni; ++i) k[(items_raw[2 * c * kResChunk + i].w >> 28) & 3] += 1;
+    }
+    // per-bin exclusive offsets within the block, two bins per 64-bit word
+    // (at most 2^17 items per bin and block)
+    int64_t t01, t23;
+    const int64_t p01 = block_excl_scan(static_cast<int64_t>(k[0]) | (static_cast<int64_t>(k[1]) << 32), sh, &t01);
+    const int64_t p23 = block_excl_scan(static_cast<int64_t>(k[2]) | (static_cast<int64_t>(k[3]) << 32), sh, &t23);
+    if (threadIdx.x < kBins) {
+      const int64_t t = threadIdx.x < 2 ? t01 : t23;
+      const unsigned long long kb = static_cast<unsigned long long>((t >> (32 * (threadIdx.x & 1))) & 0xFFFFFFFF);
+      if (kb) {
+        if (!kFill) atomicAdd(&acc[kAccBinCount + threadIdx.x], kb);
+        else s_base[threadIdx.x] = acc[kAccBinOff + threadIdx.x] + atomicAdd(&acc[kAccBinCur + threadIdx.x], kb);
+      }
+    }
+    __syncthreads();
+    if (kFill && ni) {
+      int64_t pos[kBins] = {static_cast<int64_t>(s_base[0]) + (p01 & 0xFFFFFFFF), static_cast<int64_t>(s_base[1]) + (p01 >> 32),
+                            static_cast<int64_t>(s_base[2]) + (p23 & 0xFFFFFFFF), static_cast<int64_t>(s_base[3]) + (p23 >> 32)};
+      for (int i = 0; i < ni; ++i) {
+        const int4 item = items_raw[2 * c * kResChunk + i];
+        const int b = (item.w >> 28) & 3;
+        int64_t q;
+        if (b == 0) q = pos[0]++;
+        else if (b == 1) q = pos[1]++;
+        else if (b == 2) q = pos[2]++;
+        else q = pos[3]++;
+        items[q] = item;
       }
     }
     __syncthreads();
   }
+  if (!kFill) block_acc(acc, kAccRecs, recs, sh);
 }
 
 __global__ void bin_offsets_kernel(unsigned long long* acc) {
@@ -454,6 +526,7 @@ __global__ void bin_offsets_kernel(unsigned long long* acc) {
   acc[kAccItems] = run;
 }
 
+// ------------------------------------------------------------ streaming
 __device__ __forceinline__ uint32_t hslot(int32_t key, int shift) {
   return (static_cast<uint32_t>(key) * 0x9E3779B1u) >> shift;
 }
@@ -494,6 +567,7 @@ __device__ __forceinline__ uint32_t probe(const ProbeSet& ps, int32_t t, bool up
 // unconditionally and masked.
 constexpr int kChunk = 8;
 constexpr int kWinIters = 8;  // chunk rounds of the block per window
+constexpr int kClaim = 4;     // work items a block claims at once
 static_assert(kChunk <= kColPad, "chunk tail must stay inside the padded columns");
 
 template <int MODE, bool kPV>
@@ -606,8 +680,8 @@ __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_
 // says whether the anchor's table is a bitmap or a hash table.  Stream records are
 // loaded D at a time (R per thread), the non-empty ones are compacted into
 // LDS with their first chunk, and run_chunks streams them.
-template <int WORDS, int THREADS, int D, bool kPV>
-__global__ __launch_bounds__(THREADS) void heavy_kernel(const int32_t* lc, const VMeta* meta, int bin,
+template <int WORDS, int THREADS, int D, int WPE, bool kPV>
+__global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, const VMeta* meta, int bin,
                                                         const int4* items, const int64_t* sbeg,
                                                         const int32_t* slen, const int32_t* soth,
                                                         unsigned long long* acc, int64_t* pv) {
@@ -630,16 +704,21 @@ __global__ __launch_bounds__(THREADS) void heavy_kernel(const int32_t* lc, const
   const int tid = threadIdx.x;
   int64_t cnt = 0, elems = 0, builds = 0;
   int32_t cur_x = -1;
-  for (;;) {
-    if (tid == 0) s_item = atomicAdd(&acc[kAccBinNext + bin], 1ull);
-    __syncthreads();
-    const unsigned long long it = s_item;
-    __syncthreads();
-    if (it >= count) break;
+  // blocks claim kClaim consecutive items at a time (consecutive items of
+  // one anchor share the table); the next claim is fetched while the
+  // current one is processed
+  if (tid == 0) s_item = atomicAdd(&acc[kAccBinNext + bin], static_cast<unsigned long long>(kClaim));
+  __syncthreads();
+  unsigned long long claim = s_item;
+  while (claim < count) {
+    unsigned long long next = 0;
+    if (tid == 0) next = atomicAdd(&acc[kAccBinNext + bin], static_cast<unsigned long long>(kClaim));
+    const unsigned long long claim_end = min(claim + kClaim, count);
+    for (unsigned long long it = claim; it < claim_end; ++it) {
     const int4 item = items[first + it];
     const int32_t x = item.x;
     const int64_t sa = static_cast<int64_t>(static_cast<uint32_t>(item.y)) | (static_cast<int64_t>(item.z) << 32);
-    const int64_t sb = sa + (item.w & (kItemBitmap - 1));
+    const int64_t sb = sa + (item.w & kItemCountMask);
     const VMeta mx = meta[x];
     const int P = mx.up + (mx.sfe - mx.hfb);
     ProbeSet ps;
@@ -735,6 +814,11 @@ __global__ __launch_bounds__(THREADS) void heavy_kernel(const int32_t* lc, const
         cnt += run_chunks<kHash, THREADS, kPV>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, pv);
       }
     }
+    }
+    __syncthreads();
+    if (tid == 0) s_item = next;
+    __syncthreads();
+    claim = s_item;
   }
   block_acc(acc, kAccT, cnt, sh);
   block_acc(acc, kAccHeavyElems, elems, sh);
@@ -742,15 +826,16 @@ __global__ __launch_bounds__(THREADS) void heavy_kernel(const int32_t* lc, const
   block_acc(acc, kAccBuild, builds, sh);
 }
 
-__global__ void finish_kernel(const unsigned long long* acc, const int64_t* h_off, int64_t n, const int64_t* so,
-                              int64_t* triangles, int64_t* h_count, int64_t* stats) {
+
+__global__ void finish_kernel(const unsigned long long* acc, const int64_t* so, int64_t n, int64_t* triangles,
+                              int64_t* h_count, int64_t* stats) {
   *triangles = static_cast<int64_t>(acc[kAccT]);
-  if (h_count) *h_count = h_off[n];
-  stats[2] = h_off[n];
+  if (h_count) *h_count = static_cast<int64_t>(acc[kAccH]);
+  stats[2] = static_cast<int64_t>(acc[kAccH]);
   stats[4] = static_cast<int64_t>(acc[kAccElems] + acc[kAccHeavyElems]);
-  stats[5] = static_cast<int64_t>(acc[kAccLight]);
+  stats[5] = static_cast<int64_t>(acc[kAccLightRecs]);
   stats[6] = static_cast<int64_t>(acc[kAccItems]);
-  stats[7] = so[n];
+  stats[7] = static_cast<int64_t>(acc[kAccRecs]);
   stats[8] = static_cast<int64_t>(acc[kAccHeavyElems]);
   stats[9] = static_cast<int64_t>(acc[kAccBuild]);
   stats[10] = static_cast<int64_t>(acc[kAccElems]);
@@ -758,6 +843,7 @@ __global__ void finish_kernel(const unsigned long long* acc, const int64_t* h_of
     stats[11 + b] = static_cast<int64_t>(acc[kAccBinElems + b]);
     stats[11 + kBins + b] = static_cast<int64_t>(acc[kAccBinCount + b]);
   }
+  stats[19] = n > 0 ? so[n] : 0;
 }
 
 __global__ void forward_meta_kernel(const int64_t* off, const int32_t* cols, int64_t n, VMeta* meta) {
@@ -770,9 +856,12 @@ __global__ void forward_meta_kernel(const int64_t* off, const int32_t* cols, int
   }
 }
 
-template <int WORDS, int THREADS, int D, bool kPV>
+
+// WPE: waves per SIMD the kernel is compiled for (HIP's second launch
+// bound), matched to the blocks per CU that the bin's LDS allows.
+template <int WORDS, int THREADS, int D, int WPE, bool kPV>
 int launch_heavy(const CountArgs& a, CountWs& w, int bin, int blocks_per_cu, hipStream_t s) {
-  heavy_kernel<WORDS, THREADS, D, kPV><<<static_cast<unsigned>(num_cus() * blocks_per_cu), THREADS, 0, s>>>(
+  heavy_kernel<WORDS, THREADS, D, WPE, kPV><<<static_cast<unsigned>(num_cus() * blocks_per_cu), THREADS, 0, s>>>(
       a.cols, a.meta, bin, w.items, w.sbeg, w.slen, w.soth, w.acc, a.per_vertex_out);
   TC_HIP(hipGetLastError());
   return TC_OK;
@@ -780,67 +869,42 @@ int launch_heavy(const CountArgs& a, CountWs& w, int bin, int blocks_per_cu, hip
 
 template <bool kCover, bool kPV>
 int launch_all(const CountArgs& a, CountWs& w, hipStream_t s) {
-  const tc_csr* g = a.g;
-  const int64_t n = g->n;
-  const unsigned gedge = static_cast<unsigned>(num_cus() * 16);
+  const int64_t n = a.g->n;
   const unsigned gv = grid_for(n, kThreads, 16384);
-  plan_kernel<kCover, kPV, false><<<gedge, kThreads, 0, s>>>(
-      a.cols, a.meta, n, w.h_off, w.h_u, w.h_v, a.light_max, w.ecnt, w.task_off, w.ecur, w.task_begin,
-      w.task_len, w.task_owner, w.acc, a.per_vertex_out);
+  const unsigned gp = static_cast<unsigned>(num_cus() * 16);
+  plan_kernel<kCover><<<gv, kThreads, 0, s>>>(a.cols, a.meta, n, w.ndesc, w.vinfo, w.acc);
   TC_HIP(hipGetLastError());
-  prof_stage("light_down");
-  if (kCover) {
-    light_down_kernel<kPV><<<grid_for(n * kDnLight, kThreads, 32768), kThreads, 0, s>>>(
-        a.cols, a.meta, n, a.light_max, w.acc, a.per_vertex_out);
-    TC_HIP(hipGetLastError());
+  {
+    Carver sc(w.scratch);
+    TC_TRY(scan_exclusive<int32_t>(w.ndesc, w.so, n, sc, s));
   }
-  prof_stage("plan_tasks");
-  Carver sc(w.scratch);
-  TC_TRY(scan_exclusive<int32_t>(w.ecnt, w.task_off, n, sc, s));
-  plan_kernel<kCover, kPV, true><<<gedge, kThreads, 0, s>>>(
-      a.cols, a.meta, n, w.h_off, w.h_u, w.h_v, a.light_max, w.ecnt, w.task_off, w.ecur, w.task_begin,
-      w.task_len, w.task_owner, w.acc, a.per_vertex_out);
+  TC_TRY(fill_i32(reinterpret_cast<int32_t*>(w.ccnt), 0, 4 * w.nchunk_cap, s));
+  chunk_start_kernel<<<gv, kThreads, 0, s>>>(w.so, n, w.cx0);
+  TC_HIP(hipGetLastError());
   prof_stage("resolve");
-  TC_TRY(fill_i64(reinterpret_cast<int64_t*>(w.acc) + kAccChunks, 0, 1, s));
-  desc_plan_kernel<false><<<gv, kThreads, 0, s>>>(a.meta, n, w.task_off, kCover, a.light_max, w.ndesc, w.rchunks,
-                                                  w.rcap, w.acc);
-  desc_plan_kernel<true><<<gv, kThreads, 0, s>>>(a.meta, n, w.task_off, kCover, a.light_max, w.ndesc, w.rchunks,
-                                                 w.rcap, w.acc);
-  {
-    Carver sc2(w.scratch);
-    TC_TRY(scan_exclusive<int32_t>(w.ndesc, w.so, n, sc2, s));
-  }
-  resolve_kernel<kCover><<<static_cast<unsigned>(num_cus() * 16), kThreads, 0, s>>>(
-      a.cols, a.meta, w.task_off, w.task_begin, w.task_len, w.task_owner, w.rchunks, w.rcap, w.acc, w.so, w.scap,
-      w.sbeg, w.slen, w.soth);
+  resolve_kernel<kCover><<<gp, kResThreads, 0, s>>>(a.cols, a.meta, w.vinfo, w.so, w.cx0, n, w.sbeg, w.slen, w.soth,
+                                                    w.sx, w.items_raw, w.ccnt);
   TC_HIP(hipGetLastError());
-  // element prefix over the streams actually written
-  int64_t nstreams = 0;
-  TC_HIP(hipMemcpyAsync(&nstreams, w.so + n, sizeof nstreams, hipMemcpyDeviceToHost, s));
-  TC_HIP(hipStreamSynchronize(s));
-  // a symmetric simple graph has at most 2 nnz descriptors (deg + |Hfwd| +
-  // emitted tasks per anchor); more means an unvalidated asymmetric input
-  if (nstreams > w.scap)
-    return fail(TC_ERR_NOT_SYMMETRIC, "tc_count: %lld intersection descriptors exceed the bound 2 nnz of a "
-                "symmetric graph (validate the input with TC_VALIDATE)", (long long)nstreams);
-  const int64_t sc_n = nstreams;
   {
-    Carver sc3(w.scratch);
-    TC_TRY(scan_exclusive_masked(w.slen, kLenMask, w.epre, sc_n, sc3, s));
+    Carver sc(w.scratch);
+    TC_TRY(scan_exclusive_strided(reinterpret_cast<const int32_t*>(w.ccnt) + 1, 4, w.lpre, w.nchunk_cap, sc, s));
   }
-  items_kernel<false><<<gv, kThreads, 0, s>>>(a.cols, a.meta, n, w.ndesc, w.so, w.epre, sc_n, w.items, w.acc);
+  light_kernel<kPV><<<gp, kThreads, 0, s>>>(a.cols, a.meta, w.so, n, w.lpre, w.nchunk_cap, w.sbeg, w.slen, w.soth,
+                                            w.sx, w.acc, a.per_vertex_out);
+  TC_HIP(hipGetLastError());
+  bin_split_kernel<false><<<gp, kThreads, 0, s>>>(w.so, n, w.ccnt, w.items_raw, w.items, w.acc);
   bin_offsets_kernel<<<1, 1, 0, s>>>(w.acc);
-  items_kernel<true><<<gv, kThreads, 0, s>>>(a.cols, a.meta, n, w.ndesc, w.so, w.epre, sc_n, w.items, w.acc);
+  bin_split_kernel<true><<<gp, kThreads, 0, s>>>(w.so, n, w.ccnt, w.items_raw, w.items, w.acc);
   TC_HIP(hipGetLastError());
   prof_stage("heavy");
   // the bins are independent: run them side by side
   Fork* f = fork_for_device();
   if (!f) return TC_ERR_HIP;
   TC_TRY(fork_begin(f, s));
-  TC_TRY((launch_heavy<kBinWords2, 1024, 1024, kPV>(a, w, 2, 1, s)));
-  TC_TRY((launch_heavy<kBinWords1, 512, 1024, kPV>(a, w, 1, 3, f->aux[0])));
-  TC_TRY((launch_heavy<kBinWords0, 64, 256, kPV>(a, w, 0, 24, f->aux[1])));
-  TC_TRY((launch_heavy<0, 512, 1024, kPV>(a, w, 3, 4, f->aux[2])));
+  TC_TRY((launch_heavy<kBinWords2, 1024, 1024, 4, kPV>(a, w, 2, 1, s)));
+  TC_TRY((launch_heavy<kBinWords1, 512, 1024, 6, kPV>(a, w, 1, 3, f->aux[0])));
+  TC_TRY((launch_heavy<kBinWords0, 64, 256, 6, kPV>(a, w, 0, 24, f->aux[1])));
+  TC_TRY((launch_heavy<0, 512, 1024, 4, kPV>(a, w, 3, 4, f->aux[2])));
   TC_TRY(fork_end(f, s));
   prof_stage("finish");
   return TC_OK;
@@ -850,32 +914,27 @@ int launch_all(const CountArgs& a, CountWs& w, hipStream_t s) {
 
 CountWs count_reserve(Carver& c, int64_t n, int64_t nnz) {
   CountWs w;
-  // |H| <= nnz/2 for a symmetric graph; nnz bounds it for any input
-  const int64_t hmax = nnz + 1;
-  w.h_off = c.take<int64_t>(n + 2);
-  w.h_u = c.take<int32_t>(hmax);
-  w.h_v = c.take<int32_t>(hmax);
-  w.ecnt = c.take<int32_t>(n + 1);
-  w.ecur = c.take<int32_t>(n + 1);
-  w.task_off = c.take<int64_t>(n + 2);
-  w.task_begin = c.take<int64_t>(hmax);
-  w.task_len = c.take<int32_t>(hmax);
-  w.task_owner = c.take<int32_t>(hmax);
   w.ndesc = c.take<int32_t>(n + 1);
+  w.vinfo = c.take<uint8_t>(n + 1);
   w.so = c.take<int64_t>(n + 2);
-  // descriptors of a simple graph: at most deg + |Hfwd| + emitted tasks per
-  // anchor, i.e. <= 2 nnz in total; records beyond the capacity are dropped
-  w.scap = 2 * nnz + 2;
-  w.rcap = n + w.scap / kResolveChunk + 8;
-  w.rchunks = c.take<int2>(w.rcap);
-  w.sbeg = c.take<int64_t>(w.scap);
-  w.slen = c.take<int32_t>(w.scap);
-  w.soth = c.take<int32_t>(w.scap);
-  w.epre = c.take<int64_t>(w.scap + 1);
-  w.items = c.take<int4>(w.scap + 8);
+  // a vertex has at most deg(x) descriptors and a descriptor at most two
+  // tasks, so 2 nnz bounds the stream records of heavy anchors (front) plus
+  // the tasks of light anchors (back), and the work items, for any input
+  w.rcap = 2 * nnz + 2;
+  w.sbeg = c.take<int64_t>(w.rcap);
+  w.slen = c.take<int32_t>(w.rcap);
+  w.soth = c.take<int32_t>(w.rcap);
+  w.sx = c.take<int32_t>(w.rcap);
+  w.items_raw = c.take<int4>(w.rcap);
+  w.items = c.take<int4>(w.rcap);
+  // descriptors are at most nnz, so chunks at most nnz / kResChunk + 1
+  w.nchunk_cap = nnz / kResChunk + 2;
+  w.cx0 = c.take<int32_t>(w.nchunk_cap + 1);
+  w.ccnt = c.take<int4>(w.nchunk_cap);
+  w.lpre = c.take<int64_t>(w.nchunk_cap + 1);
   w.acc = c.take<unsigned long long>(kAccSlots);
   w.stats = c.take<int64_t>(24);
-  w.scratch = c.take<char>(scan_ws_bytes(w.scap + 1) + (n + 1) * sizeof(int32_t) + 256);
+  w.scratch = c.take<char>(scan_ws_bytes(n + w.nchunk_cap + 1) + 256);
   return w;
 }
 
@@ -887,28 +946,20 @@ int forward_meta_run(const tc_csr* g, VMeta* meta, hipStream_t s) {
 }
 
 int count_run(const CountArgs& a, CountWs& w, int64_t* triangles, int64_t* h_count, hipStream_t s) {
-  const tc_csr* g = a.g;
-  const int64_t n = g->n;
+  const int64_t n = a.g->n;
   TC_TRY(fill_i64(reinterpret_cast<int64_t*>(w.acc), 0, kAccSlots, s));
   TC_TRY(fill_i64(w.stats, 0, 24, s));
-  if (n == 0) {
-    TC_TRY(fill_i64(triangles, 0, 1, s));
-    if (h_count) TC_TRY(fill_i64(h_count, 0, 1, s));
-    return TC_OK;
+  prof_stage("plan");
+  if (n > 0) {
+    if (a.cover) {
+      if (a.per_vertex) TC_TRY((launch_all<true, true>(a, w, s)));
+      else TC_TRY((launch_all<true, false>(a, w, s)));
+    } else {
+      if (a.per_vertex) TC_TRY((launch_all<false, true>(a, w, s)));
+      else TC_TRY((launch_all<false, false>(a, w, s)));
+    }
   }
-  TC_TRY(fill_i32(w.ecnt, 0, n, s));
-  TC_TRY(fill_i32(w.ecur, 0, n, s));
-  prof_stage("hlist");
-  TC_TRY(hlist_run(g, a.meta, a.cols, w.h_off, w.h_u, w.h_v, g->nnz + 1, nullptr, w.scratch, s));
-  prof_stage("plan_light");
-  if (a.cover) {
-    if (a.per_vertex) TC_TRY((launch_all<true, true>(a, w, s)));
-    else TC_TRY((launch_all<true, false>(a, w, s)));
-  } else {
-    if (a.per_vertex) TC_TRY((launch_all<false, true>(a, w, s)));
-    else TC_TRY((launch_all<false, false>(a, w, s)));
-  }
-  finish_kernel<<<1, 1, 0, s>>>(w.acc, w.h_off, n, w.so, triangles, h_count, w.stats);
+  finish_kernel<<<1, 1, 0, s>>>(w.acc, w.so, n, triangles, h_count, w.stats);
   TC_HIP(hipGetLastError());
   return TC_OK;
 }

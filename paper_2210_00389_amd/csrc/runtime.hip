@@ -182,10 +182,10 @@ struct LoadAll {
   __device__ __forceinline__ int64_t operator()(int64_t i) const { return static_cast<int64_t>(p[i]); }
 };
 
-struct LoadMasked {
+struct LoadStrided {
   const int32_t* p;
-  int32_t mask;
-  __device__ __forceinline__ int64_t operator()(int64_t i) const { return static_cast<int64_t>(p[i] & mask); }
+  int64_t stride;
+  __device__ __forceinline__ int64_t operator()(int64_t i) const { return static_cast<int64_t>(p[i * stride]); }
 };
 
 template <class F>
@@ -260,9 +260,9 @@ int scan_exclusive(const T* in, int64_t* out, int64_t count, Carver& ws, hipStre
   return scan_impl(LoadAll<T>{in}, out, count, ws, s);
 }
 
-int scan_exclusive_masked(const int32_t* in, int32_t mask, int64_t* out, int64_t count, Carver& ws,
-                          hipStream_t s) {
-  return scan_impl(LoadMasked{in, mask}, out, count, ws, s);
+int scan_exclusive_strided(const int32_t* in, int64_t stride, int64_t* out, int64_t count, Carver& ws,
+                           hipStream_t s) {
+  return scan_impl(LoadStrided{in, stride}, out, count, ws, s);
 }
 
 template int scan_exclusive<int32_t>(const int32_t*, int64_t*, int64_t, Carver&, hipStream_t);

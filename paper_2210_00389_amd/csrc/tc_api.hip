@@ -231,8 +231,6 @@ int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles, 
   a.cover = true;
   a.per_vertex = pv;
   a.per_vertex_out = p.pv_new;
-  a.light_max = 32;
-  a.heavy_chunk = 1024;
   TC_TRY(count_run(a, p.count, triangles, h_count, s));
   if (pv && g->n > 0) {
     pv_back_kernel<<<grid_for(g->n, 256, 16384), 256, 0, s>>>(p.pv_new, p.relabel.order, g->n, per_vertex);
@@ -264,8 +262,6 @@ int tc_count_edge_baseline(const tc_csr* g, uint32_t flags, int64_t* triangles, 
   a.cover = false;
   a.per_vertex = false;
   a.per_vertex_out = nullptr;
-  a.light_max = 32;
-  a.heavy_chunk = 1024;
   TC_TRY(count_run(a, p.count, triangles, nullptr, s));
   stats_kernel<<<1, 1, 0, s>>>(p.stats, g->n, g->nnz, 0);
   TC_HIP(hipGetLastError());

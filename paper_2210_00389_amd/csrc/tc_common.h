@@ -187,9 +187,9 @@ __device__ __forceinline__ T load_relaxed(const T* p) {
 // Temporary space comes from the carver.
 template <class T>
 int scan_exclusive(const T* in, int64_t* out, int64_t count, Carver& ws, hipStream_t s);
-// The same over in[i] & mask.
-int scan_exclusive_masked(const int32_t* in, int32_t mask, int64_t* out, int64_t count, Carver& ws,
-                          hipStream_t s);
+// The same over in[i * stride].
+int scan_exclusive_strided(const int32_t* in, int64_t stride, int64_t* out, int64_t count, Carver& ws,
+                           hipStream_t s);
 size_t scan_ws_bytes(int64_t count);
 
 // Fill helpers (kernels, never hipMemset, so the call sequence stays

@@ -108,29 +108,23 @@ int hlist_run(const tc_csr* g, const VMeta* meta, const int32_t* cols, int64_t* 
 constexpr int kColPad = 64;
 
 struct CountWs {
-  int64_t* h_off;     // [n + 1]
-  int32_t* h_u;       // [nnz / 2]
-  int32_t* h_v;
-  int32_t* ecnt;      // per anchor: emitted tasks
-  int32_t* ecur;
-  int64_t* task_off;  // [n + 1]
-  int64_t* task_begin;
-  int32_t* task_len;
-  int32_t* task_owner;
-  // heavy anchors: descriptors resolved into stream records, then work
-  // items of about kElemChunk elements each
-  int32_t* ndesc;     // per vertex: descriptors of a heavy anchor, else 0
-  int64_t* so;        // exclusive scan of ndesc [n + 2]
-  int2* rchunks;      // resolution chunks (anchor, chunk) [rcap]
+  int32_t* ndesc;      // per vertex: descriptors [n + 1]
+  uint8_t* vinfo;      // per vertex: heavy flag, table bin and kind
+  int64_t* so;         // exclusive scan of ndesc [n + 1]
+  // stream records of heavy anchors (compacted) and their work items
+  int64_t* sbeg;       // [rcap]
+  int32_t* slen;       // length | flags
+  int32_t* soth;       // the vertex whose list is streamed
+  int32_t* sx;         // light tasks: the anchor
+  int4* items_raw;     // (anchor, first record lo/hi, count | bin | kind) [rcap]
+  int4* items;         // the same grouped by bin [rcap]
+  int32_t* cx0;        // first vertex of every descriptor chunk
+  int4* ccnt;          // per chunk: heavy records, light tasks, items
+  int64_t* lpre;       // scan of the per-chunk light task counts
+  int64_t nchunk_cap;
   int64_t rcap;
-  int64_t* sbeg;      // stream records [scap]
-  int32_t* slen;      // length | flags
-  int32_t* soth;      // the vertex the streamed list belongs to
-  int64_t* epre;      // element prefix of the streams [scap + 1]
-  int64_t scap;
-  int4* items;        // (anchor, first stream lo/hi, stream count)
   unsigned long long* acc;
-  int64_t* stats;     // tc_stats mirror
+  int64_t* stats;      // tc_stats mirror
   char* scratch;
 };
 CountWs count_reserve(Carver& c, int64_t n, int64_t nnz);
@@ -142,8 +136,6 @@ struct CountArgs {
   bool cover;           // cover edges (three classes) or the comparator
   bool per_vertex;
   int64_t* per_vertex_out;
-  int32_t light_max;
-  int32_t heavy_chunk;
 };
 int count_run(const CountArgs& a, CountWs& w, int64_t* triangles, int64_t* h_count,
               hipStream_t s);
