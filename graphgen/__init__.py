@@ -334,9 +334,17 @@ def from_spec(spec) -> Graph:
 
 
 def batch_mix(num_graphs: int = 4096, seed_base: int = 4096, n_min: int = 64,
-              n_max: int = 65536):
-    """The batched workload as a list of raw graphs (see :func:`batch_specs`)."""
-    return [from_spec(s) for s in batch_specs(num_graphs, seed_base, n_min, n_max)]
+              n_max: int = 65536, threads: int = 8):
+    """The batched workload as a list of raw graphs (see :func:`batch_specs`).
+    Graphs are generated on `threads` host threads (the C generators release
+    the interpreter lock and depend only on their own seeds)."""
+    specs = batch_specs(num_graphs, seed_base, n_min, n_max)
+    _load()
+    if threads <= 1:
+        return [from_spec(s) for s in specs]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(from_spec, specs))
 
 
 def serving_specs(pool_size: int = 128, seed_base: int = 9000, scale_min: int = 12,

@@ -104,15 +104,17 @@ typedef struct tc_batch {
 
 #define TC_BATCH_MAX_N 65536
 
-/* Tuning knobs; a NULL tc_tuning* means the compiled-in defaults. */
+/* Tuning knobs of tc_count_batch; a NULL tc_tuning* (or a zero field) means
+ * the compiled-in default.  The autotuner of the Python package picks them
+ * per batch shape. */
 typedef struct tc_tuning {
-  int32_t light_probe_max;    /* probe lists up to this length use the
-                                 per-task merge path (default 32) */
-  int32_t heavy_chunk;        /* descriptors per heavy work item (1024) */
-  int32_t batch_block;        /* threads per block of the batched kernel (256) */
-  int32_t batch_blocks_per_cu;/* resident blocks per CU for the batched
-                                 persistent launch (0 = occupancy query) */
-  int32_t reserved[4];
+  int32_t batch_block;        /* threads per block of the counting kernel:
+                                 256 (default) or 512 */
+  int32_t batch_piece;        /* CSR entries per work piece (>= 1024,
+                                 default 16384) */
+  int32_t batch_blocks_per_cu;/* resident blocks per CU of the persistent
+                                 counting kernel (0 = as many as LDS allows) */
+  int32_t reserved[5];
 } tc_tuning;
 
 /* Bytes of workspace `op` needs for a graph with n vertices and nnz entries

@@ -8,3 +8,4 @@ first use and raises if it has not been built (see build.py).
 from .api import (CountResult, Graph, TcError, Workspace, bfs_levels, build_csr, count,  # noqa: F401
                   count_edge_baseline, cover_edges, default_workspace, from_host_csr, from_host_pairs,
                   profile_enable, profile_read, read_stats, validate, workspace_bytes)
+from .batch import Batch, BatchResult, CapturedBatch, autotune, count_batch  # noqa: F401,E402

@@ -49,9 +49,8 @@ class TcBatch(ctypes.Structure):
 
 
 class TcTuning(ctypes.Structure):
-    _fields_ = [("light_probe_max", ctypes.c_int32), ("heavy_chunk", ctypes.c_int32),
-                ("batch_block", ctypes.c_int32), ("batch_blocks_per_cu", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+    _fields_ = [("batch_block", ctypes.c_int32), ("batch_piece", ctypes.c_int32),
+                ("batch_blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class TcProfile(ctypes.Structure):

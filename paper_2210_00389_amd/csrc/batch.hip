@@ -1,19 +1,377 @@
-// batch.hip -- many small graphs in one persistent launch (placeholder until
-// the persistent kernel lands; reports an explicit error).
+// batch.hip -- tc_count_batch: Alg. 1 on many small graphs (n <= 65536 each)
+// in two kernels that issue no host synchronisation and no memset, so a
+// caller can capture the whole call in one hipGraph.
+//
+// Kernel 1 (one block per graph): BFS levels of Alg. 1 with the level array
+// resident in LDS as uint16 (128 KB for 65536 vertices).  The first root is
+// the highest-degree vertex (smallest id on ties); every other component is
+// then searched from its smallest unvisited id, as in the scan order of
+// Alg. 1, and isolated vertices get level 0.  Each level is one pass over the
+// vertices: top-down from the frontier (vertices of degree above kBigDeg are
+// expanded by a whole wave) or, when the last level was large, bottom-up.
+// The block writes the level parity as a bit array (Lemma 1: for adjacent
+// vertices L(x) = L(y) iff their parities agree, so the parity is all the
+// count needs), the optional int32 levels, and the graph's work pieces:
+// vertex ranges holding about `piece` CSR entries each.
+//
+// Kernel 2 (persistent, pieces claimed from a counter): a wave takes one
+// vertex u at a time, sets the bits of N(u) in its own 65536-bit LDS bitmap,
+// and for every cover edge (u, v), v > u with equal parity, streams N(v)
+// flattened across the lanes and counts the w whose bit is set and that pass
+// the test of Alg. 1 (parity of w differs from u's, or w > v).  Counts and
+// |H| are reduced per block and added to the graph's outputs.
 #include "tc_internal.h"
 
 namespace tc {
 
-size_t batch_ws_bytes(int64_t total_n, int64_t total_nnz, int32_t num_graphs) {
-  (void)total_n;
-  (void)total_nnz;
-  (void)num_graphs;
-  return 256;
+namespace {
+
+constexpr int kBfsThreads = 1024;
+constexpr uint16_t kUnvisited = 0xFFFF;
+constexpr int kBigDeg = 64;      // frontier vertices above this degree are expanded by a wave
+constexpr int kBigCap = 1024;    // LDS list of such vertices per pass (overflow: expanded by the thread)
+constexpr int kBitmapWords = TC_BATCH_MAX_N / 32;
+constexpr int kPieceMin = 1024;  // smallest piece size accepted (sizes the piece slots)
+constexpr int kClaim = 2;        // pieces a block claims at once
+
+// Piece slots of graph g start at row_offsets[vbase[g]] / piece + g, parity
+// words at vbase[g] / 32 + g: both leave room for ceil(size / unit) entries.
+__device__ __forceinline__ int64_t piece_base(int64_t e0, int piece, int g) { return e0 / piece + g; }
+__device__ __forceinline__ int64_t parity_base(int64_t v0, int g) { return v0 / 32 + g; }
+
+__device__ __forceinline__ int64_t block_max_i64(int64_t v, int64_t* sh) {
+  v = wave_max(v);
+  const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  if (lane() == 0) sh[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t m = sh[0];
+    for (int i = 1; i < nw; ++i) m = sh[i] > m ? sh[i] : m;
+    sh[nw] = m;
+  }
+  __syncthreads();
+  const int64_t r = sh[nw];
+  __syncthreads();
+  return r;
 }
 
-int batch_run(const tc_batch*, const tc_tuning*, uint32_t, int64_t*, int64_t*, int32_t*, void*, size_t,
-              hipStream_t) {
-  return fail(TC_ERR_INVALID_ARG, "tc_count_batch: not available in this build");
+// Level-synchronous BFS over the vertices already set to level `base`
+// (the roots), with L resident in LDS.
+__device__ void bfs_levels_lds(uint16_t* L, const int64_t* rows, const int32_t* cols, int n, int* s_cnt,
+                               int32_t* s_big, int* s_nbig, int roots) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int wv = tid / kWave, nw = nt / kWave, ln = lane();
+  int level = 0;
+  int last = roots;  // vertices found at the previous level
+  for (;;) {
+    const bool bottom_up = last > n / 32;
+    if (tid == 0) {
+      *s_cnt = 0;
+      *s_nbig = 0;
+    }
+    __syncthreads();
+    int found = 0;
+    const uint16_t cur = static_cast<uint16_t>(level), nxt = static_cast<uint16_t>(level + 1);
+    if (bottom_up) {
+      for (int i = tid; i < n; i += nt) {
+        if (L[i] != kUnvisited) continue;
+        for (int64_t k = rows[i]; k < rows[i + 1]; ++k)
+          if (L[cols[k]] == cur) {
+            L[i] = nxt;
+            ++found;
+            break;
+          }
+      }
+    } else {
+      for (int i = tid; i < n; i += nt) {
+        if (L[i] != cur) continue;
+        const int64_t b = rows[i], e = rows[i + 1];
+        if (e - b > kBigDeg) {
+          const int q = atomicAdd(s_nbig, 1);
+          if (q < kBigCap) {
+            s_big[q] = i;
+            continue;
+          }
+        }
+        for (int64_t k = b; k < e; ++k) {
+          const int32_t w = cols[k];
+          if (L[w] == kUnvisited) {
+            L[w] = nxt;
+            ++found;
+          }
+        }
+      }
+      __syncthreads();
+      const int nbig = min(*s_nbig, kBigCap);
+      for (int q = wv; q < nbig; q += nw) {
+        const int i = s_big[q];
+        for (int64_t k = rows[i] + ln; k < rows[i + 1]; k += kWave) {
+          const int32_t w = cols[k];
+          if (L[w] == kUnvisited) {
+            L[w] = nxt;
+            ++found;
+          }
+        }
+      }
+    }
+    // `found` may count a vertex more than once in the top-down pass (two
+    // parents in one level); it only steers the direction and the stop test
+    found = wave_sum(found);
+    if (ln == 0 && found) atomicAdd(s_cnt, found);
+    __syncthreads();
+    last = *s_cnt;
+    __syncthreads();
+    if (last == 0) break;
+    ++level;
+  }
+}
+
+__global__ __launch_bounds__(kBfsThreads) void batch_bfs_kernel(const int64_t* vbase, const int64_t* row_offsets,
+                                                                const int32_t* cols, int piece, int32_t* levels,
+                                                                uint32_t* parity, int4* pieces, int64_t* T,
+                                                                int64_t* H) {
+  __shared__ uint16_t L[TC_BATCH_MAX_N];
+  __shared__ int32_t s_big[kBigCap];
+  __shared__ int64_t sh[kBfsThreads / kWave + 1];
+  __shared__ int s_cnt, s_nbig;
+  const int g = blockIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t v0 = vbase[g];
+  const int n = static_cast<int>(vbase[g + 1] - v0);
+  const int64_t* rows = row_offsets + v0;  // rows[i] = global position of local row i
+  const int64_t e0 = rows[0];
+  if (tid == 0) {
+    T[g] = 0;
+    H[g] = 0;
+  }
+  if (n == 0) return;
+  // root: highest degree, smallest id on ties; isolated vertices get level 0
+  int64_t key = -1;
+  for (int i = tid; i < n; i += nt) {
+    const int64_t d = rows[i + 1] - rows[i];
+    L[i] = d == 0 ? 0 : kUnvisited;
+    const int64_t k = (d << 32) | static_cast<int64_t>(0xFFFFFFFFu - static_cast<uint32_t>(i));
+    key = k > key ? k : key;
+  }
+  key = block_max_i64(key, sh);
+  const int root = static_cast<int>(0xFFFFFFFFu - static_cast<uint32_t>(key & 0xFFFFFFFF));
+  if (tid == 0) L[root] = 0;
+  __syncthreads();
+  bfs_levels_lds(L, rows, cols, n, &s_cnt, s_big, &s_nbig, 1);
+  // remaining components, each from its smallest unvisited id
+  for (;;) {
+    int64_t cand = -1;  // max of (n - i) over unvisited i = smallest i
+    for (int i = tid; i < n; i += nt)
+      if (L[i] == kUnvisited) {
+        cand = n - i;
+        break;
+      }
+    cand = block_max_i64(cand, sh);
+    if (cand < 0) break;
+    if (tid == 0) L[n - cand] = 0;
+    __syncthreads();
+    bfs_levels_lds(L, rows, cols, n, &s_cnt, s_big, &s_nbig, 1);
+  }
+  // outputs: parity bits, levels, pieces
+  uint32_t* par = parity + parity_base(v0, g);
+  const int words = (n + 31) / 32;
+  for (int wi = tid; wi < words; wi += nt) {
+    uint32_t b = 0;
+    for (int j = 0; j < 32; ++j) {
+      const int i = wi * 32 + j;
+      if (i < n) b |= static_cast<uint32_t>(L[i] & 1) << j;
+    }
+    par[wi] = b;
+  }
+  if (levels)
+    for (int i = tid; i < n; i += nt) levels[v0 + i] = L[i];
+  const int64_t nnz = rows[n] - e0;
+  const int64_t np = (nnz + piece - 1) / piece;
+  int4* pc = pieces + piece_base(e0, piece, g);
+  for (int64_t p = tid; p < np; p += nt) {
+    // piece p: first vertex whose row starts at or after e0 + p * piece
+    const int vb = p == 0 ? 0 : static_cast<int>(lower_bound_dev(rows, 0, n, e0 + p * piece));
+    const int ve = p + 1 == np ? n : static_cast<int>(lower_bound_dev(rows, 0, n, e0 + (p + 1) * piece));
+    pc[p] = make_int4(g, vb, ve, 0);
+  }
+}
+
+__device__ __forceinline__ uint32_t par_bit(const uint32_t* p, int32_t i) { return (p[i >> 5] >> (i & 31)) & 1u; }
+
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vbase, const int64_t* row_offsets,
+                                                              const int32_t* cols, const uint32_t* parity,
+                                                              const int4* pieces, int64_t nslots,
+                                                              unsigned long long* ctr, int64_t* T, int64_t* H) {
+  constexpr int NW = THREADS / kWave;
+  __shared__ uint32_t s_par[kBitmapWords];
+  __shared__ uint32_t s_bm[NW][kBitmapWords];
+  __shared__ int32_t s_off[NW][kWave + 1];
+  __shared__ int64_t s_beg[NW][kWave];
+  __shared__ int32_t s_v[NW][kWave];
+  __shared__ int64_t sh[NW + 1];
+  __shared__ unsigned long long s_claim;
+  __shared__ int s_next;
+  const int tid = threadIdx.x, wv = tid / kWave, ln = lane();
+  uint32_t* bm = s_bm[wv];
+  for (int i = ln; i < kBitmapWords; i += kWave) bm[i] = 0u;
+  int cur_g = -1;
+  if (tid == 0) s_claim = atomicAdd(ctr, static_cast<unsigned long long>(kClaim));
+  __syncthreads();
+  unsigned long long claim = s_claim;
+  while (claim < static_cast<unsigned long long>(nslots)) {
+    unsigned long long next = 0;
+    if (tid == 0) next = atomicAdd(ctr, static_cast<unsigned long long>(kClaim));
+    const unsigned long long cend = min(claim + kClaim, static_cast<unsigned long long>(nslots));
+    for (unsigned long long sl = claim; sl < cend; ++sl) {
+      const int4 pc = pieces[sl];
+      if (pc.x < 0 || pc.y >= pc.z) continue;  // empty slot (block-uniform)
+      const int g = pc.x;
+      const int64_t v0 = vbase[g];
+      const int n = static_cast<int>(vbase[g + 1] - v0);
+      const int64_t* rows = row_offsets + v0;
+      if (g != cur_g) {
+        __syncthreads();
+        const uint32_t* par = parity + parity_base(v0, g);
+        for (int i = tid; i < (n + 31) / 32; i += THREADS) s_par[i] = par[i];
+        cur_g = g;
+      }
+      if (tid == 0) s_next = pc.y;
+      __syncthreads();
+      int64_t cnt = 0, hc = 0;
+      for (;;) {
+        int u = 0;
+        if (ln == 0) u = atomicAdd(&s_next, 1);
+        u = __shfl(u, 0, kWave);
+        if (u >= pc.z) break;
+        const int64_t ru = rows[u], du = rows[u + 1] - ru;
+        const uint32_t pu = par_bit(s_par, u);
+        for (int64_t k = ln; k < du; k += kWave) {
+          const int32_t w = cols[ru + k];
+          atomicOr(&bm[w >> 5], 1u << (w & 31));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int64_t base = 0; base < du; base += kWave) {
+          // cover edges (u, v), v > u, in this chunk of N(u)
+          const int64_t k = base + ln;
+          int32_t v = -1;
+          int len = 0;
+          int64_t vb = 0;
+          if (k < du) {
+            v = cols[ru + k];
+            if (v > u && par_bit(s_par, v) == pu) {
+              vb = rows[v];
+              len = static_cast<int>(rows[v + 1] - vb);
+              ++hc;
+            }
+          }
+          const int incl = wave_incl_scan(len);
+          const int total = __shfl(incl, kWave - 1, kWave);
+          s_off[wv][ln] = incl - len;
+          s_beg[wv][ln] = vb;
+          s_v[wv][ln] = v;
+          if (ln == 0) s_off[wv][kWave] = total;
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          for (int e = ln; e < total; e += kWave) {
+            int lo = 0, hi = kWave;  // last j with s_off[j] <= e
+            while (hi - lo > 1) {
+              const int mid = (lo + hi) >> 1;
+              if (s_off[wv][mid] <= e) lo = mid;
+              else hi = mid;
+            }
+            const int32_t w = cols[s_beg[wv][lo] + (e - s_off[wv][lo])];
+            const int32_t vv = s_v[wv][lo];
+            if (((bm[w >> 5] >> (w & 31)) & 1u) && (par_bit(s_par, w) != pu || w > vv)) ++cnt;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+        for (int64_t k = ln; k < du; k += kWave) bm[cols[ru + k] >> 5] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      }
+      cnt = block_sum(cnt, sh);
+      hc = block_sum(hc, sh);
+      if (tid == 0) {
+        if (cnt) atomicAdd(reinterpret_cast<unsigned long long*>(&T[g]), static_cast<unsigned long long>(cnt));
+        if (hc) atomicAdd(reinterpret_cast<unsigned long long*>(&H[g]), static_cast<unsigned long long>(hc));
+      }
+    }
+    __syncthreads();
+    if (tid == 0) s_claim = next;
+    __syncthreads();
+    claim = s_claim;
+  }
+}
+
+__global__ void empty_pieces_kernel(int4* pieces, int64_t nslots) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nslots; i += (int64_t)gridDim.x * blockDim.x)
+    pieces[i] = make_int4(-1, 0, 0, 0);
+}
+
+struct BatchPlan {
+  uint32_t* parity;
+  int4* pieces;
+  unsigned long long* ctr;
+  int64_t nslots_cap;
+  size_t bytes;
+};
+
+BatchPlan plan_batch(void* base, int64_t total_n, int64_t total_nnz, int32_t G) {
+  BatchPlan p;
+  Carver c(base);
+  p.ctr = c.take<unsigned long long>(4);
+  p.parity = c.take<uint32_t>(total_n / 32 + G + 2);
+  p.nslots_cap = total_nnz / kPieceMin + G + 2;
+  p.pieces = c.take<int4>(p.nslots_cap);
+  p.bytes = c.used();
+  return p;
+}
+
+template <int THREADS>
+int launch_count(const tc_batch* b, const BatchPlan& p, int64_t nslots, int blocks_per_cu, int64_t* T, int64_t* H,
+                 hipStream_t s) {
+  batch_count_kernel<THREADS><<<static_cast<unsigned>(num_cus() * blocks_per_cu), THREADS, 0, s>>>(
+      b->vbase, b->row_offsets, b->cols, p.parity, p.pieces, nslots, p.ctr, T, H);
+  TC_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+}  // namespace
+
+size_t batch_ws_bytes(int64_t total_n, int64_t total_nnz, int32_t num_graphs) {
+  return plan_batch(nullptr, total_n, total_nnz, num_graphs).bytes;
+}
+
+int batch_run(const tc_batch* b, const tc_tuning* t, uint32_t flags, int64_t* triangles, int64_t* h_count,
+              int32_t* levels, void* ws, size_t ws_bytes, hipStream_t s) {
+  (void)flags;
+  const int G = b->num_graphs;
+  if (G == 0) return TC_OK;
+  int threads = 256, piece = 16384, bpc = 0;
+  if (t) {
+    if (t->batch_block) threads = t->batch_block;
+    if (t->batch_piece) piece = t->batch_piece;
+    bpc = t->batch_blocks_per_cu;
+  }
+  if (threads != 256 && threads != 512)
+    return fail(TC_ERR_INVALID_ARG, "tc_count_batch: batch_block must be 256 or 512 (got %d)", threads);
+  if (piece < kPieceMin) return fail(TC_ERR_INVALID_ARG, "tc_count_batch: batch_piece must be >= %d", kPieceMin);
+  // LDS per block: parity and one bitmap per wave of 8 KB, plus staging
+  const int max_bpc = threads == 256 ? 3 : 2;
+  if (bpc <= 0 || bpc > max_bpc) bpc = max_bpc;
+  BatchPlan p = plan_batch(ws, b->total_vertices, b->total_nnz, G);
+  if (ws_bytes < p.bytes) return fail(TC_ERR_WORKSPACE, "tc_count_batch: workspace %zu < %zu", ws_bytes, p.bytes);
+  const int64_t nslots = b->total_nnz / piece + G + 2;
+  prof_stage("batch_bfs");
+  TC_TRY(fill_i64(reinterpret_cast<int64_t*>(p.ctr), 0, 4, s));
+  empty_pieces_kernel<<<grid_for(nslots, 256, 8192), 256, 0, s>>>(p.pieces, nslots);
+  TC_HIP(hipGetLastError());
+  batch_bfs_kernel<<<static_cast<unsigned>(G), kBfsThreads, 0, s>>>(b->vbase, b->row_offsets, b->cols, piece, levels,
+                                                                    p.parity, p.pieces, triangles, h_count);
+  TC_HIP(hipGetLastError());
+  prof_stage("batch_count");
+  if (threads == 256) TC_TRY(launch_count<256>(b, p, nslots, bpc, triangles, h_count, s));
+  else TC_TRY(launch_count<512>(b, p, nslots, bpc, triangles, h_count, s));
+  return TC_OK;
 }
 
 }  // namespace tc
