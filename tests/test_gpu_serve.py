@@ -1,0 +1,43 @@
+"""The request loop on the GPU: every request's (T, |H|) in a mix of
+overlapping requests on several slots equals the same graph counted alone,
+and the oracle's T."""
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _pool_graphs():
+    return [graphgen.rmat(10, seed=1), graphgen.rmat(12, seed=2), graphgen.rmat(13, seed=3),
+            graphgen.chung_lu(10000, 2.1, 20.0, seed=4), graphgen.chung_lu(30000, 2.1, 20.0, seed=5),
+            graphgen.rmat(11, seed=6), graphgen.complete(60), graphgen.grid(40, 40)]
+
+
+@pytest.mark.parametrize("budget_scale", [4.0, 0.35])
+def test_serving_mix_equals_alone(budget_scale):
+    import torch
+    import paper_2210_00389_amd as tc
+    from paper_2210_00389_amd import serve
+    graphs = _pool_graphs()
+    pool, sizes = serve.build_pool(graphs)
+    alone = {}
+    for gid, g in enumerate(graphs):
+        G = tc.from_host_pairs(g.n, g.src, g.dst)
+        r = tc.count(G)
+        alone[gid] = (r.T, r.h)
+        assert r.T == oracle.triangle_count(oracle.from_graph(g)), gid
+    total = sum(gb + serve.count_ws_bytes(n, nnz) for n, nnz, gb in sizes.values())
+    biggest = max(gb + serve.count_ws_bytes(n, nnz) for n, nnz, gb in sizes.values())
+    budget = max(int(total * budget_scale), 2 * biggest)
+    reqs = serve.make_requests(sizes, serve.count_ws_bytes, rate=3000.0, count=80, seed=11)
+    print(f"case: serving mix budget={budget}", flush=True)
+    st = serve.Server(serve.GpuExecutor(pool, 3), slots=3, budget_bytes=budget).run(reqs)
+    torch.cuda.synchronize()
+    for r in reqs:
+        assert (r.triangles, r.h) == alone[r.graph_id], (r.rid, r.graph_id)
+    assert st["max_running"] > 1
+    assert st["p99_ms"] >= st["p50_ms"] > 0
+    if budget_scale < 1:
+        assert st["evictions"] > 0

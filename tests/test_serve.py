@@ -1,0 +1,119 @@
+"""Host logic of the request loop (admission, residency, LRU eviction,
+arrivals, statistics) with a fake executor; no GPU."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2210_00389_amd.serve import (Request, ResidentCache, Scheduler, Server, make_requests, percentile,
+                                        poisson_arrivals)
+
+
+def req(rid, gid, t=0.0, gb=100, ws=10):
+    return Request(rid, gid, t, n=10, nnz=20, graph_bytes=gb, ws_bytes=ws)
+
+
+def test_resident_cache_lru_and_pins():
+    c = ResidentCache()
+    c.put(1, 50, pinned=False)
+    c.put(2, 50, pinned=True)
+    c.put(3, 50, pinned=False)
+    c.touch(1)  # order now 2, 3, 1
+    assert c.evictable_bytes() == 100
+    assert c.evict(60) == [3, 1]  # oldest unpinned first; 2 is pinned
+    assert c.has(2) and not c.has(1) and not c.has(3)
+    c.unpin(2)
+    assert c.evict(1) == [2]
+
+
+def test_scheduler_fifo_slots_and_budget():
+    s = Scheduler(slots=2, budget_bytes=300)
+    for i in range(4):
+        s.submit(req(i, gid=i, gb=100, ws=20))
+    started, ev = s.admit(0.0)
+    assert [r.rid for r in started] == [0, 1] and ev == []  # two slots
+    assert s.used() == 2 * 120
+    s.complete(started[0], 1.0)
+    started2, ev2 = s.admit(1.0)
+    # request 2 needs 120 B; 240 - 20 + 120 = 340 > 300 -> graph 0 (idle) is evicted
+    assert [r.rid for r in started2] == [2] and ev2 == [0]
+    assert started2[0].uploaded and s.evictions == 1
+
+
+def test_scheduler_reuses_resident_graph():
+    s = Scheduler(slots=1, budget_bytes=1000)
+    s.submit(req(0, gid=7))
+    (r0,), _ = s.admit(0.0)
+    s.complete(r0, 0.5)
+    s.submit(req(1, gid=7))
+    (r1,), _ = s.admit(0.6)
+    assert r0.uploaded and not r1.uploaded
+
+
+def test_scheduler_waits_when_memory_is_pinned():
+    s = Scheduler(slots=3, budget_bytes=200)
+    s.submit(req(0, gid=0, gb=100, ws=20))
+    s.submit(req(1, gid=1, gb=100, ws=20))
+    started, _ = s.admit(0.0)
+    assert [r.rid for r in started] == [0]  # 1 does not fit while 0 runs (its graph is pinned)
+    s.complete(started[0], 1.0)
+    started, ev = s.admit(1.0)
+    assert [r.rid for r in started] == [1] and ev == [0]
+
+
+def test_scheduler_rejects_oversized_request():
+    s = Scheduler(slots=1, budget_bytes=50)
+    with pytest.raises(ValueError):
+        s.submit(req(0, gid=0, gb=100))
+
+
+def test_poisson_rate_and_percentile():
+    a = poisson_arrivals(1000.0, 20000, seed=3)
+    assert np.all(np.diff(a) > 0)
+    assert abs(len(a) / a[-1] - 1000.0) < 30.0
+    assert percentile([1, 2, 3, 4], 50) == 2.5 and percentile([5], 99) == 5
+
+
+class FakeExecutor:
+    """Sleeps a size-dependent time and answers a deterministic function of
+    the graph id; records the peak number of concurrent runs."""
+
+    def __init__(self):
+        self.active = 0
+        self.peak = 0
+        self.lock = threading.Lock()
+        self.evicted = []
+
+    def run(self, slot, r, upload):
+        with self.lock:
+            self.active += 1
+            self.peak = max(self.peak, self.active)
+        time.sleep(0.002 + 0.0005 * (r.graph_id % 4))
+        with self.lock:
+            self.active -= 1
+        return r.graph_id * 7 + 1, r.graph_id + 3
+
+    def evict(self, gid):
+        self.evicted.append(gid)
+
+
+def test_server_overlaps_and_answers_every_request():
+    sizes = {g: (100 + g, 400 + 2 * g, 5000 + 10 * g) for g in range(12)}
+    reqs = make_requests(sizes, lambda n, nnz: 1000, rate=2000.0, count=120, seed=5)
+    ex = FakeExecutor()
+    st = Server(ex, slots=4, budget_bytes=40000).run(reqs)
+    assert st["requests"] == 120
+    assert all(r.triangles == r.graph_id * 7 + 1 and r.h == r.graph_id + 3 for r in reqs)
+    assert ex.peak > 1 and st["max_running"] > 1
+    assert st["p99_ms"] >= st["p50_ms"] > 0
+    assert all(r.t_admit >= r.arrival and r.t_done >= r.t_admit for r in reqs)
+
+
+def test_server_evicts_under_a_small_budget():
+    sizes = {g: (100, 400, 5000) for g in range(10)}
+    reqs = make_requests(sizes, lambda n, nnz: 1000, rate=500.0, count=60, seed=9)
+    ex = FakeExecutor()
+    st = Server(ex, slots=2, budget_bytes=15000).run(reqs)
+    assert st["evictions"] > 0 and set(ex.evicted) <= set(sizes)
+    assert all(r.triangles == r.graph_id * 7 + 1 for r in reqs)
