@@ -132,6 +132,90 @@ def cpu_baseline(g, n, m, budget_s):
     }
 
 
+def bench_batch(args):
+    """4096 ER/BA graphs in one captured tc_count_batch replay per step."""
+    import numpy as np
+    import torch
+    import graphgen
+    import paper_2210_00389_amd as tc
+    log("[bench] generating the 4096-graph batch")
+    graphs = graphgen.batch_mix(4096)
+    b = tc.Batch.from_graphs(graphs)
+    del graphs
+    torch.cuda.synchronize()
+    log(f"[bench] batch: G={b.num_graphs} sum n={b.total_vertices} sum m={b.total_edges}")
+    tuning = tc.autotune(b, verbose=True, use_cache=False)
+    cap = tc.CapturedBatch(b, tuning)
+    for _ in range(args.warmup):
+        cap.replay()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, z in ev:
+        a.record()
+        cap.replay()
+        z.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [a.elapsed_time(z) for a, z in ev]
+    T = cap.out.triangles.cpu().numpy()
+    H = cap.out.h_count.cpu().numpy()
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", "batch_mix.json")
+    if os.path.exists(gpath):
+        gd = json.load(open(gpath))["graphs"]
+        golden = {"graphs": len(gd), "all_match": all(T[g["i"]] == g["triangles"] and H[g["i"]] == g["h"]
+                                                       for g in gd)}
+    ms = 1000 * wall / args.steps
+    return {
+        "metric": "cover-edge TC edges/s (batched, 4096 graphs per launch)", "value": b.total_edges / (wall / args.steps),
+        "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "4096 graphs: 2048 Erdos-Renyi (mean degree U[8,64]) + 2048 Barabasi-Albert "
+                               "(m U{2..16}), n log-uniform in [64, 65536], seed base 4096; one captured "
+                               "tc_count_batch per step", "num_graphs": b.num_graphs,
+                   "sum_n": b.total_vertices, "sum_m": b.total_edges, "tuning": tuning},
+        "triangles_per_s": float(T.sum()) / (wall / args.steps),
+        "p50_ms": percentile(per, 50), "p99_ms": percentile(per, 99), "golden": golden,
+    }
+
+
+def bench_serving(args):
+    """Poisson request stream over a pool of R-MAT and Chung-Lu graphs."""
+    import torch
+    import graphgen
+    from paper_2210_00389_amd import serve
+    specs = graphgen.serving_specs(args.pool, scale_max=args.serve_scale_max,
+                                   cl_n_max=args.serve_cl_n_max)
+    log(f"[bench] building the serving pool ({len(specs)} graphs)")
+    graphs = [graphgen.from_spec(sp) for sp in specs]
+    pool, sizes = serve.build_pool(graphs)
+    del graphs
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free * args.serve_budget_frac)
+    runs = []
+    for rate in args.rates:
+        reqs = serve.make_requests(sizes, serve.count_ws_bytes, rate=rate, count=args.requests, seed=int(rate))
+        ex = serve.GpuExecutor(pool, args.slots)
+        st = serve.Server(ex, slots=args.slots, budget_bytes=budget).run(reqs)
+        st["rate_req_s"] = rate
+        log(f"[bench] rate {rate}: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms "
+            f"edges/s {st['edges_per_s']:.3e} busy {st['busy_fraction']:.2f}")
+        runs.append(st)
+    top = runs[-1]
+    return {
+        "metric": "served cover-edge TC latency p50/p99 and edges/s", "value": top["edges_per_s"],
+        "unit": "edges/s", "n_gpus": 1, "steps": args.requests, "warmup": 0, "ms_per_step": top["mean_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"Poisson arrivals over a pool of {len(specs)} graphs (half R-MAT scale "
+                               f"12-{args.serve_scale_max} ef16, half Chung-Lu gamma 2.1 mean degree 20 n "
+                               f"1e4-{args.serve_cl_n_max:.0e}); {args.slots} slots; HBM budget "
+                               f"{args.serve_budget_frac:.2f} of free", "rates": args.rates,
+                   "requests_per_rate": args.requests},
+        "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"], "runs": runs,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +228,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--json-out", default=None)
+    ap.add_argument("--workload", choices=("rmat", "batch", "serving"), default="rmat")
+    ap.add_argument("--pool", type=int, default=32, help="serving: graphs in the request pool")
+    ap.add_argument("--rates", type=float, nargs="+", default=[50, 200, 1000, 2000])
+    ap.add_argument("--requests", type=int, default=500, help="serving: requests per rate")
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--serve-scale-max", type=int, default=20)
+    ap.add_argument("--serve-cl-n-max", type=int, default=10**6)
+    ap.add_argument("--serve-budget-frac", type=float, default=0.5)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -158,6 +250,14 @@ def main():
     import paper_2210_00389_amd as tc
 
     torch.cuda.set_device(0)
+    if args.workload != "rmat":
+        out = bench_batch(args) if args.workload == "batch" else bench_serving(args)
+        line = json.dumps(out)
+        print(line, flush=True)
+        if args.json_out:
+            with open(args.json_out, "w") as f:
+                f.write(line + "\n")
+        return
     dev = torch.device("cuda:0")
     log(f"[bench] generating R-MAT scale {args.scale} ef {args.edge_factor} seed {args.seed}")
     t = time.perf_counter()

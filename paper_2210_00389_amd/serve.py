@@ -280,7 +280,10 @@ class GpuExecutor:
         from . import api
         self.torch, self.api = torch, api
         self.pool = pool
-        self.dev = torch.device(device)
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device(dev.type, torch.cuda.current_device())
+        self.dev = dev
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(slots)]
         self.ws = [api.Workspace(self.dev) for _ in range(slots)]
         self.resident: dict[int, object] = {}
