@@ -2,22 +2,25 @@
 // a BFS from r0 (given, or the largest-degree vertex with the smallest id on
 // ties), then every component not reached is levelled from its smallest id.
 //
-// GPU structure:
-//   * top-down steps expand a frontier queue edge-balanced: the frontier's
-//     degree prefix maps a flat edge index to (frontier vertex, offset), so a
-//     hub row is spread over many waves and every read of cols is coalesced;
-//     new vertices are claimed with an atomic OR on a visited bitmap (n bits,
-//     L2-resident) and appended with one atomic per wave;
-//   * bottom-up steps (Beamer et al.'s direction optimisation) let every
-//     unvisited vertex look for a neighbour in the frontier bitmap and stop
-//     at the first hit; they run when the frontier's edges outnumber the
-//     unexplored edges / alpha;
+// GPU structure (frontiers are bitmaps; three rotate so that the bitmap of
+// the level after next is cleared while the current one is read):
+//   * a top-down step lets every frontier vertex expand its row; rows above
+//     kBig entries are listed and expanded edge-balanced by a second kernel
+//     (flat edge index over the listed rows, so a hub's row is spread over
+//     the whole grid); new vertices are claimed with an atomic OR on the
+//     visited bitmap;
+//   * a bottom-up step (Beamer et al.'s direction optimisation) lets every
+//     unvisited vertex look for a neighbour in the frontier and stop at the
+//     first hit; a wave composes its 64 vertices' bits with ballots;
+//   * per-block counts (new vertices, their edges) go to an array that a
+//     one-block kernel sums to decide the next direction (alpha 14, beta 24)
+//     and the stop, all on the device; the host launches levels in groups
+//     of kLevelsPerSync and reads the state once per group;
 //   * the remaining components: union-find over the unreached vertices where
 //     a root is always hooked under the smaller root, so every component's
 //     final root is its smallest id; those roots then start one multi-source
 //     BFS (components are disjoint, so the per-component distances are
 //     exactly those of separate BFS runs).
-// The host reads two counters per level (frontier size and its edge count).
 #include "tc_internal.h"
 
 namespace tc {
@@ -47,150 +50,256 @@ __global__ void root_key_kernel(const int64_t* off, int64_t n, unsigned long lon
   }
 }
 
-// Starts the BFS from one root (either the argmax key or a given root):
-// level 0, visited, first queue entry, counters.
-__global__ void start_kernel(const int64_t* off, const unsigned long long* key, int64_t given_root,
-                             int32_t* L, uint32_t* vis, int32_t* q, int64_t* ctr, int64_t* root_out) {
+
+constexpr int kBig = 4096;         // frontier rows above this length are expanded edge-balanced
+constexpr int kBigCap = 4096;      // listed rows per level (more: expanded by their thread)
+constexpr int kMaxParts = 4096;    // blocks of the step kernels (partials per kernel)
+constexpr int kLevelsPerSync = 8;  // levels launched between two reads of the state
+
+// Device-side state of one BFS (see BfsWs::st).
+struct BfsState {
+  int64_t f, ef;         // frontier size and its row entries
+  int64_t unexplored;    // row entries not yet in any frontier
+  int64_t nbig;          // listed big rows of the current level
+  int32_t level;         // level of the current frontier
+  int32_t bottom_up;     // direction of the step that expands it
+  int32_t prev_bu;       // direction of the previous step
+  int32_t done;          // the frontier is empty
+  int32_t num_levels;    // deepest level + 1 once done
+  int32_t pad;
+};
+
+__device__ __forceinline__ uint32_t* bm_at(uint32_t* base, int64_t words, int32_t level, int k) {
+  return base + static_cast<int64_t>((level + k) % 3) * words;
+}
+
+// Block sums of (new vertices, their entries) -> part[2 * blockIdx.x + 0/1].
+__device__ __forceinline__ void block_partial(int64_t cnt, int64_t edg, int64_t* part, int64_t* sh) {
+  cnt = block_sum(cnt, sh);
+  edg = block_sum(edg, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = cnt;
+    part[2 * blockIdx.x + 1] = edg;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void step_kernel(const int64_t* off, const int32_t* cols, int64_t n,
+                                                        BfsState* st, int32_t* L, uint32_t* vis, uint32_t* bms,
+                                                        int32_t* big, int64_t* part) {
+  __shared__ int64_t sh[kThreads / kWave + 1];
+  __shared__ int32_t s_off[kThreads / kWave][kWave + 1];
+  __shared__ int64_t s_beg[kThreads / kWave][kWave];
+  const int64_t words = (n + 31) / 32 + 1;
+  const int32_t level = st->level;
+  int64_t cnt = 0, edg = 0;
+  if (!st->done) {
+    const uint32_t* cur = bm_at(bms, words, level, 0);
+    uint32_t* nxt = bm_at(bms, words, level, 1);
+    uint32_t* old = bm_at(bms, words, level, 2);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t i = t0; i < words; i += stride) old[i] = 0u;  // the bitmap of the level after next
+    const int32_t nl = level + 1;
+    if (st->bottom_up) {
+      // 64 consecutive vertices per wave and round: words 2k, 2k+1 are this wave's
+      for (int64_t v0 = (t0 / kWave) * kWave; v0 < n; v0 += stride) {
+        const int64_t v = v0 + lane();
+        bool take = false;
+        if (v < n && !((vis[v >> 5] >> (v & 31)) & 1u)) {
+          const int64_t b = off[v], e = off[v + 1];
+          for (int64_t j = b; j < e; ++j) {
+            const int32_t w = cols[j];
+            if ((cur[w >> 5] >> (w & 31)) & 1u) {
+              take = true;
+              break;
+            }
+          }
+          if (take) {
+            L[v] = nl;
+            ++cnt;
+            edg += e - b;
+          }
+        }
+        const uint64_t m = __ballot(take);
+        if (m && (lane() & 31) == 0) {
+          const uint32_t word = static_cast<uint32_t>(m >> lane());
+          if (word) {
+            nxt[v >> 5] |= word;
+            vis[v >> 5] |= word;
+          }
+        }
+      }
+    } else {
+      // 64 consecutive vertices per wave and round; the rows of the group's
+      // frontier vertices are flattened across the lanes
+      const int wv = threadIdx.x / kWave;
+      for (int64_t v0 = (t0 / kWave) * kWave; v0 < n; v0 += stride) {
+        const uint64_t fw = static_cast<uint64_t>(cur[v0 >> 5]) | (static_cast<uint64_t>(cur[(v0 >> 5) + 1]) << 32);
+        if (fw == 0) continue;  // uniform per wave
+        const int64_t v = v0 + lane();
+        int64_t b = 0;
+        int d = 0;
+        if (((fw >> lane()) & 1ull) && v < n) {
+          b = off[v];
+          const int64_t e = off[v + 1];
+          if (e - b > kBig) {
+            const unsigned long long q = atomicAdd(reinterpret_cast<unsigned long long*>(&st->nbig), 1ull);
+            if (q < static_cast<unsigned long long>(kBigCap)) big[q] = static_cast<int32_t>(v);
+            else d = static_cast<int>(e - b);  // list full: flattened here
+          } else {
+            d = static_cast<int>(e - b);
+          }
+        }
+        const int incl = wave_incl_scan(d);
+        const int total = __shfl(incl, kWave - 1, kWave);
+        s_off[wv][lane()] = incl - d;
+        s_beg[wv][lane()] = b;
+        if (lane() == 0) s_off[wv][kWave] = total;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int k = lane(); k < total; k += kWave) {
+          int lo = 0, hi = kWave;  // last j with s_off[j] <= k
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_off[wv][mid] <= k) lo = mid;
+            else hi = mid;
+          }
+          const int32_t w = cols[s_beg[wv][lo] + (k - s_off[wv][lo])];
+          const uint32_t bit = 1u << (w & 31);
+          if (load_relaxed(&vis[w >> 5]) & bit) continue;
+          if (atomicOr(&vis[w >> 5], bit) & bit) continue;
+          atomicOr(&nxt[w >> 5], bit);
+          L[w] = nl;
+          ++cnt;
+          edg += off[w + 1] - off[w];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      }
+    }
+  }
+  block_partial(cnt, edg, part, sh);
+}
+
+// Top-down expansion of the listed big rows: flat entry index over them.
+__global__ __launch_bounds__(kThreads) void big_kernel(const int64_t* off, const int32_t* cols, int64_t n,
+                                                       BfsState* st, int32_t* L, uint32_t* vis, uint32_t* bms,
+                                                       const int32_t* big, int64_t* part) {
+  __shared__ int64_t sh[kThreads / kWave + 1];
+  __shared__ int64_t s_pre[kBigCap + 1];
+  const int64_t words = (n + 31) / 32 + 1;
+  int64_t cnt = 0, edg = 0;
+  const int64_t nb = min(st->nbig, static_cast<int64_t>(kBigCap));
+  if (!st->done && !st->bottom_up && nb > 0) {
+    uint32_t* nxt = bm_at(bms, words, st->level, 1);
+    const int32_t nl = st->level + 1;
+    // prefix of the listed rows' lengths (each block computes it)
+    int64_t run = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kThreads) {
+      const int64_t i = b0 + threadIdx.x;
+      const int64_t d = i < nb ? off[big[i] + 1] - off[big[i]] : 0;
+      int64_t tot;
+      const int64_t ex = block_excl_scan(d, sh, &tot);
+      if (i < nb) s_pre[i] = run + ex;
+      run += tot;
+    }
+    if (threadIdx.x == 0) s_pre[nb] = run;
+    __syncthreads();
+    const int64_t total = run;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {
+      int64_t lo = 0, hi = nb;  // last row with s_pre <= k
+      while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (s_pre[mid] <= k) lo = mid;
+        else hi = mid;
+      }
+      const int32_t v = big[lo];
+      const int32_t w = cols[off[v] + (k - s_pre[lo])];
+      const uint32_t bit = 1u << (w & 31);
+      if (load_relaxed(&vis[w >> 5]) & bit) continue;
+      if (atomicOr(&vis[w >> 5], bit) & bit) continue;
+      atomicOr(&nxt[w >> 5], bit);
+      L[w] = nl;
+      ++cnt;
+      edg += off[w + 1] - off[w];
+    }
+  }
+  block_partial(cnt, edg, part, sh);
+}
+
+// Sums the partials of both kernels, decides the next step, advances.
+__global__ __launch_bounds__(kThreads) void decide_kernel(int64_t n, BfsState* st, const int64_t* part,
+                                                          int nparts) {
+  __shared__ int64_t sh[kThreads / kWave + 1];
+  if (st->done) return;  // uniform
+  int64_t cnt = 0, edg = 0;
+  for (int i = threadIdx.x; i < nparts; i += kThreads) {
+    cnt += part[2 * i];
+    edg += part[2 * i + 1];
+  }
+  cnt = block_sum(cnt, sh);
+  edg = block_sum(edg, sh);
+  if (threadIdx.x == 0) {
+    const int64_t alpha = 14, beta = 24;
+    st->prev_bu = st->bottom_up;
+    st->nbig = 0;
+    if (cnt == 0) {
+      st->done = 1;
+      st->num_levels = st->level + 1;
+      st->f = 0;
+      st->ef = 0;
+      return;
+    }
+    st->level += 1;
+    st->f = cnt;
+    st->ef = edg;
+    st->unexplored -= edg;
+    // Beamer's rule on the new frontier
+    st->bottom_up = !st->prev_bu ? (edg > st->unexplored / alpha && cnt > n / 256) : (cnt >= n / beta);
+  }
+}
+
+// Initial state of a BFS whose level-0 frontier is already in the bitmap of
+// level 0 (start_kernel or the component roots); counts from part.
+__global__ __launch_bounds__(kThreads) void init_state_kernel(int64_t n, BfsState* st, const int64_t* part,
+                                                              int nparts, int64_t unexplored) {
+  __shared__ int64_t sh[kThreads / kWave + 1];
+  int64_t cnt = 0, edg = 0;
+  for (int i = threadIdx.x; i < nparts; i += kThreads) {
+    cnt += part[2 * i];
+    edg += part[2 * i + 1];
+  }
+  cnt = block_sum(cnt, sh);
+  edg = block_sum(edg, sh);
+  if (threadIdx.x == 0) {
+    st->f = cnt;
+    st->ef = edg;
+    st->unexplored = (unexplored < 0 ? st->unexplored : unexplored) - edg;
+    st->nbig = 0;
+    st->level = 0;
+    st->prev_bu = 0;
+    st->bottom_up = edg > st->unexplored / 14 && cnt > n / 256;
+    st->done = cnt == 0;
+    st->num_levels = cnt == 0 ? 0 : 1;
+  }
+}
+
+__global__ void copy_words_kernel(const uint32_t* src, uint32_t* dst, int64_t words) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// Starts the BFS from one root (either the argmax key or a given root).
+// The partials must be zero beforehand.
+__global__ void start_kernel(const int64_t* off, const unsigned long long* key, int64_t given_root, int32_t* L,
+                             uint32_t* vis, uint32_t* bm0, int64_t* part, int64_t* root_out) {
   int64_t r = given_root;
   if (r < 0) r = static_cast<int64_t>(0xFFFFFFFFull - (*key & 0xFFFFFFFFull));
   L[r] = 0;
   vis[r >> 5] |= 1u << (r & 31);
-  q[0] = static_cast<int32_t>(r);
-  ctr[0] = 1;
-  ctr[1] = row_deg(off, r);
+  bm0[r >> 5] |= 1u << (r & 31);
+  part[0] = 1;
+  part[1] = row_deg(off, r);
   *root_out = r;
-}
-
-__global__ void zero_ctr_kernel(int64_t* ctr) {
-  if (threadIdx.x < 4) ctr[threadIdx.x] = 0;
-}
-
-__global__ void frontier_deg_kernel(const int64_t* off, const int32_t* q, int64_t f, int64_t* fdeg) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < f;
-       i += (int64_t)gridDim.x * blockDim.x)
-    fdeg[i] = row_deg(off, q[i]);
-}
-
-// Block-aggregated append: the lanes with `take` set write `item` to the
-// queue q at consecutive slots reserved with one atomic per block on
-// ctr[slot]; ctr[1] accumulates their `weight` (edge counts).  Every thread
-// of the block must call it (it synchronises).
-struct AppendLds {
-  int64_t cnt[kThreads / kWave];
-  int64_t edg[kThreads / kWave];
-  int64_t base;
-};
-
-__device__ __forceinline__ void block_append(bool take, int32_t item, int64_t weight, int32_t* q, int64_t* ctr,
-                                             int slot, AppendLds& L) {
-  const int w = threadIdx.x / kWave;
-  const uint64_t m = __ballot(take);
-  const int64_t we = wave_sum(take ? weight : int64_t(0));
-  if (lane() == 0) {
-    L.cnt[w] = __popcll(m);
-    L.edg[w] = we;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t tc = 0, te = 0;
-    for (int i = 0; i < kThreads / kWave; ++i) {
-      const int64_t c = L.cnt[i];
-      L.cnt[i] = tc;
-      tc += c;
-      te += L.edg[i];
-    }
-    L.base = tc ? static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[slot]),
-                                                 static_cast<unsigned long long>(tc)))
-                : 0;
-    if (te) atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[1]), static_cast<unsigned long long>(te));
-  }
-  __syncthreads();
-  if (take && q) q[L.base + L.cnt[w] + __popcll(m & lanemask_lt())] = item;
-  __syncthreads();
-}
-
-// Top-down: flat edge index k in [0, ef) -> frontier slot i with
-// pre[i] <= k < pre[i+1].
-__global__ __launch_bounds__(kThreads) void topdown_kernel(const int64_t* off, const int32_t* cols,
-                                                           const int32_t* q, int64_t f,
-                                                           const int64_t* pre, int64_t ef,
-                                                           int32_t next_level, int32_t* L,
-                                                           uint32_t* vis, int32_t* qn, int64_t* ctr) {
-  __shared__ AppendLds lds;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k0 = blockIdx.x * (int64_t)blockDim.x; k0 < ef; k0 += stride) {
-    const int64_t k = k0 + threadIdx.x;
-    bool take = false;
-    int32_t w = 0;
-    int64_t dw = 0;
-    if (k < ef) {
-      int64_t i = upper_bound_dev(pre, 0, f + 1, k) - 1;
-      int32_t v = q[i];
-      w = cols[off[v] + (k - pre[i])];
-      uint32_t bit = 1u << (w & 31);
-      if (!(load_relaxed(&vis[w >> 5]) & bit)) {
-        uint32_t old = atomicOr(&vis[w >> 5], bit);
-        if (!(old & bit)) {
-          take = true;
-          L[w] = next_level;
-          dw = row_deg(off, w);
-        }
-      }
-    }
-    block_append(take, w, dw, qn, ctr, 0, lds);
-  }
-}
-
-// Frontier queue -> frontier bitmap (bits must be clear beforehand).
-__global__ void queue_to_bits_kernel(const int32_t* q, int64_t f, uint32_t* bits) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < f;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    int32_t v = q[i];
-    atomicOr(&bits[v >> 5], 1u << (v & 31));
-  }
-}
-
-// Bottom-up: every unvisited vertex scans its row for a frontier neighbour.
-__global__ __launch_bounds__(kThreads) void bottomup_kernel(const int64_t* off, const int32_t* cols,
-                                                            int64_t n, const uint32_t* fbits,
-                                                            int32_t next_level, int32_t* L,
-                                                            uint32_t* vis, uint32_t* nbits,
-                                                            int64_t* ctr) {
-  __shared__ AppendLds lds;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += stride) {
-    const int64_t v = v0 + threadIdx.x;
-    bool take = false;
-    int64_t dv = 0;
-    if (v < n && !(vis[v >> 5] & (1u << (v & 31)))) {
-      const int64_t b = off[v], e = off[v + 1];
-      for (int64_t j = b; j < e; ++j) {
-        int32_t w = cols[j];
-        if (fbits[w >> 5] & (1u << (w & 31))) {
-          take = true;
-          break;
-        }
-      }
-      if (take) {
-        L[v] = next_level;
-        dv = e - b;
-        atomicOr(&nbits[v >> 5], 1u << (v & 31));
-        atomicOr(&vis[v >> 5], 1u << (v & 31));
-      }
-    }
-    block_append(take, 0, dv, nullptr, ctr, 0, lds);
-  }
-}
-
-// Bitmap -> queue (order within the queue is irrelevant).
-__global__ void bits_to_queue_kernel(const uint32_t* bits, int64_t n, int32_t* q, int64_t* ctr) {
-  __shared__ AppendLds lds;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += stride) {
-    const int64_t v = v0 + threadIdx.x;
-    const bool take = v < n && (bits[v >> 5] & (1u << (v & 31)));
-    block_append(take, static_cast<int32_t>(v), 0, q, ctr, 2, lds);
-  }
 }
 
 // ------------------------------------------------- remaining components
@@ -240,26 +349,27 @@ __global__ void uf_hook_kernel(const int64_t* off, const int32_t* cols, int64_t 
   }
 }
 
-// Roots of the unreached components start the multi-source BFS at level 0;
-// isolated vertices get level 0 and need no expansion.
-__global__ void uf_roots_kernel(const int64_t* off, int64_t n, int32_t* parent, int32_t* L,
-                                uint32_t* vis, int32_t* q, int64_t* ctr) {
-  __shared__ AppendLds lds;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += stride) {
-    const int64_t v = v0 + threadIdx.x;
-    bool take = false;
-    int64_t dv = 0;
-    if (v < n && !(vis[v >> 5] & (1u << (v & 31)))) {
-      if (uf_find(parent, static_cast<int32_t>(v)) == v) {
-        L[v] = 0;
-        atomicOr(&vis[v >> 5], 1u << (v & 31));
-        dv = row_deg(off, v);
-        take = dv > 0;
-      }
+// Roots of the unreached components start the multi-source BFS at level 0
+// (bits in the level-0 frontier bitmap); isolated vertices get level 0 and
+// need no expansion.  Per-block counts go to part.
+__global__ __launch_bounds__(kThreads) void uf_roots_kernel(const int64_t* off, int64_t n, int32_t* parent,
+                                                            int32_t* L, uint32_t* vis, uint32_t* bm0,
+                                                            int64_t* part) {
+  __shared__ int64_t sh[kThreads / kWave + 1];
+  int64_t cnt = 0, edg = 0;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    if ((vis[v >> 5] >> (v & 31)) & 1u) continue;
+    if (uf_find(parent, static_cast<int32_t>(v)) != v) continue;
+    L[v] = 0;
+    atomicOr(&vis[v >> 5], 1u << (v & 31));
+    const int64_t d = row_deg(off, v);
+    if (d > 0) {
+      atomicOr(&bm0[v >> 5], 1u << (v & 31));
+      ++cnt;
+      edg += d;
     }
-    block_append(take, static_cast<int32_t>(v), dv, q, ctr, 0, lds);
   }
+  block_partial(cnt, edg, part, sh);
 }
 
 }  // namespace
@@ -268,97 +378,49 @@ BfsWs bfs_reserve(Carver& c, int64_t n) {
   BfsWs w;
   const int64_t words = (n + 31) / 32 + 1;
   w.vis = c.take<uint32_t>(words);
-  w.fbits = c.take<uint32_t>(words);
-  w.nbits = c.take<uint32_t>(words);
-  w.q0 = c.take<int32_t>(n + 1);
-  w.q1 = c.take<int32_t>(n + 1);
-  w.fdeg = c.take<int64_t>(n + 1);
-  w.pre = c.take<int64_t>(n + 2);
+  w.bms = c.take<uint32_t>(3 * words);
+  w.big = c.take<int32_t>(kBigCap);
   w.parent = c.take<int32_t>(n + 1);
-  w.ctr = c.take<int64_t>(8);
+  w.part = c.take<int64_t>(4 * kMaxParts);  // step and big kernels, (count, entries) each
+  w.st = c.take<char>(sizeof(BfsState));
   w.key = c.take<unsigned long long>(1);
   w.root = c.take<int64_t>(1);
-  w.scratch = c.take<char>(scan_ws_bytes(n + 1));
-  w.scratch_bytes = scan_ws_bytes(n + 1);
   w.comp0 = nullptr;
   return w;
 }
 
-// Runs one level-synchronous BFS from the queue currently in w.q0 (ctr[0] =
-// size, ctr[1] = its edges, already read into f / ef).  Returns the number
-// of levels (deepest level + 1).
-static int bfs_loop(const tc_csr* g, int32_t* L, BfsWs& w, int64_t f, int64_t ef,
-                    int64_t& unexplored_edges, int32_t* levels_out, hipStream_t s) {
-  const int64_t n = g->n;
-  const int64_t words = (n + 31) / 32 + 1;
-  int32_t* q = w.q0;
-  int32_t* qn = w.q1;
-  bool bottom_up = false;   // direction of the previous step
-  bool queue_valid = true;  // q holds the frontier (else only fbits does)
-  int32_t level = 0;
-  int64_t host[4];
-  const int64_t alpha = 14, beta = 24;
-  while (f > 0) {
-    unexplored_edges -= ef;
-    bool go_bottom_up;
-    if (!bottom_up) go_bottom_up = ef > unexplored_edges / alpha && f > n / 256;
-    else go_bottom_up = f >= n / beta;
-    zero_ctr_kernel<<<1, 64, 0, s>>>(w.ctr);
-    if (go_bottom_up) {
-      if (!bottom_up) {  // frontier bitmap from the queue
-        TC_TRY(fill_i32(reinterpret_cast<int32_t*>(w.fbits), 0, words, s));
-        queue_to_bits_kernel<<<grid_for(f, kThreads, 65536), kThreads, 0, s>>>(q, f, w.fbits);
-      }
-      TC_TRY(fill_i32(reinterpret_cast<int32_t*>(w.nbits), 0, words, s));
-      bottomup_kernel<<<grid_for(n, kThreads, 65536), kThreads, 0, s>>>(
-          g->row_offsets, g->cols, n, w.fbits, level + 1, L, w.vis, w.nbits, w.ctr);
-      TC_HIP(hipGetLastError());
-      // the new frontier's bitmap becomes the current one
-      uint32_t* t = w.fbits;
-      w.fbits = w.nbits;
-      w.nbits = t;
-      queue_valid = false;
-    } else {
-      if (!queue_valid) {  // rebuild the queue from the frontier bitmap
-        bits_to_queue_kernel<<<grid_for(n, kThreads, 65536), kThreads, 0, s>>>(w.fbits, n, q, w.ctr);
-        TC_HIP(hipGetLastError());
-        zero_ctr_kernel<<<1, 64, 0, s>>>(w.ctr);
-      }
-      frontier_deg_kernel<<<grid_for(f, kThreads, 65536), kThreads, 0, s>>>(g->row_offsets, q, f,
-                                                                              w.fdeg);
-      Carver sc(w.scratch);
-      TC_TRY(scan_exclusive<int64_t>(w.fdeg, w.pre, f, sc, s));
-      if (ef > 0) {
-        topdown_kernel<<<grid_for(ef, kThreads, 8 * num_cus() * 8), kThreads, 0, s>>>(
-            g->row_offsets, g->cols, q, f, w.pre, ef, level + 1, L, w.vis, qn, w.ctr);
-        TC_HIP(hipGetLastError());
-      }
-      int32_t* t = q;
-      q = qn;
-      qn = t;
-      queue_valid = true;
-    }
-    bottom_up = go_bottom_up;
-    TC_HIP(hipMemcpyAsync(host, w.ctr, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    TC_HIP(hipStreamSynchronize(s));
-    f = host[0];
-    ef = host[1];
-    if (f > 0) ++level;
-  }
-  if (q != w.q0) {  // keep the convention that the caller's next queue is q0
-    int32_t* t = w.q0;
-    w.q0 = w.q1;
-    w.q1 = t;
-  }
-  *levels_out = level + 1;
-  return TC_OK;
+namespace {
+
+unsigned step_grid() {
+  const int g = num_cus() * 8;
+  return static_cast<unsigned>(g < kMaxParts ? g : kMaxParts);
 }
 
-__global__ void copy_words_kernel(const uint32_t* src, uint32_t* dst, int64_t words) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
-       i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = src[i];
+// Runs the levels of the BFS whose state and level-0 bitmap are set, in
+// groups of kLevelsPerSync, until the frontier is empty.  Returns its level
+// count.
+int bfs_levels_loop(const tc_csr* g, int32_t* L, BfsWs& w, int32_t* levels_out, hipStream_t s) {
+  BfsState* st = reinterpret_cast<BfsState*>(w.st);
+  const unsigned gs = step_grid();
+  for (;;) {
+    for (int k = 0; k < kLevelsPerSync; ++k) {
+      step_kernel<<<gs, kThreads, 0, s>>>(g->row_offsets, g->cols, g->n, st, L, w.vis, w.bms, w.big, w.part);
+      big_kernel<<<gs, kThreads, 0, s>>>(g->row_offsets, g->cols, g->n, st, L, w.vis, w.bms, w.big,
+                                         w.part + 2 * gs);
+      decide_kernel<<<1, kThreads, 0, s>>>(g->n, st, w.part, static_cast<int>(2 * gs));
+    }
+    TC_HIP(hipGetLastError());
+    BfsState h;
+    TC_HIP(hipMemcpyAsync(&h, st, sizeof h, hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    if (h.done) {
+      *levels_out = h.num_levels;
+      return TC_OK;
+    }
+  }
 }
+
+}  // namespace
 
 int bfs_run(const tc_csr* g, int64_t root, int32_t* L, int32_t* num_levels, BfsWs& w,
             hipStream_t s, int32_t* first_levels) {
@@ -369,22 +431,23 @@ int bfs_run(const tc_csr* g, int64_t root, int32_t* L, int32_t* num_levels, BfsW
     return TC_OK;
   }
   const int64_t words = (n + 31) / 32 + 1;
+  BfsState* st = reinterpret_cast<BfsState*>(w.st);
+  const unsigned gs = step_grid();
   TC_TRY(fill_i32(L, -1, n, s));
   TC_TRY(fill_i32(reinterpret_cast<int32_t*>(w.vis), 0, words, s));
-  zero_ctr_kernel<<<1, 64, 0, s>>>(w.ctr);
+  TC_TRY(fill_i32(reinterpret_cast<int32_t*>(w.bms), 0, 3 * words, s));
   if (root < 0) {
     TC_TRY(fill_i64(reinterpret_cast<int64_t*>(w.key), 0, 1, s));
-    root_key_kernel<<<grid_for(n, kThreads, 4096), kThreads, 0, s>>>(g->row_offsets, n, w.key);
+    root_key_kernel<<<grid_for(n, kThreads, static_cast<unsigned>(num_cus() * 2)), kThreads, 0, s>>>(
+        g->row_offsets, n, w.key);
     TC_HIP(hipGetLastError());
   }
-  start_kernel<<<1, 1, 0, s>>>(g->row_offsets, w.key, root, L, w.vis, w.q0, w.ctr, w.root);
+  TC_TRY(fill_i64(w.part, 0, 4 * static_cast<int64_t>(gs), s));
+  start_kernel<<<1, 1, 0, s>>>(g->row_offsets, w.key, root, L, w.vis, w.bms, w.part, w.root);
+  init_state_kernel<<<1, kThreads, 0, s>>>(n, st, w.part, static_cast<int>(2 * gs), g->nnz);
   TC_HIP(hipGetLastError());
-  int64_t host[2];
-  TC_HIP(hipMemcpyAsync(host, w.ctr, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  TC_HIP(hipStreamSynchronize(s));
   int32_t lv0 = 0;
-  int64_t unexplored = g->nnz;
-  TC_TRY(bfs_loop(g, L, w, host[0], host[1], unexplored, &lv0, s));
+  TC_TRY(bfs_levels_loop(g, L, w, &lv0, s));
   if (first_levels) *first_levels = lv0;
   if (w.comp0) {
     copy_words_kernel<<<grid_for(words, kThreads, 16384), kThreads, 0, s>>>(w.vis, w.comp0, words);
@@ -394,16 +457,13 @@ int bfs_run(const tc_csr* g, int64_t root, int32_t* L, int32_t* num_levels, BfsW
   // union-find pass over the unreached vertices gives each component its
   // smallest id as root.
   uf_init_kernel<<<grid_for(n, kThreads, 65536), kThreads, 0, s>>>(w.parent, n);
-  uf_hook_kernel<<<grid_for(n, kThreads, 65536), kThreads, 0, s>>>(g->row_offsets, g->cols, n, w.vis,
-                                                                   w.parent);
-  zero_ctr_kernel<<<1, 64, 0, s>>>(w.ctr);
-  uf_roots_kernel<<<grid_for(n, kThreads, 65536), kThreads, 0, s>>>(g->row_offsets, n, w.parent, L,
-                                                                    w.vis, w.q0, w.ctr);
+  uf_hook_kernel<<<grid_for(n, kThreads, 65536), kThreads, 0, s>>>(g->row_offsets, g->cols, n, w.vis, w.parent);
+  TC_TRY(fill_i32(reinterpret_cast<int32_t*>(w.bms), 0, 3 * words, s));
+  uf_roots_kernel<<<gs, kThreads, 0, s>>>(g->row_offsets, n, w.parent, L, w.vis, w.bms, w.part);
+  init_state_kernel<<<1, kThreads, 0, s>>>(n, st, w.part, static_cast<int>(gs), -1);
   TC_HIP(hipGetLastError());
-  TC_HIP(hipMemcpyAsync(host, w.ctr, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  TC_HIP(hipStreamSynchronize(s));
   int32_t lv1 = 0;
-  if (host[0] > 0) TC_TRY(bfs_loop(g, L, w, host[0], host[1], unexplored, &lv1, s));
+  TC_TRY(bfs_levels_loop(g, L, w, &lv1, s));
   if (num_levels) *num_levels = lv0 > lv1 ? lv0 : lv1;
   return TC_OK;
 }

@@ -83,11 +83,10 @@ __device__ __forceinline__ int choose_bin(int64_t R, int P, int64_t D, bool* bit
 }
 
 enum Acc {
-  kAccT = 0, kAccElems = 1, kAccLight = 2, kAccBuild = 3, kAccRecs = 4, kAccItems = 5, kAccHeavyElems = 6,
-  kAccH = 7, kAccBinCount = 8, kAccBinOff = 12, kAccBinCur = 16, kAccBinNext = 20, kAccBinElems = 24,
-  kAccLightRecs = 28
+  kAccT = 0, kAccElems = 1, kAccBuild = 3, kAccRecs = 4, kAccItems = 5, kAccHeavyElems = 6,
+  kAccH = 7, kAccBinCount = 8, kAccBinOff = 12, kAccBinCur = 16, kAccBinNext = 20, kAccBinElems = 24
 };
-constexpr int kAccSlots = 29;
+constexpr int kAccSlots = 28;
 constexpr int64_t kElemChunk = 65536;  // elements per work item (target; a power of two)
 constexpr int kElemChunkLog = 16;
 static_assert(kElemChunk == (int64_t(1) << kElemChunkLog), "kElemChunk must be 2^kElemChunkLog");
@@ -827,13 +826,13 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
 }
 
 
-__global__ void finish_kernel(const unsigned long long* acc, const int64_t* so, int64_t n, int64_t* triangles,
-                              int64_t* h_count, int64_t* stats) {
+__global__ void finish_kernel(const unsigned long long* acc, const int64_t* so, int64_t n, const int64_t* lpre,
+                              int64_t nchunk_cap, int64_t* triangles, int64_t* h_count, int64_t* stats) {
   *triangles = static_cast<int64_t>(acc[kAccT]);
   if (h_count) *h_count = static_cast<int64_t>(acc[kAccH]);
   stats[2] = static_cast<int64_t>(acc[kAccH]);
   stats[4] = static_cast<int64_t>(acc[kAccElems] + acc[kAccHeavyElems]);
-  stats[5] = static_cast<int64_t>(acc[kAccLightRecs]);
+  stats[5] = n > 0 ? lpre[nchunk_cap] : 0;
   stats[6] = static_cast<int64_t>(acc[kAccItems]);
   stats[7] = static_cast<int64_t>(acc[kAccRecs]);
   stats[8] = static_cast<int64_t>(acc[kAccHeavyElems]);
@@ -959,7 +958,7 @@ int count_run(const CountArgs& a, CountWs& w, int64_t* triangles, int64_t* h_cou
       else TC_TRY((launch_all<false, false>(a, w, s)));
     }
   }
-  finish_kernel<<<1, 1, 0, s>>>(w.acc, w.so, n, triangles, h_count, w.stats);
+  finish_kernel<<<1, 1, 0, s>>>(w.acc, w.so, n, w.lpre, w.nchunk_cap, triangles, h_count, w.stats);
   TC_HIP(hipGetLastError());
   return TC_OK;
 }

@@ -34,6 +34,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kShort = 32;
 constexpr int kSeg = 2048;
+constexpr int kRounds = 4;  // 64-entry rounds of a long row loaded at once
 
 // ---------------------------------------------------------- layouts
 // A layout maps output row i to an input row and classifies its entries:
@@ -95,7 +96,9 @@ struct RelabelLayout {
   }
 };
 
-// Rows of at most kShort entries: one thread, two passes (count, scatter).
+// Rows of at most kShort entries: one thread; the row and the classes of its
+// entries are loaded into registers first (all gathers in flight at once),
+// then counted and scattered.
 template <class Lay>
 __global__ __launch_bounds__(kThreads) void lay_short_kernel(Lay lay, const int32_t* cols, int64_t n, int32_t* out,
                                                              VMeta* meta, int32_t* nseg) {
@@ -107,20 +110,26 @@ __global__ __launch_bounds__(kThreads) void lay_short_kernel(Lay lay, const int3
       continue;
     }
     nseg[i] = 0;
+    int32_t wv[kShort];
+#pragma unroll
+    for (int q = 0; q < kShort; ++q) wv[q] = q < deg ? cols[c.ib + q] : 0;
+    int32_t vv[kShort];
+    int kc[kShort];
+#pragma unroll
+    for (int q = 0; q < kShort; ++q) kc[q] = q < deg ? lay.cls(c, wv[q], vv[q]) : 3;
     int up = 0, same = 0, slt = 0;
-    for (int64_t j = c.ib; j < c.ie; ++j) {
-      int32_t v;
-      const int k = lay.cls(c, cols[j], v);
-      up += k == 0;
-      same += k == 1;
-      slt += (k == 1) & (v < c.self);
+#pragma unroll
+    for (int q = 0; q < kShort; ++q) {
+      up += kc[q] == 0;
+      same += kc[q] == 1;
+      slt += (kc[q] == 1) & (vv[q] < c.self);
     }
     int pu = 0, ps = up, pd = up + same;
-    for (int64_t j = c.ib; j < c.ie; ++j) {
-      int32_t v;
-      const int k = lay.cls(c, cols[j], v);
-      const int pos = k == 0 ? pu++ : (k == 1 ? ps++ : pd++);
-      out[c.ob + pos] = v;
+#pragma unroll
+    for (int q = 0; q < kShort; ++q) {
+      if (kc[q] == 3) continue;
+      const int pos = kc[q] == 0 ? pu++ : (kc[q] == 1 ? ps++ : pd++);
+      out[c.ob + pos] = vv[q];
     }
     meta[i] = VMeta{c.ob, up, up + slt, up + same, deg, {c.key, 0}};
   }
@@ -149,14 +158,22 @@ __global__ __launch_bounds__(kThreads) void lay_seg_count_kernel(Lay lay, const 
     const int64_t b = c.ib + s * kSeg;
     const int64_t e = min(c.ie, b + kSeg);
     int up = 0, same = 0, slt = 0;
-    for (int64_t j0 = b; j0 < e; j0 += kWave) {
-      const int64_t j = j0 + lane();
-      int k = 3;
-      int32_t v = 0;
-      if (j < e) k = lay.cls(c, cols[j], v);
-      up += __popcll(__ballot(k == 0));
-      same += __popcll(__ballot(k == 1));
-      slt += __popcll(__ballot((k == 1) & (v < c.self)));
+    for (int64_t j0 = b; j0 < e; j0 += kRounds * kWave) {
+      int32_t wv[kRounds];
+#pragma unroll
+      for (int u = 0; u < kRounds; ++u) {
+        const int64_t j = j0 + u * kWave + lane();
+        wv[u] = j < e ? cols[j] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < kRounds; ++u) {
+        int k = 3;
+        int32_t v = 0;
+        if (wv[u] >= 0) k = lay.cls(c, wv[u], v);
+        up += __popcll(__ballot(k == 0));
+        same += __popcll(__ballot(k == 1));
+        slt += __popcll(__ballot((k == 1) & (v < c.self)));
+      }
     }
     if (lane() == 0) {
       seg_cnt[3 * sg + 0] = up;
@@ -208,18 +225,28 @@ __global__ __launch_bounds__(kThreads) void lay_seg_write_kernel(Lay lay, const 
     int64_t pu = seg_pre[3 * sg + 0];
     int64_t ps = m.up + seg_pre[3 * sg + 1];
     int64_t pd = m.sfe + (s * kSeg - seg_pre[3 * sg + 0] - seg_pre[3 * sg + 1]);
-    for (int64_t j0 = b; j0 < e; j0 += kWave) {
-      const int64_t j = j0 + lane();
-      int k = 3;
-      int32_t v = 0;
-      if (j < e) k = lay.cls(c, cols[j], v);
-      const uint64_t mu = __ballot(k == 0), ms = __ballot(k == 1), md = __ballot(k == 2);
-      if (k == 0) out[c.ob + pu + __popcll(mu & lt)] = v;
-      else if (k == 1) out[c.ob + ps + __popcll(ms & lt)] = v;
-      else if (k == 2) out[c.ob + pd + __popcll(md & lt)] = v;
-      pu += __popcll(mu);
-      ps += __popcll(ms);
-      pd += __popcll(md);
+    for (int64_t j0 = b; j0 < e; j0 += kRounds * kWave) {
+      int32_t wv[kRounds];
+#pragma unroll
+      for (int u = 0; u < kRounds; ++u) {
+        const int64_t j = j0 + u * kWave + lane();
+        wv[u] = j < e ? cols[j] : -1;
+      }
+      int32_t vv[kRounds];
+      int kc[kRounds];
+#pragma unroll
+      for (int u = 0; u < kRounds; ++u) kc[u] = wv[u] >= 0 ? lay.cls(c, wv[u], vv[u]) : 3;
+#pragma unroll
+      for (int u = 0; u < kRounds; ++u) {
+        const int k = kc[u];
+        const uint64_t mu = __ballot(k == 0), ms = __ballot(k == 1), md = __ballot(k == 2);
+        if (k == 0) out[c.ob + pu + __popcll(mu & lt)] = vv[u];
+        else if (k == 1) out[c.ob + ps + __popcll(ms & lt)] = vv[u];
+        else if (k == 2) out[c.ob + pd + __popcll(md & lt)] = vv[u];
+        pu += __popcll(mu);
+        ps += __popcll(ms);
+        pd += __popcll(md);
+      }
     }
   }
 }
@@ -364,7 +391,9 @@ int relabel_run(const tc_csr* g, const int32_t* L, const uint32_t* comp0, int32_
   if (n == 0) return TC_OK;
   const unsigned gv = grid_for(n, kThreads, 16384);
   TC_TRY(fill_i32(w.lstart_cnt, 0, nvl + 1, s));
-  vl_hist_kernel<<<gv, kThreads, 0, s>>>(L, comp0, d0, n, nvl, w.lstart_cnt);
+  // few blocks: each adds its LDS histogram to the shared counts once
+  vl_hist_kernel<<<grid_for(n, kThreads, static_cast<unsigned>(num_cus() * 2)), kThreads, 0, s>>>(
+      L, comp0, d0, n, nvl, w.lstart_cnt);
   TC_HIP(hipGetLastError());
   {
     Carver sc(w.scratch);

@@ -12,19 +12,14 @@ void prof_enable(int on);
 
 // ---------------------------------------------------------------- BFS
 struct BfsWs {
-  uint32_t* vis;
-  uint32_t* fbits;
-  uint32_t* nbits;
-  int32_t* q0;
-  int32_t* q1;
-  int64_t* fdeg;
-  int64_t* pre;
-  int32_t* parent;
-  int64_t* ctr;
+  uint32_t* vis;     // visited bitmap [n/32 + 1]
+  uint32_t* bms;     // three rotating frontier bitmaps
+  int32_t* big;      // long frontier rows of the current level
+  int32_t* parent;   // union-find over the unreached vertices
+  int64_t* part;     // per-block (count, entries) of the last step
+  char* st;          // device state of the running BFS
   unsigned long long* key;
   int64_t* root;
-  char* scratch;
-  size_t scratch_bytes;
   uint32_t* comp0;  // optional (caller-owned, n/32+1 words): r0's component
 };
 BfsWs bfs_reserve(Carver& c, int64_t n);
