@@ -216,6 +216,126 @@ def bench_serving(args):
     }
 
 
+COUNT_SRC = os.path.join(ROOT, "paper_2210_00389_amd", "csrc", "count.hip")
+
+
+def source_sha(path=COUNT_SRC):
+    import hashlib
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def traffic_record(scale):
+    """Counter-measured HBM bytes per heavy-stage launch, from the committed
+    summary of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a
+    1 GiB copy; None when missing or taken on another kernel source."""
+    path = os.path.join(ROOT, "profiles", f"heavy_rmat{scale}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != source_sha():
+        return None
+    return rec
+
+
+def bench_pmc(args):
+    """Program run under rocprofv3 --pmc: a few counts of the R-MAT graph,
+    then one plain 1 GiB device copy for the counter calibration."""
+    import torch
+    import graphgen
+    import paper_2210_00389_amd as tc
+    g = graphgen.rmat(args.scale, args.edge_factor, seed=args.seed)
+    G = tc.from_host_pairs(g.n, g.src, g.dst)
+    ws = tc.Workspace(torch.device("cuda"))
+    for i in range(args.warmup + args.steps):
+        r = tc.count(G, ws=ws)
+        torch.cuda.synchronize()
+        log(f"[pmc] count {i}: T={r.T}")
+    x = torch.empty(256 * 2**20, dtype=torch.int32, device="cuda").fill_(1)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    log("[pmc] copy of 1 GiB done")
+    print(json.dumps({"pmc_program": "done", "scale": args.scale, "counted_steps": args.warmup + args.steps,
+                      "copy_bytes": 2**30}), flush=True)
+
+
+def _csv_rows(d, name):
+    import csv
+    import glob
+    out = []
+    for f in glob.glob(os.path.join(d, "**", f"*{name}"), recursive=True):
+        out += list(csv.DictReader(open(f)))
+    return out
+
+
+def summarize(args):
+    """Turn rocprofv3 CSV output into the short text summaries kept under
+    profiles/ (kernel statistics, heavy-stage spans, counter traffic)."""
+    out_md = [f"# {args.title}", "", "Command:", "", "```", args.cmd, "```", ""]
+    rec = {}
+    if args.trace_dir:
+        stats = _csv_rows(args.trace_dir, "kernel_stats.csv")
+        stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+        out_md += ["Top kernels (rocprofv3 --kernel-trace --stats):", "",
+                   "| kernel | calls | total ms | average us | share |", "|---|---|---|---|---|"]
+        for r in stats[:16]:
+            out_md.append(f"| {r['Name'][:60]} | {r['Calls']} | {float(r['TotalDurationNs'])/1e6:.3f} | "
+                          f"{float(r['AverageNs'])/1e3:.1f} | {float(r['Percentage']):.1f}% |")
+        trace = sorted(_csv_rows(args.trace_dir, "kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
+        heavy = [r for r in trace if "heavy_kernel" in r["Kernel_Name"]]
+        spans = []
+        for i in range(0, len(heavy) - 3, 4):  # the four bins of one call run side by side
+            grp = heavy[i:i + 4]
+            spans.append((max(int(r["End_Timestamp"]) for r in grp) - min(int(r["Start_Timestamp"]) for r in grp)) / 1e6)
+        if spans:
+            out_md += ["", f"Heavy stage (four bin kernels launched side by side) span per call, ms: "
+                           f"{', '.join(f'{x:.3f}' for x in spans)}; mean {statistics.mean(spans):.3f}", ""]
+            rec["heavy_span_ms"] = spans
+    if args.fetch_dir and args.write_dir:
+        def per_dispatch(d, counter):
+            rows = _csv_rows(d, "counter_collection.csv")
+            acc = {}
+            for r in rows:
+                if r["Counter_Name"] != counter:
+                    continue
+                k = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+                acc[k] = acc.get(k, 0.0) + float(r["Counter_Value"])
+            return sorted(acc.items())
+        fetch = per_dispatch(args.fetch_dir, "FETCH_SIZE")
+        write = per_dispatch(args.write_dir, "WRITE_SIZE")
+        copy_f = [v for (d, k), v in fetch if "copy" in k.lower()]
+        copy_w = [v for (d, k), v in write if "copy" in k.lower()]
+        hf = [v for (d, k), v in fetch if "heavy_kernel" in k]
+        hw = [v for (d, k), v in write if "heavy_kernel" in k]
+        gib_kib = 2**30 / 1024
+        ff = gib_kib / max(copy_f) if copy_f else None
+        wf = gib_kib / max(copy_w) if copy_w else None
+        steps = len(hf) // 4
+        fetch_launch = [sum(hf[4 * i:4 * i + 4]) * 1024 * ff for i in range(steps)] if ff else []
+        write_launch = [sum(hw[4 * i:4 * i + 4]) * 1024 * wf for i in range(len(hw) // 4)] if wf else []
+        rec.update({"source_sha256": source_sha(), "fetch_factor": ff, "write_factor": wf,
+                    "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
+                    "fetch_bytes_per_launch": fetch_launch, "write_bytes_per_launch": write_launch,
+                    "traffic_bytes": (statistics.mean(fetch_launch[1:] or fetch_launch) +
+                                      statistics.mean(write_launch[1:] or write_launch))
+                    if fetch_launch and write_launch else None})
+        out_md += ["Counter traffic of the heavy stage (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, "
+                   "KiB per dispatch summed over the four bin kernels of a call):", "",
+                   f"- calibration: a 1 GiB device copy reads FETCH_SIZE {copy_f} KiB, WRITE_SIZE {copy_w} KiB "
+                   f"-> factors {ff:.3f} (fetch), {wf:.3f} (write)" if ff and wf else "- calibration missing",
+                   f"- fetch per call (scaled), GB: {', '.join(f'{x/1e9:.3f}' for x in fetch_launch)}",
+                   f"- write per call (scaled), GB: {', '.join(f'{x/1e9:.4f}' for x in write_launch)}",
+                   f"- traffic per call (mean after the first): {rec['traffic_bytes']/1e9:.3f} GB"
+                   if rec.get("traffic_bytes") else "", ""]
+    with open(args.out + ".md", "w") as f:
+        f.write("\n".join(out_md) + "\n")
+    if args.fetch_dir:
+        with open(args.out + ".json", "w") as f:
+            json.dump(rec, f, indent=1)
+    print(json.dumps({"summary": args.out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,7 +348,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--json-out", default=None)
-    ap.add_argument("--workload", choices=("rmat", "batch", "serving"), default="rmat")
+    ap.add_argument("--workload", choices=("rmat", "batch", "serving", "pmc"), default="rmat")
+    ap.add_argument("--summarize", action="store_true", help="summarise rocprofv3 output into --out(.md/.json)")
+    ap.add_argument("--trace-dir", default=None)
+    ap.add_argument("--fetch-dir", default=None)
+    ap.add_argument("--write-dir", default=None)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--title", default="rocprofv3 summary")
+    ap.add_argument("--cmd", default="")
     ap.add_argument("--pool", type=int, default=32, help="serving: graphs in the request pool")
     ap.add_argument("--rates", type=float, nargs="+", default=[50, 200, 1000, 2000])
     ap.add_argument("--requests", type=int, default=500, help="serving: requests per rate")
@@ -238,6 +365,9 @@ def main():
     ap.add_argument("--serve-budget-frac", type=float, default=0.5)
     args = ap.parse_args()
 
+    if args.summarize:
+        summarize(args)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -250,6 +380,9 @@ def main():
     import paper_2210_00389_amd as tc
 
     torch.cuda.set_device(0)
+    if args.workload == "pmc":
+        bench_pmc(args)
+        return
     if args.workload != "rmat":
         out = bench_batch(args) if args.workload == "batch" else bench_serving(args)
         line = json.dumps(out)
@@ -311,8 +444,10 @@ def main():
     roof = None
     if dom_bytes is not None:
         ach = dom_bytes / (stage_avg[dom] / 1000.0) / 1e9
+        tr = traffic_record(args.scale) if dom == "heavy" else None
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": int(tr["traffic_bytes"]) if tr and tr.get("traffic_bytes") else None,
                 "algorithmic_bytes_per_launch": int(dom_bytes), "avg_launch_ms": round(stage_avg[dom], 4)}
     stage_roofs = {}
     for k, v in stage_avg.items():
