@@ -55,6 +55,7 @@ constexpr int kBig = 4096;         // frontier rows above this length are expand
 constexpr int kBigCap = 4096;      // listed rows per level (more: expanded by their thread)
 constexpr int kMaxParts = 4096;    // blocks of the step kernels (partials per kernel)
 constexpr int kLevelsPerSync = 8;  // levels launched between two reads of the state
+constexpr int kLevelsPerSyncRest = 4;
 
 // Device-side state of one BFS (see BfsWs::st).
 struct BfsState {
@@ -399,11 +400,11 @@ unsigned step_grid() {
 // Runs the levels of the BFS whose state and level-0 bitmap are set, in
 // groups of kLevelsPerSync, until the frontier is empty.  Returns its level
 // count.
-int bfs_levels_loop(const tc_csr* g, int32_t* L, BfsWs& w, int32_t* levels_out, hipStream_t s) {
+int bfs_levels_loop(const tc_csr* g, int32_t* L, BfsWs& w, int group, int32_t* levels_out, hipStream_t s) {
   BfsState* st = reinterpret_cast<BfsState*>(w.st);
   const unsigned gs = step_grid();
   for (;;) {
-    for (int k = 0; k < kLevelsPerSync; ++k) {
+    for (int k = 0; k < group; ++k) {
       step_kernel<<<gs, kThreads, 0, s>>>(g->row_offsets, g->cols, g->n, st, L, w.vis, w.bms, w.big, w.part);
       big_kernel<<<gs, kThreads, 0, s>>>(g->row_offsets, g->cols, g->n, st, L, w.vis, w.bms, w.big,
                                          w.part + 2 * gs);
@@ -447,7 +448,7 @@ int bfs_run(const tc_csr* g, int64_t root, int32_t* L, int32_t* num_levels, BfsW
   init_state_kernel<<<1, kThreads, 0, s>>>(n, st, w.part, static_cast<int>(2 * gs), g->nnz);
   TC_HIP(hipGetLastError());
   int32_t lv0 = 0;
-  TC_TRY(bfs_levels_loop(g, L, w, &lv0, s));
+  TC_TRY(bfs_levels_loop(g, L, w, kLevelsPerSync, &lv0, s));
   if (first_levels) *first_levels = lv0;
   if (w.comp0) {
     copy_words_kernel<<<grid_for(words, kThreads, 16384), kThreads, 0, s>>>(w.vis, w.comp0, words);
@@ -463,7 +464,8 @@ int bfs_run(const tc_csr* g, int64_t root, int32_t* L, int32_t* num_levels, BfsW
   init_state_kernel<<<1, kThreads, 0, s>>>(n, st, w.part, static_cast<int>(gs), -1);
   TC_HIP(hipGetLastError());
   int32_t lv1 = 0;
-  TC_TRY(bfs_levels_loop(g, L, w, &lv1, s));
+  // the remaining components are usually shallow: shorter groups
+  TC_TRY(bfs_levels_loop(g, L, w, kLevelsPerSyncRest, &lv1, s));
   if (num_levels) *num_levels = lv0 > lv1 ? lv0 : lv1;
   return TC_OK;
 }
