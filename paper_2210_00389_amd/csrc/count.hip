@@ -209,7 +209,8 @@ __global__ __launch_bounds__(kThreads) void plan_kernel(const int32_t* lc, const
 // stream records (from the front of the record arrays), tasks of light
 // anchors go to the light list (from the back), merged by light_kernel.
 constexpr int kResThreads = 256;
-constexpr int kResChunk = kResThreads;
+constexpr int kResPer = 2;  // descriptors per thread, resolved in lockstep
+constexpr int kResChunk = kResThreads * kResPer;
 constexpr int kResRecs = 2 * kResChunk;
 constexpr int kResSpan = 2 * kResChunk;  // vertex offsets staged in LDS
 
@@ -219,36 +220,93 @@ struct Task {
   int32_t oth;  // vertex whose list is streamed
 };
 
-// Tasks of descriptor k of vertex x (x is the anchor of every returned task).
+enum DescKind { kDown = 0, kFwd = 1, kBwd = 2, kNone = 3 };
+
+// Tasks of kResPer descriptors (vertex x[j], index k[j] in its descriptor
+// space) with x[j] as the anchor of every returned task.  The steps run in
+// lockstep over the descriptors so that their dependent loads (neighbour
+// id, its record, the search of x in Hfwd(u)) are in flight together.
 template <bool kCover>
-__device__ __forceinline__ void describe(const int32_t* lc, const VMeta* meta, int32_t x, const VMeta& mx, int k,
-                                         Task& ta, Task& tb) {
-  ta = Task{0, 0, 0};
-  tb = Task{0, 0, 0};
-  const int hf = mx.sfe - mx.hfb;
-  const int nB = (kCover && hf > 0) ? mx.deg - mx.sfe : 0;
-  if (k < nB) {  // down class: stream Up(w)
-    const int32_t w = lc[mx.begin + mx.sfe + k];
-    const VMeta mw = meta[w];
-    if (mw.up > 0) ta = Task{mw.begin, mw.up, w};
-  } else if ((k -= nB) < hf) {  // forward cover edge (x, v)
-    const int32_t v = lc[mx.begin + mx.hfb + k];
-    const VMeta mv = meta[v];
-    if (kCover && mv.up > 0 && mv.up <= mx.up) ta = Task{mv.begin, mv.up | kFlagUp, v};
-    const int a = hf - k - 1, b = mv.sfe - mv.hfb;
-    if (a > 0 && b > 0 && b < a) tb = Task{mv.begin + mv.hfb, b, v};
-  } else {  // backward cover edge (u, x), u < x
-    k -= hf;
-    const int32_t u = lc[mx.begin + mx.up + k];
-    const VMeta mu = meta[u];
-    if (kCover && mu.up > 0 && mu.up < mx.up) ta = Task{mu.begin, mu.up | kFlagUp, u};
-    const int hu = mu.sfe - mu.hfb;
-    if (hf > 0 && hu > 0) {
-      // a = |Hfwd(u) ∩ (x, inf)|; x itself is in Hfwd(u)
-      const int64_t e = mu.begin + mu.sfe;
-      const int64_t pos = lower_bound_dev(lc, mu.begin + mu.hfb, e, x);
-      const int a = static_cast<int>(e - pos) - 1;
-      if (a > 0 && hf >= a) tb = Task{pos + 1, a, u};
+__device__ __forceinline__ void describe_all(const int32_t* lc, const VMeta* meta, const int32_t* x,
+                                             const VMeta* mx, const int* kin, Task* ta, Task* tb) {
+  int kind[kResPer], k[kResPer];
+  int32_t nb[kResPer];
+#pragma unroll
+  for (int j = 0; j < kResPer; ++j) {
+    ta[j] = Task{0, 0, 0};
+    tb[j] = Task{0, 0, 0};
+    kind[j] = kNone;
+    k[j] = kin[j];
+    if (k[j] < 0) continue;
+    const int hf = mx[j].sfe - mx[j].hfb;
+    const int nB = (kCover && hf > 0) ? mx[j].deg - mx[j].sfe : 0;
+    int64_t pos;
+    if (k[j] < nB) {
+      kind[j] = kDown;
+      pos = mx[j].begin + mx[j].sfe + k[j];
+    } else if (k[j] - nB < hf) {
+      kind[j] = kFwd;
+      k[j] -= nB;
+      pos = mx[j].begin + mx[j].hfb + k[j];
+    } else {
+      kind[j] = kBwd;
+      k[j] -= nB + hf;
+      pos = mx[j].begin + mx[j].up + k[j];
+    }
+    nb[j] = lc[pos];
+  }
+  VMeta mo[kResPer];
+#pragma unroll
+  for (int j = 0; j < kResPer; ++j)
+    if (kind[j] != kNone) mo[j] = meta[nb[j]];
+  // backward same class needs a = |Hfwd(u) ∩ (x, inf)|: joint lower bound
+  int64_t lo[kResPer], hi[kResPer];
+  bool srch[kResPer];
+#pragma unroll
+  for (int j = 0; j < kResPer; ++j) {
+    srch[j] = false;
+    lo[j] = hi[j] = 0;
+    if (kind[j] == kBwd && mx[j].sfe > mx[j].hfb && mo[j].sfe > mo[j].hfb) {
+      srch[j] = true;
+      lo[j] = mo[j].begin + mo[j].hfb;
+      hi[j] = mo[j].begin + mo[j].sfe;
+    }
+  }
+  for (;;) {
+    bool any = false;
+    int32_t v[kResPer];
+    int64_t mid[kResPer];
+#pragma unroll
+    for (int j = 0; j < kResPer; ++j) {
+      mid[j] = lo[j] + ((hi[j] - lo[j]) >> 1);
+      v[j] = (srch[j] && lo[j] < hi[j]) ? lc[mid[j]] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < kResPer; ++j) {
+      if (!(srch[j] && lo[j] < hi[j])) continue;
+      if (v[j] < x[j]) lo[j] = mid[j] + 1;
+      else hi[j] = mid[j];
+      any |= lo[j] < hi[j];
+    }
+    if (!any) break;
+  }
+#pragma unroll
+  for (int j = 0; j < kResPer; ++j) {
+    const VMeta& m = mx[j];
+    const VMeta& o = mo[j];
+    const int hf = m.sfe - m.hfb;
+    if (kind[j] == kDown) {  // stream Up(w)
+      if (o.up > 0) ta[j] = Task{o.begin, o.up, nb[j]};
+    } else if (kind[j] == kFwd) {  // forward cover edge (x, v)
+      if (kCover && o.up > 0 && o.up <= m.up) ta[j] = Task{o.begin, o.up | kFlagUp, nb[j]};
+      const int a = hf - k[j] - 1, b = o.sfe - o.hfb;
+      if (a > 0 && b > 0 && b < a) tb[j] = Task{o.begin + o.hfb, b, nb[j]};
+    } else if (kind[j] == kBwd) {  // backward cover edge (u, x), u < x
+      if (kCover && o.up > 0 && o.up < m.up) ta[j] = Task{o.begin, o.up | kFlagUp, nb[j]};
+      if (srch[j]) {
+        const int a = static_cast<int>(o.begin + o.sfe - lo[j]) - 1;  // lo = position of x
+        if (a > 0 && hf >= a) tb[j] = Task{lo[j] + 1, a, nb[j]};
+      }
     }
   }
 }
@@ -270,12 +328,13 @@ __global__ void chunk_start_kernel(const int64_t* so, int64_t n, int32_t* cx0) {
 // records of heavy anchors from the front, tasks of light anchors from the
 // back, its work items at the same offsets of items_raw; ccnt[c] = (heavy
 // records, light tasks, items).  No counter is shared between blocks.
+// Thread t takes descriptors d0 + t + j * kResThreads; records are placed in
+// descriptor order (j-major).
 template <bool kCover>
 __global__ __launch_bounds__(kResThreads) void resolve_kernel(
     const int32_t* lc, const VMeta* meta, const uint8_t* vinfo, const int64_t* so, const int32_t* cx0, int64_t n,
     int64_t* sbeg, int32_t* slen, int32_t* soth, int32_t* sx, int4* items_raw, int4* ccnt) {
   __shared__ int64_t sh[kResThreads / kWave + 1];
-  __shared__ int32_t shi[kResThreads / kWave + 1];
   __shared__ int64_t s_so[kResSpan];
   __shared__ int32_t s_x[kResRecs];
   __shared__ int64_t s_pre[kResRecs];
@@ -292,11 +351,16 @@ __global__ __launch_bounds__(kResThreads) void resolve_kernel(
     if (staged)
       for (int i = tid; i < span; i += kResThreads) s_so[i] = so[xa + i];
     __syncthreads();
-    Task ta{0, 0, 0}, tb{0, 0, 0};
-    int32_t xi = 0;
-    bool heavy = false;
-    const int64_t d = d0 + tid;
-    if (d < d1) {
+    int32_t xi[kResPer];
+    int kk[kResPer];
+    bool heavy[kResPer];
+#pragma unroll
+    for (int j = 0; j < kResPer; ++j) {
+      const int64_t d = d0 + tid + j * kResThreads;
+      xi[j] = 0;
+      kk[j] = -1;
+      heavy[j] = false;
+      if (d >= d1) continue;
       int64_t x, xb;
       if (staged) {
         int lo = 0, hi = static_cast<int>(span);  // first index with s_so > d
@@ -311,68 +375,115 @@ __global__ __launch_bounds__(kResThreads) void resolve_kernel(
         x = upper_bound_dev(so, xa, xz + 2, d) - 1;
         xb = so[x];
       }
-      xi = static_cast<int32_t>(x);
-      const VMeta mx = meta[x];
-      heavy = (vinfo[x] & kViHeavy) != 0;
-      describe<kCover>(lc, meta, xi, mx, static_cast<int>(d - xb), ta, tb);
+      xi[j] = static_cast<int32_t>(x);
+      kk[j] = static_cast<int>(d - xb);
     }
-    const int nl = heavy ? 0 : (ta.len != 0) + (tb.len != 0);
-    const int nh = heavy ? (ta.len != 0) + (tb.len != 0) : 0;
-    int32_t ltot, htot;
-    const int lslot = block_excl_scan(nl, shi, &ltot);
-    const int hslot0 = block_excl_scan(nh, shi, &htot);
-    const int64_t he = heavy ? static_cast<int64_t>(ta.len & kLenMask) + (tb.len & kLenMask) : 0;
-    int64_t etot;
-    int64_t epre = block_excl_scan(he, sh, &etot);
+    VMeta mx[kResPer];
+#pragma unroll
+    for (int j = 0; j < kResPer; ++j) {
+      if (kk[j] < 0) continue;
+      mx[j] = meta[xi[j]];
+      heavy[j] = (vinfo[xi[j]] & kViHeavy) != 0;
+    }
+    Task ta[kResPer], tb[kResPer];
+    describe_all<kCover>(lc, meta, xi, mx, kk, ta, tb);
+    // ---- counts: light tasks, heavy records, heavy elements (per j, j-major)
+    int64_t nl = 0, nh = 0;
+    int64_t he[kResPer];
+#pragma unroll
+    for (int j = 0; j < kResPer; ++j) {
+      const int64_t cnt = (ta[j].len != 0) + (tb[j].len != 0);
+      he[j] = heavy[j] ? static_cast<int64_t>(ta[j].len & kLenMask) + (tb[j].len & kLenMask) : 0;
+      nl |= (heavy[j] ? 0 : cnt) << (16 * j);  // kResPer * 16 bits: counts <= 2 per descriptor
+      nh |= (heavy[j] ? cnt : 0) << (16 * j);
+    }
+    int64_t ltot_p, htot_p;
+    const int64_t lpre_p = block_excl_scan(nl, sh, &ltot_p);
+    const int64_t hpre_p = block_excl_scan(nh, sh, &htot_p);
+    int32_t lslot[kResPer], hslot[kResPer];
+    int32_t ltot = 0, htot = 0;
+#pragma unroll
+    for (int j = 0; j < kResPer; ++j) {
+      // slots of descriptor group j start after all groups before it
+      lslot[j] = ltot + static_cast<int32_t>((lpre_p >> (16 * j)) & 0xFFFF);
+      hslot[j] = htot + static_cast<int32_t>((hpre_p >> (16 * j)) & 0xFFFF);
+      ltot += static_cast<int32_t>((ltot_p >> (16 * j)) & 0xFFFF);
+      htot += static_cast<int32_t>((htot_p >> (16 * j)) & 0xFFFF);
+    }
+    int64_t ebase = 0;
+    int64_t epre[kResPer];
+#pragma unroll
+    for (int j = 0; j < kResPer; ++j) {
+      int64_t et;
+      epre[j] = ebase + block_excl_scan(he[j], sh, &et);
+      ebase += et;
+    }
     const int64_t rbase = 2 * d0, rend = 2 * d1;
-    // ---- light tasks to the back of the region
-    if (nl) {
-      int64_t pos = rend - 1 - lslot;
-      if (ta.len) {
-        sbeg[pos] = ta.beg;
-        slen[pos] = ta.len;
-        soth[pos] = ta.oth;
-        sx[pos] = xi;
-        --pos;
-      }
-      if (tb.len) {
-        sbeg[pos] = tb.beg;
-        slen[pos] = tb.len;
-        soth[pos] = tb.oth;
-        sx[pos] = xi;
+#pragma unroll
+    for (int j = 0; j < kResPer; ++j) {
+      const Task* tt[2] = {&ta[j], &tb[j]};
+      if (!heavy[j]) {  // light tasks to the back of the region
+        int64_t pos = rend - 1 - lslot[j];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if (!tt[q]->len) continue;
+          sbeg[pos] = tt[q]->beg;
+          slen[pos] = tt[q]->len;
+          soth[pos] = tt[q]->oth;
+          sx[pos] = xi[j];
+          --pos;
+        }
+      } else {  // heavy records to the front
+        int sl = hslot[j];
+        int64_t e = epre[j];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if (!tt[q]->len) continue;
+          sbeg[rbase + sl] = tt[q]->beg;
+          slen[rbase + sl] = tt[q]->len;
+          soth[rbase + sl] = tt[q]->oth;
+          s_x[sl] = xi[j];
+          s_pre[sl] = e;
+          e += tt[q]->len & kLenMask;
+          ++sl;
+        }
       }
     }
-    // ---- heavy records to the front, in descriptor order
-    if (nh) {
-      int sl = hslot0;
-      if (ta.len) {
-        sbeg[rbase + sl] = ta.beg;
-        slen[rbase + sl] = ta.len;
-        soth[rbase + sl] = ta.oth;
-        s_x[sl] = xi;
-        s_pre[sl] = epre;
-        epre += ta.len & kLenMask;
-        ++sl;
-      }
-      if (tb.len) {
-        sbeg[rbase + sl] = tb.beg;
-        slen[rbase + sl] = tb.len;
-        soth[rbase + sl] = tb.oth;
-        s_x[sl] = xi;
-        s_pre[sl] = epre;
-      }
+    if (htot == 0) {  // block-uniform
+      if (tid == 0) ccnt[c] = make_int4(0, ltot, 0, 0);
+      continue;
     }
     __syncthreads();
     // ---- cut into work items: a new item starts where the anchor changes
     // or the record's element offset enters the next kElemChunk
-    int ns = 0;
-    for (int q = hslot0; q < hslot0 + nh; ++q)
-      ns += (q == 0 || s_x[q] != s_x[q - 1] || (s_pre[q] >> kElemChunkLog) != (s_pre[q - 1] >> kElemChunkLog));
-    int32_t nitems;
-    int it = block_excl_scan(ns, shi, &nitems);
-    for (int q = hslot0; q < hslot0 + nh; ++q)
-      if (q == 0 || s_x[q] != s_x[q - 1] || (s_pre[q] >> kElemChunkLog) != (s_pre[q - 1] >> kElemChunkLog))
-        s_first[it++] = q;
+    // item starts are numbered in slot order: per descriptor group j (the
+    // slots of group j follow all of group j - 1), like the records
+    int64_t ns = 0;
+#pragma unroll
+    for (int j = 0; j < kResPer; ++j) {
+      const int cnt = heavy[j] ? (ta[j].len != 0) + (tb[j].len != 0) : 0;
+      int64_t nsj = 0;
+      for (int q = hslot[j]; q < hslot[j] + cnt; ++q)
+        nsj += (q == 0 || s_x[q] != s_x[q - 1] || (s_pre[q] >> kElemChunkLog) != (s_pre[q - 1] >> kElemChunkLog));
+      ns |= nsj << (16 * j);  // at most 2 per thread, at most kResRecs per group
+    }
+    int64_t ns_tot;
+    const int64_t ns_pre = block_excl_scan(ns, sh, &ns_tot);
+    int nitems = 0;
+    int itj[kResPer];
+#pragma unroll
+    for (int j = 0; j < kResPer; ++j) {
+      itj[j] = nitems + static_cast<int>((ns_pre >> (16 * j)) & 0xFFFF);
+      nitems += static_cast<int>((ns_tot >> (16 * j)) & 0xFFFF);
+    }
+#pragma unroll
+    for (int j = 0; j < kResPer; ++j) {
+      const int cnt = heavy[j] ? (ta[j].len != 0) + (tb[j].len != 0) : 0;
+      int it = itj[j];
+      for (int q = hslot[j]; q < hslot[j] + cnt; ++q)
+        if (q == 0 || s_x[q] != s_x[q - 1] || (s_pre[q] >> kElemChunkLog) != (s_pre[q - 1] >> kElemChunkLog))
+          s_first[it++] = q;
+    }
     if (tid == 0) {
       s_first[nitems] = htot;
       ccnt[c] = make_int4(htot, ltot, nitems, 0);
