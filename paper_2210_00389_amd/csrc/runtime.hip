@@ -182,6 +182,15 @@ struct LoadAll {
   __device__ __forceinline__ int64_t operator()(int64_t i) const { return static_cast<int64_t>(p[i]); }
 };
 
+struct LoadPair {
+  const int32_t* p;
+  int32_t a, b;
+  __device__ __forceinline__ int64_t operator()(int64_t i) const {
+    const int32_t v = p[i];
+    return v == a ? 1 : (v == b ? (int64_t(1) << 32) : 0);
+  }
+};
+
 struct LoadStrided {
   const int32_t* p;
   int64_t stride;
@@ -258,6 +267,12 @@ static int scan_impl(F in, int64_t* out, int64_t count, Carver& ws, hipStream_t 
 template <class T>
 int scan_exclusive(const T* in, int64_t* out, int64_t count, Carver& ws, hipStream_t s) {
   return scan_impl(LoadAll<T>{in}, out, count, ws, s);
+}
+
+int scan_exclusive_pair(const int32_t* in, int32_t a, int32_t b, int64_t* out, int64_t count, Carver& ws,
+                        hipStream_t s) {
+  if (count >= (int64_t(1) << 32)) return TC_ERR_INVALID_ARG;
+  return scan_impl(LoadPair{in, a, b}, out, count, ws, s);
 }
 
 int scan_exclusive_strided(const int32_t* in, int64_t stride, int64_t* out, int64_t count, Carver& ws,

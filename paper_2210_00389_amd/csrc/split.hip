@@ -22,9 +22,11 @@
 //     count are unchanged; each level becomes a contiguous id range, which
 //     keeps the probe sets of the counting kernels inside a small id window.
 //
-// Rows of up to kShort entries are handled by one thread each; longer rows
-// are cut into segments of kSeg entries handled by one wave each (counts,
-// then a per-row prefix over its segments, then a stable ballot scatter).
+// Rows of up to kShort entries are handled by one thread each; longer rows of
+// up to kMidCap entries by one wave, of up to kBigCap by one block, each held
+// in registers between the counting and the scatter; longer rows are cut into
+// segments of kSeg entries handled by one wave each (counts, then a per-row
+// prefix over its segments, then a stable ballot scatter).
 #include "tc_internal.h"
 
 namespace tc {
@@ -35,6 +37,15 @@ constexpr int kThreads = 256;
 constexpr int kShort = 32;
 constexpr int kSeg = 2048;
 constexpr int kRounds = 4;  // 64-entry rounds of a long row loaded at once
+// Rows longer than kShort: up to kMidCap entries one wave each, up to
+// kBigCap one block each, held in registers; longer rows in kSeg-entry
+// segments (count pass, prefix, scatter pass).
+constexpr int kMidR = 16;                    // registers per lane, wave per row
+constexpr int kMidCap = kMidR * 64;          // 1024
+constexpr int kBigWaves = 16;                // block of 1024 threads per row
+constexpr int kBigR = 16;
+constexpr int kBigCap = kBigWaves * kBigR * 64;  // 16384
+enum RowCat { kRowShort = 0, kRowMid = 1, kRowBig = 2, kRowHuge = 3 };
 
 // ---------------------------------------------------------- layouts
 // A layout maps output row i to an input row and classifies its entries:
@@ -101,14 +112,17 @@ struct RelabelLayout {
 // then counted and scattered.
 template <class Lay>
 __global__ __launch_bounds__(kThreads) void lay_short_kernel(Lay lay, const int32_t* cols, int64_t n, int32_t* out,
-                                                             VMeta* meta, int32_t* nseg) {
+                                                             VMeta* meta, int32_t* nseg, int32_t* rcat) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const RowCtx c = lay.ctx(i);
     const int32_t deg = static_cast<int32_t>(c.ie - c.ib);
     if (deg > kShort) {
-      nseg[i] = (deg + kSeg - 1) / kSeg;
+      const int cat = deg <= kMidCap ? kRowMid : (deg <= kBigCap ? kRowBig : kRowHuge);
+      rcat[i] = cat;
+      nseg[i] = cat == kRowHuge ? (deg + kSeg - 1) / kSeg : 0;
       continue;
     }
+    rcat[i] = kRowShort;
     nseg[i] = 0;
     int32_t wv[kShort];
 #pragma unroll
@@ -132,6 +146,112 @@ __global__ __launch_bounds__(kThreads) void lay_short_kernel(Lay lay, const int3
       out[c.ob + pos] = vv[q];
     }
     meta[i] = VMeta{c.ob, up, up + slt, up + same, deg, {c.key, 0}};
+  }
+}
+
+// Row lists of the two staged categories from their packed scan, as row
+// contexts: the kernels that lay these rows out then start with one load
+// instead of the chain of dependent loads ctx() makes.
+template <class Lay>
+__global__ void row_list_kernel(Lay lay, const int32_t* rcat, int64_t n, const int64_t* pre, RowCtx* mid_ctx,
+                                RowCtx* big_ctx) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = rcat[i];
+    if (c == kRowMid) mid_ctx[pre[i] & 0xFFFFFFFFll] = lay.ctx(i);
+    else if (c == kRowBig) big_ctx[pre[i] >> 32] = lay.ctx(i);
+  }
+}
+
+// WPR waves per row, each holding a contiguous part of R * 64 entries in
+// registers: the row is read once and gathered once (R loads in flight per
+// lane), the parts' class counts are combined across the row's waves, and
+// each wave writes its entries with ballot offsets, so every class region
+// is written in runs of consecutive addresses.
+template <class Lay, int WPR, int R, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void lay_rows_kernel(Lay lay, const int32_t* cols, const RowCtx* rows,
+                                                         const int64_t* count, int shift, int32_t* out,
+                                                         VMeta* meta) {
+  constexpr int kPart = R * kWave;
+  constexpr int kGroups = BLOCK / (WPR * kWave);  // rows in flight per block
+  static_assert(WPR == 1 || kGroups == 1, "a row spans either one wave or the whole block");
+  __shared__ int32_t s_cnt[WPR > 1 ? WPR : 1][3];
+  const int wave = threadIdx.x / kWave;
+  const int wr = wave % WPR;
+  const int64_t nrows = (*count >> shift) & 0xFFFFFFFFll;
+  const uint64_t lt = lanemask_lt();
+  for (int64_t r = (int64_t)blockIdx.x * kGroups + wave / WPR; r - wave / WPR < nrows;
+       r += (int64_t)gridDim.x * kGroups) {
+    if (WPR == 1 && r >= nrows) break;
+    const bool active = r < nrows;
+    RowCtx c{};
+    int deg = 0;
+    if (active) {
+      c = rows[r];
+      deg = static_cast<int>(c.ie - c.ib);
+    }
+    const int pb = wr * kPart;
+    const int lim = deg - pb;  // entries of this wave's part (may be <= 0)
+    int32_t wv[R], vv[R];
+    int kc[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int j = u * kWave + lane();
+      wv[u] = j < lim ? cols[c.ib + pb + j] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      vv[u] = 0;
+      kc[u] = wv[u] >= 0 ? lay.cls(c, wv[u], vv[u]) : 3;
+    }
+    int up = 0, same = 0, slt = 0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      up += __popcll(__ballot(kc[u] == 0));
+      same += __popcll(__ballot(kc[u] == 1));
+      slt += __popcll(__ballot((kc[u] == 1) & (vv[u] < c.self)));
+    }
+    int64_t pu = 0, ps = up, pd = up + same;
+    if (WPR > 1) {
+      if (lane() == 0) {
+        s_cnt[wr][0] = up;
+        s_cnt[wr][1] = same;
+        s_cnt[wr][2] = slt;
+      }
+      __syncthreads();
+      int tu = 0, ts = 0, tl = 0, bu = 0, bs = 0, bd = 0;
+      for (int q = 0; q < WPR; ++q) {
+        const int qu = s_cnt[q][0], qs = s_cnt[q][1];
+        if (q < wr) {
+          bu += qu;
+          bs += qs;
+          bd += max(0, min(kPart, deg - q * kPart)) - qu - qs;
+        }
+        tu += qu;
+        ts += qs;
+        tl += s_cnt[q][2];
+      }
+      up = tu;
+      same = ts;
+      slt = tl;
+      pu = bu;
+      ps = tu + bs;
+      pd = tu + ts + bd;
+    }
+    if (active) {
+      if (wr == 0 && lane() == 0) meta[c.self] = VMeta{c.ob, up, up + slt, up + same, deg, {c.key, 0}};
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int k = kc[u];
+        const uint64_t mu = __ballot(k == 0), ms = __ballot(k == 1), md = __ballot(k == 2);
+        if (k == 0) out[c.ob + pu + __popcll(mu & lt)] = vv[u];
+        else if (k == 1) out[c.ob + ps + __popcll(ms & lt)] = vv[u];
+        else if (k == 2) out[c.ob + pd + __popcll(md & lt)] = vv[u];
+        pu += __popcll(mu);
+        ps += __popcll(ms);
+        pd += __popcll(md);
+      }
+    }
+    if (WPR > 1) __syncthreads();  // s_cnt is rewritten for the next row
   }
 }
 
@@ -255,7 +375,20 @@ template <class Lay>
 int layout_run(const Lay& lay, const int32_t* cols, int64_t n, SplitWs& w, hipStream_t s) {
   const unsigned gv = grid_for(n, kThreads, 16384);
   const unsigned gw = static_cast<unsigned>(num_cus() * 8);
-  lay_short_kernel<Lay><<<gv, kThreads, 0, s>>>(lay, cols, n, w.scols, w.meta, w.nseg);
+  lay_short_kernel<Lay><<<gv, kThreads, 0, s>>>(lay, cols, n, w.scols, w.meta, w.nseg, w.rcat);
+  TC_HIP(hipGetLastError());
+  {
+    Carver sc(w.scratch);
+    TC_TRY(scan_exclusive_pair(w.rcat, kRowMid, kRowBig, w.cat_pre, n, sc, s));
+  }
+  RowCtx* mid_ctx = reinterpret_cast<RowCtx*>(w.mid_ctx);
+  RowCtx* big_ctx = reinterpret_cast<RowCtx*>(w.big_ctx);
+  row_list_kernel<Lay><<<gv, kThreads, 0, s>>>(lay, w.rcat, n, w.cat_pre, mid_ctx, big_ctx);
+  lay_rows_kernel<Lay, 1, kMidR, kThreads><<<static_cast<unsigned>(num_cus() * 8), kThreads, 0, s>>>(
+      lay, cols, mid_ctx, w.cat_pre + n, 0, w.scols, w.meta);
+  lay_rows_kernel<Lay, kBigWaves, kBigR, kBigWaves * 64>
+      <<<static_cast<unsigned>(num_cus() * 2), kBigWaves * 64, 0, s>>>(lay, cols, big_ctx, w.cat_pre + n, 32,
+                                                                       w.scols, w.meta);
   TC_HIP(hipGetLastError());
   Carver sc(w.scratch);
   TC_TRY(scan_exclusive<int32_t>(w.nseg, w.seg_off, n, sc, s));
@@ -354,11 +487,17 @@ SplitWs split_reserve(Carver& c, int64_t n, int64_t nnz) {
   w.res = c.take<uint32_t>(1);
   w.nseg = c.take<int32_t>(n + 1);
   w.seg_off = c.take<int64_t>(n + 2);
-  const int64_t max_segs = nnz / (kShort + 1) + 1;  // every long row has > kShort entries
+  // Segmented rows have deg > kBigCap entries and ceil(deg / kSeg) <= deg / kSeg + deg / kBigCap segments.
+  const int64_t max_segs = nnz / kSeg + nnz / kBigCap + 2;
   w.seg_vtx = c.take<int32_t>(max_segs + 1);
   w.seg_cnt = c.take<int32_t>(3 * max_segs + 3);
   w.seg_pre = c.take<int32_t>(3 * max_segs + 3);
   w.ctr = c.take<int64_t>(4);
+  w.rcat = c.take<int32_t>(n + 1);
+  w.cat_pre = c.take<int64_t>(n + 1);
+  static_assert(sizeof(RowCtx) == 6 * sizeof(int64_t), "row contexts are stored as six int64 words");
+  w.mid_ctx = c.take<int64_t>(6 * (std::min(n, nnz / (kShort + 1)) + 2));
+  w.big_ctx = c.take<int64_t>(6 * (nnz / (kMidCap + 1) + 2));
   w.scratch = c.take<char>(scan_ws_bytes(n + 1));
   return w;
 }

@@ -187,6 +187,10 @@ __device__ __forceinline__ T load_relaxed(const T* p) {
 // Temporary space comes from the carver.
 template <class T>
 int scan_exclusive(const T* in, int64_t* out, int64_t count, Carver& ws, hipStream_t s);
+// Two counts at once, packed in one int64 (count < 2^32): the low half scans
+// (in[i] == a), the high half (in[i] == b).
+int scan_exclusive_pair(const int32_t* in, int32_t a, int32_t b, int64_t* out, int64_t count, Carver& ws,
+                        hipStream_t s);
 // The same over in[i * stride].
 int scan_exclusive_strided(const int32_t* in, int64_t stride, int64_t* out, int64_t count, Carver& ws,
                            hipStream_t s);

@@ -59,6 +59,10 @@ struct SplitWs {
   int32_t* seg_cnt;   // per segment: up, same, same-below-x counts (x3)
   int32_t* seg_pre;   // per segment: prefix of the three counts (x3)
   int64_t* ctr;
+  int32_t* rcat;      // per vertex: row category (short, mid, big, segmented)
+  int64_t* cat_pre;   // packed scans of the mid (low half) / big (high half) categories
+  int64_t* mid_ctx;   // per-row contexts of each category (six words per row)
+  int64_t* big_ctx;
   char* scratch;
 };
 SplitWs split_reserve(Carver& c, int64_t n, int64_t nnz);
