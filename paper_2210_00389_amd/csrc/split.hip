@@ -38,13 +38,15 @@ constexpr int kShort = 32;
 constexpr int kSeg = 2048;
 constexpr int kRounds = 4;  // 64-entry rounds of a long row loaded at once
 // Rows longer than kShort: up to kMidCap entries one wave each, up to
-// kBigCap one block each, held in registers; longer rows in kSeg-entry
-// segments (count pass, prefix, scatter pass).
-constexpr int kMidR = 16;                    // registers per lane, wave per row
-constexpr int kMidCap = kMidR * 64;          // 1024
-constexpr int kBigWaves = 16;                // block of 1024 threads per row
+// kBigCap one block of 256 threads each, held in registers; longer rows in
+// kSeg-entry segments, one wave each (a count pass that keeps the gathered
+// ids, a per-row prefix, a scatter pass).
+constexpr int kMidR = 8;                         // registers per lane, wave per row
+constexpr int kMidCap = kMidR * 64;              // 512
+constexpr int kBigWaves = 4;                     // block of 256 threads per row
 constexpr int kBigR = 16;
-constexpr int kBigCap = kBigWaves * kBigR * 64;  // 16384
+constexpr int kBigCap = kBigWaves * kBigR * 64;  // 4096
+static_assert(kBigCap >= kSeg, "a segmented row has at least one full segment");
 enum RowCat { kRowShort = 0, kRowMid = 1, kRowBig = 2, kRowHuge = 3 };
 
 // ---------------------------------------------------------- layouts
@@ -52,6 +54,7 @@ enum RowCat { kRowShort = 0, kRowMid = 1, kRowBig = 2, kRowHuge = 3 };
 //   ctx(i)          per-row context
 //   cls(c, w, v)    class of input entry w (0 up, 1 same, 2 down); v gets
 //                   the value written to the output row
+//   recls(c, v)     the same class, from the output value v
 struct RowCtx {
   int64_t ib, ie, ob;  // input range, output begin
   int32_t self;        // the row's own id in the output numbering
@@ -76,6 +79,11 @@ struct IdentityLayout {
     v = w;
     const int lw = L[w];
     return lw < c.key ? 0 : (lw == c.key ? 1 : 2);
+  }
+  // class of an entry from its output value
+  __device__ __forceinline__ int recls(const RowCtx& c, int32_t v) const {
+    const int lv = L[v];
+    return lv < c.key ? 0 : (lv == c.key ? 1 : 2);
   }
 };
 
@@ -103,8 +111,9 @@ struct RelabelLayout {
   }
   __device__ __forceinline__ int cls(const RowCtx& c, int32_t w, int32_t& v) const {
     v = perm[w];
-    return v < c.lo ? 0 : (v < c.hi ? 1 : 2);
+    return recls(c, v);
   }
+  __device__ __forceinline__ int recls(const RowCtx& c, int32_t v) const { return v < c.lo ? 0 : (v < c.hi ? 1 : 2); }
 };
 
 // Rows of at most kShort entries: one thread; the row and the classes of its
@@ -162,96 +171,137 @@ __global__ void row_list_kernel(Lay lay, const int32_t* rcat, int64_t n, const i
   }
 }
 
-// WPR waves per row, each holding a contiguous part of R * 64 entries in
-// registers: the row is read once and gathered once (R loads in flight per
-// lane), the parts' class counts are combined across the row's waves, and
-// each wave writes its entries with ballot offsets, so every class region
-// is written in runs of consecutive addresses.
-template <class Lay, int WPR, int R, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void lay_rows_kernel(Lay lay, const int32_t* cols, const RowCtx* rows,
-                                                         const int64_t* count, int shift, int32_t* out,
-                                                         VMeta* meta) {
-  constexpr int kPart = R * kWave;
-  constexpr int kGroups = BLOCK / (WPR * kWave);  // rows in flight per block
-  static_assert(WPR == 1 || kGroups == 1, "a row spans either one wave or the whole block");
-  __shared__ int32_t s_cnt[WPR > 1 ? WPR : 1][3];
-  const int wave = threadIdx.x / kWave;
-  const int wr = wave % WPR;
-  const int64_t nrows = (*count >> shift) & 0xFFFFFFFFll;
+// A wave's part of a row: up to R * 64 entries from part_begin, held in
+// registers (lane l has entries part_begin + u * 64 + l); -1 past the end.
+template <int R>
+__device__ __forceinline__ void load_part(const int32_t* cols, const RowCtx& c, int part_begin, int32_t (&wv)[R]) {
+  const int lim = static_cast<int>(c.ie - c.ib) - part_begin;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int j = u * kWave + lane();
+    wv[u] = j < lim ? cols[c.ib + part_begin + j] : -1;
+  }
+}
+
+// Classes of a part (2 bits per entry in *kp, 3 = none) and its output ids;
+// returns the part's counts packed as up | same << 16 | same-below-x << 32
+// | down << 48 (each < 2^16).
+template <class Lay, int R>
+__device__ __forceinline__ uint64_t classify_part(const Lay& lay, const RowCtx& c, const int32_t (&wv)[R],
+                                                  int32_t (&vv)[R], uint32_t* kp) {
+  uint32_t k2 = 0;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    vv[u] = 0;
+    const int k = wv[u] >= 0 ? lay.cls(c, wv[u], vv[u]) : 3;
+    k2 |= static_cast<uint32_t>(k) << (2 * u);
+  }
+  uint64_t up = 0, same = 0, slt = 0, down = 0;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const uint32_t k = (k2 >> (2 * u)) & 3u;
+    up += __popcll(__ballot(k == 0));
+    same += __popcll(__ballot(k == 1));
+    slt += __popcll(__ballot((k == 1) & (vv[u] < c.self)));
+    down += __popcll(__ballot(k == 2));
+  }
+  *kp = k2;
+  return up | (same << 16) | (slt << 32) | (down << 48);
+}
+
+// Scatter of a part: the class regions continue at pu / ps / pd (absolute
+// output positions); entries keep their order inside each class.
+template <int R>
+__device__ __forceinline__ void write_part(const int32_t (&vv)[R], uint32_t k2, int64_t pu, int64_t ps, int64_t pd,
+                                           int32_t* out) {
   const uint64_t lt = lanemask_lt();
-  for (int64_t r = (int64_t)blockIdx.x * kGroups + wave / WPR; r - wave / WPR < nrows;
-       r += (int64_t)gridDim.x * kGroups) {
-    if (WPR == 1 && r >= nrows) break;
-    const bool active = r < nrows;
-    RowCtx c{};
-    int deg = 0;
-    if (active) {
-      c = rows[r];
-      deg = static_cast<int>(c.ie - c.ib);
-    }
-    const int pb = wr * kPart;
-    const int lim = deg - pb;  // entries of this wave's part (may be <= 0)
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const uint32_t k = (k2 >> (2 * u)) & 3u;
+    const uint64_t mu = __ballot(k == 0), ms = __ballot(k == 1), md = __ballot(k == 2);
+    if (k == 0) out[pu + __popcll(mu & lt)] = vv[u];
+    else if (k == 1) out[ps + __popcll(ms & lt)] = vv[u];
+    else if (k == 2) out[pd + __popcll(md & lt)] = vv[u];
+    pu += __popcll(mu);
+    ps += __popcll(ms);
+    pd += __popcll(md);
+  }
+}
+
+constexpr uint64_t kF16 = 0xFFFF;
+
+// Rows of up to R * 64 entries, one wave each.  The wave loads the context
+// and the columns of its next row before it classifies and writes the
+// current one, so the memory latencies of two rows overlap.
+template <class Lay, int R>
+__global__ __launch_bounds__(kThreads) void lay_mid_kernel(Lay lay, const int32_t* cols, const RowCtx* rows,
+                                                           const int64_t* count, int32_t* out, VMeta* meta) {
+  static_assert(R * kWave < (1 << 16), "part counts are packed in 16-bit fields");
+  const int64_t nrows = *count & 0xFFFFFFFFll;
+  const int64_t nw = (int64_t)gridDim.x * (kThreads / kWave);
+  int64_t r = (int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+  if (r >= nrows) return;
+  RowCtx c = rows[r];
+  int32_t wv[R];
+  load_part<R>(cols, c, 0, wv);
+  for (;;) {
+    const int64_t rn = r + nw;
+    const bool more = rn < nrows;
+    RowCtx cn = c;
+    if (more) cn = rows[rn];
+    int32_t vv[R];
+    uint32_t k2;
+    const uint64_t pk = classify_part<Lay, R>(lay, c, wv, vv, &k2);
+    int32_t wn[R];
+    if (more) load_part<R>(cols, cn, 0, wn);
+    const int up = static_cast<int>(pk & kF16), same = static_cast<int>((pk >> 16) & kF16);
+    const int slt = static_cast<int>((pk >> 32) & kF16);
+    const int deg = static_cast<int>(c.ie - c.ib);
+    if (lane() == 0) meta[c.self] = VMeta{c.ob, up, up + slt, up + same, deg, {c.key, 0}};
+    write_part<R>(vv, k2, c.ob, c.ob + up, c.ob + up + same, out);
+    if (!more) break;
+    r = rn;
+    c = cn;
+#pragma unroll
+    for (int u = 0; u < R; ++u) wv[u] = wn[u];
+  }
+}
+
+// Rows of up to WPR * R * 64 entries, one block of WPR waves each; wave q
+// holds entries [q * R * 64, (q + 1) * R * 64) and the waves' class counts
+// are combined through LDS.
+template <class Lay, int WPR, int R>
+__global__ __launch_bounds__(WPR * kWave) void lay_block_kernel(Lay lay, const int32_t* cols, const RowCtx* rows,
+                                                                const int64_t* count, int32_t* out, VMeta* meta) {
+  constexpr int kPart = R * kWave;
+  static_assert(WPR * kPart < (1 << 16), "row counts are packed in 16-bit fields");
+  __shared__ uint64_t s_pk[WPR];
+  const int wave = threadIdx.x / kWave;
+  const int64_t nrows = *count >> 32;
+  for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+    const RowCtx c = rows[r];
     int32_t wv[R], vv[R];
-    int kc[R];
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-      const int j = u * kWave + lane();
-      wv[u] = j < lim ? cols[c.ib + pb + j] : -1;
+    uint32_t k2;
+    load_part<R>(cols, c, wave * kPart, wv);
+    const uint64_t pk = classify_part<Lay, R>(lay, c, wv, vv, &k2);
+    if (lane() == 0) s_pk[wave] = pk;
+    __syncthreads();
+    uint64_t before = 0, tot = 0;
+    for (int q = 0; q < WPR; ++q) {
+      const uint64_t x = s_pk[q];
+      if (q < wave) before += x;
+      tot += x;
     }
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-      vv[u] = 0;
-      kc[u] = wv[u] >= 0 ? lay.cls(c, wv[u], vv[u]) : 3;
-    }
-    int up = 0, same = 0, slt = 0;
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-      up += __popcll(__ballot(kc[u] == 0));
-      same += __popcll(__ballot(kc[u] == 1));
-      slt += __popcll(__ballot((kc[u] == 1) & (vv[u] < c.self)));
-    }
-    int64_t pu = 0, ps = up, pd = up + same;
-    if (WPR > 1) {
-      if (lane() == 0) {
-        s_cnt[wr][0] = up;
-        s_cnt[wr][1] = same;
-        s_cnt[wr][2] = slt;
-      }
-      __syncthreads();
-      int tu = 0, ts = 0, tl = 0, bu = 0, bs = 0, bd = 0;
-      for (int q = 0; q < WPR; ++q) {
-        const int qu = s_cnt[q][0], qs = s_cnt[q][1];
-        if (q < wr) {
-          bu += qu;
-          bs += qs;
-          bd += max(0, min(kPart, deg - q * kPart)) - qu - qs;
-        }
-        tu += qu;
-        ts += qs;
-        tl += s_cnt[q][2];
-      }
-      up = tu;
-      same = ts;
-      slt = tl;
-      pu = bu;
-      ps = tu + bs;
-      pd = tu + ts + bd;
-    }
-    if (active) {
-      if (wr == 0 && lane() == 0) meta[c.self] = VMeta{c.ob, up, up + slt, up + same, deg, {c.key, 0}};
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        const int k = kc[u];
-        const uint64_t mu = __ballot(k == 0), ms = __ballot(k == 1), md = __ballot(k == 2);
-        if (k == 0) out[c.ob + pu + __popcll(mu & lt)] = vv[u];
-        else if (k == 1) out[c.ob + ps + __popcll(ms & lt)] = vv[u];
-        else if (k == 2) out[c.ob + pd + __popcll(md & lt)] = vv[u];
-        pu += __popcll(mu);
-        ps += __popcll(ms);
-        pd += __popcll(md);
-      }
-    }
-    if (WPR > 1) __syncthreads();  // s_cnt is rewritten for the next row
+    const int64_t up = static_cast<int64_t>(tot & kF16), same = static_cast<int64_t>((tot >> 16) & kF16);
+    const int64_t slt = static_cast<int64_t>((tot >> 32) & kF16);
+    const int deg = static_cast<int>(c.ie - c.ib);
+    if (threadIdx.x == 0)
+      meta[c.self] = VMeta{c.ob, static_cast<int>(up), static_cast<int>(up + slt), static_cast<int>(up + same), deg,
+                           {c.key, 0}};
+    write_part<R>(vv, k2, c.ob + static_cast<int64_t>(before & kF16),
+                  c.ob + up + static_cast<int64_t>((before >> 16) & kF16),
+                  c.ob + up + same + static_cast<int64_t>((before >> 48) & kF16), out);
+    __syncthreads();  // s_pk is rewritten for the next row
   }
 }
 
@@ -267,7 +317,7 @@ __global__ void seg_vtx_kernel(const int32_t* nseg, const int64_t* seg_off, int6
 template <class Lay>
 __global__ __launch_bounds__(kThreads) void lay_seg_count_kernel(Lay lay, const int32_t* cols, int64_t n,
                                                                  const int64_t* seg_off, const int32_t* seg_vtx,
-                                                                 int32_t* seg_cnt) {
+                                                                 int32_t* seg_cnt, int32_t* stash) {
   const int64_t nsegs = seg_off[n];
   const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -289,7 +339,10 @@ __global__ __launch_bounds__(kThreads) void lay_seg_count_kernel(Lay lay, const 
       for (int u = 0; u < kRounds; ++u) {
         int k = 3;
         int32_t v = 0;
-        if (wv[u] >= 0) k = lay.cls(c, wv[u], v);
+        if (wv[u] >= 0) {
+          k = lay.cls(c, wv[u], v);
+          stash[j0 + u * kWave + lane()] = v;  // the scatter pass reads the ids back instead of gathering again
+        }
         up += __popcll(__ballot(k == 0));
         same += __popcll(__ballot(k == 1));
         slt += __popcll(__ballot((k == 1) & (v < c.self)));
@@ -327,7 +380,7 @@ __global__ void lay_seg_prefix_kernel(Lay lay, int64_t n, const int32_t* nseg, c
 
 // One wave per segment: stable scatter of the segment's entries.
 template <class Lay>
-__global__ __launch_bounds__(kThreads) void lay_seg_write_kernel(Lay lay, const int32_t* cols, int64_t n,
+__global__ __launch_bounds__(kThreads) void lay_seg_write_kernel(Lay lay, const int32_t* stash, int64_t n,
                                                                  const int64_t* seg_off, const int32_t* seg_vtx,
                                                                  const int32_t* seg_pre, const VMeta* meta,
                                                                  int32_t* out) {
@@ -346,16 +399,15 @@ __global__ __launch_bounds__(kThreads) void lay_seg_write_kernel(Lay lay, const 
     int64_t ps = m.up + seg_pre[3 * sg + 1];
     int64_t pd = m.sfe + (s * kSeg - seg_pre[3 * sg + 0] - seg_pre[3 * sg + 1]);
     for (int64_t j0 = b; j0 < e; j0 += kRounds * kWave) {
-      int32_t wv[kRounds];
-#pragma unroll
-      for (int u = 0; u < kRounds; ++u) {
-        const int64_t j = j0 + u * kWave + lane();
-        wv[u] = j < e ? cols[j] : -1;
-      }
       int32_t vv[kRounds];
       int kc[kRounds];
 #pragma unroll
-      for (int u = 0; u < kRounds; ++u) kc[u] = wv[u] >= 0 ? lay.cls(c, wv[u], vv[u]) : 3;
+      for (int u = 0; u < kRounds; ++u) {
+        const int64_t j = j0 + u * kWave + lane();
+        vv[u] = j < e ? stash[j] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < kRounds; ++u) kc[u] = vv[u] >= 0 ? lay.recls(c, vv[u]) : 3;
 #pragma unroll
       for (int u = 0; u < kRounds; ++u) {
         const int k = kc[u];
@@ -384,18 +436,17 @@ int layout_run(const Lay& lay, const int32_t* cols, int64_t n, SplitWs& w, hipSt
   RowCtx* mid_ctx = reinterpret_cast<RowCtx*>(w.mid_ctx);
   RowCtx* big_ctx = reinterpret_cast<RowCtx*>(w.big_ctx);
   row_list_kernel<Lay><<<gv, kThreads, 0, s>>>(lay, w.rcat, n, w.cat_pre, mid_ctx, big_ctx);
-  lay_rows_kernel<Lay, 1, kMidR, kThreads><<<static_cast<unsigned>(num_cus() * 8), kThreads, 0, s>>>(
-      lay, cols, mid_ctx, w.cat_pre + n, 0, w.scols, w.meta);
-  lay_rows_kernel<Lay, kBigWaves, kBigR, kBigWaves * 64>
-      <<<static_cast<unsigned>(num_cus() * 2), kBigWaves * 64, 0, s>>>(lay, cols, big_ctx, w.cat_pre + n, 32,
-                                                                       w.scols, w.meta);
+  lay_mid_kernel<Lay, kMidR><<<static_cast<unsigned>(num_cus() * 8), kThreads, 0, s>>>(lay, cols, mid_ctx,
+                                                                                      w.cat_pre + n, w.scols, w.meta);
+  lay_block_kernel<Lay, kBigWaves, kBigR><<<static_cast<unsigned>(num_cus() * 4), kBigWaves * kWave, 0, s>>>(
+      lay, cols, big_ctx, w.cat_pre + n, w.scols, w.meta);
   TC_HIP(hipGetLastError());
   Carver sc(w.scratch);
   TC_TRY(scan_exclusive<int32_t>(w.nseg, w.seg_off, n, sc, s));
   seg_vtx_kernel<<<gv, kThreads, 0, s>>>(w.nseg, w.seg_off, n, w.seg_vtx);
-  lay_seg_count_kernel<Lay><<<gw, kThreads, 0, s>>>(lay, cols, n, w.seg_off, w.seg_vtx, w.seg_cnt);
+  lay_seg_count_kernel<Lay><<<gw, kThreads, 0, s>>>(lay, cols, n, w.seg_off, w.seg_vtx, w.seg_cnt, w.stash);
   lay_seg_prefix_kernel<Lay><<<gv, kThreads, 0, s>>>(lay, n, w.nseg, w.seg_off, w.seg_cnt, w.seg_pre, w.meta);
-  lay_seg_write_kernel<Lay><<<gw, kThreads, 0, s>>>(lay, cols, n, w.seg_off, w.seg_vtx, w.seg_pre, w.meta,
+  lay_seg_write_kernel<Lay><<<gw, kThreads, 0, s>>>(lay, w.stash, n, w.seg_off, w.seg_vtx, w.seg_pre, w.meta,
                                                     w.scols);
   TC_HIP(hipGetLastError());
   return TC_OK;
@@ -498,6 +549,7 @@ SplitWs split_reserve(Carver& c, int64_t n, int64_t nnz) {
   static_assert(sizeof(RowCtx) == 6 * sizeof(int64_t), "row contexts are stored as six int64 words");
   w.mid_ctx = c.take<int64_t>(6 * (std::min(n, nnz / (kShort + 1)) + 2));
   w.big_ctx = c.take<int64_t>(6 * (nnz / (kMidCap + 1) + 2));
+  w.stash = c.take<int32_t>(nnz + 1);
   w.scratch = c.take<char>(scan_ws_bytes(n + 1));
   return w;
 }

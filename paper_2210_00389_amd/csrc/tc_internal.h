@@ -63,6 +63,7 @@ struct SplitWs {
   int64_t* cat_pre;   // packed scans of the mid (low half) / big (high half) categories
   int64_t* mid_ctx;   // per-row contexts of each category (six words per row)
   int64_t* big_ctx;
+  int32_t* stash;     // output ids of segmented rows, in input order [nnz]
   char* scratch;
 };
 SplitWs split_reserve(Carver& c, int64_t n, int64_t nnz);
