@@ -463,6 +463,17 @@ def main():
         gd = json.load(open(gpath))
         golden = {"triangles": gd["triangles"], "h": gd["h"], "match": gd["triangles"] == T and gd["h"] == h}
 
+    # Distributed-variant context: the communication model of the parallel
+    # algorithm for this graph's measured k, on one node of 8 GPUs
+    import numpy as np
+    from paper_2210_00389_amd import comm_model
+    deg = np.diff(G.row_offsets.cpu().numpy())
+    wedges = int((deg * (deg - 1) // 2).sum())
+    cmr = comm_model.volume_for_count(n, m, h, st["num_levels"], p=8, wedges=wedges)
+    comm = {"p": 8, "k": round(cmr.k, 4), "level_bits": cmr.level_bits, "wedges": wedges,
+            "cover_bytes": int(cmr.cover_bytes), "wedge_check_bytes": int(cmr.previous_bytes),
+            "reduction": round(cmr.reduction, 2)}
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle sample")
@@ -486,6 +497,7 @@ def main():
         "stages": stage_roofs,
         "work": st,
         "golden": golden,
+        "comm_model": comm,
         "cpu_baseline": cpu,
     }
     line = json.dumps(out)
