@@ -98,6 +98,10 @@ def _bind(lib):
     lib.oracle_edge_count.restype = i64
     lib.oracle_count_rows.argtypes = [i64, p, p, p, c_int, i64, i64, p]
     lib.oracle_count_rows.restype = c_int
+    lib.oracle_list_triangles.argtypes = [i64, p, p, p, p, i64, p]
+    lib.oracle_list_triangles.restype = c_int
+    lib.oracle_edge_supports.argtypes = [i64, p, p, p, p]
+    lib.oracle_edge_supports.restype = c_int
     return lib
 
 
@@ -239,6 +243,33 @@ def edge_support(csr: CSR, levels: np.ndarray, u: int, v: int) -> int:
     """c(u, v) of one horizontal edge (u < v) by two-pointer merge."""
     L = np.ascontiguousarray(levels, dtype=np.int32)
     return int(_load().oracle_edge_support(_p(csr.row_offsets), _p(csr.cols), _p(L), u, v))
+
+
+def list_triangles(csr: CSR, levels: np.ndarray) -> np.ndarray:
+    """Triangle finding by Alg. 1's enumeration: int32 [T, 3], each row the
+    three ids ascending, rows in the order the count finds them."""
+    lib = _load()
+    cols = csr.cols if csr.cols.size else np.zeros(1, dtype=np.int32)
+    L = np.ascontiguousarray(levels, dtype=np.int32)
+    if L.size == 0:
+        L = np.zeros(1, dtype=np.int32)
+    T = np.zeros(1, dtype=np.int64)
+    _check(lib.oracle_list_triangles(csr.n, _p(csr.row_offsets), _p(cols), _p(L), None, 0, _p(T)))
+    tri = np.zeros((max(int(T[0]), 1), 3), dtype=np.int32)
+    _check(lib.oracle_list_triangles(csr.n, _p(csr.row_offsets), _p(cols), _p(L), _p(tri), int(T[0]), _p(T)))
+    return tri[: int(T[0])].copy()
+
+
+def edge_supports(csr: CSR, levels: np.ndarray) -> np.ndarray:
+    """Triangles on each edge, int64 per CSR entry (both orientations)."""
+    lib = _load()
+    cols = csr.cols if csr.cols.size else np.zeros(1, dtype=np.int32)
+    L = np.ascontiguousarray(levels, dtype=np.int32)
+    if L.size == 0:
+        L = np.zeros(1, dtype=np.int32)
+    sup = np.zeros(max(csr.nnz, 1), dtype=np.int64)
+    _check(lib.oracle_edge_supports(csr.n, _p(csr.row_offsets), _p(cols), _p(L), _p(sup)))
+    return sup[: csr.nnz].copy()
 
 
 def edge_count(csr: CSR) -> int:

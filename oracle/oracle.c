@@ -23,6 +23,12 @@
  *                        count w when L(u) != L(w), or L(u) = L(w) and v < w
  *                        (Alg. 1, counting test; Thm. 2 proves it exact).
  *                        Full integer levels are compared, never parities.
+ *   oracle_list_triangles  triangle finding: every (u, v, w) the count
+ *                        accepts, written as its three ids ascending, in the
+ *                        order Alg. 1 visits them.
+ *   oracle_edge_supports the number of triangles on each edge, from that
+ *                        enumeration (+1 on both orientations of the three
+ *                        edges of every found triangle).
  *   oracle_edge_count    the plain direction-oriented edge iterator of the
  *                        related-work section: every edge (u, v), u < v,
  *                        counts the w in N(u) ∩ N(v) with w > v.  It uses no
@@ -322,6 +328,110 @@ int64_t oracle_edge_support(const int64_t* off, const int32_t* cols, const int32
     }
   }
   return c;
+}
+
+/* Position of v in the sorted row of u, or -1 (binary search). */
+static int64_t find_in_row(const int64_t* off, const int32_t* cols, int32_t u, int32_t v) {
+  int64_t lo = off[u], hi = off[u + 1];
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (cols[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < off[u + 1] && cols[lo] == v) ? lo : -1;
+}
+
+static void sort3(int32_t* t) {
+  int32_t x;
+  if (t[0] > t[1]) { x = t[0]; t[0] = t[1]; t[1] = x; }
+  if (t[1] > t[2]) { x = t[1]; t[1] = t[2]; t[2] = x; }
+  if (t[0] > t[1]) { x = t[0]; t[0] = t[1]; t[1] = x; }
+}
+
+/* Alg. 1's enumeration with a two-pointer merge per horizontal edge: every
+ * accepted (u, v, w) is handed to `emit` as an ascending triple. */
+static int enumerate(int64_t n, const int64_t* off, const int32_t* cols, const int32_t* L,
+                     void (*emit)(void*, const int32_t*), void* ctx, int64_t* T) {
+  if (n < 0 || !off || !T || (n > 0 && !L)) return OR_EINVAL;
+  int64_t total = 0;
+  for (int64_t u = 0; u < n; ++u) {
+    for (int64_t i = off[u]; i < off[u + 1]; ++i) {
+      int32_t v = cols[i];
+      if (v <= u || L[u] != L[v]) continue; /* only the horizontal edges */
+      int64_t a = off[u], ae = off[u + 1], b = off[v], be = off[v + 1];
+      while (a < ae && b < be) {
+        if (cols[a] < cols[b]) ++a;
+        else if (cols[a] > cols[b]) ++b;
+        else {
+          int32_t w = cols[a];
+          if (counts(L, (int32_t)u, v, w)) {
+            int32_t t[3] = {(int32_t)u, v, w};
+            sort3(t);
+            emit(ctx, t);
+            ++total;
+          }
+          ++a;
+          ++b;
+        }
+      }
+    }
+  }
+  *T = total;
+  return OR_OK;
+}
+
+struct list_ctx {
+  int32_t* tri;
+  int64_t cap, at;
+};
+
+static void emit_list(void* p, const int32_t* t) {
+  struct list_ctx* c = (struct list_ctx*)p;
+  if (c->at < c->cap) {
+    c->tri[3 * c->at] = t[0];
+    c->tri[3 * c->at + 1] = t[1];
+    c->tri[3 * c->at + 2] = t[2];
+  }
+  c->at++;
+}
+
+/* Triangle finding: writes the first min(T, cap) triangles found (each as
+ * three ascending ids) to tri[3 * cap]; *T is the total. */
+int oracle_list_triangles(int64_t n, const int64_t* off, const int32_t* cols, const int32_t* L, int32_t* tri,
+                          int64_t cap, int64_t* T) {
+  if (cap < 0 || (cap > 0 && !tri)) return OR_EINVAL;
+  struct list_ctx c = {tri, cap, 0};
+  return enumerate(n, off, cols, L, emit_list, &c, T);
+}
+
+struct support_ctx {
+  const int64_t* off;
+  const int32_t* cols;
+  int64_t* support;
+};
+
+static void add_edge(struct support_ctx* c, int32_t a, int32_t b) {
+  c->support[find_in_row(c->off, c->cols, a, b)]++;
+  c->support[find_in_row(c->off, c->cols, b, a)]++;
+}
+
+static void emit_support(void* p, const int32_t* t) {
+  struct support_ctx* c = (struct support_ctx*)p;
+  add_edge(c, t[0], t[1]);
+  add_edge(c, t[0], t[2]);
+  add_edge(c, t[1], t[2]);
+}
+
+/* Triangles on each edge: support[e] for every CSR entry e (both
+ * orientations of an edge hold the same number). */
+int oracle_edge_supports(int64_t n, const int64_t* off, const int32_t* cols, const int32_t* L, int64_t* support) {
+  if (n < 0 || !off) return OR_EINVAL;
+  int64_t nnz = n > 0 ? off[n] : 0;
+  if (nnz > 0 && !support) return OR_EINVAL;
+  for (int64_t e = 0; e < nnz; ++e) support[e] = 0;
+  struct support_ctx c = {off, cols, support};
+  int64_t T = 0;
+  return enumerate(n, off, cols, L, emit_support, &c, &T);
 }
 
 /* Plain edge iterator, direction-oriented by vertex id: every edge (u, v)

@@ -36,6 +36,12 @@ MUTANTS = {
     "stamp_wrong_owner": ("if (stamp[w] == u && counts", "if (stamp[w] == v && counts"),
     "edge_iter_wrong_bound": ("if (cols[a] > v) ++total;", "if (cols[a] > u) ++total;"),
     "loops_kept": ("    if (s == d) continue;\n    deg[s] += 1;", "    deg[s] += 1;"),
+    "sort3_last_swap_missing": ("  if (t[1] > t[2]) { x = t[1]; t[1] = t[2]; t[2] = x; }\n  if (t[0] > t[1]) { x = t[0]; t[0] = t[1]; t[1] = x; }\n}",
+                                "  if (t[1] > t[2]) { x = t[1]; t[1] = t[2]; t[2] = x; }\n}"),
+    "list_wrong_slot": ("    c->tri[3 * c->at + 2] = t[2];", "    c->tri[3 * c->at + 2] = t[1];"),
+    "support_one_orientation": ("  c->support[find_in_row(c->off, c->cols, b, a)]++;\n", ""),
+    "support_skips_an_edge": ("  add_edge(c, t[1], t[2]);\n", ""),
+    "list_both_orientations": ("if (v <= u || L[u] != L[v]) continue;", "if (v == u || L[u] != L[v]) continue;"),
 }
 
 
@@ -88,6 +94,23 @@ def battery():
 
     for seed in (1, 2):
         check(f"brute {seed}", lambda: brute_case(seed))
+
+    def listing_case(seed):
+        g = graphgen.disjoint_union([graphgen.erdos_renyi(30, 0.3, seed), graphgen.wheel(7)])
+        c = oracle.from_graph(g)
+        L = oracle.bfs_levels(c).levels
+        got = sorted(map(tuple, oracle.list_triangles(c, L).tolist()))
+        ok = got == brute.triangles(brute.adjacency(g.n, g.src, g.dst))
+        sup = oracle.edge_supports(c, L)
+        for u in range(c.n):
+            for e in range(c.row_offsets[u], c.row_offsets[u + 1]):
+                v = c.cols[e]
+                ok &= sup[e] == np.intersect1d(c.cols[c.row_offsets[u]:c.row_offsets[u + 1]],
+                                               c.cols[c.row_offsets[v]:c.row_offsets[v + 1]]).size
+        return bool(ok)
+
+    for seed in (3, 4):
+        check(f"listing {seed}", lambda: listing_case(seed))
     return bad
 
 
