@@ -132,6 +132,58 @@ def cpu_baseline(g, n, m, budget_s):
     }
 
 
+def bench_list(args):
+    """Triangle finding on R-MAT: tc_list_triangles into an exact-size buffer
+    (count pass recording per-unit counts, offsets, write pass), then the
+    per-edge supports from the list (tc_edge_support)."""
+    import torch
+    import paper_2210_00389_amd as tc
+    dev = torch.device("cuda:0")
+    g = graphgen.rmat(args.scale, args.edge_factor, seed=args.seed)
+    G = tc.from_host_pairs(g.n, g.src, g.dst, device=dev)
+    del g
+    ws = tc.Workspace(dev)
+    T = tc.count(G, ws=ws).T
+    res = tc.list_triangles(G, cap=T, ws=ws)
+    tc.profile_enable(True)
+    for _ in range(args.warmup):
+        tc.list_triangles(G, cap=T, ws=ws, out=res)
+    torch.cuda.synchronize()
+    log(f"[bench] listing {T} triangles, {args.steps} steps")
+    wall, per, stages = run_timed(lambda: tc.list_triangles(G, cap=T, ws=ws, out=res), args.steps,
+                                  torch.cuda.synchronize)
+    tc.profile_enable(False)
+    assert res.T == T
+    sup_ms = []
+    for _ in range(max(3, args.steps // 4)):
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record()
+        sup = tc.edge_support(G, res.tri)
+        s1.record()
+        torch.cuda.synchronize()
+        sup_ms.append(s0.elapsed_time(s1))
+    assert int(sup.to(torch.int64).sum().item()) == 6 * T
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", f"rmat_s{args.scale}.json")
+    if args.edge_factor == 16 and args.seed == 1 and os.path.exists(gpath):
+        golden = {"triangles": json.load(open(gpath))["triangles"]}
+        golden["match"] = golden["triangles"] == T
+    ms = 1000 * wall / args.steps
+    return {
+        "metric": "triangles listed/s", "value": T / (wall / args.steps), "unit": "triangles/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"R-MAT scale {args.scale}, edge factor {args.edge_factor}, seed {args.seed}: "
+                               "triangle finding into an exact-size buffer (12 bytes per triangle), then "
+                               "per-edge supports", "n": G.n, "m": G.m, "triangles": T},
+        "p50_ms": percentile(per, 50), "p99_ms": percentile(per, 99),
+        "stages": {k: round(statistics.mean(v), 4) for k, v in stages.items()},
+        "output_GB_per_s": 12 * T / (wall / args.steps) / 1e9,
+        "support_ms": statistics.median(sup_ms),
+        "golden": golden,
+    }
+
+
 def bench_batch(args):
     """4096 ER/BA graphs in one captured tc_count_batch replay per step."""
     import numpy as np
@@ -348,7 +400,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--json-out", default=None)
-    ap.add_argument("--workload", choices=("rmat", "batch", "serving", "pmc"), default="rmat")
+    ap.add_argument("--workload", choices=("rmat", "batch", "serving", "pmc", "list"), default="rmat")
     ap.add_argument("--summarize", action="store_true", help="summarise rocprofv3 output into --out(.md/.json)")
     ap.add_argument("--trace-dir", default=None)
     ap.add_argument("--fetch-dir", default=None)
@@ -384,7 +436,7 @@ def main():
         bench_pmc(args)
         return
     if args.workload != "rmat":
-        out = bench_batch(args) if args.workload == "batch" else bench_serving(args)
+        out = {"batch": bench_batch, "serving": bench_serving, "list": bench_list}[args.workload](args)
         line = json.dumps(out)
         print(line, flush=True)
         if args.json_out:

@@ -177,6 +177,41 @@ int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles,
              int64_t* h_count, int32_t* levels, int64_t* per_vertex, void* ws,
              size_t ws_bytes, tc_stream_t stream);
 
+/* Triangle finding (the paper counts and finds triangles; Alg. 1 visits each
+ * triangle exactly once, at one horizontal edge and one apex): the same
+ * levels, H and count as tc_count, then every triangle written once.
+ * Two passes: the count records how many triangles each unit of work finds,
+ * a prefix sum turns those into output offsets, and a second pass over the
+ * same work writes each triangle at its unit's offset.
+ *   tri          device int32 [3 * cap] (output): min(T, cap) triangles, each
+ *                as its three vertex ids in ascending order; the order of the
+ *                triangles is unspecified (it may differ between calls), the
+ *                set is exact.  If cap < T, which cap triangles are written
+ *                is unspecified: call tc_count first for T, or pass cap >= T.
+ *                May be NULL when cap = 0.
+ *   cap          capacity of `tri` in triangles (>= 0)
+ *   triangles    device int64 [1] (output): T
+ *   h_count      device int64 [1] (nullable output): |H|
+ *   levels       device int32 [n] (nullable output): the BFS levels used
+ * flags: TC_VALIDATE only (TC_PER_VERTEX is rejected).  Workspace: the
+ * tc_count size (TC_OP_COUNT).  Synchronises `stream` once per BFS level
+ * and once between the two passes. */
+int tc_list_triangles(const tc_csr* g, int64_t root, uint32_t flags, int32_t* tri, int64_t cap,
+                      int64_t* triangles, int64_t* h_count, int32_t* levels, void* ws,
+                      size_t ws_bytes, tc_stream_t stream);
+
+/* Triangles per edge (the support of a k-truss decomposition) from a list
+ * of triangles such as tc_list_triangles writes: support[e] = number of
+ * listed triangles containing the edge of CSR entry e; both orientations of
+ * an edge hold the same value.  support is cleared first.  A triple with an
+ * id outside [0, n) is skipped; a triple whose pair is not an edge adds
+ * nothing for that pair.
+ *   tri          device int32 [3 * num_triangles]
+ *   support      device int32 [nnz] (output)
+ * Asynchronous; needs no workspace. */
+int tc_edge_support(const tc_csr* g, const int32_t* tri, int64_t num_triangles, int32_t* support,
+                    tc_stream_t stream);
+
 /* Comparator: the plain direction-oriented edge iterator (related-work
  * section: every edge (u, v) with u < v counts the w in N(u) ∩ N(v) with
  * w > v), on the same intersection kernels as tc_count.
@@ -231,7 +266,7 @@ typedef struct tc_stats {
   int64_t heavy_builds;    /* probe-set elements inserted into on-chip tables */
   int64_t light_elems;     /* list elements streamed by the per-task merges */
   int64_t bin_elems[4];    /* anchored-kernel elements per table bin (2 KB,
-                              16 KB, 128 KB, row search) */
+                              32 KB, 128 KB, row search) */
   int64_t bin_items[4];    /* work items per table bin */
   int64_t descriptors;     /* per-vertex task descriptors examined */
 } tc_stats;

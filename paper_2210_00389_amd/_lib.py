@@ -31,7 +31,8 @@ STATUS_NAMES = {
 
 EXPORTS = [
     "tc_workspace_bytes", "tc_build_csr", "tc_validate_csr", "tc_bfs_levels", "tc_cover_edges",
-    "tc_count", "tc_count_edge_baseline", "tc_count_batch", "tc_status_string", "tc_last_error",
+    "tc_count", "tc_list_triangles", "tc_edge_support", "tc_count_edge_baseline", "tc_count_batch",
+    "tc_status_string", "tc_last_error",
     "tc_profile_enable", "tc_profile_read", "tc_read_stats",
 ]
 
@@ -94,6 +95,10 @@ def load(path: str | None = None):
     lib.tc_cover_edges.restype = c_int
     lib.tc_count.argtypes = [ctypes.POINTER(TcCsr), i64, u32, P, P, P, P, P, sz, P]
     lib.tc_count.restype = c_int
+    lib.tc_list_triangles.argtypes = [ctypes.POINTER(TcCsr), i64, u32, P, i64, P, P, P, P, sz, P]
+    lib.tc_list_triangles.restype = c_int
+    lib.tc_edge_support.argtypes = [ctypes.POINTER(TcCsr), P, i64, P, P]
+    lib.tc_edge_support.restype = c_int
     lib.tc_count_edge_baseline.argtypes = [ctypes.POINTER(TcCsr), u32, P, P, sz, P]
     lib.tc_count_edge_baseline.restype = c_int
     lib.tc_count_batch.argtypes = [ctypes.POINTER(TcBatch), ctypes.POINTER(TcTuning), u32, P, P, P, P, sz, P]

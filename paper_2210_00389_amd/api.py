@@ -197,6 +197,57 @@ def count(g: Graph, root: int = -1, per_vertex: bool = False, validate: bool = F
     return res
 
 
+@dataclass
+class ListResult:
+    tri: torch.Tensor        # int32 [min(T, cap), 3], each row ascending; row order unspecified
+    triangles: torch.Tensor  # int64 [1]: T
+    h_count: torch.Tensor    # int64 [1]: |H|
+    tri_buf: torch.Tensor | None = None  # the whole output buffer [max(cap, 1), 3]
+
+    @property
+    def T(self) -> int:
+        return int(self.triangles.item())
+
+
+def list_triangles(g: Graph, root: int = -1, cap: int | None = None, validate: bool = False,
+                   ws: Workspace | None = None, stream=None, out: ListResult | None = None) -> ListResult:
+    """Triangle finding (tc_list_triangles).  With cap=None the triangles are
+    counted first (tc_count) and the buffer is sized exactly; `out` (from an
+    earlier call with the same cap) reuses its buffers."""
+    lib = L.load()
+    dev = g.cols.device
+    if cap is None:
+        cap = out.tri_buf.shape[0] if out is not None else count(g, root=root, validate=validate, ws=ws,
+                                                                  stream=stream).T
+    if out is not None and out.tri_buf.shape[0] >= max(cap, 1):
+        res = out
+    else:
+        res = ListResult(torch.empty((max(cap, 1), 3), dtype=torch.int32, device=dev),
+                         torch.zeros(1, dtype=torch.int64, device=dev), torch.zeros(1, dtype=torch.int64, device=dev))
+        res.tri_buf = res.tri
+    flags = L.TC_VALIDATE if validate else 0
+    buf = (ws or default_workspace(dev)).get(workspace_bytes(L.OP_COUNT, g.n, g.nnz))
+    csr = g.csr()
+    _check(lib.tc_list_triangles(ctypes.byref(csr), root, flags, _ptr(res.tri_buf), cap, _ptr(res.triangles),
+                                 _ptr(res.h_count), None, _ptr(buf), buf.numel(), _stream(stream)),
+           "tc_list_triangles")
+    res.tri = res.tri_buf[: min(cap, res.T)]
+    return res
+
+
+def edge_support(g: Graph, tri: torch.Tensor, stream=None) -> torch.Tensor:
+    """Triangles per CSR entry from a triangle list (tc_edge_support)."""
+    lib = L.load()
+    tri = tri.contiguous()
+    if tri.dtype != torch.int32 or (tri.dim() != 2 or tri.shape[1] != 3) and tri.numel() > 0:
+        raise ValueError("tri must be an int32 [k, 3] tensor")
+    sup = torch.empty(max(g.nnz, 1), dtype=torch.int32, device=g.cols.device)
+    csr = g.csr()
+    _check(lib.tc_edge_support(ctypes.byref(csr), _ptr(tri) if tri.numel() else None, tri.shape[0] if tri.numel() else 0,
+                               _ptr(sup), _stream(stream)), "tc_edge_support")
+    return sup[: g.nnz]
+
+
 def count_edge_baseline(g: Graph, validate: bool = False, ws: Workspace | None = None, stream=None,
                         out: torch.Tensor | None = None) -> torch.Tensor:
     """Plain direction-oriented edge-iterator count (tc_count_edge_baseline)."""

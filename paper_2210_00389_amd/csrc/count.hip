@@ -106,25 +106,47 @@ __device__ __forceinline__ void add_pv(int64_t* pv, int32_t a, int32_t b, int32_
   atomicAdd(reinterpret_cast<unsigned long long*>(&pv[c]), 1ull);
 }
 
-// |{t in S : t > lo} ∩ P| by a two-pointer merge (both ascending).
-template <bool kPV>
-__device__ __forceinline__ int64_t merge_count(const int32_t* S, int ns, const int32_t* P, int np,
-                                               int32_t lo, int64_t* pv, int32_t f1, int32_t f2) {
-  int i = 0, j = 0;
-  int64_t c = 0;
-  while (i < ns && j < np) {
-    int32_t s = S[i], p = P[j];
-    if (s <= lo) { ++i; continue; }
-    if (s < p) ++i;
-    else if (s > p) ++j;
-    else {
-      ++c;
-      if (kPV) add_pv(pv, f1, f2, s);
-      ++i;
-      ++j;
-    }
+// What the counting kernels do with each triangle they find:
+//   kOutNone  count only;
+//   kOutPV    also add one to each of its three vertices (per-vertex counts);
+//   kOutRec   also record every work unit's count (ucnt: heavy items by their
+//             index in the item array, then light tasks by their index);
+//   kOutEmit  write it at its work unit's offset (uoff) as three caller ids,
+//             ascending (the second pass of triangle finding).
+enum OutKind { kOutNone = 0, kOutPV = 1, kOutRec = 2, kOutEmit = 3 };
+
+struct Out {
+  int64_t* pv;
+  int32_t* ucnt;
+  const int64_t* uoff;
+  int32_t* tri;          // [3 * cap]
+  int64_t cap;
+  const int32_t* order;  // layout id -> caller id (null: the same)
+};
+
+__host__ __device__ constexpr bool needs_oth(int k) { return k == kOutPV || k == kOutEmit; }
+
+__device__ __forceinline__ void write_tri(const Out& o, int64_t at, int32_t a, int32_t b, int32_t c) {
+  if (at >= o.cap) return;
+  if (o.order) {
+    a = o.order[a];
+    b = o.order[b];
+    c = o.order[c];
   }
-  return c;
+  int32_t t;
+  if (a > b) { t = a; a = b; b = t; }
+  if (b > c) { t = b; b = c; c = t; }
+  if (a > b) { t = a; a = b; b = t; }
+  o.tri[3 * at] = a;
+  o.tri[3 * at + 1] = b;
+  o.tri[3 * at + 2] = c;
+}
+
+// One triangle {x, oth, w} found by a thread that writes sequentially.
+template <int kOut>
+__device__ __forceinline__ void on_hit(const Out& o, int32_t x, int32_t oth, int32_t w, int64_t& at) {
+  if (kOut == kOutPV) add_pv(o.pv, x, oth, w);
+  else if (kOut == kOutEmit) write_tri(o, at++, x, oth, w);
 }
 
 // Membership of t in a sorted list [p, p + len) in global memory.
@@ -508,22 +530,26 @@ __global__ __launch_bounds__(kResThreads) void resolve_kernel(
 // compared pairwise; a longer stream (down class) is searched for every
 // probe id, all searches advancing together.
 
-template <bool kPV>
+template <int kOut>
 __global__ __launch_bounds__(kThreads) void light_kernel(const int32_t* lc, const VMeta* meta, const int64_t* so,
                                                          int64_t n, const int64_t* lpre, int64_t nchunk_cap,
                                                          const int64_t* sbeg, const int32_t* slen,
                                                          const int32_t* soth, const int32_t* sx,
-                                                         unsigned long long* acc, int64_t* pv) {
+                                                         unsigned long long* acc, Out o) {
   __shared__ int64_t sh[kThreads / kWave + 1];
   const int64_t total = so[n];
   const int64_t nl = lpre[nchunk_cap];
+  // light tasks follow the heavy items in the unit numbering
+  const int64_t ubase = (kOut == kOutRec || kOut == kOutEmit) ? static_cast<int64_t>(acc[kAccItems]) : 0;
   int64_t cnt = 0, elems = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nl; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = upper_bound_dev(lpre, 0, nchunk_cap + 1, i) - 1;
     const int64_t pos = 2 * min((c + 1) * kResChunk, total) - 1 - (i - lpre[c]);
     const int32_t x = sx[pos];
     const int32_t lf = slen[pos];
-    const int32_t oth = kPV ? soth[pos] : 0;
+    const int32_t oth = needs_oth(kOut) ? soth[pos] : 0;
+    int64_t at = kOut == kOutEmit ? o.uoff[ubase + i] : 0;
+    int64_t tc = 0;
     const VMeta mx = meta[x];
     const int len = lf & kLenMask;
     const bool up = (lf & kFlagUp) != 0;
@@ -542,8 +568,8 @@ __global__ __launch_bounds__(kThreads) void light_kernel(const int32_t* lc, cons
         int m = 0;
 #pragma unroll
         for (int j = 0; j < kLightMax; ++j) m |= sv[q] == pr[j];
-        cnt += m;
-        if (kPV && m) add_pv(pv, x, oth, sv[q]);
+        tc += m;
+        if (m) on_hit<kOut>(o, x, oth, sv[q], at);
       }
       elems += len;
     } else {
@@ -563,14 +589,18 @@ __global__ __launch_bounds__(kThreads) void light_kernel(const int32_t* lc, cons
 #pragma unroll
       for (int q = 0; q < kLightMax; ++q) {
         const bool m = q < np && lo[q] < len && S[lo[q]] == pr[q];
-        cnt += m;
-        if (kPV && m) add_pv(pv, x, oth, pr[q]);
+        tc += m;
+        if (m) on_hit<kOut>(o, x, oth, pr[q], at);
       }
       elems += np;
     }
+    cnt += tc;
+    if (kOut == kOutRec) o.ucnt[ubase + i] = static_cast<int32_t>(tc);
   }
-  block_acc(acc, kAccT, cnt, sh);
-  block_acc(acc, kAccElems, elems, sh);
+  if (kOut != kOutEmit) {
+    block_acc(acc, kAccT, cnt, sh);
+    block_acc(acc, kAccElems, elems, sh);
+  }
 }
 
 // Items grouped by bin, in chunk order within each block of chunks (so the
@@ -680,9 +710,9 @@ constexpr int kWinIters = 8;  // chunk rounds of the block per window
 constexpr int kClaim = 4;     // work items a block claims at once
 static_assert(kChunk <= kColPad, "chunk tail must stay inside the padded columns");
 
-template <int MODE, bool kPV>
+template <int MODE, int kOut>
 __device__ __forceinline__ uint32_t chunk_hits(const int32_t* p, int len, const ProbeSet& ps, bool up_side,
-                                               int32_t x, int32_t oth, int64_t* pv) {
+                                               int32_t x, int32_t oth, const Out& o, int64_t ebase, int* s_pos) {
   int32_t v[kChunk];
 #pragma unroll
   for (int q = 0; q < kChunk; ++q) v[q] = p[q];
@@ -717,10 +747,17 @@ __device__ __forceinline__ uint32_t chunk_hits(const int32_t* p, int len, const 
     for (int q = 0; q < kChunk; ++q) hits |= probe<MODE>(ps, v[q], up_side) << q;
   }
   hits &= lenmask;
-  if (kPV && hits) {
+  if (kOut == kOutPV && hits) {
 #pragma unroll
     for (int q = 0; q < kChunk; ++q)
-      if ((hits >> q) & 1u) add_pv(pv, x, oth, v[q]);
+      if ((hits >> q) & 1u) add_pv(o.pv, x, oth, v[q]);
+  }
+  if (kOut == kOutEmit && hits) {
+    // the item's triangles fill [ebase, ebase + its count) in any order
+    int64_t at = ebase + atomicAdd(s_pos, __popc(hits));
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q)
+      if ((hits >> q) & 1u) write_tri(o, at++, x, oth, v[q]);
   }
   return static_cast<uint32_t>(__popc(hits));
 }
@@ -731,11 +768,11 @@ __device__ __forceinline__ uint32_t chunk_hits(const int32_t* p, int len, const 
 // the number of streams that start before it (s_tb) and a 64-bit mask of the
 // streams that start inside it (s_M).  Lane i of a wave then finds the
 // stream of its chunk as s_tb + popcount(mask bits <= i) - 1, with no search.
-template <int MODE, int THREADS, bool kPV>
+template <int MODE, int THREADS, int kOut>
 __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_cl, const int64_t* s_beg,
                                                const int32_t* s_oth, const uint8_t* s_up, uint64_t* s_M,
                                                int32_t* s_tb, const int32_t* lc, const ProbeSet& ps, int32_t x,
-                                               int64_t* pv) {
+                                               const Out& o, int64_t ebase, int* s_pos) {
   constexpr int kWin = THREADS * kWinIters;
   constexpr int kTiles = kWin / kWave;
   static_assert(THREADS % kWave == 0, "block must be whole waves");
@@ -776,8 +813,8 @@ __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_
         const int2 cl = s_cl[j];
         const int k = c - cl.x;
         const int32_t* p = lc + s_beg[j] + static_cast<int64_t>(k) * kChunk;
-        cnt += chunk_hits<MODE, kPV>(p, cl.y - k * kChunk, ps, MODE == kSearch && s_up[j] != 0, x,
-                                     kPV ? s_oth[j] : 0, pv);
+        cnt += chunk_hits<MODE, kOut>(p, cl.y - k * kChunk, ps, MODE == kSearch && s_up[j] != 0, x,
+                                      needs_oth(kOut) ? s_oth[j] : 0, o, ebase, s_pos);
       }
     }
     __syncthreads();
@@ -790,18 +827,19 @@ __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_
 // says whether the anchor's table is a bitmap or a hash table.  Stream records are
 // loaded D at a time (R per thread), the non-empty ones are compacted into
 // LDS with their first chunk, and run_chunks streams them.
-template <int WORDS, int THREADS, int D, int WPE, bool kPV>
+template <int WORDS, int THREADS, int D, int WPE, int kOut>
 __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, const VMeta* meta, int bin,
                                                         const int4* items, const int64_t* sbeg,
                                                         const int32_t* slen, const int32_t* soth,
-                                                        unsigned long long* acc, int64_t* pv) {
+                                                        unsigned long long* acc, Out o) {
   constexpr int R = D / THREADS;  // records loaded per thread
   static_assert(R * THREADS == D, "D must be a multiple of THREADS");
   constexpr int kTiles = THREADS * kWinIters / kWave;
   __shared__ uint32_t tab[WORDS > 0 ? WORDS : 1];
   __shared__ int64_t s_beg[D];
   __shared__ int2 s_cl[D + 1];  // (first chunk, length) of each non-empty stream
-  __shared__ int32_t s_oth[kPV ? D : 1];
+  __shared__ int32_t s_oth[needs_oth(kOut) ? D : 1];
+  __shared__ int s_pos;  // triangles of the current item written so far (kOutEmit)
   __shared__ uint8_t s_up[WORDS == 0 ? D : 1];
   __shared__ uint64_t s_M[kTiles];
   __shared__ int32_t s_tb[kTiles];
@@ -825,7 +863,8 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
     if (tid == 0) next = atomicAdd(&acc[kAccBinNext + bin], static_cast<unsigned long long>(kClaim));
     const unsigned long long claim_end = min(claim + kClaim, count);
     for (unsigned long long it = claim; it < claim_end; ++it) {
-    const int4 item = items[first + it];
+    const int64_t gi = static_cast<int64_t>(first + it);  // unit index of this item
+    const int4 item = items[gi];
     const int32_t x = item.x;
     const int64_t sa = static_cast<int64_t>(static_cast<uint32_t>(item.y)) | (static_cast<int64_t>(item.z) << 32);
     const int64_t sb = sa + (item.w & kItemCountMask);
@@ -874,6 +913,13 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
         builds += tid == 0 ? P : 0;
       }
     }
+    int64_t ebase = 0;
+    if (kOut == kOutEmit) {
+      ebase = o.uoff[gi];
+      if (tid == 0) s_pos = 0;
+      __syncthreads();
+    }
+    int64_t icnt = 0;
     for (int64_t bs = sa; bs < sb; bs += D) {
       const int nd = static_cast<int>(min(static_cast<int64_t>(D), sb - bs));
       int64_t lbeg[R];
@@ -893,7 +939,7 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
           lbeg[r] = sbeg[k];
           llen[r] = lf & kLenMask;
           lup[r] = (lf & kFlagUp) != 0;
-          if (kPV) loth[r] = soth[k];
+          if (needs_oth(kOut)) loth[r] = soth[k];
         }
         if (llen[r] > 0) {
           ++nne;
@@ -909,7 +955,7 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
         if (llen[r] <= 0) continue;
         s_cl[slot] = make_int2(cb, llen[r]);
         s_beg[slot] = lbeg[r];
-        if (kPV) s_oth[slot] = loth[r];
+        if (needs_oth(kOut)) s_oth[slot] = loth[r];
         if (WORDS == 0) s_up[slot] = lup[r] ? 1 : 0;
         cb += (llen[r] + kChunk - 1) / kChunk;
         ++slot;
@@ -917,12 +963,20 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
       if (tid == 0) s_cl[nslots] = make_int2(C, 0);
       __syncthreads();
       if (WORDS == 0) {
-        cnt += run_chunks<kSearch, THREADS, kPV>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, pv);
+        icnt += run_chunks<kSearch, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, o,
+                                                   ebase, &s_pos);
       } else if (mode == kBitmap) {
-        cnt += run_chunks<kBitmap, THREADS, kPV>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, pv);
+        icnt += run_chunks<kBitmap, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, o,
+                                                   ebase, &s_pos);
       } else {
-        cnt += run_chunks<kHash, THREADS, kPV>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, pv);
+        icnt += run_chunks<kHash, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, o,
+                                                 ebase, &s_pos);
       }
+    }
+    cnt += icnt;
+    if (kOut == kOutRec) {
+      const int64_t t = block_sum(icnt, sh);
+      if (tid == 0) o.ucnt[gi] = static_cast<int32_t>(t);
     }
     }
     __syncthreads();
@@ -930,6 +984,7 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
     __syncthreads();
     claim = s_item;
   }
+  if (kOut == kOutEmit) return;
   block_acc(acc, kAccT, cnt, sh);
   block_acc(acc, kAccHeavyElems, elems, sh);
   block_acc(acc, kAccBinElems + bin, elems, sh);
@@ -969,16 +1024,37 @@ __global__ void forward_meta_kernel(const int64_t* off, const int32_t* cols, int
 
 // WPE: waves per SIMD the kernel is compiled for (HIP's second launch
 // bound), matched to the blocks per CU that the bin's LDS allows.
-template <int WORDS, int THREADS, int D, int WPE, bool kPV>
-int launch_heavy(const CountArgs& a, CountWs& w, int bin, int blocks_per_cu, hipStream_t s) {
-  heavy_kernel<WORDS, THREADS, D, WPE, kPV><<<static_cast<unsigned>(num_cus() * blocks_per_cu), THREADS, 0, s>>>(
-      a.cols, a.meta, bin, w.items, w.sbeg, w.slen, w.soth, w.acc, a.per_vertex_out);
+template <int WORDS, int THREADS, int D, int WPE, int kOut>
+int launch_heavy(const CountArgs& a, CountWs& w, const Out& o, int bin, int blocks_per_cu, hipStream_t s) {
+  heavy_kernel<WORDS, THREADS, D, WPE, kOut><<<static_cast<unsigned>(num_cus() * blocks_per_cu), THREADS, 0, s>>>(
+      a.cols, a.meta, bin, w.items, w.sbeg, w.slen, w.soth, w.acc, o);
   TC_HIP(hipGetLastError());
   return TC_OK;
 }
 
-template <bool kCover, bool kPV>
-int launch_all(const CountArgs& a, CountWs& w, hipStream_t s) {
+// The four bins of heavy items side by side on forked streams.
+template <int kOut>
+int launch_bins(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
+  Fork* f = fork_for_device();
+  if (!f) return TC_ERR_HIP;
+  TC_TRY(fork_begin(f, s));
+  TC_TRY((launch_heavy<kBinWords2, 1024, 1024, 4, kOut>(a, w, o, 2, 1, s)));
+  TC_TRY((launch_heavy<kBinWords1, 512, 1024, 6, kOut>(a, w, o, 1, 3, f->aux[0])));
+  TC_TRY((launch_heavy<kBinWords0, 64, 256, 6, kOut>(a, w, o, 0, 24, f->aux[1])));
+  TC_TRY((launch_heavy<0, 512, 1024, 4, kOut>(a, w, o, 3, 4, f->aux[2])));
+  return fork_end(f, s);
+}
+
+template <int kOut>
+int launch_light(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
+  light_kernel<kOut><<<static_cast<unsigned>(num_cus() * 16), kThreads, 0, s>>>(
+      a.cols, a.meta, w.so, a.g->n, w.lpre, w.nchunk_cap, w.sbeg, w.slen, w.soth, w.sx, w.acc, o);
+  TC_HIP(hipGetLastError());
+  return TC_OK;
+}
+
+template <bool kCover, int kOut>
+int launch_all(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
   const int64_t n = a.g->n;
   const unsigned gv = grid_for(n, kThreads, 16384);
   const unsigned gp = static_cast<unsigned>(num_cus() * 16);
@@ -999,25 +1075,27 @@ int launch_all(const CountArgs& a, CountWs& w, hipStream_t s) {
     Carver sc(w.scratch);
     TC_TRY(scan_exclusive_strided(reinterpret_cast<const int32_t*>(w.ccnt) + 1, 4, w.lpre, w.nchunk_cap, sc, s));
   }
-  light_kernel<kPV><<<gp, kThreads, 0, s>>>(a.cols, a.meta, w.so, n, w.lpre, w.nchunk_cap, w.sbeg, w.slen, w.soth,
-                                            w.sx, w.acc, a.per_vertex_out);
-  TC_HIP(hipGetLastError());
   bin_split_kernel<false><<<gp, kThreads, 0, s>>>(w.so, n, w.ccnt, w.items_raw, w.items, w.acc);
   bin_offsets_kernel<<<1, 1, 0, s>>>(w.acc);
   bin_split_kernel<true><<<gp, kThreads, 0, s>>>(w.so, n, w.ccnt, w.items_raw, w.items, w.acc);
   TC_HIP(hipGetLastError());
+  // after the item split: kOutRec keeps its unit counts where the raw items were
+  TC_TRY(launch_light<kOut>(a, w, o, s));
   prof_stage("heavy");
-  // the bins are independent: run them side by side
-  Fork* f = fork_for_device();
-  if (!f) return TC_ERR_HIP;
-  TC_TRY(fork_begin(f, s));
-  TC_TRY((launch_heavy<kBinWords2, 1024, 1024, 4, kPV>(a, w, 2, 1, s)));
-  TC_TRY((launch_heavy<kBinWords1, 512, 1024, 6, kPV>(a, w, 1, 3, f->aux[0])));
-  TC_TRY((launch_heavy<kBinWords0, 64, 256, 6, kPV>(a, w, 0, 24, f->aux[1])));
-  TC_TRY((launch_heavy<0, 512, 1024, 4, kPV>(a, w, 3, 4, f->aux[2])));
-  TC_TRY(fork_end(f, s));
+  TC_TRY(launch_bins<kOut>(a, w, o, s));
   prof_stage("finish");
   return TC_OK;
+}
+
+// Unit counts and offsets of triangle finding live in the raw-item buffer,
+// which is dead once the items are split by bin: rcap int32 counts, then
+// rcap + 1 int64 offsets (12 rcap + 8 <= 16 rcap bytes for rcap >= 2).
+Out unit_out(CountWs& w) {
+  Out o{};
+  char* base = reinterpret_cast<char*>(w.items_raw);
+  o.ucnt = reinterpret_cast<int32_t*>(base);
+  o.uoff = reinterpret_cast<int64_t*>(base + ((4 * w.rcap + 7) & ~int64_t(7)));
+  return o;
 }
 
 }  // namespace
@@ -1044,7 +1122,8 @@ CountWs count_reserve(Carver& c, int64_t n, int64_t nnz) {
   w.lpre = c.take<int64_t>(w.nchunk_cap + 1);
   w.acc = c.take<unsigned long long>(kAccSlots);
   w.stats = c.take<int64_t>(24);
-  w.scratch = c.take<char>(scan_ws_bytes(n + w.nchunk_cap + 1) + 256);
+  // scans over vertices, over chunks and over the work units of triangle finding (<= rcap)
+  w.scratch = c.take<char>(scan_ws_bytes(std::max(n + w.nchunk_cap + 1, w.rcap)) + 256);
   return w;
 }
 
@@ -1061,17 +1140,46 @@ int count_run(const CountArgs& a, CountWs& w, int64_t* triangles, int64_t* h_cou
   TC_TRY(fill_i64(w.stats, 0, 24, s));
   prof_stage("plan");
   if (n > 0) {
-    if (a.cover) {
-      if (a.per_vertex) TC_TRY((launch_all<true, true>(a, w, s)));
-      else TC_TRY((launch_all<true, false>(a, w, s)));
-    } else {
-      if (a.per_vertex) TC_TRY((launch_all<false, true>(a, w, s)));
-      else TC_TRY((launch_all<false, false>(a, w, s)));
-    }
+    Out o = unit_out(w);
+    o.pv = a.per_vertex_out;
+    o.order = a.order;
+    if (!a.cover) TC_TRY((launch_all<false, kOutNone>(a, w, o, s)));
+    else if (a.record_units) TC_TRY((launch_all<true, kOutRec>(a, w, o, s)));
+    else if (a.per_vertex) TC_TRY((launch_all<true, kOutPV>(a, w, o, s)));
+    else TC_TRY((launch_all<true, kOutNone>(a, w, o, s)));
   }
   finish_kernel<<<1, 1, 0, s>>>(w.acc, w.so, n, w.lpre, w.nchunk_cap, triangles, h_count, w.stats);
   TC_HIP(hipGetLastError());
   return TC_OK;
+}
+
+int list_run(const CountArgs& a, CountWs& w, int32_t* tri, int64_t cap, int64_t* triangles, int64_t* h_count,
+             hipStream_t s) {
+  CountArgs ra = a;
+  ra.record_units = true;
+  ra.per_vertex = false;
+  TC_TRY(count_run(ra, w, triangles, h_count, s));
+  if (a.g->n == 0 || cap == 0) return TC_OK;
+  prof_stage("emit");
+  // pass two: every work unit writes its triangles at the scanned offset of
+  // its count (the number of units is read back first)
+  int64_t host[2] = {0, 0};
+  TC_HIP(hipMemcpyAsync(&host[0], w.acc + kAccItems, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipMemcpyAsync(&host[1], w.lpre + w.nchunk_cap, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  TC_HIP(hipStreamSynchronize(s));
+  const int64_t units = host[0] + host[1];
+  if (units < 0 || units > w.rcap) return TC_ERR_HIP;
+  Out o = unit_out(w);
+  o.tri = tri;
+  o.cap = cap;
+  o.order = a.order;
+  {
+    Carver sc(w.scratch);
+    TC_TRY(scan_exclusive<int32_t>(o.ucnt, const_cast<int64_t*>(o.uoff), units, sc, s));
+  }
+  TC_TRY(fill_i64(reinterpret_cast<int64_t*>(w.acc + kAccBinNext), 0, kBins, s));
+  TC_TRY(launch_light<kOutEmit>(a, w, o, s));
+  return launch_bins<kOutEmit>(a, w, o, s);
 }
 
 }  // namespace tc

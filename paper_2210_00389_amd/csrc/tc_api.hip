@@ -199,17 +199,13 @@ int tc_cover_edges(const tc_csr* g, const int32_t* levels, int32_t* h_u, int32_t
   return hlist_run(g, p.split.meta, p.split.scols, p.h_off, h_u, h_v, g->nnz / 2, h_count, p.hscratch, s);
 }
 
-int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles, int64_t* h_count, int32_t* levels,
-             int64_t* per_vertex, void* ws, size_t ws_bytes, tc_stream_t stream) {
-  TC_TRY(check_csr(g, "tc_count"));
-  if (!triangles) return fail(TC_ERR_INVALID_ARG, "tc_count: triangles is NULL");
-  if (root >= g->n || root < -1) return fail(TC_ERR_INVALID_ARG, "tc_count: root %lld out of range", (long long)root);
+namespace {
+
+// BFS, relabel and layout, then the count or (list) triangle finding into
+// tri[3 * cap].
+int cover_call(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles, int64_t* h_count, int32_t* levels,
+               int64_t* per_vertex, bool list, int32_t* tri, int64_t cap, void* ws, hipStream_t s) {
   const bool pv = flags & TC_PER_VERTEX;
-  if (pv && g->n > 0 && !per_vertex) return fail(TC_ERR_INVALID_ARG, "tc_count: per_vertex is NULL");
-  const size_t need = plan_count(nullptr, g->n, g->nnz).bytes;
-  TC_TRY(check_ws(ws, ws_bytes, need, "tc_count"));
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  CallScope scope(s);
   TC_TRY(maybe_validate(g, flags, ws, s));
   CountPlan p = plan_count(ws, g->n, g->nnz);
   int32_t* L = levels ? levels : p.L;
@@ -231,7 +227,9 @@ int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles, 
   a.cover = true;
   a.per_vertex = pv;
   a.per_vertex_out = p.pv_new;
-  TC_TRY(count_run(a, p.count, triangles, h_count, s));
+  a.order = p.relabel.order;
+  if (list) TC_TRY(list_run(a, p.count, tri, cap, triangles, h_count, s));
+  else TC_TRY(count_run(a, p.count, triangles, h_count, s));
   if (pv && g->n > 0) {
     pv_back_kernel<<<grid_for(g->n, 256, 16384), 256, 0, s>>>(p.pv_new, p.relabel.order, g->n, per_vertex);
     TC_HIP(hipGetLastError());
@@ -239,6 +237,48 @@ int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles, 
   stats_kernel<<<1, 1, 0, s>>>(p.stats, g->n, g->nnz, nl);
   TC_HIP(hipGetLastError());
   return TC_OK;
+}
+
+}  // namespace
+
+int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles, int64_t* h_count, int32_t* levels,
+             int64_t* per_vertex, void* ws, size_t ws_bytes, tc_stream_t stream) {
+  TC_TRY(check_csr(g, "tc_count"));
+  if (!triangles) return fail(TC_ERR_INVALID_ARG, "tc_count: triangles is NULL");
+  if (root >= g->n || root < -1) return fail(TC_ERR_INVALID_ARG, "tc_count: root %lld out of range", (long long)root);
+  const bool pv = flags & TC_PER_VERTEX;
+  if (pv && g->n > 0 && !per_vertex) return fail(TC_ERR_INVALID_ARG, "tc_count: per_vertex is NULL");
+  const size_t need = plan_count(nullptr, g->n, g->nnz).bytes;
+  TC_TRY(check_ws(ws, ws_bytes, need, "tc_count"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CallScope scope(s);
+  return cover_call(g, root, flags, triangles, h_count, levels, per_vertex, false, nullptr, 0, ws, s);
+}
+
+int tc_list_triangles(const tc_csr* g, int64_t root, uint32_t flags, int32_t* tri, int64_t cap, int64_t* triangles,
+                      int64_t* h_count, int32_t* levels, void* ws, size_t ws_bytes, tc_stream_t stream) {
+  TC_TRY(check_csr(g, "tc_list_triangles"));
+  if (!triangles) return fail(TC_ERR_INVALID_ARG, "tc_list_triangles: triangles is NULL");
+  if (cap < 0 || (cap > 0 && !tri)) return fail(TC_ERR_INVALID_ARG, "tc_list_triangles: bad output buffer");
+  if (flags & TC_PER_VERTEX) return fail(TC_ERR_INVALID_ARG, "tc_list_triangles: TC_PER_VERTEX not supported");
+  if (root >= g->n || root < -1)
+    return fail(TC_ERR_INVALID_ARG, "tc_list_triangles: root %lld out of range", (long long)root);
+  const size_t need = plan_count(nullptr, g->n, g->nnz).bytes;
+  TC_TRY(check_ws(ws, ws_bytes, need, "tc_list_triangles"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CallScope scope(s);
+  return cover_call(g, root, flags, triangles, h_count, levels, nullptr, true, tri, cap, ws, s);
+}
+
+int tc_edge_support(const tc_csr* g, const int32_t* tri, int64_t num_triangles, int32_t* support,
+                    tc_stream_t stream) {
+  TC_TRY(check_csr(g, "tc_edge_support"));
+  if (num_triangles < 0 || (num_triangles > 0 && !tri)) return fail(TC_ERR_INVALID_ARG, "tc_edge_support: bad list");
+  if (g->nnz > 0 && !support) return fail(TC_ERR_INVALID_ARG, "tc_edge_support: support is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CallScope scope(s);
+  prof_stage("support");
+  return support_run(g, tri, num_triangles, support, s);
 }
 
 int tc_count_edge_baseline(const tc_csr* g, uint32_t flags, int64_t* triangles, void* ws, size_t ws_bytes,

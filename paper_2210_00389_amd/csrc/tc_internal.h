@@ -136,9 +136,19 @@ struct CountArgs {
   bool cover;           // cover edges (three classes) or the comparator
   bool per_vertex;
   int64_t* per_vertex_out;
+  const int32_t* order = nullptr;  // layout id -> caller id (cover layout)
+  bool record_units = false;       // first pass of triangle finding
 };
 int count_run(const CountArgs& a, CountWs& w, int64_t* triangles, int64_t* h_count,
               hipStream_t s);
+// Triangle finding (cover layout): count_run recording per-unit counts, a
+// scan, and a second pass writing min(T, cap) triangles to tri[3 * cap] as
+// ascending caller ids.  Synchronises the stream once (unit count).
+int list_run(const CountArgs& a, CountWs& w, int32_t* tri, int64_t cap, int64_t* triangles, int64_t* h_count,
+             hipStream_t s);
+// Triangles per edge from a triangle list: support[e] for both CSR entries
+// of each of the three edges of every listed triangle (cleared first).
+int support_run(const tc_csr* g, const int32_t* tri, int64_t ntri, int32_t* support, hipStream_t s);
 
 // Comparator layout: meta with up = 0, hfb = first neighbour > x, sfe = deg.
 int forward_meta_run(const tc_csr* g, VMeta* meta, hipStream_t s);
