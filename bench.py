@@ -137,6 +137,7 @@ def bench_list(args):
     (count pass recording per-unit counts, offsets, write pass), then the
     per-edge supports from the list (tc_edge_support)."""
     import torch
+    import graphgen
     import paper_2210_00389_amd as tc
     dev = torch.device("cuda:0")
     g = graphgen.rmat(args.scale, args.edge_factor, seed=args.seed)
@@ -401,6 +402,8 @@ def main():
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--workload", choices=("rmat", "batch", "serving", "pmc", "list"), default="rmat")
+    ap.add_argument("--root-candidates", type=int, default=0,
+                    help="also choose the root by |H| among this many highest-degree vertices and time it")
     ap.add_argument("--summarize", action="store_true", help="summarise rocprofv3 output into --out(.md/.json)")
     ap.add_argument("--trace-dir", default=None)
     ap.add_argument("--fetch-dir", default=None)
@@ -526,6 +529,22 @@ def main():
             "cover_bytes": int(cmr.cover_bytes), "wedge_check_bytes": int(cmr.previous_bytes),
             "reduction": round(cmr.reduction, 2)}
 
+    root_choice = None
+    if args.root_candidates > 0:
+        # the paper's goal of the smallest k: choose the root among the
+        # highest-degree vertices by |H|, then time the count from it
+        log(f"[bench] root choice over {args.root_candidates} candidates")
+        t0 = time.perf_counter()
+        rc = tc.select_root(G, args.root_candidates, ws=ws)
+        t_sel = time.perf_counter() - t0
+        res_r = tc.count(G, root=rc.root, ws=ws)
+        wall_r, per_r, _ = run_timed(lambda: tc.count(G, root=rc.root, ws=ws, out=res_r), args.steps,
+                                     torch.cuda.synchronize)
+        assert res_r.T == T
+        root_choice = {"candidates": rc.candidates, "h": rc.h, "root": rc.root, "k": min(rc.h) / m,
+                       "k_default_root": h / m, "select_ms": 1000 * t_sel,
+                       "count_ms_chosen_root": 1000 * wall_r / args.steps}
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle sample")
@@ -550,6 +569,7 @@ def main():
         "work": st,
         "golden": golden,
         "comm_model": comm,
+        "root_choice": root_choice,
         "cpu_baseline": cpu,
     }
     line = json.dumps(out)

@@ -76,7 +76,8 @@ typedef enum tc_op {
   TC_OP_COUNT = 4,
   TC_OP_COUNT_BATCH = 5,
   TC_OP_EDGE_BASELINE = 6,
-  TC_OP_VALIDATE = 7
+  TC_OP_VALIDATE = 7,
+  TC_OP_SELECT_ROOT = 8
 } tc_op;
 
 /* A graph in CSR form (all pointers device). */
@@ -199,6 +200,24 @@ int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles,
 int tc_list_triangles(const tc_csr* g, int64_t root, uint32_t flags, int32_t* tri, int64_t cap,
                       int64_t* triangles, int64_t* h_count, int32_t* levels, void* ws,
                       size_t ws_bytes, tc_stream_t stream);
+
+/* Root choice for a small cover-edge set: the paper's goal is the
+ * cover-edge set with the smallest k = |H| / m, and H depends on the BFS
+ * root.  The candidates are the num_candidates vertices of largest degree
+ * (smallest id first on ties); for each, the levels of tc_bfs_levels with
+ * that root are computed and |H| is counted; the candidate with the
+ * smallest |H| is returned (the earlier one on ties).  Pass it as `root` to
+ * tc_count or tc_list_triangles (T does not depend on the root, Thm. 2).
+ *   num_candidates  1 .. TC_MAX_ROOT_CANDIDATES (fewer if n is smaller)
+ *   root_out        host int64 (output): the chosen root (-1 if n = 0)
+ *   candidates_out  host int64 [num_candidates] (nullable output)
+ *   h_out           host int64 [num_candidates] (nullable output): |H| of
+ *                   each candidate, in candidate order
+ * Workspace: TC_OP_SELECT_ROOT.  Synchronises `stream`. */
+#define TC_MAX_ROOT_CANDIDATES 64
+int tc_select_root(const tc_csr* g, int32_t num_candidates, uint32_t flags, int64_t* root_out,
+                   int64_t* candidates_out, int64_t* h_out, void* ws, size_t ws_bytes,
+                   tc_stream_t stream);
 
 /* Triangles per edge (the support of a k-truss decomposition) from a list
  * of triangles such as tc_list_triangles writes: support[e] = number of

@@ -22,6 +22,8 @@ OP_COUNT = 4
 OP_COUNT_BATCH = 5
 OP_EDGE_BASELINE = 6
 OP_VALIDATE = 7
+OP_SELECT_ROOT = 8
+MAX_ROOT_CANDIDATES = 64
 
 STATUS_NAMES = {
     0: "TC_OK", -1: "TC_ERR_INVALID_ARG", -2: "TC_ERR_WORKSPACE", -3: "TC_ERR_NOT_SORTED",
@@ -31,7 +33,8 @@ STATUS_NAMES = {
 
 EXPORTS = [
     "tc_workspace_bytes", "tc_build_csr", "tc_validate_csr", "tc_bfs_levels", "tc_cover_edges",
-    "tc_count", "tc_list_triangles", "tc_edge_support", "tc_count_edge_baseline", "tc_count_batch",
+    "tc_count", "tc_list_triangles", "tc_edge_support", "tc_select_root", "tc_count_edge_baseline",
+    "tc_count_batch",
     "tc_status_string", "tc_last_error",
     "tc_profile_enable", "tc_profile_read", "tc_read_stats",
 ]
@@ -97,6 +100,8 @@ def load(path: str | None = None):
     lib.tc_count.restype = c_int
     lib.tc_list_triangles.argtypes = [ctypes.POINTER(TcCsr), i64, u32, P, i64, P, P, P, P, sz, P]
     lib.tc_list_triangles.restype = c_int
+    lib.tc_select_root.argtypes = [ctypes.POINTER(TcCsr), i32, u32, P, P, P, P, sz, P]
+    lib.tc_select_root.restype = c_int
     lib.tc_edge_support.argtypes = [ctypes.POINTER(TcCsr), P, i64, P, P]
     lib.tc_edge_support.restype = c_int
     lib.tc_count_edge_baseline.argtypes = [ctypes.POINTER(TcCsr), u32, P, P, sz, P]

@@ -235,6 +235,31 @@ def list_triangles(g: Graph, root: int = -1, cap: int | None = None, validate: b
     return res
 
 
+@dataclass
+class RootChoice:
+    root: int                 # the candidate with the smallest |H|
+    candidates: list[int]     # largest degree first (smallest id on ties)
+    h: list[int]              # |H| with each candidate as root
+
+
+def select_root(g: Graph, num_candidates: int = 8, validate: bool = False, ws: Workspace | None = None,
+                stream=None) -> RootChoice:
+    """Root choice for a small cover-edge set (tc_select_root)."""
+    lib = L.load()
+    dev = g.cols.device
+    k = max(0, min(num_candidates, L.MAX_ROOT_CANDIDATES))
+    root = ctypes.c_int64(-1)
+    cand = (ctypes.c_int64 * max(k, 1))()
+    hs = (ctypes.c_int64 * max(k, 1))()
+    buf = (ws or default_workspace(dev)).get(workspace_bytes(L.OP_SELECT_ROOT, g.n, g.nnz))
+    csr = g.csr()
+    _check(lib.tc_select_root(ctypes.byref(csr), num_candidates, L.TC_VALIDATE if validate else 0,
+                              ctypes.byref(root), cand, hs, _ptr(buf), buf.numel(), _stream(stream)),
+           "tc_select_root")
+    used = min(k, g.n)
+    return RootChoice(int(root.value), list(cand[:used]), list(hs[:used]))
+
+
 def edge_support(g: Graph, tri: torch.Tensor, stream=None) -> torch.Tensor:
     """Triangles per CSR entry from a triangle list (tc_edge_support)."""
     lib = L.load()

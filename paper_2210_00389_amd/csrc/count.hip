@@ -962,19 +962,23 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
       }
       if (tid == 0) s_cl[nslots] = make_int2(C, 0);
       __syncthreads();
+      uint32_t got;
       if (WORDS == 0) {
-        icnt += run_chunks<kSearch, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, o,
-                                                   ebase, &s_pos);
-      } else if (mode == kBitmap) {
-        icnt += run_chunks<kBitmap, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, o,
-                                                   ebase, &s_pos);
-      } else {
-        icnt += run_chunks<kHash, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, o,
+        got = run_chunks<kSearch, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, o,
                                                  ebase, &s_pos);
+      } else if (mode == kBitmap) {
+        got = run_chunks<kBitmap, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, o,
+                                                 ebase, &s_pos);
+      } else {
+        got = run_chunks<kHash, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, o,
+                                               ebase, &s_pos);
       }
+      // the per-item count is kept only where it is recorded
+      if (kOut == kOutRec) icnt += got;
+      else cnt += got;
     }
-    cnt += icnt;
     if (kOut == kOutRec) {
+      cnt += icnt;
       const int64_t t = block_sum(icnt, sh);
       if (tid == 0) o.ucnt[gi] = static_cast<int32_t>(t);
     }

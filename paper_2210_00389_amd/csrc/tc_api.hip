@@ -143,6 +143,7 @@ size_t tc_workspace_bytes(int op, int64_t n, int64_t nnz, int32_t num_graphs) {
     case TC_OP_COUNT_BATCH: b = batch_ws_bytes(n, nnz, num_graphs); break;
     case TC_OP_EDGE_BASELINE: b = plan_baseline(nullptr, n, nnz).bytes; break;
     case TC_OP_VALIDATE: b = validate_ws_bytes(n, nnz); break;
+    case TC_OP_SELECT_ROOT: b = select_root_ws_bytes(n); break;
     default: return 0;
   }
   const size_t v = validate_ws_bytes(n, nnz);
@@ -268,6 +269,25 @@ int tc_list_triangles(const tc_csr* g, int64_t root, uint32_t flags, int32_t* tr
   hipStream_t s = static_cast<hipStream_t>(stream);
   CallScope scope(s);
   return cover_call(g, root, flags, triangles, h_count, levels, nullptr, true, tri, cap, ws, s);
+}
+
+int tc_select_root(const tc_csr* g, int32_t num_candidates, uint32_t flags, int64_t* root_out,
+                   int64_t* candidates_out, int64_t* h_out, void* ws, size_t ws_bytes, tc_stream_t stream) {
+  TC_TRY(check_csr(g, "tc_select_root"));
+  if (!root_out) return fail(TC_ERR_INVALID_ARG, "tc_select_root: root_out is NULL");
+  if (num_candidates < 1 || num_candidates > TC_MAX_ROOT_CANDIDATES)
+    return fail(TC_ERR_INVALID_ARG, "tc_select_root: num_candidates %d outside 1..%d", num_candidates,
+                TC_MAX_ROOT_CANDIDATES);
+  TC_TRY(check_ws(ws, ws_bytes, tc_workspace_bytes(TC_OP_SELECT_ROOT, g->n, g->nnz, 0), "tc_select_root"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CallScope scope(s);
+  TC_TRY(maybe_validate(g, flags, ws, s));
+  if (g->n == 0) {
+    *root_out = -1;
+    return TC_OK;
+  }
+  prof_stage("select_root");
+  return select_root_run(g, num_candidates, root_out, candidates_out, h_out, ws, s);
 }
 
 int tc_edge_support(const tc_csr* g, const int32_t* tri, int64_t num_triangles, int32_t* support,

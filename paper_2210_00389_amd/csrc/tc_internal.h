@@ -27,6 +27,12 @@ BfsWs bfs_reserve(Carver& c, int64_t n);
 int bfs_run(const tc_csr* g, int64_t root, int32_t* L, int32_t* num_levels, BfsWs& w,
             hipStream_t s, int32_t* first_levels = nullptr);
 
+// Root choice by |H| over the vertices of largest degree (root_select.hip).
+constexpr int kMaxRootCandidates = 64;
+size_t select_root_ws_bytes(int64_t n);
+int select_root_run(const tc_csr* g, int num, int64_t* root_out, int64_t* cand_out, int64_t* h_out, void* ws,
+                    hipStream_t s);
+
 // ------------------------------------------------------ radix sort
 // LSD radix sort of 64-bit keys on bits [bit_lo, bit_hi), 8 bits per pass,
 // stable.  Returns the buffer holding the result (keys or tmp).
