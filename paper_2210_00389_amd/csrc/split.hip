@@ -50,40 +50,49 @@ static_assert(kBigCap >= kSeg, "a segmented row has at least one full segment");
 enum RowCat { kRowShort = 0, kRowMid = 1, kRowBig = 2, kRowHuge = 3 };
 
 // ---------------------------------------------------------- layouts
-// A layout maps output row i to an input row and classifies its entries:
+// A row is written as [Up | Same | Down], each ascending in the output
+// numbering.  In the relabelled numbering every level is itself split in two
+// id ranges, vertices of degree at most kHubDeg first, then the others
+// (hubs), so each class region is two ascending runs: the layout is a
+// stable partition of the sorted input row into six groups
+//   0 up, 1 up hubs, 2 same, 3 same hubs, 4 down, 5 down hubs
+// (the identity layout uses groups 0, 2, 4 only).
+constexpr int kGroups = 6;
+constexpr int kNoGroup = 7;
+constexpr int kHubDeg = 2048;
+
+// A layout maps output row i to an input row and groups its entries:
 //   ctx(i)          per-row context
-//   cls(c, w, v)    class of input entry w (0 up, 1 same, 2 down); v gets
-//                   the value written to the output row
-//   recls(c, v)     the same class, from the output value v
+//   cls(c, w, v)    group of input entry w; v gets the value written out
+//   recls(c, v)     the same group, from the output value v
 struct RowCtx {
   int64_t ib, ie, ob;  // input range, output begin
   int32_t self;        // the row's own id in the output numbering
   int32_t key;         // the row's (virtual) level
-  int64_t lo, hi;      // same-level id window (relabelled layout)
+  int32_t b[5];        // relabelled: first id of groups 1..5 (ascending)
+  int32_t pad;
 };
+static_assert(sizeof(RowCtx) == 56, "row contexts are stored as seven int64 words");
 
 struct IdentityLayout {
   const int64_t* off;
   const int32_t* L;
   __device__ __forceinline__ RowCtx ctx(int64_t i) const {
-    RowCtx c;
+    RowCtx c{};
     c.ib = off[i];
     c.ie = off[i + 1];
     c.ob = c.ib;
     c.self = static_cast<int32_t>(i);
     c.key = L[i];
-    c.lo = c.hi = 0;
     return c;
+  }
+  __device__ __forceinline__ int recls(const RowCtx& c, int32_t v) const {
+    const int lv = L[v];
+    return lv < c.key ? 0 : (lv == c.key ? 2 : 4);
   }
   __device__ __forceinline__ int cls(const RowCtx& c, int32_t w, int32_t& v) const {
     v = w;
-    const int lw = L[w];
-    return lw < c.key ? 0 : (lw == c.key ? 1 : 2);
-  }
-  // class of an entry from its output value
-  __device__ __forceinline__ int recls(const RowCtx& c, int32_t v) const {
-    const int lv = L[v];
-    return lv < c.key ? 0 : (lv == c.key ? 1 : 2);
+    return recls(c, w);
   }
 };
 
@@ -95,9 +104,9 @@ struct RelabelLayout {
   const int32_t* L;
   const uint32_t* comp0;
   int32_t d0;
-  const int64_t* lstart;
+  const int64_t* gstart;  // first new id of each (virtual level, hub) group: 2 vl + hub
   __device__ __forceinline__ RowCtx ctx(int64_t i) const {
-    RowCtx c;
+    RowCtx c{};
     const int32_t x = order[i];
     c.ib = off[x];
     c.ie = off[x + 1];
@@ -105,18 +114,29 @@ struct RelabelLayout {
     c.self = static_cast<int32_t>(i);
     const int vl = L[x] + (((comp0[x >> 5] >> (x & 31)) & 1u) ? 0 : d0);
     c.key = vl;
-    c.lo = lstart[vl];
-    c.hi = lstart[vl + 1];
+    c.b[0] = static_cast<int32_t>(gstart[vl > 0 ? 2 * vl - 1 : 0]);
+#pragma unroll
+    for (int j = 1; j < 5; ++j) c.b[j] = static_cast<int32_t>(gstart[2 * vl + j - 1]);
     return c;
+  }
+  // every neighbour lies in the level above, the same or the level below
+  __device__ __forceinline__ int recls(const RowCtx& c, int32_t v) const {
+    return (v >= c.b[0]) + (v >= c.b[1]) + (v >= c.b[2]) + (v >= c.b[3]) + (v >= c.b[4]);
   }
   __device__ __forceinline__ int cls(const RowCtx& c, int32_t w, int32_t& v) const {
     v = perm[w];
     return recls(c, v);
   }
-  __device__ __forceinline__ int recls(const RowCtx& c, int32_t v) const { return v < c.lo ? 0 : (v < c.hi ? 1 : 2); }
 };
 
-// Rows of at most kShort entries: one thread; the row and the classes of its
+__device__ __forceinline__ bool is_same(int g) { return (g >> 1) == 1; }
+
+__device__ __forceinline__ VMeta row_meta(const RowCtx& c, const int (&cnt)[kGroups], int slt) {
+  const int up = cnt[0] + cnt[1], same = cnt[2] + cnt[3];
+  return VMeta{c.ob, up, up + slt, up + same, static_cast<int32_t>(c.ie - c.ib), {c.key, 0}};
+}
+
+// Rows of at most kShort entries: one thread; the row and the groups of its
 // entries are loaded into registers first (all gathers in flight at once),
 // then counted and scattered.
 template <class Lay>
@@ -139,22 +159,32 @@ __global__ __launch_bounds__(kThreads) void lay_short_kernel(Lay lay, const int3
     int32_t vv[kShort];
     int kc[kShort];
 #pragma unroll
-    for (int q = 0; q < kShort; ++q) kc[q] = q < deg ? lay.cls(c, wv[q], vv[q]) : 3;
-    int up = 0, same = 0, slt = 0;
+    for (int q = 0; q < kShort; ++q) {
+      vv[q] = 0;
+      kc[q] = q < deg ? lay.cls(c, wv[q], vv[q]) : kNoGroup;
+    }
+    int cnt[kGroups] = {0, 0, 0, 0, 0, 0};
+    int slt = 0;
 #pragma unroll
     for (int q = 0; q < kShort; ++q) {
-      up += kc[q] == 0;
-      same += kc[q] == 1;
-      slt += (kc[q] == 1) & (vv[q] < c.self);
+#pragma unroll
+      for (int g = 0; g < kGroups; ++g) cnt[g] += kc[q] == g;
+      slt += is_same(kc[q]) & (vv[q] < c.self);
     }
-    int pu = 0, ps = up, pd = up + same;
+    int pos[kGroups];
+    pos[0] = 0;
+#pragma unroll
+    for (int g = 1; g < kGroups; ++g) pos[g] = pos[g - 1] + cnt[g - 1];
 #pragma unroll
     for (int q = 0; q < kShort; ++q) {
-      if (kc[q] == 3) continue;
-      const int pos = kc[q] == 0 ? pu++ : (kc[q] == 1 ? ps++ : pd++);
-      out[c.ob + pos] = vv[q];
+      if (kc[q] == kNoGroup) continue;
+      int at = 0;
+#pragma unroll
+      for (int g = 0; g < kGroups; ++g)
+        if (kc[q] == g) at = pos[g]++;
+      out[c.ob + at] = vv[q];
     }
-    meta[i] = VMeta{c.ob, up, up + slt, up + same, deg, {c.key, 0}};
+    meta[i] = row_meta(c, cnt, slt);
   }
 }
 
@@ -183,56 +213,81 @@ __device__ __forceinline__ void load_part(const int32_t* cols, const RowCtx& c, 
   }
 }
 
-// Classes of a part (2 bits per entry in *kp, 3 = none) and its output ids;
-// returns the part's counts packed as up | same << 16 | same-below-x << 32
-// | down << 48 (each < 2^16).
+// Group counts of a wave's part (or of a row), 16 bits per field:
+// a = g0 | g1 << 16 | g2 << 32 | g3 << 48, b = g4 | g5 << 16 | same-below-x << 32.
+struct Counts {
+  uint64_t a, b;
+};
+constexpr uint64_t kF16 = 0xFFFF;
+
+__device__ __forceinline__ void unpack(const Counts& k, int (&cnt)[kGroups], int& slt) {
+#pragma unroll
+  for (int g = 0; g < 4; ++g) cnt[g] = static_cast<int>((k.a >> (16 * g)) & kF16);
+  cnt[4] = static_cast<int>(k.b & kF16);
+  cnt[5] = static_cast<int>((k.b >> 16) & kF16);
+  slt = static_cast<int>((k.b >> 32) & kF16);
+}
+
+// Groups of a part (3 bits per entry in *kp) and its output ids.
 template <class Lay, int R>
-__device__ __forceinline__ uint64_t classify_part(const Lay& lay, const RowCtx& c, const int32_t (&wv)[R],
-                                                  int32_t (&vv)[R], uint32_t* kp) {
-  uint32_t k2 = 0;
+__device__ __forceinline__ Counts classify_part(const Lay& lay, const RowCtx& c, const int32_t (&wv)[R],
+                                                int32_t (&vv)[R], uint64_t* kp) {
+  static_assert(3 * R <= 64, "group codes are packed in one 64-bit word");
+  uint64_t k3 = 0;
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     vv[u] = 0;
-    const int k = wv[u] >= 0 ? lay.cls(c, wv[u], vv[u]) : 3;
-    k2 |= static_cast<uint32_t>(k) << (2 * u);
+    const int k = wv[u] >= 0 ? lay.cls(c, wv[u], vv[u]) : kNoGroup;
+    k3 |= static_cast<uint64_t>(k) << (3 * u);
   }
-  uint64_t up = 0, same = 0, slt = 0, down = 0;
+  uint64_t cnt[kGroups] = {0, 0, 0, 0, 0, 0};
+  uint64_t slt = 0;
 #pragma unroll
   for (int u = 0; u < R; ++u) {
-    const uint32_t k = (k2 >> (2 * u)) & 3u;
-    up += __popcll(__ballot(k == 0));
-    same += __popcll(__ballot(k == 1));
-    slt += __popcll(__ballot((k == 1) & (vv[u] < c.self)));
-    down += __popcll(__ballot(k == 2));
+    const int k = static_cast<int>((k3 >> (3 * u)) & 7u);
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) cnt[g] += __popcll(__ballot(k == g));
+    slt += __popcll(__ballot(is_same(k) & (vv[u] < c.self)));
   }
-  *kp = k2;
-  return up | (same << 16) | (slt << 32) | (down << 48);
+  *kp = k3;
+  return Counts{cnt[0] | (cnt[1] << 16) | (cnt[2] << 32) | (cnt[3] << 48), cnt[4] | (cnt[5] << 16) | (slt << 32)};
 }
 
-// Scatter of a part: the class regions continue at pu / ps / pd (absolute
-// output positions); entries keep their order inside each class.
+// Scatter of a part: group g continues at p[g] (absolute output position);
+// entries keep their order inside each group.
 template <int R>
-__device__ __forceinline__ void write_part(const int32_t (&vv)[R], uint32_t k2, int64_t pu, int64_t ps, int64_t pd,
+__device__ __forceinline__ void write_part(const int32_t (&vv)[R], uint64_t k3, int64_t (&p)[kGroups],
                                            int32_t* out) {
   const uint64_t lt = lanemask_lt();
 #pragma unroll
   for (int u = 0; u < R; ++u) {
-    const uint32_t k = (k2 >> (2 * u)) & 3u;
-    const uint64_t mu = __ballot(k == 0), ms = __ballot(k == 1), md = __ballot(k == 2);
-    if (k == 0) out[pu + __popcll(mu & lt)] = vv[u];
-    else if (k == 1) out[ps + __popcll(ms & lt)] = vv[u];
-    else if (k == 2) out[pd + __popcll(md & lt)] = vv[u];
-    pu += __popcll(mu);
-    ps += __popcll(ms);
-    pd += __popcll(md);
+    const int k = static_cast<int>((k3 >> (3 * u)) & 7u);
+    uint64_t m[kGroups];
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) m[g] = __ballot(k == g);
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) {
+      if (k == g) out[p[g] + __popcll(m[g] & lt)] = vv[u];
+      p[g] += __popcll(m[g]);
+    }
   }
 }
 
-constexpr uint64_t kF16 = 0xFFFF;
+// Absolute group starts of a row from its counts, plus the offsets `before`
+// (counts of earlier parts of the same row) inside each group.
+__device__ __forceinline__ void group_starts(const RowCtx& c, const int (&tot)[kGroups], const int (&before)[kGroups],
+                                             int64_t (&p)[kGroups]) {
+  int64_t run = c.ob;
+#pragma unroll
+  for (int g = 0; g < kGroups; ++g) {
+    p[g] = run + before[g];
+    run += tot[g];
+  }
+}
 
 // Rows of up to R * 64 entries, one wave each.  The wave loads the context
-// and the columns of its next row before it classifies and writes the
-// current one, so the memory latencies of two rows overlap.
+// and the columns of its next row before it groups and writes the current
+// one, so the memory latencies of two rows overlap.
 template <class Lay, int R>
 __global__ __launch_bounds__(kThreads) void lay_mid_kernel(Lay lay, const int32_t* cols, const RowCtx* rows,
                                                            const int64_t* count, int32_t* out, VMeta* meta) {
@@ -250,15 +305,17 @@ __global__ __launch_bounds__(kThreads) void lay_mid_kernel(Lay lay, const int32_
     RowCtx cn = c;
     if (more) cn = rows[rn];
     int32_t vv[R];
-    uint32_t k2;
-    const uint64_t pk = classify_part<Lay, R>(lay, c, wv, vv, &k2);
+    uint64_t k3;
+    const Counts pk = classify_part<Lay, R>(lay, c, wv, vv, &k3);
     int32_t wn[R];
     if (more) load_part<R>(cols, cn, 0, wn);
-    const int up = static_cast<int>(pk & kF16), same = static_cast<int>((pk >> 16) & kF16);
-    const int slt = static_cast<int>((pk >> 32) & kF16);
-    const int deg = static_cast<int>(c.ie - c.ib);
-    if (lane() == 0) meta[c.self] = VMeta{c.ob, up, up + slt, up + same, deg, {c.key, 0}};
-    write_part<R>(vv, k2, c.ob, c.ob + up, c.ob + up + same, out);
+    int cnt[kGroups], slt;
+    unpack(pk, cnt, slt);
+    if (lane() == 0) meta[c.self] = row_meta(c, cnt, slt);
+    const int zero[kGroups] = {0, 0, 0, 0, 0, 0};
+    int64_t p[kGroups];
+    group_starts(c, cnt, zero, p);
+    write_part<R>(vv, k3, p, out);
     if (!more) break;
     r = rn;
     c = cn;
@@ -268,40 +325,45 @@ __global__ __launch_bounds__(kThreads) void lay_mid_kernel(Lay lay, const int32_
 }
 
 // Rows of up to WPR * R * 64 entries, one block of WPR waves each; wave q
-// holds entries [q * R * 64, (q + 1) * R * 64) and the waves' class counts
+// holds entries [q * R * 64, (q + 1) * R * 64) and the waves' group counts
 // are combined through LDS.
 template <class Lay, int WPR, int R>
 __global__ __launch_bounds__(WPR * kWave) void lay_block_kernel(Lay lay, const int32_t* cols, const RowCtx* rows,
                                                                 const int64_t* count, int32_t* out, VMeta* meta) {
   constexpr int kPart = R * kWave;
   static_assert(WPR * kPart < (1 << 16), "row counts are packed in 16-bit fields");
-  __shared__ uint64_t s_pk[WPR];
+  __shared__ uint64_t s_a[WPR], s_b[WPR];
   const int wave = threadIdx.x / kWave;
   const int64_t nrows = *count >> 32;
   for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
     const RowCtx c = rows[r];
     int32_t wv[R], vv[R];
-    uint32_t k2;
+    uint64_t k3;
     load_part<R>(cols, c, wave * kPart, wv);
-    const uint64_t pk = classify_part<Lay, R>(lay, c, wv, vv, &k2);
-    if (lane() == 0) s_pk[wave] = pk;
-    __syncthreads();
-    uint64_t before = 0, tot = 0;
-    for (int q = 0; q < WPR; ++q) {
-      const uint64_t x = s_pk[q];
-      if (q < wave) before += x;
-      tot += x;
+    const Counts pk = classify_part<Lay, R>(lay, c, wv, vv, &k3);
+    if (lane() == 0) {
+      s_a[wave] = pk.a;
+      s_b[wave] = pk.b;
     }
-    const int64_t up = static_cast<int64_t>(tot & kF16), same = static_cast<int64_t>((tot >> 16) & kF16);
-    const int64_t slt = static_cast<int64_t>((tot >> 32) & kF16);
-    const int deg = static_cast<int>(c.ie - c.ib);
-    if (threadIdx.x == 0)
-      meta[c.self] = VMeta{c.ob, static_cast<int>(up), static_cast<int>(up + slt), static_cast<int>(up + same), deg,
-                           {c.key, 0}};
-    write_part<R>(vv, k2, c.ob + static_cast<int64_t>(before & kF16),
-                  c.ob + up + static_cast<int64_t>((before >> 16) & kF16),
-                  c.ob + up + same + static_cast<int64_t>((before >> 48) & kF16), out);
-    __syncthreads();  // s_pk is rewritten for the next row
+    __syncthreads();
+    Counts before{0, 0}, tot{0, 0};
+    for (int q = 0; q < WPR; ++q) {
+      const uint64_t xa = s_a[q], xb = s_b[q];
+      if (q < wave) {
+        before.a += xa;
+        before.b += xb;
+      }
+      tot.a += xa;
+      tot.b += xb;
+    }
+    int cnt[kGroups], slt, bef[kGroups], bslt;
+    unpack(tot, cnt, slt);
+    unpack(before, bef, bslt);
+    if (threadIdx.x == 0) meta[c.self] = row_meta(c, cnt, slt);
+    int64_t p[kGroups];
+    group_starts(c, cnt, bef, p);
+    write_part<R>(vv, k3, p, out);
+    __syncthreads();  // s_a, s_b are rewritten for the next row
   }
 }
 
@@ -313,7 +375,10 @@ __global__ void seg_vtx_kernel(const int32_t* nseg, const int64_t* seg_off, int6
   }
 }
 
-// One wave per segment of a long row: class counts of the segment.
+constexpr int kSegCnt = kGroups + 1;  // per segment: group counts, then same-below-x
+
+// One wave per segment of a long row: group counts of the segment; the
+// output ids are kept (stash) for the scatter pass.
 template <class Lay>
 __global__ __launch_bounds__(kThreads) void lay_seg_count_kernel(Lay lay, const int32_t* cols, int64_t n,
                                                                  const int64_t* seg_off, const int32_t* seg_vtx,
@@ -327,7 +392,8 @@ __global__ __launch_bounds__(kThreads) void lay_seg_count_kernel(Lay lay, const 
     const int64_t s = sg - seg_off[i];
     const int64_t b = c.ib + s * kSeg;
     const int64_t e = min(c.ie, b + kSeg);
-    int up = 0, same = 0, slt = 0;
+    int cnt[kGroups] = {0, 0, 0, 0, 0, 0};
+    int slt = 0;
     for (int64_t j0 = b; j0 < e; j0 += kRounds * kWave) {
       int32_t wv[kRounds];
 #pragma unroll
@@ -337,44 +403,57 @@ __global__ __launch_bounds__(kThreads) void lay_seg_count_kernel(Lay lay, const 
       }
 #pragma unroll
       for (int u = 0; u < kRounds; ++u) {
-        int k = 3;
+        int k = kNoGroup;
         int32_t v = 0;
         if (wv[u] >= 0) {
           k = lay.cls(c, wv[u], v);
           stash[j0 + u * kWave + lane()] = v;  // the scatter pass reads the ids back instead of gathering again
         }
-        up += __popcll(__ballot(k == 0));
-        same += __popcll(__ballot(k == 1));
-        slt += __popcll(__ballot((k == 1) & (v < c.self)));
+#pragma unroll
+        for (int g = 0; g < kGroups; ++g) cnt[g] += __popcll(__ballot(k == g));
+        slt += __popcll(__ballot(is_same(k) & (v < c.self)));
       }
     }
-    if (lane() == 0) {
-      seg_cnt[3 * sg + 0] = up;
-      seg_cnt[3 * sg + 1] = same;
-      seg_cnt[3 * sg + 2] = slt;
+    if (lane() < kSegCnt) {
+      int x = slt;
+#pragma unroll
+      for (int g = 0; g < kGroups; ++g)
+        if (lane() == g) x = cnt[g];
+      seg_cnt[kSegCnt * sg + lane()] = x;
     }
   }
 }
 
-// Per long row: prefix of its segments' counts, and the row record.
+// Per segmented row: the row record, and per segment the absolute output
+// position of each of its groups.
 template <class Lay>
 __global__ void lay_seg_prefix_kernel(Lay lay, int64_t n, const int32_t* nseg, const int64_t* seg_off,
-                                      const int32_t* seg_cnt, int32_t* seg_pre, VMeta* meta) {
+                                      const int32_t* seg_cnt, int64_t* seg_pre, VMeta* meta) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int k = nseg[i];
     if (k == 0) continue;
     const int64_t s0 = seg_off[i];
-    int up = 0, same = 0, slt = 0;
+    int tot[kGroups] = {0, 0, 0, 0, 0, 0};
+    int slt = 0;
     for (int j = 0; j < k; ++j) {
-      const int64_t sg = s0 + j;
-      seg_pre[3 * sg + 0] = up;
-      seg_pre[3 * sg + 1] = same;
-      up += seg_cnt[3 * sg + 0];
-      same += seg_cnt[3 * sg + 1];
-      slt += seg_cnt[3 * sg + 2];
+      const int32_t* sc = seg_cnt + kSegCnt * (s0 + j);
+#pragma unroll
+      for (int g = 0; g < kGroups; ++g) tot[g] += sc[g];
+      slt += sc[kGroups];
     }
     const RowCtx c = lay.ctx(i);
-    meta[i] = VMeta{c.ob, up, up + slt, up + same, static_cast<int32_t>(c.ie - c.ib), {c.key, 0}};
+    meta[i] = row_meta(c, tot, slt);
+    int64_t p[kGroups];
+    const int zero[kGroups] = {0, 0, 0, 0, 0, 0};
+    group_starts(c, tot, zero, p);
+    for (int j = 0; j < k; ++j) {
+      const int32_t* sc = seg_cnt + kSegCnt * (s0 + j);
+#pragma unroll
+      for (int g = 0; g < kGroups; ++g) {
+        seg_pre[kGroups * (s0 + j) + g] = p[g];
+        p[g] += sc[g];
+      }
+    }
   }
 }
 
@@ -382,43 +461,31 @@ __global__ void lay_seg_prefix_kernel(Lay lay, int64_t n, const int32_t* nseg, c
 template <class Lay>
 __global__ __launch_bounds__(kThreads) void lay_seg_write_kernel(Lay lay, const int32_t* stash, int64_t n,
                                                                  const int64_t* seg_off, const int32_t* seg_vtx,
-                                                                 const int32_t* seg_pre, const VMeta* meta,
-                                                                 int32_t* out) {
+                                                                 const int64_t* seg_pre, int32_t* out) {
   const int64_t nsegs = seg_off[n];
   const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  const uint64_t lt = lanemask_lt();
   for (int64_t sg = wid; sg < nsegs; sg += nw) {
     const int32_t i = seg_vtx[sg];
     const RowCtx c = lay.ctx(i);
     const int64_t s = sg - seg_off[i];
     const int64_t b = c.ib + s * kSeg;
     const int64_t e = min(c.ie, b + kSeg);
-    const VMeta m = meta[i];
-    int64_t pu = seg_pre[3 * sg + 0];
-    int64_t ps = m.up + seg_pre[3 * sg + 1];
-    int64_t pd = m.sfe + (s * kSeg - seg_pre[3 * sg + 0] - seg_pre[3 * sg + 1]);
+    int64_t p[kGroups];
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) p[g] = seg_pre[kGroups * sg + g];
     for (int64_t j0 = b; j0 < e; j0 += kRounds * kWave) {
       int32_t vv[kRounds];
-      int kc[kRounds];
+      uint64_t k3 = 0;
 #pragma unroll
       for (int u = 0; u < kRounds; ++u) {
         const int64_t j = j0 + u * kWave + lane();
         vv[u] = j < e ? stash[j] : -1;
       }
 #pragma unroll
-      for (int u = 0; u < kRounds; ++u) kc[u] = vv[u] >= 0 ? lay.recls(c, vv[u]) : 3;
-#pragma unroll
-      for (int u = 0; u < kRounds; ++u) {
-        const int k = kc[u];
-        const uint64_t mu = __ballot(k == 0), ms = __ballot(k == 1), md = __ballot(k == 2);
-        if (k == 0) out[c.ob + pu + __popcll(mu & lt)] = vv[u];
-        else if (k == 1) out[c.ob + ps + __popcll(ms & lt)] = vv[u];
-        else if (k == 2) out[c.ob + pd + __popcll(md & lt)] = vv[u];
-        pu += __popcll(mu);
-        ps += __popcll(ms);
-        pd += __popcll(md);
-      }
+      for (int u = 0; u < kRounds; ++u)
+        k3 |= static_cast<uint64_t>(vv[u] >= 0 ? lay.recls(c, vv[u]) : kNoGroup) << (3 * u);
+      write_part<kRounds>(vv, k3, p, out);
     }
   }
 }
@@ -446,8 +513,7 @@ int layout_run(const Lay& lay, const int32_t* cols, int64_t n, SplitWs& w, hipSt
   seg_vtx_kernel<<<gv, kThreads, 0, s>>>(w.nseg, w.seg_off, n, w.seg_vtx);
   lay_seg_count_kernel<Lay><<<gw, kThreads, 0, s>>>(lay, cols, n, w.seg_off, w.seg_vtx, w.seg_cnt, w.stash);
   lay_seg_prefix_kernel<Lay><<<gv, kThreads, 0, s>>>(lay, n, w.nseg, w.seg_off, w.seg_cnt, w.seg_pre, w.meta);
-  lay_seg_write_kernel<Lay><<<gw, kThreads, 0, s>>>(lay, w.stash, n, w.seg_off, w.seg_vtx, w.seg_pre, w.meta,
-                                                    w.scols);
+  lay_seg_write_kernel<Lay><<<gw, kThreads, 0, s>>>(lay, w.stash, n, w.seg_off, w.seg_vtx, w.seg_pre, w.scols);
   TC_HIP(hipGetLastError());
   return TC_OK;
 }
@@ -458,28 +524,36 @@ __device__ __forceinline__ int vlevel(const int32_t* L, const uint32_t* comp0, i
   return L[v] + (((comp0[v >> 5] >> (v & 31)) & 1u) ? 0 : d0);
 }
 
-__global__ __launch_bounds__(kThreads) void vl_hist_kernel(const int32_t* L, const uint32_t* comp0, int32_t d0,
-                                                           int64_t n, int32_t nvl, int32_t* cnt) {
+// Relabel group of a vertex: 2 * virtual level + (degree > kHubDeg).
+__device__ __forceinline__ int vgroup(const int64_t* off, const int32_t* L, const uint32_t* comp0, int32_t d0,
+                                      int64_t v) {
+  return 2 * vlevel(L, comp0, d0, v) + ((off[v + 1] - off[v]) > kHubDeg ? 1 : 0);
+}
+
+__global__ __launch_bounds__(kThreads) void vl_hist_kernel(const int64_t* off, const int32_t* L,
+                                                           const uint32_t* comp0, int32_t d0, int64_t n,
+                                                           int32_t ngroups, int32_t* cnt) {
   constexpr int kLds = 1024;
   __shared__ int32_t h[kLds];
-  const bool local = nvl <= kLds;
+  const bool local = ngroups <= kLds;
   if (local)
-    for (int i = threadIdx.x; i < nvl; i += kThreads) h[i] = 0;
+    for (int i = threadIdx.x; i < ngroups; i += kThreads) h[i] = 0;
   __syncthreads();
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const int vl = vlevel(L, comp0, d0, v);
-    if (local) atomicAdd(&h[vl], 1);
-    else atomicAdd(&cnt[vl], 1);
+    const int gr = vgroup(off, L, comp0, d0, v);
+    if (local) atomicAdd(&h[gr], 1);
+    else atomicAdd(&cnt[gr], 1);
   }
   __syncthreads();
   if (local)
-    for (int i = threadIdx.x; i < nvl; i += kThreads)
+    for (int i = threadIdx.x; i < ngroups; i += kThreads)
       if (h[i]) atomicAdd(&cnt[i], h[i]);
 }
 
-__global__ void vl_keys_kernel(const int32_t* L, const uint32_t* comp0, int32_t d0, int64_t n, uint64_t* keys) {
+__global__ void vl_keys_kernel(const int64_t* off, const int32_t* L, const uint32_t* comp0, int32_t d0, int64_t n,
+                               uint64_t* keys) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    keys[v] = (static_cast<uint64_t>(vlevel(L, comp0, d0, v)) << 32) | static_cast<uint64_t>(v);
+    keys[v] = (static_cast<uint64_t>(vgroup(off, L, comp0, d0, v)) << 32) | static_cast<uint64_t>(v);
 }
 
 __global__ void order_kernel(const uint64_t* sorted, int64_t n, const int64_t* off, int32_t* order, int32_t* perm,
@@ -541,14 +615,15 @@ SplitWs split_reserve(Carver& c, int64_t n, int64_t nnz) {
   // Segmented rows have deg > kBigCap entries and ceil(deg / kSeg) <= deg / kSeg + deg / kBigCap segments.
   const int64_t max_segs = nnz / kSeg + nnz / kBigCap + 2;
   w.seg_vtx = c.take<int32_t>(max_segs + 1);
-  w.seg_cnt = c.take<int32_t>(3 * max_segs + 3);
-  w.seg_pre = c.take<int32_t>(3 * max_segs + 3);
+  w.seg_cnt = c.take<int32_t>(kSegCnt * (max_segs + 1));
+  w.seg_pre = c.take<int64_t>(kGroups * (max_segs + 1));
   w.ctr = c.take<int64_t>(4);
   w.rcat = c.take<int32_t>(n + 1);
   w.cat_pre = c.take<int64_t>(n + 1);
-  static_assert(sizeof(RowCtx) == 6 * sizeof(int64_t), "row contexts are stored as six int64 words");
-  w.mid_ctx = c.take<int64_t>(6 * (std::min(n, nnz / (kShort + 1)) + 2));
-  w.big_ctx = c.take<int64_t>(6 * (nnz / (kMidCap + 1) + 2));
+  constexpr int kCtxWords = sizeof(RowCtx) / sizeof(int64_t);
+  static_assert(sizeof(RowCtx) == kCtxWords * sizeof(int64_t), "row contexts are whole int64 words");
+  w.mid_ctx = c.take<int64_t>(kCtxWords * (std::min(n, nnz / (kShort + 1)) + 2));
+  w.big_ctx = c.take<int64_t>(kCtxWords * (nnz / (kMidCap + 1) + 2));
   w.stash = c.take<int32_t>(nnz + 1);
   w.scratch = c.take<char>(scan_ws_bytes(n + 1));
   return w;
@@ -566,8 +641,9 @@ RelabelWs relabel_reserve(Carver& c, int64_t n, int64_t max_vlevels) {
   w.order = c.take<int32_t>(n + 1);
   w.perm = c.take<int32_t>(n + 1);
   w.off = c.take<int64_t>(n + 2);
-  w.lstart_cnt = c.take<int32_t>(max_vlevels + 2);
-  w.lstart = c.take<int64_t>(max_vlevels + 3);
+  // two groups per virtual level, plus the two (empty) groups of the level after the last
+  w.lstart_cnt = c.take<int32_t>(2 * max_vlevels + 4);
+  w.lstart = c.take<int64_t>(2 * max_vlevels + 5);
   w.keys = c.take<uint64_t>(n + 1);
   w.keys_tmp = c.take<uint64_t>(n + 1);
   w.deg = c.take<int32_t>(n + 1);
@@ -581,18 +657,26 @@ int relabel_run(const tc_csr* g, const int32_t* L, const uint32_t* comp0, int32_
   const int64_t n = g->n;
   if (n == 0) return TC_OK;
   const unsigned gv = grid_for(n, kThreads, 16384);
-  TC_TRY(fill_i32(w.lstart_cnt, 0, nvl + 1, s));
+  // New ids: by virtual level, inside a level the vertices of degree at most
+  // kHubDeg first, then the others, each part in id order.  The counting
+  // test compares ids only inside one level, and any total order there gives
+  // the same H (as a set), T and per-vertex counts: a triangle with one
+  // horizontal edge is counted at that edge, an all-horizontal one {a, b, c}
+  // once, at its first edge with its last vertex as apex.  Putting the hubs
+  // last keeps their forward same-level lists short.
+  const int32_t ngroups = 2 * (nvl + 1);
+  TC_TRY(fill_i32(w.lstart_cnt, 0, ngroups + 1, s));
   // few blocks: each adds its LDS histogram to the shared counts once
   vl_hist_kernel<<<grid_for(n, kThreads, static_cast<unsigned>(num_cus() * 2)), kThreads, 0, s>>>(
-      L, comp0, d0, n, nvl, w.lstart_cnt);
+      g->row_offsets, L, comp0, d0, n, ngroups, w.lstart_cnt);
   TC_HIP(hipGetLastError());
   {
     Carver sc(w.scratch);
-    TC_TRY(scan_exclusive<int32_t>(w.lstart_cnt, w.lstart, nvl, sc, s));
+    TC_TRY(scan_exclusive<int32_t>(w.lstart_cnt, w.lstart, ngroups, sc, s));
   }
-  vl_keys_kernel<<<gv, kThreads, 0, s>>>(L, comp0, d0, n, w.keys);
+  vl_keys_kernel<<<gv, kThreads, 0, s>>>(g->row_offsets, L, comp0, d0, n, w.keys);
   int bits = 0;
-  while ((int64_t(1) << bits) < nvl) ++bits;
+  while ((int64_t(1) << bits) < ngroups) ++bits;
   uint64_t* sorted = w.keys;
   TC_TRY(radix_sort_u64(w.keys, w.keys_tmp, n, 32, 32 + bits, w.scratch, s, &sorted));
   order_kernel<<<gv, kThreads, 0, s>>>(sorted, n, g->row_offsets, w.order, w.perm, w.deg);

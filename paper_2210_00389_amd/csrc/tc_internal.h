@@ -62,12 +62,12 @@ struct SplitWs {
   int32_t* nseg;      // per vertex: segments of a long row
   int64_t* seg_off;   // scan of nseg
   int32_t* seg_vtx;   // segment -> vertex
-  int32_t* seg_cnt;   // per segment: up, same, same-below-x counts (x3)
-  int32_t* seg_pre;   // per segment: prefix of the three counts (x3)
+  int32_t* seg_cnt;   // per segment: six group counts and same-below-x (x7)
+  int64_t* seg_pre;   // per segment: output position of each group (x6)
   int64_t* ctr;
   int32_t* rcat;      // per vertex: row category (short, mid, big, segmented)
   int64_t* cat_pre;   // packed scans of the mid (low half) / big (high half) categories
-  int64_t* mid_ctx;   // per-row contexts of each category (six words per row)
+  int64_t* mid_ctx;   // per-row contexts of each category (seven words per row)
   int64_t* big_ctx;
   int32_t* stash;     // output ids of segmented rows, in input order [nnz]
   char* scratch;
@@ -87,8 +87,8 @@ struct RelabelWs {
   int32_t* order;     // new id -> old id
   int32_t* perm;      // old id -> new id
   int64_t* off;       // relabelled row offsets [n + 1]
-  int32_t* lstart_cnt;  // virtual-level histogram
-  int64_t* lstart;    // virtual-level starts
+  int32_t* lstart_cnt;  // histogram of (virtual level, hub) groups
+  int64_t* lstart;    // first new id of each group
   uint64_t* keys;
   uint64_t* keys_tmp;
   int32_t* deg;
