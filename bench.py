@@ -281,7 +281,7 @@ def traffic_record(scale):
     """Counter-measured HBM bytes per heavy-stage launch, from the committed
     summary of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a
     1 GiB copy; None when missing or taken on another kernel source."""
-    path = os.path.join(ROOT, "profiles", f"heavy_rmat{scale}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"heavy_rmat{scale}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
