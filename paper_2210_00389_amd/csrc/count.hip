@@ -126,13 +126,11 @@ struct Out {
 
 __host__ __device__ constexpr bool needs_oth(int k) { return k == kOutPV || k == kOutEmit; }
 
+// a and b are caller ids already (mapped once per task or stream), c is a
+// layout id.
 __device__ __forceinline__ void write_tri(const Out& o, int64_t at, int32_t a, int32_t b, int32_t c) {
   if (at >= o.cap) return;
-  if (o.order) {
-    a = o.order[a];
-    b = o.order[b];
-    c = o.order[c];
-  }
+  if (o.order) c = o.order[c];
   int32_t t;
   if (a > b) { t = a; a = b; b = t; }
   if (b > c) { t = b; b = c; c = t; }
@@ -142,7 +140,10 @@ __device__ __forceinline__ void write_tri(const Out& o, int64_t at, int32_t a, i
   o.tri[3 * at + 2] = c;
 }
 
-// One triangle {x, oth, w} found by a thread that writes sequentially.
+__device__ __forceinline__ int32_t caller_id(const Out& o, int32_t v) { return o.order ? o.order[v] : v; }
+
+// One triangle {x, oth, w} found by a thread that writes sequentially (for
+// kOutEmit x and oth are caller ids, w a layout id).
 template <int kOut>
 __device__ __forceinline__ void on_hit(const Out& o, int32_t x, int32_t oth, int32_t w, int64_t& at) {
   if (kOut == kOutPV) add_pv(o.pv, x, oth, w);
@@ -549,6 +550,9 @@ __global__ __launch_bounds__(kThreads) void light_kernel(const int32_t* lc, cons
     const int32_t lf = slen[pos];
     const int32_t oth = needs_oth(kOut) ? soth[pos] : 0;
     int64_t at = kOut == kOutEmit ? o.uoff[ubase + i] : 0;
+    // the ids a hit reports: caller ids when writing triangles
+    const int32_t hx = kOut == kOutEmit ? caller_id(o, x) : x;
+    const int32_t ho = kOut == kOutEmit ? caller_id(o, oth) : oth;
     int64_t tc = 0;
     const VMeta mx = meta[x];
     const int len = lf & kLenMask;
@@ -569,7 +573,7 @@ __global__ __launch_bounds__(kThreads) void light_kernel(const int32_t* lc, cons
 #pragma unroll
         for (int j = 0; j < kLightMax; ++j) m |= sv[q] == pr[j];
         tc += m;
-        if (m) on_hit<kOut>(o, x, oth, sv[q], at);
+        if (m) on_hit<kOut>(o, hx, ho, sv[q], at);
       }
       elems += len;
     } else {
@@ -590,7 +594,7 @@ __global__ __launch_bounds__(kThreads) void light_kernel(const int32_t* lc, cons
       for (int q = 0; q < kLightMax; ++q) {
         const bool m = q < np && lo[q] < len && S[lo[q]] == pr[q];
         tc += m;
-        if (m) on_hit<kOut>(o, x, oth, pr[q], at);
+        if (m) on_hit<kOut>(o, hx, ho, pr[q], at);
       }
       elems += np;
     }
@@ -752,9 +756,21 @@ __device__ __forceinline__ uint32_t chunk_hits(const int32_t* p, int len, const 
     for (int q = 0; q < kChunk; ++q)
       if ((hits >> q) & 1u) add_pv(o.pv, x, oth, v[q]);
   }
-  if (kOut == kOutEmit && hits) {
-    // the item's triangles fill [ebase, ebase + its count) in any order
-    int64_t at = ebase + atomicAdd(s_pos, __popc(hits));
+  if (kOut == kOutEmit) {
+    // The item's triangles fill [ebase, ebase + its count) in any order; a
+    // wave takes one range per round and its lanes write consecutive parts
+    // of it (called by every lane of the wave).
+    const int nh = __popc(hits);
+    int incl = nh;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int t = __shfl_up(incl, d, kWave);
+      if (lane() >= d) incl += t;
+    }
+    int wbase = 0;
+    if (lane() == kWave - 1 && incl > 0) wbase = atomicAdd(s_pos, incl);
+    wbase = __shfl(wbase, kWave - 1, kWave);
+    int64_t at = ebase + wbase + (incl - nh);
 #pragma unroll
     for (int q = 0; q < kChunk; ++q)
       if ((hits >> q) & 1u) write_tri(o, at++, x, oth, v[q]);
@@ -804,7 +820,28 @@ __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_
     for (int i = 0; i < kWinIters; ++i) {
       const int rel = i * THREADS + tid;
       const int c = w0 + rel;
-      if (c < C) {
+      if (kOut == kOutEmit) {
+        // the whole wave takes part (the writes are placed by a wave scan);
+        // lanes past the end probe nothing
+        const int32_t* p = lc;
+        int len = 0;
+        int32_t ot = 0;
+        bool upside = false;
+        if (c < C) {
+          const int t = rel >> 6;
+          const uint64_t M = s_M[t];
+          const int below = static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+              static_cast<uint32_t>(M >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(M), 0u)));
+          const int j = s_tb[t] + below + static_cast<int>((M >> ln) & 1ull) - 1;
+          const int2 cl = s_cl[j];
+          const int k = c - cl.x;
+          p = lc + s_beg[j] + static_cast<int64_t>(k) * kChunk;
+          len = cl.y - k * kChunk;
+          ot = s_oth[j];
+          upside = MODE == kSearch && s_up[j] != 0;
+        }
+        cnt += chunk_hits<MODE, kOut>(p, len, ps, upside, x, ot, o, ebase, s_pos);
+      } else if (c < C) {
         const int t = rel >> 6;
         const uint64_t M = s_M[t];
         const int below = static_cast<int>(__builtin_amdgcn_mbcnt_hi(
@@ -914,7 +951,9 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
       }
     }
     int64_t ebase = 0;
+    int32_t hx = x;  // the anchor as hits report it (a caller id when writing triangles)
     if (kOut == kOutEmit) {
+      hx = caller_id(o, x);
       ebase = o.uoff[gi];
       if (tid == 0) s_pos = 0;
       __syncthreads();
@@ -939,7 +978,7 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
           lbeg[r] = sbeg[k];
           llen[r] = lf & kLenMask;
           lup[r] = (lf & kFlagUp) != 0;
-          if (needs_oth(kOut)) loth[r] = soth[k];
+          if (needs_oth(kOut)) loth[r] = kOut == kOutEmit ? caller_id(o, soth[k]) : soth[k];
         }
         if (llen[r] > 0) {
           ++nne;
@@ -964,13 +1003,13 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
       __syncthreads();
       uint32_t got;
       if (WORDS == 0) {
-        got = run_chunks<kSearch, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, o,
+        got = run_chunks<kSearch, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
                                                  ebase, &s_pos);
       } else if (mode == kBitmap) {
-        got = run_chunks<kBitmap, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, o,
+        got = run_chunks<kBitmap, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
                                                  ebase, &s_pos);
       } else {
-        got = run_chunks<kHash, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, x, o,
+        got = run_chunks<kHash, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
                                                ebase, &s_pos);
       }
       // the per-item count is kept only where it is recorded
