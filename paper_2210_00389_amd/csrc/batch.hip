@@ -16,9 +16,11 @@
 //
 // Kernel 2 (persistent, pieces claimed from a counter): a wave takes one
 // vertex u at a time, sets the bits of N(u) in its own 65536-bit LDS bitmap,
-// and for every cover edge (u, v), v > u with equal parity, streams N(v)
-// flattened across the lanes and counts the w whose bit is set and that pass
-// the test of Alg. 1 (parity of w differs from u's, or w > v).  Counts and
+// and for every cover edge (u, v), v > u with equal parity, streams N(v) in
+// chunks of kBChunk consecutive entries per lane (the stream of a lane's
+// chunk comes from a 64-bit mask of stream starts, no search) and counts the
+// w whose bit is set and that pass the test of Alg. 1 (parity of w differs
+// from u's, or w > v).  Counts and
 // |H| are reduced per block and added to the graph's outputs.
 #include "tc_internal.h"
 
@@ -198,6 +200,18 @@ __global__ __launch_bounds__(kBfsThreads) void batch_bfs_kernel(const int64_t* v
 
 __device__ __forceinline__ uint32_t par_bit(const uint32_t* p, int32_t i) { return (p[i >> 5] >> (i & 31)) & 1u; }
 
+constexpr int kBChunk = 8;  // consecutive list entries a lane takes at once
+
+__device__ __forceinline__ uint64_t wave_or_u64(uint64_t x) {
+  uint32_t lo = static_cast<uint32_t>(x), hi = static_cast<uint32_t>(x >> 32);
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    lo |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(lo), d, kWave));
+    hi |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(hi), d, kWave));
+  }
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vbase, const int64_t* row_offsets,
                                                               const int32_t* cols, const uint32_t* parity,
@@ -206,7 +220,8 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
   constexpr int NW = THREADS / kWave;
   __shared__ uint32_t s_par[kBitmapWords];
   __shared__ uint32_t s_bm[NW][kBitmapWords];
-  __shared__ int32_t s_off[NW][kWave + 1];
+  __shared__ int32_t s_off[NW][kWave];  // first chunk of each compacted stream
+  __shared__ int32_t s_len[NW][kWave];
   __shared__ int64_t s_beg[NW][kWave];
   __shared__ int32_t s_v[NW][kWave];
   __shared__ int64_t sh[NW + 1];
@@ -265,23 +280,44 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
               ++hc;
             }
           }
-          const int incl = wave_incl_scan(len);
-          const int total = __shfl(incl, kWave - 1, kWave);
-          s_off[wv][ln] = incl - len;
-          s_beg[wv][ln] = vb;
-          s_v[wv][ln] = v;
-          if (ln == 0) s_off[wv][kWave] = total;
+          // N(v) of these edges in chunks of kBChunk consecutive entries;
+          // the non-empty streams are compacted in LDS with their first chunk
+          const int nch = (len + kBChunk - 1) / kBChunk;
+          const uint64_t ne = __ballot(nch > 0);
+          const int incl = wave_incl_scan(nch);
+          const int cst = incl - nch;
+          const int C = __shfl(incl, kWave - 1, kWave);
+          if (nch > 0) {
+            const int r = __popcll(ne & lanemask_lt());
+            s_beg[wv][r] = vb;
+            s_v[wv][r] = v;
+            s_off[wv][r] = cst;
+            s_len[wv][r] = len;
+          }
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          for (int e = ln; e < total; e += kWave) {
-            int lo = 0, hi = kWave;  // last j with s_off[j] <= e
-            while (hi - lo > 1) {
-              const int mid = (lo + hi) >> 1;
-              if (s_off[wv][mid] <= e) lo = mid;
-              else hi = mid;
+          for (int t0 = 0; t0 < C; t0 += kWave) {
+            // streams whose first chunk lies in [t0, t0 + 64): a 64-bit mask of
+            // those first chunks, and the number of streams begun before t0;
+            // lane i's chunk t0 + i then belongs to stream
+            // before + |{starts <= i}| - 1
+            const bool starts_here = nch > 0 && cst >= t0 && cst < t0 + kWave;
+            const uint64_t M = wave_or_u64(starts_here ? (1ull << (cst - t0)) : 0ull);
+            const int before = __popcll(__ballot(nch > 0 && cst < t0));
+            const int c = t0 + ln;
+            if (c < C) {
+              const int j = before + __popcll(M & ((2ull << ln) - 1ull)) - 1;
+              const int kk = c - s_off[wv][j];
+              const int64_t p0 = s_beg[wv][j] + static_cast<int64_t>(kk) * kBChunk;
+              const int rem = s_len[wv][j] - kk * kBChunk;
+              const int32_t vv = s_v[wv][j];
+              int32_t w[kBChunk];
+#pragma unroll
+              for (int q = 0; q < kBChunk; ++q) w[q] = q < rem ? cols[p0 + q] : -1;
+#pragma unroll
+              for (int q = 0; q < kBChunk; ++q)
+                if (w[q] >= 0 && ((bm[w[q] >> 5] >> (w[q] & 31)) & 1u) && (par_bit(s_par, w[q]) != pu || w[q] > vv))
+                  ++cnt;
             }
-            const int32_t w = cols[s_beg[wv][lo] + (e - s_off[wv][lo])];
-            const int32_t vv = s_v[wv][lo];
-            if (((bm[w >> 5] >> (w & 31)) & 1u) && (par_bit(s_par, w) != pu || w > vv)) ++cnt;
           }
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
