@@ -342,7 +342,7 @@ def summarize(args):
             grp = heavy[i:i + 4]
             spans.append((max(int(r["End_Timestamp"]) for r in grp) - min(int(r["Start_Timestamp"]) for r in grp)) / 1e6)
         if spans:
-            out_md += ["", f"Heavy stage (four bin kernels launched side by side) span per call, ms: "
+            out_md += ["", f"Heavy stage (the four bin kernels: in sequence for the cover count, side by side for the comparator) span per call, ms: "
                            f"{', '.join(f'{x:.3f}' for x in spans)}; mean {statistics.mean(spans):.3f}", ""]
             rec["heavy_span_ms"] = spans
     if args.fetch_dir and args.write_dir:
