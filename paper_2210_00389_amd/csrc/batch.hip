@@ -218,7 +218,6 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
                                                               const int4* pieces, int64_t nslots,
                                                               unsigned long long* ctr, int64_t* T, int64_t* H) {
   constexpr int NW = THREADS / kWave;
-  __shared__ uint32_t s_par[kBitmapWords];
   __shared__ uint32_t s_bm[NW][kBitmapWords];
   __shared__ int32_t s_off[NW][kWave];  // first chunk of each compacted stream
   __shared__ int32_t s_len[NW][kWave];
@@ -230,7 +229,6 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
   const int tid = threadIdx.x, wv = tid / kWave, ln = lane();
   uint32_t* bm = s_bm[wv];
   for (int i = ln; i < kBitmapWords; i += kWave) bm[i] = 0u;
-  int cur_g = -1;
   if (tid == 0) s_claim = atomicAdd(ctr, static_cast<unsigned long long>(kClaim));
   __syncthreads();
   unsigned long long claim = s_claim;
@@ -245,12 +243,10 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
       const int64_t v0 = vbase[g];
       const int n = static_cast<int>(vbase[g + 1] - v0);
       const int64_t* rows = row_offsets + v0;
-      if (g != cur_g) {
-        __syncthreads();
-        const uint32_t* par = parity + parity_base(v0, g);
-        for (int i = tid; i < (n + 31) / 32; i += THREADS) s_par[i] = par[i];
-        cur_g = g;
-      }
+      // the graph's parity bits stay in global memory (at most 8 KB, cached):
+      // keeping them out of LDS leaves room for more blocks per CU
+      const uint32_t* s_par = parity + parity_base(v0, g);
+      (void)n;
       if (tid == 0) s_next = pc.y;
       __syncthreads();
       int64_t cnt = 0, hc = 0;
@@ -391,8 +387,8 @@ int batch_run(const tc_batch* b, const tc_tuning* t, uint32_t flags, int64_t* tr
   if (threads != 256 && threads != 512)
     return fail(TC_ERR_INVALID_ARG, "tc_count_batch: batch_block must be 256 or 512 (got %d)", threads);
   if (piece < kPieceMin) return fail(TC_ERR_INVALID_ARG, "tc_count_batch: batch_piece must be >= %d", kPieceMin);
-  // LDS per block: parity and one bitmap per wave of 8 KB, plus staging
-  const int max_bpc = threads == 256 ? 3 : 2;
+  // LDS per block: one bitmap per wave of 8 KB, plus staging
+  const int max_bpc = threads == 256 ? 4 : 2;  // blocks that fit a CU's LDS
   if (bpc <= 0 || bpc > max_bpc) bpc = max_bpc;
   BatchPlan p = plan_batch(ws, b->total_vertices, b->total_nnz, G);
   if (ws_bytes < p.bytes) return fail(TC_ERR_WORKSPACE, "tc_count_batch: workspace %zu < %zu", ws_bytes, p.bytes);
