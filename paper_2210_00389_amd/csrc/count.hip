@@ -233,6 +233,7 @@ __global__ __launch_bounds__(kThreads) void plan_kernel(const int32_t* lc, const
 // anchors go to the light list (from the back), merged by light_kernel.
 constexpr int kResThreads = 256;
 constexpr int kResPer = 2;  // descriptors per thread, resolved in lockstep
+constexpr int kSampStride = 32;  // one column sample per 128-byte line
 constexpr int kResChunk = kResThreads * kResPer;
 constexpr int kResRecs = 2 * kResChunk;
 constexpr int kResSpan = 2 * kResChunk;  // vertex offsets staged in LDS
@@ -250,8 +251,8 @@ enum DescKind { kDown = 0, kFwd = 1, kBwd = 2, kNone = 3 };
 // lockstep over the descriptors so that their dependent loads (neighbour
 // id, its record, the search of x in Hfwd(u)) are in flight together.
 template <bool kCover>
-__device__ __forceinline__ void describe_all(const int32_t* lc, const VMeta* meta, const int32_t* x,
-                                             const VMeta* mx, const int* kin, Task* ta, Task* tb) {
+__device__ __forceinline__ void describe_all(const int32_t* lc, const int32_t* samp, const VMeta* meta,
+                                             const int32_t* x, const VMeta* mx, const int* kin, Task* ta, Task* tb) {
   int kind[kResPer], k[kResPer];
   int32_t nb[kResPer];
 #pragma unroll
@@ -295,6 +296,48 @@ __device__ __forceinline__ void describe_all(const int32_t* lc, const VMeta* met
       hi[j] = mo[j].begin + mo[j].sfe;
     }
   }
+  // First over the column samples (every kSampStride-th column, a compact
+  // array): the first sampled block start >= x narrows the range to one
+  // block, so the search touches about two cache lines instead of one per
+  // halving of a long list.
+  {
+    int64_t blo[kResPer], bhi[kResPer];
+#pragma unroll
+    for (int j = 0; j < kResPer; ++j) {
+      blo[j] = (lo[j] + kSampStride - 1) / kSampStride;  // samples inside [lo, hi)
+      bhi[j] = srch[j] ? (hi[j] - 1) / kSampStride + 1 : blo[j];
+      if (bhi[j] < blo[j]) bhi[j] = blo[j];
+    }
+    const int64_t b0[kResPer] = {blo[0], blo[1]};
+    static_assert(kResPer == 2, "the sample search is written for two descriptors");
+    for (;;) {  // first sample index in [blo, bhi) whose value is >= x
+      bool any = false;
+      int32_t v[kResPer];
+      int64_t mid[kResPer];
+#pragma unroll
+      for (int j = 0; j < kResPer; ++j) {
+        mid[j] = blo[j] + ((bhi[j] - blo[j]) >> 1);
+        v[j] = blo[j] < bhi[j] ? samp[mid[j]] : 0;
+      }
+#pragma unroll
+      for (int j = 0; j < kResPer; ++j) {
+        if (!(blo[j] < bhi[j])) continue;
+        if (v[j] < x[j]) blo[j] = mid[j] + 1;
+        else bhi[j] = mid[j];
+        any |= blo[j] < bhi[j];
+      }
+      if (!any) break;
+    }
+#pragma unroll
+    for (int j = 0; j < kResPer; ++j) {
+      if (!srch[j]) continue;
+      // samples b0 .. blo-1 are < x, so entries up to (blo-1) * stride are < x;
+      // the sample at blo (if inside the range) is >= x
+      if (blo[j] > b0[j]) lo[j] = (blo[j] - 1) * kSampStride + 1;
+      const int64_t cap = blo[j] * kSampStride;
+      if (cap < hi[j]) hi[j] = cap;
+    }
+  }
   for (;;) {
     bool any = false;
     int32_t v[kResPer];
@@ -334,6 +377,13 @@ __device__ __forceinline__ void describe_all(const int32_t* lc, const VMeta* met
   }
 }
 
+// Column samples for the searches of the resolution: samp[b] = lc[b * kSampStride].
+__global__ void sample_kernel(const int32_t* lc, int64_t nnz, int32_t* samp) {
+  const int64_t nb = (nnz + kSampStride - 1) / kSampStride;
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb; b += (int64_t)gridDim.x * blockDim.x)
+    samp[b] = lc[b * kSampStride];
+}
+
 // First vertex of every chunk of kResChunk descriptors: chunk c starts at
 // descriptor c * kResChunk, owned by the vertex x with so[x] <= it < so[x+1].
 // cx0[nchunks] = n - 1 closes the last chunk.
@@ -355,8 +405,9 @@ __global__ void chunk_start_kernel(const int64_t* so, int64_t n, int32_t* cx0) {
 // descriptor order (j-major).
 template <bool kCover>
 __global__ __launch_bounds__(kResThreads) void resolve_kernel(
-    const int32_t* lc, const VMeta* meta, const uint8_t* vinfo, const int64_t* so, const int32_t* cx0, int64_t n,
-    int64_t* sbeg, int32_t* slen, int32_t* soth, int32_t* sx, int4* items_raw, int4* ccnt) {
+    const int32_t* lc, const int32_t* samp, const VMeta* meta, const uint8_t* vinfo, const int64_t* so,
+    const int32_t* cx0, int64_t n, int64_t* sbeg, int32_t* slen, int32_t* soth, int32_t* sx, int4* items_raw,
+    int4* ccnt) {
   __shared__ int64_t sh[kResThreads / kWave + 1];
   __shared__ int64_t s_so[kResSpan];
   __shared__ int32_t s_x[kResRecs];
@@ -409,7 +460,7 @@ __global__ __launch_bounds__(kResThreads) void resolve_kernel(
       heavy[j] = (vinfo[xi[j]] & kViHeavy) != 0;
     }
     Task ta[kResPer], tb[kResPer];
-    describe_all<kCover>(lc, meta, xi, mx, kk, ta, tb);
+    describe_all<kCover>(lc, samp, meta, xi, mx, kk, ta, tb);
     // ---- counts: light tasks, heavy records, heavy elements (per j, j-major)
     int64_t nl = 0, nh = 0;
     int64_t he[kResPer];
@@ -1124,8 +1175,10 @@ int launch_all(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
   chunk_start_kernel<<<gv, kThreads, 0, s>>>(w.so, n, w.cx0);
   TC_HIP(hipGetLastError());
   prof_stage("resolve");
-  resolve_kernel<kCover><<<gp, kResThreads, 0, s>>>(a.cols, a.meta, w.vinfo, w.so, w.cx0, n, w.sbeg, w.slen, w.soth,
-                                                    w.sx, w.items_raw, w.ccnt);
+  sample_kernel<<<grid_for(a.g->nnz / kSampStride + 1, kThreads, 16384), kThreads, 0, s>>>(a.cols, a.g->nnz,
+                                                                                           w.samp);
+  resolve_kernel<kCover><<<gp, kResThreads, 0, s>>>(a.cols, w.samp, a.meta, w.vinfo, w.so, w.cx0, n, w.sbeg, w.slen,
+                                                    w.soth, w.sx, w.items_raw, w.ccnt);
   TC_HIP(hipGetLastError());
   {
     Carver sc(w.scratch);
@@ -1176,6 +1229,7 @@ CountWs count_reserve(Carver& c, int64_t n, int64_t nnz) {
   w.cx0 = c.take<int32_t>(w.nchunk_cap + 1);
   w.ccnt = c.take<int4>(w.nchunk_cap);
   w.lpre = c.take<int64_t>(w.nchunk_cap + 1);
+  w.samp = c.take<int32_t>(nnz / kSampStride + 2);
   w.acc = c.take<unsigned long long>(kAccSlots);
   w.stats = c.take<int64_t>(24);
   // scans over vertices, over chunks and over the work units of triangle finding (<= rcap)

@@ -127,6 +127,7 @@ struct CountWs {
   int32_t* cx0;        // first vertex of every descriptor chunk
   int4* ccnt;          // per chunk: heavy records, light tasks, items
   int64_t* lpre;       // scan of the per-chunk light task counts
+  int32_t* samp;       // every 32nd layout column, for the searches of the resolution
   int64_t nchunk_cap;
   int64_t rcap;
   unsigned long long* acc;
