@@ -1139,7 +1139,12 @@ int launch_bins(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
   if (a.cover) {
     TC_TRY((launch_heavy<kBinWords2, 1024, 1024, 4, kOut>(a, w, o, 2, 1, s)));
     TC_TRY((launch_heavy<kBinWords1, 512, 1024, 6, kOut>(a, w, o, 1, 3, s)));
-    TC_TRY((launch_heavy<kBinWords0, 64, 256, 6, kOut>(a, w, o, 0, 24, s)));
+    // Bin 0 (tables of 2 KB): on smaller graphs its items are short (about
+    // 500 elements at R-MAT S20) and two waves per block with half the
+    // blocks finish sooner (0.16 ms of 2.05 at S20); on large graphs (2400
+    // elements per item at S24) one wave per block and 24 blocks per CU do.
+    if (a.g->nnz < (int64_t(1) << 27)) TC_TRY((launch_heavy<kBinWords0, 128, 256, 6, kOut>(a, w, o, 0, 12, s)));
+    else TC_TRY((launch_heavy<kBinWords0, 64, 256, 6, kOut>(a, w, o, 0, 24, s)));
     return launch_heavy<0, 512, 1024, 4, kOut>(a, w, o, 3, 4, s);
   }
   Fork* f = fork_for_device();
