@@ -250,16 +250,37 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
       if (tid == 0) s_next = pc.y;
       __syncthreads();
       int64_t cnt = 0, hc = 0;
-      for (;;) {
-        int u = 0;
-        if (ln == 0) u = atomicAdd(&s_next, 1);
-        u = __shfl(u, 0, kWave);
-        if (u >= pc.z) break;
-        const int64_t ru = rows[u], du = rows[u + 1] - ru;
+      // one vertex ahead: the next vertex's row bounds, and for a row of at
+      // most 64 entries its neighbours, are loaded while the current vertex
+      // is counted; a short row's neighbours stay in registers (one a lane)
+      int u = 0;
+      if (ln == 0) u = atomicAdd(&s_next, 1);
+      u = __shfl(u, 0, kWave);
+      int64_t ru = 0, du = 0;
+      int32_t nbr = -1;
+      if (u < pc.z) {
+        ru = rows[u];
+        du = rows[u + 1] - ru;
+        if (du <= kWave && ln < du) nbr = cols[ru + ln];
+      }
+      while (u < pc.z) {
+        int un = 0;
+        if (ln == 0) un = atomicAdd(&s_next, 1);
+        un = __shfl(un, 0, kWave);
+        int64_t run = 0, dun = 0;
+        if (un < pc.z) {
+          run = rows[un];
+          dun = rows[un + 1] - run;
+        }
         const uint32_t pu = par_bit(s_par, u);
-        for (int64_t k = ln; k < du; k += kWave) {
-          const int32_t w = cols[ru + k];
-          atomicOr(&bm[w >> 5], 1u << (w & 31));
+        const bool shortrow = du <= kWave;
+        if (shortrow) {
+          if (nbr >= 0) atomicOr(&bm[nbr >> 5], 1u << (nbr & 31));
+        } else {
+          for (int64_t k = ln; k < du; k += kWave) {
+            const int32_t w = cols[ru + k];
+            atomicOr(&bm[w >> 5], 1u << (w & 31));
+          }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         for (int64_t base = 0; base < du; base += kWave) {
@@ -269,7 +290,7 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
           int len = 0;
           int64_t vb = 0;
           if (k < du) {
-            v = cols[ru + k];
+            v = shortrow ? nbr : cols[ru + k];
             if (v > u && par_bit(s_par, v) == pu) {
               vb = rows[v];
               len = static_cast<int>(rows[v + 1] - vb);
@@ -317,8 +338,19 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
           }
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
-        for (int64_t k = ln; k < du; k += kWave) bm[cols[ru + k] >> 5] = 0u;
+        if (shortrow) {
+          if (nbr >= 0) bm[nbr >> 5] = 0u;
+        } else {
+          for (int64_t k = ln; k < du; k += kWave) bm[cols[ru + k] >> 5] = 0u;
+        }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // the next vertex's neighbours (short rows) for the next round
+        int32_t nbn = -1;
+        if (un < pc.z && dun <= kWave && ln < dun) nbn = cols[run + ln];
+        u = un;
+        ru = run;
+        du = dun;
+        nbr = nbn;
       }
       cnt = block_sum(cnt, sh);
       hc = block_sum(hc, sh);
