@@ -96,6 +96,32 @@ def read_profile():
     return tc.profile_read()
 
 
+def stream_bandwidth(torch, dev, nbytes=1 << 30, reps=5):
+    """What plain streaming reaches on this device: a device-to-device copy
+    (reads and writes nbytes each) and a read-only float32 sum over nbytes,
+    median of reps launches timed with events on the current stream.  The
+    buffers are 4x the 256 MB last-level cache, so both stream from HBM."""
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+
+    def timed(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b) / 1000.0)
+        return statistics.median(ts)
+    t_copy = timed(lambda: y.copy_(x))
+    t_read = timed(lambda: x.sum())
+    del x, y
+    return {"bytes": nbytes, "copy_GBps": round(2 * nbytes / t_copy / 1e9, 1),
+            "read_GBps": round(nbytes / t_read / 1e9, 1)}
+
+
 def cpu_baseline(g, n, m, budget_s):
     """Oracle on the host: full BFS + cover edges, count over a row prefix."""
     import numpy as np
@@ -400,6 +426,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle count in the CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--no-stream", action="store_true", help="skip the copy/read bandwidth reference")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--workload", choices=("rmat", "batch", "serving", "pmc", "list"), default="rmat")
     ap.add_argument("--root-candidates", type=int, default=0,
@@ -529,6 +556,13 @@ def main():
             "cover_bytes": int(cmr.cover_bytes), "wedge_check_bytes": int(cmr.previous_bytes),
             "reduction": round(cmr.reduction, 2)}
 
+    stream = None
+    if not args.no_stream:
+        log("[bench] copy/read bandwidth reference")
+        stream = stream_bandwidth(torch, dev)
+        if roof is not None:
+            stream["dominant_vs_copy"] = round(roof["achieved"] / stream["copy_GBps"], 4)
+
     root_choice = None
     if args.root_candidates > 0:
         # the paper's goal of the smallest k: choose the root among the
@@ -565,6 +599,7 @@ def main():
         "comparator": comp,
         "speedup_vs_comparator": (comp["ms_per_step"] / ms) if comp else None,
         "roofline": roof,
+        "stream_bw": stream,
         "stages": stage_roofs,
         "work": st,
         "golden": golden,

@@ -628,24 +628,29 @@ __global__ __launch_bounds__(kThreads) void light_kernel(const int32_t* lc, cons
       }
       elems += len;
     } else {
-      // lower bound of every probe id in S, all at once
-      int lo[kLightMax];
+      // probes in groups of 8: lower bound of each in S by binary lifting
+      for (int q0 = 0; q0 < np; q0 += 8) {
+        int32_t pv[8];
+        int lo[8];
 #pragma unroll
-      for (int q = 0; q < kLightMax; ++q) lo[q] = 0;
-      for (int step = 1 << (31 - __clz(len)); step > 0; step >>= 1) {
-#pragma unroll
-        for (int q = 0; q < kLightMax; ++q) {
-          // binary lifting over powers of two: lo ends as |{s in S : s < p}|
-          const int probe_at = lo[q] + step - 1;
-          const int32_t v = probe_at < len ? S[probe_at] : 0x7FFFFFFF;
-          if (v < pr[q]) lo[q] += step;
+        for (int j = 0; j < 8; ++j) {
+          pv[j] = q0 + j < np ? P[q0 + j] : 0x7FFFFFFF;
+          lo[j] = 0;
         }
-      }
+        for (int step = 1 << (31 - __clz(len)); step > 0; step >>= 1) {
 #pragma unroll
-      for (int q = 0; q < kLightMax; ++q) {
-        const bool m = q < np && lo[q] < len && S[lo[q]] == pr[q];
-        tc += m;
-        if (m) on_hit<kOut>(o, hx, ho, pr[q], at);
+          for (int j = 0; j < 8; ++j) {
+            const int probe_at = lo[j] + step - 1;
+            const int32_t v = (q0 + j < np && probe_at < len) ? S[probe_at] : 0x7FFFFFFF;
+            if (v < pv[j]) lo[j] += step;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const bool m = q0 + j < np && lo[j] < len && S[lo[j]] == pv[j];
+          tc += m;
+          if (m) on_hit<kOut>(o, hx, ho, pv[j], at);
+        }
       }
       elems += np;
     }
@@ -915,7 +920,7 @@ __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_
 // says whether the anchor's table is a bitmap or a hash table.  Stream records are
 // loaded D at a time (R per thread), the non-empty ones are compacted into
 // LDS with their first chunk, and run_chunks streams them.
-template <int WORDS, int THREADS, int D, int WPE, int kOut>
+template <int WORDS, int THREADS, int D, int WPE, int kOut, bool kRoundRobin>
 __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, const VMeta* meta, int bin,
                                                         const int4* items, const int64_t* sbeg,
                                                         const int32_t* slen, const int32_t* soth,
@@ -942,14 +947,20 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
   int32_t cur_x = -1;
   // blocks claim kClaim consecutive items at a time (consecutive items of
   // one anchor share the table); the next claim is fetched while the
-  // current one is processed
-  if (tid == 0) s_item = atomicAdd(&acc[kAccBinNext + bin], static_cast<unsigned long long>(kClaim));
+  // current one is processed.  kRoundRobin: block b takes items b, b + G,
+  // b + 2G, ... (G blocks) one at a time, with no counter.
+  constexpr unsigned long long kC = kRoundRobin ? 1 : kClaim;
+  if (tid == 0)
+    s_item = kRoundRobin ? static_cast<unsigned long long>(blockIdx.x)
+                         : atomicAdd(&acc[kAccBinNext + bin], static_cast<unsigned long long>(kClaim));
   __syncthreads();
   unsigned long long claim = s_item;
   while (claim < count) {
     unsigned long long next = 0;
-    if (tid == 0) next = atomicAdd(&acc[kAccBinNext + bin], static_cast<unsigned long long>(kClaim));
-    const unsigned long long claim_end = min(claim + kClaim, count);
+    if (tid == 0)
+      next = kRoundRobin ? claim + gridDim.x
+                         : atomicAdd(&acc[kAccBinNext + bin], static_cast<unsigned long long>(kClaim));
+    const unsigned long long claim_end = min(claim + kC, count);
     for (unsigned long long it = claim; it < claim_end; ++it) {
     const int64_t gi = static_cast<int64_t>(first + it);  // unit index of this item
     const int4 item = items[gi];
@@ -1118,9 +1129,9 @@ __global__ void forward_meta_kernel(const int64_t* off, const int32_t* cols, int
 
 // WPE: waves per SIMD the kernel is compiled for (HIP's second launch
 // bound), matched to the blocks per CU that the bin's LDS allows.
-template <int WORDS, int THREADS, int D, int WPE, int kOut>
+template <int WORDS, int THREADS, int D, int WPE, int kOut, bool kRoundRobin = false>
 int launch_heavy(const CountArgs& a, CountWs& w, const Out& o, int bin, int blocks_per_cu, hipStream_t s) {
-  heavy_kernel<WORDS, THREADS, D, WPE, kOut><<<static_cast<unsigned>(num_cus() * blocks_per_cu), THREADS, 0, s>>>(
+  heavy_kernel<WORDS, THREADS, D, WPE, kOut, kRoundRobin><<<static_cast<unsigned>(num_cus() * blocks_per_cu), THREADS, 0, s>>>(
       a.cols, a.meta, bin, w.items, w.sbeg, w.slen, w.soth, w.acc, o);
   TC_HIP(hipGetLastError());
   return TC_OK;
@@ -1141,9 +1152,13 @@ int launch_bins(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
     TC_TRY((launch_heavy<kBinWords1, 512, 1024, 6, kOut>(a, w, o, 1, 3, s)));
     // Bin 0 (tables of 2 KB): on smaller graphs its items are short (about
     // 500 elements at R-MAT S20) and two waves per block with half the
-    // blocks finish sooner (0.16 ms of 2.05 at S20); on large graphs (2400
-    // elements per item at S24) one wave per block and 24 blocks per CU do.
-    if (a.g->nnz < (int64_t(1) << 27)) TC_TRY((launch_heavy<kBinWords0, 128, 256, 6, kOut>(a, w, o, 0, 12, s)));
+    // blocks finish sooner (0.16 ms of 2.05 at S20), taking the items round
+    // robin: the claim counter's same-address atomics and the spread of
+    // finish times over a 4-item claim cost another 0.1 ms of 0.42 there.
+    // On large graphs (2400 elements per item at S24) the items vary more
+    // and one wave per block, 24 blocks per CU and claims do (round robin
+    // loses 2.4 ms there).
+    if (a.g->nnz < (int64_t(1) << 27)) TC_TRY((launch_heavy<kBinWords0, 128, 256, 6, kOut, true>(a, w, o, 0, 12, s)));
     else TC_TRY((launch_heavy<kBinWords0, 64, 256, 6, kOut>(a, w, o, 0, 24, s)));
     return launch_heavy<0, 512, 1024, 4, kOut>(a, w, o, 3, 4, s);
   }
