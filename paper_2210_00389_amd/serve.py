@@ -10,11 +10,16 @@ different slots overlap on the device while one slot's host thread waits on
 its own stream.  Finished requests leave their CSR resident for later
 requests on the same graph.
 
+A request's answer is (T, |H|) and, when the executor is asked for it, a
+64-bit digest of the BFS levels (:func:`levels_digest`), so a client can
+check the levels without receiving n integers.
+
 The scheduling state (:class:`Scheduler`) is plain Python and is exercised
 with a fake executor on the CPU; :class:`GpuExecutor` runs tc_count.
 """
 from __future__ import annotations
 
+import hashlib
 import math
 import queue
 import threading
@@ -41,6 +46,7 @@ class Request:
     uploaded: bool = False
     triangles: int = -1
     h: int = -1
+    levels_hash: str = ""
 
     @property
     def latency(self) -> float:
@@ -164,6 +170,13 @@ class Scheduler:
         del self.running[r.rid]
 
 
+def levels_digest(levels) -> str:
+    """Hex BLAKE2b-64 of the levels as little-endian int32 (one per vertex,
+    in vertex order)."""
+    a = np.ascontiguousarray(np.asarray(levels, dtype="<i4"))
+    return hashlib.blake2b(a.tobytes(), digest_size=8).hexdigest()
+
+
 def poisson_arrivals(rate: float, count: int, seed: int) -> np.ndarray:
     """Arrival times (s) of a Poisson process of the given rate."""
     rng = np.random.default_rng(seed)
@@ -182,7 +195,8 @@ def percentile(xs, p):
 class Server:
     """Runs a list of requests against an executor with `slots` worker
     threads.  The executor provides run(slot, request, upload: bool) ->
-    (triangles, h) (blocking, called on the slot's thread) and evict(gid)."""
+    (triangles, h) or (triangles, h, levels digest) (blocking, called on the
+    slot's thread) and evict(gid)."""
 
     def __init__(self, executor, slots: int, budget_bytes: int):
         self.ex = executor
@@ -204,7 +218,10 @@ class Server:
                 if r is None:
                     return
                 try:
-                    r.triangles, r.h = self.ex.run(s, r, r.uploaded)
+                    ans = self.ex.run(s, r, r.uploaded)
+                    r.triangles, r.h = ans[0], ans[1]
+                    if len(ans) > 2:
+                        r.levels_hash = ans[2]
                 except Exception as e:  # reported after the run
                     errors.append((r.rid, repr(e)))
                 done_q.put((r, clock()))
@@ -273,9 +290,11 @@ class Server:
 
 class GpuExecutor:
     """Runs tc_count for requests on per-slot streams.  `pool` maps graph id
-    to host CSR (row_offsets int64, cols int32) in pinned memory."""
+    to host CSR (row_offsets int64, cols int32) in pinned memory.  With
+    levels_hash, tc_count also writes the levels and the answer carries
+    their digest (the levels are copied to the host for it)."""
 
-    def __init__(self, pool: dict, slots: int, device="cuda"):
+    def __init__(self, pool: dict, slots: int, device="cuda", levels_hash: bool = False):
         import torch
         from . import api
         self.torch, self.api = torch, api
@@ -288,6 +307,7 @@ class GpuExecutor:
         self.ws = [api.Workspace(self.dev) for _ in range(slots)]
         self.resident: dict[int, object] = {}
         self.lock = threading.Lock()
+        self.levels_hash = levels_hash
 
     def graph_bytes(self, gid: int) -> int:
         off, cols = self.pool[gid]
@@ -306,8 +326,10 @@ class GpuExecutor:
             else:
                 with self.lock:
                     g = self.resident[r.graph_id]
-            res = api.count(g, ws=self.ws[slot], stream=s)
+            res = api.count(g, ws=self.ws[slot], stream=s, return_levels=self.levels_hash)
             out = torch.stack([res.triangles[0], res.h_count[0]]).cpu()
+            if self.levels_hash:
+                return int(out[0]), int(out[1]), levels_digest(res.levels.cpu().numpy())
         return int(out[0]), int(out[1])
 
     def evict(self, gid: int):

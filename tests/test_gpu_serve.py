@@ -43,3 +43,24 @@ def test_serving_mix_equals_alone(tight):
     assert st["p99_ms"] >= st["p50_ms"] > 0
     if tight:
         assert st["evictions"] > 0
+
+
+def test_serving_levels_digest():
+    """With the levels digest on, every request also carries the digest of
+    its BFS levels, equal to the digest of the oracle's levels (Alg. 1
+    scan order, default root)."""
+    import torch
+    from paper_2210_00389_amd import serve
+    graphs = _pool_graphs()[:5]
+    want = {}
+    for gid, g in enumerate(graphs):
+        c = oracle.from_graph(g)
+        want[gid] = serve.levels_digest(oracle.bfs_levels(c).levels)
+    pool, sizes = serve.build_pool(graphs)
+    reqs = serve.make_requests(sizes, serve.count_ws_bytes, rate=2000.0, count=30, seed=12)
+    print("case: serving with levels digest", flush=True)
+    budget = 4 * sum(gb + serve.count_ws_bytes(n, nnz) for n, nnz, gb in sizes.values())
+    serve.Server(serve.GpuExecutor(pool, 2, levels_hash=True), slots=2, budget_bytes=budget).run(reqs)
+    torch.cuda.synchronize()
+    for r in reqs:
+        assert r.levels_hash == want[r.graph_id], (r.rid, r.graph_id)

@@ -117,3 +117,31 @@ def test_server_evicts_under_a_small_budget():
     st = Server(ex, slots=2, budget_bytes=15000).run(reqs)
     assert st["evictions"] > 0 and set(ex.evicted) <= set(sizes)
     assert all(r.triangles == r.graph_id * 7 + 1 for r in reqs)
+
+
+def test_levels_digest():
+    """BLAKE2b-64 of the little-endian int32 levels: the empty array gives
+    the digest of no bytes, and the value depends on dtype only through the
+    int32 cast, and on the order of the vertices."""
+    import hashlib
+
+    from paper_2210_00389_amd.serve import levels_digest
+    assert levels_digest(np.zeros(0, np.int32)) == hashlib.blake2b(b"", digest_size=8).hexdigest()
+    a = np.array([0, 1, 1, 2, 0], np.int32)
+    assert levels_digest(a) == hashlib.blake2b(bytes([0, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0, 2, 0, 0, 0, 0, 0, 0, 0]),
+                                              digest_size=8).hexdigest()
+    assert levels_digest(a.astype(np.int64)) == levels_digest(a)
+    assert levels_digest(a[::-1]) != levels_digest(a)
+
+
+class DigestExecutor(FakeExecutor):
+    def run(self, slot, r, upload):
+        t, h = super().run(slot, r, upload)
+        return t, h, f"g{r.graph_id}"
+
+
+def test_server_carries_levels_digest():
+    sizes = {g: (100, 400, 5000) for g in range(6)}
+    reqs = make_requests(sizes, lambda n, nnz: 1000, rate=2000.0, count=30, seed=3)
+    Server(DigestExecutor(), slots=2, budget_bytes=40000).run(reqs)
+    assert all(r.levels_hash == f"g{r.graph_id}" for r in reqs)
