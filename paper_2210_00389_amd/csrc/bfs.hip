@@ -16,7 +16,10 @@
 //     one-block kernel sums to decide the next direction (alpha 14, beta 24)
 //     and the stop, all on the device; the host launches levels in groups
 //     of kLevelsPerSync and reads the state once per group;
-//   * the remaining components: union-find over the unreached vertices where
+//   * the state counts the row entries of the vertices not yet reached; when
+//     the BFS from r0 ends with none, every vertex left is isolated and takes
+//     level 0 in one pass;
+//   * otherwise the remaining components: union-find over the unreached vertices where
 //     a root is always hooked under the smaller root, so every component's
 //     final root is its smallest id; those roots then start one multi-source
 //     BFS (components are disjoint, so the per-component distances are
@@ -304,6 +307,13 @@ __global__ void start_kernel(const int64_t* off, const unsigned long long* key, 
 }
 
 // ------------------------------------------------- remaining components
+// When the first BFS has reached every vertex with an edge, each vertex left
+// is isolated and its own one-vertex BFS gives it level 0.
+__global__ void isolated_kernel(const uint32_t* vis, int64_t n, int32_t* L) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    if (!((vis[v >> 5] >> (v & 31)) & 1u)) L[v] = 0;
+}
+
 __device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
   for (;;) {
     int32_t p = load_relaxed(&parent[x]);
@@ -399,8 +409,10 @@ unsigned step_grid() {
 
 // Runs the levels of the BFS whose state and level-0 bitmap are set, in
 // groups of kLevelsPerSync, until the frontier is empty.  Returns its level
-// count.
-int bfs_levels_loop(const tc_csr* g, int32_t* L, BfsWs& w, int group, int32_t* levels_out, hipStream_t s) {
+// count and, in *rest_out (nullable), the row entries of the vertices it
+// left unvisited.
+int bfs_levels_loop(const tc_csr* g, int32_t* L, BfsWs& w, int group, int32_t* levels_out, hipStream_t s,
+                    int64_t* rest_out = nullptr) {
   BfsState* st = reinterpret_cast<BfsState*>(w.st);
   const unsigned gs = step_grid();
   for (;;) {
@@ -416,6 +428,7 @@ int bfs_levels_loop(const tc_csr* g, int32_t* L, BfsWs& w, int group, int32_t* l
     TC_HIP(hipStreamSynchronize(s));
     if (h.done) {
       *levels_out = h.num_levels;
+      if (rest_out) *rest_out = h.unexplored;
       return TC_OK;
     }
   }
@@ -448,11 +461,19 @@ int bfs_run(const tc_csr* g, int64_t root, int32_t* L, int32_t* num_levels, BfsW
   init_state_kernel<<<1, kThreads, 0, s>>>(n, st, w.part, static_cast<int>(2 * gs), g->nnz);
   TC_HIP(hipGetLastError());
   int32_t lv0 = 0;
-  TC_TRY(bfs_levels_loop(g, L, w, kLevelsPerSync, &lv0, s));
+  int64_t rest = 0;
+  TC_TRY(bfs_levels_loop(g, L, w, kLevelsPerSync, &lv0, s, &rest));
   if (first_levels) *first_levels = lv0;
   if (w.comp0) {
     copy_words_kernel<<<grid_for(words, kThreads, 16384), kThreads, 0, s>>>(w.vis, w.comp0, words);
     TC_HIP(hipGetLastError());
+  }
+  if (rest == 0) {
+    // no unreached vertex has an edge: no other component to level
+    isolated_kernel<<<grid_for(n, kThreads, 16384), kThreads, 0, s>>>(w.vis, n, L);
+    TC_HIP(hipGetLastError());
+    if (num_levels) *num_levels = lv0;
+    return TC_OK;
   }
   // Remaining components (Alg. 1 rescans for unvisited vertices): one
   // union-find pass over the unreached vertices gives each component its
