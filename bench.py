@@ -415,6 +415,76 @@ def summarize(args):
     print(json.dumps({"summary": args.out}), flush=True)
 
 
+def summarize_kernels(args):
+    """Per-kernel HBM traffic of one count call from two unfiltered
+    rocprofv3 --pmc runs of the pmc program (FETCH_SIZE, then WRITE_SIZE),
+    scaled by the 1 GiB copy like the heavy-stage record.  A count call is
+    the dispatches from a root_key_kernel to the next stats_kernel; the
+    table covers the last call, and the totals give the time-weighted rate
+    over all of its kernels."""
+    import re
+
+    def rows(d, counter):
+        acc, dur, name = {}, {}, {}
+        for r in _csv_rows(d, "counter_collection.csv"):
+            if r["Counter_Name"] != counter:
+                continue
+            k = int(r["Dispatch_Id"])
+            acc[k] = acc.get(k, 0.0) + float(r["Counter_Value"])
+            dur[k] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+            m = re.match(r"[A-Za-z_0-9]+", r["Kernel_Name"])  # names are truncated (-T)
+            name[k] = m.group(0) if m else r["Kernel_Name"][:40]
+        return acc, dur, name
+
+    fa, fdur, fname = rows(args.fetch_dir, "FETCH_SIZE")
+    wa, _, wname = rows(args.write_dir, "WRITE_SIZE")
+    gib_kib = 2**30 / 1024
+    cf = [v for k, v in fa.items() if "copy" in fname[k].lower()]
+    cw = [v for k, v in wa.items() if "copy" in wname[k].lower()]
+    ff, wf = gib_kib / max(cf), gib_kib / max(cw)
+
+    def last_call(names):
+        ids = sorted(names)
+        starts = [k for k in ids if names[k].startswith("root_key_kernel")]
+        a = starts[-1]
+        b = next(k for k in ids if k > a and names[k].startswith("stats_kernel"))
+        return [k for k in ids if a <= k <= b]
+
+    fc, wc = last_call(fname), last_call(wname)
+    table = {}
+    for k in fc:
+        t = table.setdefault(fname[k], [0, 0.0, 0.0, 0.0])
+        t[0] += 1
+        t[1] += fdur[k]
+        t[2] += fa[k] * 1024 * ff
+    for k in wc:
+        if wname[k] in table:
+            table[wname[k]][3] += wa[k] * 1024 * wf
+    tot_ms = sum(t[1] for t in table.values())
+    tot_b = sum(t[2] + t[3] for t in table.values())
+    out_md = [f"# {args.title}", "", "Command:", "", "```", args.cmd, "```", "",
+              f"Counter traffic of every kernel of one count call (the last of the program's calls), "
+              f"FETCH_SIZE x {ff:.3f} and WRITE_SIZE x {wf:.3f} (factors from a 1 GiB device copy); "
+              f"kernel times are those of the counter runs.", "",
+              "| kernel | dispatches | kernel ms | fetch GB | write GB | GB/s |", "|---|---|---|---|---|---|"]
+    for nm, t in sorted(table.items(), key=lambda kv: -kv[1][1]):
+        if t[1] < 0.005 * tot_ms:
+            continue
+        out_md.append(f"| {nm} | {t[0]} | {t[1]:.3f} | {t[2]/1e9:.3f} | {t[3]/1e9:.3f} | "
+                      f"{(t[2] + t[3]) / (t[1] / 1e3) / 1e9:.0f} |")
+    out_md += ["", f"All kernels of the call: {len(fc)} dispatches, {tot_ms:.2f} ms of kernel time, "
+                   f"{tot_b/1e9:.1f} GB moved: {tot_b / (tot_ms / 1e3) / 1e9:.0f} GB/s time-weighted "
+                   f"({tot_b / (tot_ms / 1e3) / 1e9 / HBM_PEAK_GBS:.2f} of 8 TB/s).", ""]
+    rec = {"fetch_factor": ff, "write_factor": wf, "kernel_ms": tot_ms, "bytes": tot_b,
+           "kernels": {nm: {"dispatches": t[0], "ms": t[1], "fetch_bytes": t[2], "write_bytes": t[3]}
+                       for nm, t in table.items()}}
+    with open(args.out + ".md", "w") as f:
+        f.write("\n".join(out_md) + "\n")
+    with open(args.out + ".json", "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps({"summary": args.out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -432,6 +502,8 @@ def main():
     ap.add_argument("--root-candidates", type=int, default=0,
                     help="also choose the root by |H| among this many highest-degree vertices and time it")
     ap.add_argument("--summarize", action="store_true", help="summarise rocprofv3 output into --out(.md/.json)")
+    ap.add_argument("--summarize-kernels", action="store_true",
+                    help="per-kernel counter traffic of one count call from unfiltered --pmc runs")
     ap.add_argument("--trace-dir", default=None)
     ap.add_argument("--fetch-dir", default=None)
     ap.add_argument("--write-dir", default=None)
@@ -449,6 +521,9 @@ def main():
 
     if args.summarize:
         summarize(args)
+        return
+    if args.summarize_kernels:
+        summarize_kernels(args)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
