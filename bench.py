@@ -267,16 +267,24 @@ def bench_serving(args):
     specs = graphgen.serving_specs(args.pool, scale_max=args.serve_scale_max,
                                    cl_n_max=args.serve_cl_n_max)
     log(f"[bench] building the serving pool ({len(specs)} graphs)")
-    graphs = [graphgen.from_spec(sp) for sp in specs]
+    graphs = []
+    for i, sp in enumerate(specs):
+        graphs.append(graphgen.from_spec(sp))
+        log(f"[bench] pool: graph {i + 1}/{len(specs)} {sp['kind']} generated")
     pool, sizes = serve.build_pool(graphs)
     del graphs
     free, _ = torch.cuda.mem_get_info()
     budget = int(free * args.serve_budget_frac)
     runs = []
+    # one executor for every rate: its streams, per-slot workspaces and
+    # resident graphs persist like a long-running server's (fresh streams per
+    # rate would strand each rate's workspaces in the caching allocator,
+    # which reuses a freed block only on the stream that allocated it)
+    ex = serve.GpuExecutor(pool, args.slots)
     for rate in args.rates:
         reqs = serve.make_requests(sizes, serve.count_ws_bytes, rate=rate, count=args.requests, seed=int(rate))
-        ex = serve.GpuExecutor(pool, args.slots)
         st = serve.Server(ex, slots=args.slots, budget_bytes=budget).run(reqs)
+        torch.cuda.synchronize()
         st["rate_req_s"] = rate
         log(f"[bench] rate {rate}: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms "
             f"edges/s {st['edges_per_s']:.3e} busy {st['busy_fraction']:.2f}")
@@ -510,11 +518,11 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--title", default="rocprofv3 summary")
     ap.add_argument("--cmd", default="")
-    ap.add_argument("--pool", type=int, default=32, help="serving: graphs in the request pool")
-    ap.add_argument("--rates", type=float, nargs="+", default=[50, 200, 1000, 2000])
-    ap.add_argument("--requests", type=int, default=500, help="serving: requests per rate")
+    ap.add_argument("--pool", type=int, default=128, help="serving: graphs in the request pool")
+    ap.add_argument("--rates", type=float, nargs="+", default=[50, 100, 200, 500, 1000, 2000])
+    ap.add_argument("--requests", type=int, default=2000, help="serving: requests per rate")
     ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--serve-scale-max", type=int, default=20)
+    ap.add_argument("--serve-scale-max", type=int, default=22)
     ap.add_argument("--serve-cl-n-max", type=int, default=10**6)
     ap.add_argument("--serve-budget-frac", type=float, default=0.5)
     args = ap.parse_args()

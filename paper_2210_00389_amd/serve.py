@@ -321,6 +321,10 @@ class GpuExecutor:
             if upload or r.graph_id not in self.resident:
                 off, cols = self.pool[r.graph_id]
                 g = api.Graph(r.n, off.to(self.dev, non_blocking=True), cols.to(self.dev, non_blocking=True))
+                # the copies run on this slot's stream: finish them before the
+                # graph is published, since other slots count it on their own
+                # streams with no wait on this one
+                s.synchronize()
                 with self.lock:
                     self.resident[r.graph_id] = g
             else:
