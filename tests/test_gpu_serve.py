@@ -64,3 +64,26 @@ def test_serving_levels_digest():
     torch.cuda.synchronize()
     for r in reqs:
         assert r.levels_hash == want[r.graph_id], (r.rid, r.graph_id)
+
+
+def test_serving_same_graph_at_once():
+    """Many requests for one graph arriving together on four slots: the
+    first admitted uploads it while the others start at once; every answer
+    equals the graph counted alone (a slot must never count a graph whose
+    upload on another slot's stream has not finished)."""
+    import torch
+    import paper_2210_00389_amd as tc
+    from paper_2210_00389_amd import serve
+    graphs = [graphgen.rmat(16, seed=21)]
+    G = tc.from_host_pairs(graphs[0].n, graphs[0].src, graphs[0].dst)
+    want = (tc.count(G).T, tc.count(G).h)
+    pool, sizes = serve.build_pool(graphs)
+    budget = 8 * sum(gb + serve.count_ws_bytes(n, nnz) for n, nnz, gb in sizes.values())
+    ex = serve.GpuExecutor(pool, 4)
+    for rnd in range(3):
+        print(f"case: same graph at once, round {rnd}", flush=True)
+        reqs = serve.make_requests(sizes, serve.count_ws_bytes, rate=1e6, count=24, seed=30 + rnd)
+        serve.Server(ex, slots=4, budget_bytes=budget).run(reqs)
+        torch.cuda.synchronize()
+        assert all((r.triangles, r.h) == want for r in reqs)
+        assert sum(r.uploaded for r in reqs) >= 1
