@@ -32,9 +32,9 @@
  *     or throws; tc_last_error() gives a thread-local description of the last
  *     failure.  Structural checks of the input graph (sorted, duplicate-free,
  *     loop-free, symmetric, ids in range) run only when TC_VALIDATE is set in
- *     `flags`; without it a non-simple graph gives unspecified counts (never
- *     an out-of-bounds access as long as ids are in range and offsets are
- *     monotone).
+ *     `flags` (the check synchronises `stream`); without it a non-simple graph
+ *     gives unspecified counts (never an out-of-bounds access as long as ids
+ *     are in range and offsets are monotone).
  *   - All counts are exact 64-bit integers; results do not depend on the
  *     scheduling of the GPU or on the tuning parameters.
  */
@@ -151,7 +151,10 @@ int tc_validate_csr(const tc_csr* g, void* ws, size_t ws_bytes, tc_stream_t stre
  *   levels       device int32 [n] (output)
  *   num_levels   host int32 (nullable): the largest level count of any one
  *                BFS (max level + 1; 0 for n = 0)
- * Synchronises `stream` once per BFS level (frontier sizes are read back). */
+ * Synchronises `stream`: the BFS state is read back once per group of up to
+ * eight levels from the root, and, if vertices with edges are left
+ * unreached, once per group of up to four levels of the remaining
+ * components. */
 int tc_bfs_levels(const tc_csr* g, int64_t root, uint32_t flags, int32_t* levels,
                   int32_t* num_levels, void* ws, size_t ws_bytes, tc_stream_t stream);
 
@@ -172,8 +175,8 @@ int tc_cover_edges(const tc_csr* g, const int32_t* levels, int32_t* h_u, int32_t
  *   levels       device int32 [n] (nullable output): the BFS levels used
  *   per_vertex   device int64 [n] (output iff flags & TC_PER_VERTEX): the
  *                number of triangles through each vertex (sums to 3T)
- * Synchronises `stream` once per BFS level; the count itself is
- * asynchronous. */
+ * Synchronises `stream` during the BFS as tc_bfs_levels does; the rest
+ * (relabelling, layout, count) is asynchronous. */
 int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles,
              int64_t* h_count, int32_t* levels, int64_t* per_vertex, void* ws,
              size_t ws_bytes, tc_stream_t stream);
@@ -195,8 +198,8 @@ int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles,
  *   h_count      device int64 [1] (nullable output): |H|
  *   levels       device int32 [n] (nullable output): the BFS levels used
  * flags: TC_VALIDATE only (TC_PER_VERTEX is rejected).  Workspace: the
- * tc_count size (TC_OP_COUNT).  Synchronises `stream` once per BFS level
- * and once between the two passes. */
+ * tc_count size (TC_OP_COUNT).  Synchronises `stream` during the BFS as
+ * tc_bfs_levels does and once between the two passes. */
 int tc_list_triangles(const tc_csr* g, int64_t root, uint32_t flags, int32_t* tri, int64_t cap,
                       int64_t* triangles, int64_t* h_count, int32_t* levels, void* ws,
                       size_t ws_bytes, tc_stream_t stream);
