@@ -535,9 +535,9 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
-        log("bench.py: only --gpus 1 is supported (single-GPU build)")
+        log("bench.py: only --gpus 1 is supported (the library runs on one GPU)")
         sys.exit(2)
 
     import torch

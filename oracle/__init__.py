@@ -1,6 +1,6 @@
 """CPU oracle for cover-edge triangle counting -- TEST INFRASTRUCTURE ONLY.
 
-This package is the checker: a plain single-threaded C implementation
+This package is the test reference: a plain single-threaded C implementation
 (``oracle.c``) of the paper's sequential algorithm (Alg. 1, CETC, of Bader et
 al., "Triangle Counting Through Cover-Edges") plus an O(n^3) brute force
 (``brute.py``).  Only the test suite, ``__graft_entry__.smoke()`` and the

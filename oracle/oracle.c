@@ -3,7 +3,7 @@
  * triangle counting (Bader et al., "Triangle Counting Through Cover-Edges",
  * arXiv 2210.00389).
  *
- * TEST INFRASTRUCTURE ONLY.  This file is the checker the GPU library is
+ * TEST INFRASTRUCTURE ONLY.  This file is the reference the GPU library is
  * compared against.  It shares no code, header, table or build step with the
  * library; only the test suite, the smoke check and the CPU-baseline leg of
  * the benchmark may load it.  No product code path may call it.
