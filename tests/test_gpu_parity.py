@@ -240,3 +240,16 @@ def test_determinism(tc):
         outs.add((r.T, r.h, hashlib.sha256(r.levels.cpu().numpy().tobytes()).hexdigest(),
                   int(tc.count_edge_baseline(G).item())))
     assert len(outs) == 1
+
+
+def test_bfs_isolated_vertices_beside_one_component(tc):
+    """The BFS from r0 reaches every vertex with an edge, so the vertices
+    left are isolated and take level 0 without the component pass; from an
+    isolated root the component pass levels the clique from its smallest id;
+    with two cliques the pass runs with vertices of degree > 0 left."""
+    g = graphgen.disjoint_union([graphgen.complete(12)] + [graphgen.path(1)] * 6)
+    check_graph(tc, g, "K12 + 6 isolated")
+    deg = np.diff(oracle.from_graph(g).row_offsets)
+    check_graph(tc, g, "K12 + 6 isolated, isolated root", root=int(np.flatnonzero(deg == 0)[0]))
+    g2 = graphgen.disjoint_union([graphgen.complete(12), graphgen.complete(7)] + [graphgen.path(1)] * 4)
+    check_graph(tc, g2, "K12 + K7 + 4 isolated")
