@@ -143,6 +143,9 @@ def cpu_baseline(g, n, m, budget_s):
         chunk = min(chunk * 2, max(1, c.n // 64))
     frac = rows_done / max(c.n, 1)
     est = t_bfs + t_h + t_count / max(frac, 1e-12)
+    # the cost measures of Alg. 1 on this graph (not timed): the list
+    # elements its intersections would scan, beside the GPU path's own count
+    work = oracle.work_counters(c, lv.levels)
     try:
         model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
     except Exception:
@@ -155,6 +158,7 @@ def cpu_baseline(g, n, m, budget_s):
                    f"(uniform sample, ids relabelled) in {t_count:.1f}s, scaled to all rows; "
                    f"estimated full run {est:.1f}s"),
         "estimated_full_seconds": est,
+        "alg1_work": work,
     }
 
 

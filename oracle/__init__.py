@@ -19,6 +19,8 @@ Parity status of every function (what pins it is in ``tests/test_oracle.py``):
 * count -- pinned (brute force, networkx, closed forms, root and relabelling
   invariance, per-vertex sum = 3T, both intersection modes).
 * edge_count -- pinned (brute force, closed forms).
+* work_counters -- pinned (brute-force loops over adjacency sets, closed
+  forms for K_n, zero for bipartite graphs; ``tests/test_oracle_work.py``).
 * per-edge support -- pinned (sum over H = T; bounded by |N(u) ∩ N(v)|).
 """
 from __future__ import annotations
@@ -276,6 +278,27 @@ def edge_count(csr: CSR) -> int:
     """Plain direction-oriented edge iterator (u < v < w); uses no levels."""
     cols = csr.cols if csr.cols.size else np.zeros(1, dtype=np.int32)
     return int(_load().oracle_edge_count(csr.n, _p(csr.row_offsets), _p(cols)))
+
+
+def work_counters(csr: CSR, levels: np.ndarray) -> dict:
+    """Work measures of the cost analysis (Sec. III), from their definitions:
+    over the horizontal edges H (u < v, equal levels) |H|, the sum of
+    min(d(u), d(v)) (Alg. 1 scans the shorter list and looks each id up in a
+    hash table of the other) and the sum of d(u) + d(v) (both lists merged);
+    for the plain edge iterator (every edge u < v, apexes w > v) the sum over
+    all edges of min(d+(u), d+(v)), where d+(x) = |{w in N(x) : w > x}|."""
+    deg = np.diff(csr.row_offsets)
+    rows = np.repeat(np.arange(csr.n, dtype=np.int64), deg)
+    cols = csr.cols.astype(np.int64)
+    up = rows < cols
+    u, v = rows[up], cols[up]
+    lv = np.asarray(levels)
+    hz = lv[u] == lv[v] if u.size else np.zeros(0, dtype=bool)
+    fwd = np.bincount(u, minlength=csr.n)
+    return dict(h=int(hz.sum()),
+                h_min_deg=int(np.minimum(deg[u[hz]], deg[v[hz]]).sum()),
+                h_sum_deg=int((deg[u[hz]] + deg[v[hz]]).sum()),
+                edge_min_fwd=int(np.minimum(fwd[u], fwd[v]).sum()))
 
 
 def triangle_count(csr: CSR, root: int = -1, mode: int = 0) -> int:
