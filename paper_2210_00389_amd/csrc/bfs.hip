@@ -415,10 +415,15 @@ int bfs_levels_loop(const tc_csr* g, int32_t* L, BfsWs& w, int group, int32_t* l
                     int64_t* rest_out = nullptr) {
   BfsState* st = reinterpret_cast<BfsState*>(w.st);
   const unsigned gs = step_grid();
+  // the big-row kernel runs every level but has work only where a frontier
+  // row exceeds kBig entries; two blocks per CU expand those rows and keep
+  // the launch cheap where there are none (its partials past this grid stay
+  // zero from the clear at the start of the BFS)
+  const unsigned gb = gs < static_cast<unsigned>(num_cus() * 2) ? gs : static_cast<unsigned>(num_cus() * 2);
   for (;;) {
     for (int k = 0; k < group; ++k) {
       step_kernel<<<gs, kThreads, 0, s>>>(g->row_offsets, g->cols, g->n, st, L, w.vis, w.bms, w.big, w.part);
-      big_kernel<<<gs, kThreads, 0, s>>>(g->row_offsets, g->cols, g->n, st, L, w.vis, w.bms, w.big,
+      big_kernel<<<gb, kThreads, 0, s>>>(g->row_offsets, g->cols, g->n, st, L, w.vis, w.bms, w.big,
                                          w.part + 2 * gs);
       decide_kernel<<<1, kThreads, 0, s>>>(g->n, st, w.part, static_cast<int>(2 * gs));
     }
