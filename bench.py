@@ -16,9 +16,21 @@ counts reported by the library) divided by its average duration, taken from
 HIP events the library records around each stage on the call's stream during
 the timed steps.
 
+traffic: counter-measured bytes of the dominant stage from the committed
+summary under profiles/ when it was taken on the current kernel source.
+
+stream_bw: what a plain 1 GiB device copy and a float32 sum reach on the same
+device, as the practical ceiling beside the 8 TB/s peak.
+
 cpu_baseline: the CPU oracle, single-threaded, on a bounded sample (full BFS
 and cover edges, then the count over a prefix of the rows -- a uniform sample
-because ids are relabelled -- scaled to all rows).
+because ids are relabelled -- scaled to all rows); alg1_work holds the
+oracle's work measures of Alg. 1 on the same graph.
+
+Other workloads: --workload batch (4096 graphs per captured launch), serving
+(Poisson request streams, p50/p99), list (triangle finding and supports), pmc
+(the program profiled for counters).  --summarize / --summarize-kernels turn
+rocprofv3 output into the summaries kept under profiles/.
 """
 import argparse
 import json
