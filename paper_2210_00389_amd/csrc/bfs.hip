@@ -402,9 +402,15 @@ BfsWs bfs_reserve(Carver& c, int64_t n) {
 
 namespace {
 
-unsigned step_grid() {
-  const int g = num_cus() * 8;
-  return static_cast<unsigned>(g < kMaxParts ? g : kMaxParts);
+// Blocks of the level kernels: one per 256 vertices (each thread then takes
+// one vertex or one 64-vertex wave group per level), at most eight per CU,
+// so that a small graph's levels launch only the blocks they can use.
+unsigned step_grid(int64_t n) {
+  int64_t g = num_cus() * 8;
+  if (g > kMaxParts) g = kMaxParts;
+  const int64_t want = (n + kThreads - 1) / kThreads;
+  if (want < g) g = want;
+  return static_cast<unsigned>(g < 1 ? 1 : g);
 }
 
 // Runs the levels of the BFS whose state and level-0 bitmap are set, in
@@ -414,7 +420,7 @@ unsigned step_grid() {
 int bfs_levels_loop(const tc_csr* g, int32_t* L, BfsWs& w, int group, int32_t* levels_out, hipStream_t s,
                     int64_t* rest_out = nullptr) {
   BfsState* st = reinterpret_cast<BfsState*>(w.st);
-  const unsigned gs = step_grid();
+  const unsigned gs = step_grid(g->n);
   // the big-row kernel runs every level but has work only where a frontier
   // row exceeds kBig entries; two blocks per CU expand those rows and keep
   // the launch cheap where there are none (its partials past this grid stay
@@ -451,7 +457,7 @@ int bfs_run(const tc_csr* g, int64_t root, int32_t* L, int32_t* num_levels, BfsW
   }
   const int64_t words = (n + 31) / 32 + 1;
   BfsState* st = reinterpret_cast<BfsState*>(w.st);
-  const unsigned gs = step_grid();
+  const unsigned gs = step_grid(g->n);
   TC_TRY(fill_i32(L, -1, n, s));
   TC_TRY(fill_i32(reinterpret_cast<int32_t*>(w.vis), 0, words, s));
   TC_TRY(fill_i32(reinterpret_cast<int32_t*>(w.bms), 0, 3 * words, s));
