@@ -1174,7 +1174,10 @@ int launch_bins(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
 
 template <int kOut>
 int launch_light(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
-  light_kernel<kOut><<<static_cast<unsigned>(num_cus() * 16), kThreads, 0, s>>>(
+  // one thread per task; there are at most two tasks per CSR entry
+  const int64_t need = (2 * (a.g->nnz + 1) + kThreads - 1) / kThreads;
+  const int64_t cap = static_cast<int64_t>(num_cus()) * 16;
+  light_kernel<kOut><<<static_cast<unsigned>(need < cap ? need : cap), kThreads, 0, s>>>(
       a.cols, a.meta, w.so, a.g->n, w.lpre, w.nchunk_cap, w.sbeg, w.slen, w.soth, w.sx, w.acc, o);
   TC_HIP(hipGetLastError());
   return TC_OK;
@@ -1184,7 +1187,12 @@ template <bool kCover, int kOut>
 int launch_all(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
   const int64_t n = a.g->n;
   const unsigned gv = grid_for(n, kThreads, 16384);
-  const unsigned gp = static_cast<unsigned>(num_cus() * 16);
+  // kernels over the resolve chunks need at most one block (resolve) or one
+  // thread (bin split) per chunk; nchunk_cap bounds the chunk count
+  const int64_t gmax = static_cast<int64_t>(num_cus()) * 16;
+  const unsigned gr = static_cast<unsigned>(w.nchunk_cap < gmax ? w.nchunk_cap : gmax);
+  const int64_t gct = (w.nchunk_cap + kThreads - 1) / kThreads;
+  const unsigned gc = static_cast<unsigned>(gct < gmax ? gct : gmax);
   plan_kernel<kCover><<<gv, kThreads, 0, s>>>(a.cols, a.meta, n, w.ndesc, w.vinfo, w.acc);
   TC_HIP(hipGetLastError());
   {
@@ -1197,16 +1205,16 @@ int launch_all(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
   prof_stage("resolve");
   sample_kernel<<<grid_for(a.g->nnz / kSampStride + 1, kThreads, 16384), kThreads, 0, s>>>(a.cols, a.g->nnz,
                                                                                            w.samp);
-  resolve_kernel<kCover><<<gp, kResThreads, 0, s>>>(a.cols, w.samp, a.meta, w.vinfo, w.so, w.cx0, n, w.sbeg, w.slen,
+  resolve_kernel<kCover><<<gr, kResThreads, 0, s>>>(a.cols, w.samp, a.meta, w.vinfo, w.so, w.cx0, n, w.sbeg, w.slen,
                                                     w.soth, w.sx, w.items_raw, w.ccnt);
   TC_HIP(hipGetLastError());
   {
     Carver sc(w.scratch);
     TC_TRY(scan_exclusive_strided(reinterpret_cast<const int32_t*>(w.ccnt) + 1, 4, w.lpre, w.nchunk_cap, sc, s));
   }
-  bin_split_kernel<false><<<gp, kThreads, 0, s>>>(w.so, n, w.ccnt, w.items_raw, w.items, w.acc);
+  bin_split_kernel<false><<<gc, kThreads, 0, s>>>(w.so, n, w.ccnt, w.items_raw, w.items, w.acc);
   bin_offsets_kernel<<<1, 1, 0, s>>>(w.acc);
-  bin_split_kernel<true><<<gp, kThreads, 0, s>>>(w.so, n, w.ccnt, w.items_raw, w.items, w.acc);
+  bin_split_kernel<true><<<gc, kThreads, 0, s>>>(w.so, n, w.ccnt, w.items_raw, w.items, w.acc);
   TC_HIP(hipGetLastError());
   // after the item split: kOutRec keeps its unit counts where the raw items were
   TC_TRY(launch_light<kOut>(a, w, o, s));
