@@ -490,10 +490,22 @@ __global__ __launch_bounds__(kThreads) void lay_seg_write_kernel(Lay lay, const 
   }
 }
 
+// Blocks for a kernel that needs at most `need` of them, at most `cap`.
+inline unsigned capped_grid(int64_t need, int64_t cap) {
+  return static_cast<unsigned>(need < 1 ? 1 : (need < cap ? need : cap));
+}
+
 template <class Lay>
-int layout_run(const Lay& lay, const int32_t* cols, int64_t n, SplitWs& w, hipStream_t s) {
+int layout_run(const Lay& lay, const int32_t* cols, int64_t n, int64_t nnz, SplitWs& w, hipStream_t s) {
   const unsigned gv = grid_for(n, kThreads, 16384);
-  const unsigned gw = static_cast<unsigned>(num_cus() * 8);
+  // the row classes hold at most nnz / (least row length) rows: a small
+  // graph launches only the blocks its mid, block and segment rows can use
+  const int64_t wpb = kThreads / kWave;
+  const int64_t mid_rows = nnz / (kShort + 1), big_rows = nnz / (kMidCap + 1);
+  const int64_t segs = nnz / kSeg + nnz / (kBigCap + 1) + 1;
+  const unsigned gmid = capped_grid((mid_rows + wpb - 1) / wpb, static_cast<int64_t>(num_cus()) * 8);
+  const unsigned gbig = capped_grid(big_rows, static_cast<int64_t>(num_cus()) * 4);
+  const unsigned gw = capped_grid((segs + wpb - 1) / wpb, static_cast<int64_t>(num_cus()) * 8);
   lay_short_kernel<Lay><<<gv, kThreads, 0, s>>>(lay, cols, n, w.scols, w.meta, w.nseg, w.rcat);
   TC_HIP(hipGetLastError());
   {
@@ -503,9 +515,9 @@ int layout_run(const Lay& lay, const int32_t* cols, int64_t n, SplitWs& w, hipSt
   RowCtx* mid_ctx = reinterpret_cast<RowCtx*>(w.mid_ctx);
   RowCtx* big_ctx = reinterpret_cast<RowCtx*>(w.big_ctx);
   row_list_kernel<Lay><<<gv, kThreads, 0, s>>>(lay, w.rcat, n, w.cat_pre, mid_ctx, big_ctx);
-  lay_mid_kernel<Lay, kMidR><<<static_cast<unsigned>(num_cus() * 8), kThreads, 0, s>>>(lay, cols, mid_ctx,
+  lay_mid_kernel<Lay, kMidR><<<gmid, kThreads, 0, s>>>(lay, cols, mid_ctx,
                                                                                       w.cat_pre + n, w.scols, w.meta);
-  lay_block_kernel<Lay, kBigWaves, kBigR><<<static_cast<unsigned>(num_cus() * 4), kBigWaves * kWave, 0, s>>>(
+  lay_block_kernel<Lay, kBigWaves, kBigR><<<gbig, kBigWaves * kWave, 0, s>>>(
       lay, cols, big_ctx, w.cat_pre + n, w.scols, w.meta);
   TC_HIP(hipGetLastError());
   Carver sc(w.scratch);
@@ -633,7 +645,7 @@ int split_run(const tc_csr* g, const int32_t* L, bool full_levels, SplitWs& w, h
   (void)full_levels;
   if (g->n == 0) return TC_OK;
   IdentityLayout lay{g->row_offsets, L};
-  return layout_run(lay, g->cols, g->n, w, s);
+  return layout_run(lay, g->cols, g->n, g->nnz, w, s);
 }
 
 RelabelWs relabel_reserve(Carver& c, int64_t n, int64_t max_vlevels) {
@@ -686,7 +698,7 @@ int relabel_run(const tc_csr* g, const int32_t* L, const uint32_t* comp0, int32_
     TC_TRY(scan_exclusive<int32_t>(w.deg, w.off, n, sc, s));
   }
   RelabelLayout lay{g->row_offsets, w.off, w.order, w.perm, L, comp0, d0, w.lstart};
-  return layout_run(lay, g->cols, n, sp, s);
+  return layout_run(lay, g->cols, n, g->nnz, sp, s);
 }
 
 int hlist_run(const tc_csr* g, const VMeta* meta, const int32_t* cols, int64_t* h_off, int32_t* h_u, int32_t* h_v,
