@@ -7,6 +7,8 @@ and int32 sorted columns.
 from __future__ import annotations
 
 import ctypes
+import functools
+import inspect
 from dataclasses import dataclass
 
 import torch
@@ -35,6 +37,23 @@ def _ptr(t: torch.Tensor | None):
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _on_stream(fn):
+    """Runs fn with its `stream` argument (when given) as torch's current
+    stream, so that the buffers it allocates -- workspace growth, outputs --
+    belong to the stream the library enqueues on, and the caching allocator
+    never hands a freed block to other work before that stream is done."""
+    idx = list(inspect.signature(fn).parameters).index("stream")
+
+    @functools.wraps(fn)
+    def wrapper(*args, **kwargs):
+        stream = kwargs.get("stream") if "stream" in kwargs else (args[idx] if len(args) > idx else None)
+        if stream is None:
+            return fn(*args, **kwargs)
+        with torch.cuda.stream(stream):
+            return fn(*args, **kwargs)
+    return wrapper
 
 
 class Workspace:
@@ -90,6 +109,7 @@ def workspace_bytes(op: int, n: int, nnz: int, num_graphs: int = 0) -> int:
     return int(L.load().tc_workspace_bytes(op, n, nnz, num_graphs))
 
 
+@_on_stream
 def build_csr(n: int, src: torch.Tensor, dst: torch.Tensor, ws: Workspace | None = None,
               stream=None) -> Graph:
     """Simple undirected CSR from raw device pairs (tc_build_csr)."""
@@ -108,6 +128,7 @@ def build_csr(n: int, src: torch.Tensor, dst: torch.Tensor, ws: Workspace | None
     return Graph(n, off, cols[: nnz.value])
 
 
+@_on_stream
 def from_host_pairs(n: int, src, dst, device="cuda", ws=None, stream=None) -> Graph:
     s = torch.as_tensor(src, dtype=torch.int32).to(device)
     d = torch.as_tensor(dst, dtype=torch.int32).to(device)
@@ -120,6 +141,7 @@ def from_host_csr(n: int, row_offsets, cols, device="cuda") -> Graph:
     return Graph(n, off, c)
 
 
+@_on_stream
 def validate(g: Graph, ws: Workspace | None = None, stream=None) -> int:
     """0 if g is a simple undirected CSR, else the negative status."""
     lib = L.load()
@@ -128,6 +150,7 @@ def validate(g: Graph, ws: Workspace | None = None, stream=None) -> int:
     return int(lib.tc_validate_csr(ctypes.byref(csr), _ptr(buf), buf.numel(), _stream(stream)))
 
 
+@_on_stream
 def bfs_levels(g: Graph, root: int = -1, validate: bool = False, ws: Workspace | None = None,
                stream=None):
     """(levels int32 tensor, num_levels) as in Alg. 1 (tc_bfs_levels)."""
@@ -141,6 +164,7 @@ def bfs_levels(g: Graph, root: int = -1, validate: bool = False, ws: Workspace |
     return levels[: g.n], int(nl.value)
 
 
+@_on_stream
 def cover_edges(g: Graph, levels: torch.Tensor, ws: Workspace | None = None, stream=None):
     """(h_u, h_v): the cover edges of `levels`, lexicographic (tc_cover_edges)."""
     lib = L.load()
@@ -174,6 +198,7 @@ class CountResult:
         return int(self.h_count.item())
 
 
+@_on_stream
 def count(g: Graph, root: int = -1, per_vertex: bool = False, validate: bool = False,
           return_levels: bool = False, ws: Workspace | None = None, stream=None,
           out: CountResult | None = None) -> CountResult:
@@ -209,6 +234,7 @@ class ListResult:
         return int(self.triangles.item())
 
 
+@_on_stream
 def list_triangles(g: Graph, root: int = -1, cap: int | None = None, validate: bool = False,
                    ws: Workspace | None = None, stream=None, out: ListResult | None = None) -> ListResult:
     """Triangle finding (tc_list_triangles).  With cap=None the triangles are
@@ -242,6 +268,7 @@ class RootChoice:
     h: list[int]              # |H| with each candidate as root
 
 
+@_on_stream
 def select_root(g: Graph, num_candidates: int = 8, validate: bool = False, ws: Workspace | None = None,
                 stream=None) -> RootChoice:
     """Root choice for a small cover-edge set (tc_select_root)."""
@@ -260,6 +287,7 @@ def select_root(g: Graph, num_candidates: int = 8, validate: bool = False, ws: W
     return RootChoice(int(root.value), list(cand[:used]), list(hs[:used]))
 
 
+@_on_stream
 def edge_support(g: Graph, tri: torch.Tensor, stream=None) -> torch.Tensor:
     """Triangles per CSR entry from a triangle list (tc_edge_support)."""
     lib = L.load()
@@ -273,6 +301,7 @@ def edge_support(g: Graph, tri: torch.Tensor, stream=None) -> torch.Tensor:
     return sup[: g.nnz]
 
 
+@_on_stream
 def count_edge_baseline(g: Graph, validate: bool = False, ws: Workspace | None = None, stream=None,
                         out: torch.Tensor | None = None) -> torch.Tensor:
     """Plain direction-oriented edge-iterator count (tc_count_edge_baseline)."""

@@ -18,7 +18,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from .api import TcError, Workspace, _check, _ptr, _stream, build_csr, default_workspace, workspace_bytes
+from .api import TcError, Workspace, _check, _on_stream, _ptr, _stream, build_csr, default_workspace, workspace_bytes
 
 MAX_N = 65536
 
@@ -99,6 +99,7 @@ def make_tuning(t: dict | None) -> L.TcTuning | None:
                       int(t.get("batch_blocks_per_cu", 0)), (ctypes.c_int32 * 5)())
 
 
+@_on_stream
 def count_batch(b: Batch, tuning: dict | None = None, return_levels: bool = False,
                 ws: Workspace | None = None, stream=None, out: BatchResult | None = None) -> BatchResult:
     """tc_count_batch: exact T and |H| of every graph (device tensors)."""
