@@ -57,7 +57,10 @@ __global__ void root_key_kernel(const int64_t* off, int64_t n, unsigned long lon
 constexpr int kBig = 4096;         // frontier rows above this length are expanded edge-balanced
 constexpr int kBigCap = 4096;      // listed rows per level (more: expanded by their thread)
 constexpr int kMaxParts = 4096;    // blocks of the step kernels (partials per kernel)
-constexpr int kLevelsPerSync = 8;  // levels launched between two reads of the state
+// levels launched between two reads of the state: six covers a small-world
+// graph searched from a hub (R-MAT S10-S20 take 5-6; deeper graphs read the
+// state again after six, and the levels past the stop cost a no-op launch each)
+constexpr int kLevelsPerSync = 6;
 constexpr int kLevelsPerSyncRest = 4;
 
 // Device-side state of one BFS (see BfsWs::st).
