@@ -231,12 +231,16 @@ __device__ __forceinline__ void unpack(const Counts& k, int (&cnt)[kGroups], int
 // Groups of a part (3 bits per entry in *kp) and its output ids.
 template <class Lay, int R>
 __device__ __forceinline__ Counts classify_part(const Lay& lay, const RowCtx& c, const int32_t (&wv)[R],
-                                                int32_t (&vv)[R], uint64_t* kp) {
+                                                int32_t (&vv)[R], uint64_t* kp, int nr = R) {
   static_assert(3 * R <= 64, "group codes are packed in one 64-bit word");
   uint64_t k3 = 0;
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     vv[u] = 0;
+    if (u >= nr) {  // past the part (uniform): no entries
+      k3 |= static_cast<uint64_t>(kNoGroup) << (3 * u);
+      continue;
+    }
     const int k = wv[u] >= 0 ? lay.cls(c, wv[u], vv[u]) : kNoGroup;
     k3 |= static_cast<uint64_t>(k) << (3 * u);
   }
@@ -244,6 +248,7 @@ __device__ __forceinline__ Counts classify_part(const Lay& lay, const RowCtx& c,
   uint64_t slt = 0;
 #pragma unroll
   for (int u = 0; u < R; ++u) {
+    if (u >= nr) break;
     const int k = static_cast<int>((k3 >> (3 * u)) & 7u);
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) cnt[g] += __popcll(__ballot(k == g));
@@ -257,10 +262,11 @@ __device__ __forceinline__ Counts classify_part(const Lay& lay, const RowCtx& c,
 // entries keep their order inside each group.
 template <int R>
 __device__ __forceinline__ void write_part(const int32_t (&vv)[R], uint64_t k3, int64_t (&p)[kGroups],
-                                           int32_t* out) {
+                                           int32_t* out, int nr = R) {
   const uint64_t lt = lanemask_lt();
 #pragma unroll
   for (int u = 0; u < R; ++u) {
+    if (u >= nr) break;
     const int k = static_cast<int>((k3 >> (3 * u)) & 7u);
     uint64_t m[kGroups];
 #pragma unroll
@@ -306,7 +312,8 @@ __global__ __launch_bounds__(kThreads) void lay_mid_kernel(Lay lay, const int32_
     if (more) cn = rows[rn];
     int32_t vv[R];
     uint64_t k3;
-    const Counts pk = classify_part<Lay, R>(lay, c, wv, vv, &k3);
+    const int nr = static_cast<int>((c.ie - c.ib + kWave - 1) / kWave);  // rounds of this row
+    const Counts pk = classify_part<Lay, R>(lay, c, wv, vv, &k3, nr);
     int32_t wn[R];
     if (more) load_part<R>(cols, cn, 0, wn);
     int cnt[kGroups], slt;
@@ -315,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void lay_mid_kernel(Lay lay, const int32_
     const int zero[kGroups] = {0, 0, 0, 0, 0, 0};
     int64_t p[kGroups];
     group_starts(c, cnt, zero, p);
-    write_part<R>(vv, k3, p, out);
+    write_part<R>(vv, k3, p, out, nr);
     if (!more) break;
     r = rn;
     c = cn;
@@ -340,7 +347,10 @@ __global__ __launch_bounds__(WPR * kWave) void lay_block_kernel(Lay lay, const i
     int32_t wv[R], vv[R];
     uint64_t k3;
     load_part<R>(cols, c, wave * kPart, wv);
-    const Counts pk = classify_part<Lay, R>(lay, c, wv, vv, &k3);
+    // rounds of this wave's part (0 past the row's end)
+    const int64_t plen = (c.ie - c.ib) - static_cast<int64_t>(wave) * kPart;
+    const int nr = plen <= 0 ? 0 : static_cast<int>(plen >= kPart ? R : (plen + kWave - 1) / kWave);
+    const Counts pk = classify_part<Lay, R>(lay, c, wv, vv, &k3, nr);
     if (lane() == 0) {
       s_a[wave] = pk.a;
       s_b[wave] = pk.b;
@@ -362,7 +372,7 @@ __global__ __launch_bounds__(WPR * kWave) void lay_block_kernel(Lay lay, const i
     if (threadIdx.x == 0) meta[c.self] = row_meta(c, cnt, slt);
     int64_t p[kGroups];
     group_starts(c, cnt, bef, p);
-    write_part<R>(vv, k3, p, out);
+    write_part<R>(vv, k3, p, out, nr);
     __syncthreads();  // s_a, s_b are rewritten for the next row
   }
 }
