@@ -152,7 +152,7 @@ int tc_validate_csr(const tc_csr* g, void* ws, size_t ws_bytes, tc_stream_t stre
  *   num_levels   host int32 (nullable): the largest level count of any one
  *                BFS (max level + 1; 0 for n = 0)
  * Synchronises `stream`: the BFS state is read back once per group of up to
- * eight levels from the root, and, if vertices with edges are left
+ * six levels from the root, and, if vertices with edges are left
  * unreached, once per group of up to four levels of the remaining
  * components. */
 int tc_bfs_levels(const tc_csr* g, int64_t root, uint32_t flags, int32_t* levels,
