@@ -134,44 +134,134 @@ def stream_bandwidth(torch, dev, nbytes=1 << 30, reps=5):
             "read_GBps": round(nbytes / t_read / 1e9, 1)}
 
 
-def cpu_baseline(g, n, m, budget_s):
-    """Oracle on the host: full BFS + cover edges, count over a row prefix."""
+def _cpu_model():
+    try:
+        return [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
+    except Exception:
+        return platform.processor()
+
+
+def row_work(c, levels):
+    """List elements the oracle's count touches per row u (its
+    direct-address mode): N(u) is stamped once if u has a cover edge (u, v),
+    v > u, and N(v) is scanned for each such edge.  A cost model for the
+    sampled CPU estimate, from degrees and levels only."""
     import numpy as np
+    deg = np.diff(c.row_offsets)
+    rows = np.repeat(np.arange(c.n, dtype=np.int64), deg)
+    cols = c.cols.astype(np.int64)
+    lv = np.asarray(levels)
+    hz = (rows < cols) & (lv[rows] == lv[cols])
+    u, v = rows[hz], cols[hz]
+    del rows, cols, hz
+    w = np.bincount(u, weights=deg[v].astype(np.float64), minlength=c.n)
+    w += np.where(np.bincount(u, minlength=c.n) > 0, deg, 0)
+    return w
+
+
+def _strided_estimate(oracle, c, levels, phase, stride, work):
+    """Time the oracle count over the rows phase, phase + stride, ... and
+    scale it to all rows by the elements those rows touch (a ratio
+    estimate: time per element of the sample times all elements)."""
+    t = time.perf_counter()
+    oracle.count_rows_strided(c, levels, phase, stride)
+    dt = time.perf_counter() - t
+    rows = len(range(phase, c.n, stride))
+    w_s = float(work[phase::stride].sum())
+    return dt, rows, dt * float(work.sum()) / max(w_s, 1.0)
+
+
+def cpu_leg(args):
+    """The CPU oracle on the benchmark graph, single-threaded, on a bounded
+    sample: full BFS and cover edges, then the count over `parts` systematic
+    row samples (rows phase, phase + stride, ... for different phases: ids
+    are relabelled uniformly at random, so every phase is a uniform sample
+    spread over the whole id range), each scaled to all rows.  Prints one
+    JSON line (run as a child process of the benchmark)."""
+    import numpy as np
+    import graphgen
     import oracle
+    g = graphgen.rmat(args.scale, args.edge_factor, seed=args.seed)
     c = oracle.from_graph(g)
+    del g
+    log(f"[cpu] oracle CSR of R-MAT scale {args.scale} built")
     t = time.perf_counter()
     lv = oracle.bfs_levels(c)
     t_bfs = time.perf_counter() - t
     t = time.perf_counter()
     hu, _ = oracle.cover_edges(c, lv.levels)
     t_h = time.perf_counter() - t
-    rows_done, t_count, chunk = 0, 0.0, max(1, c.n // 4096)
-    while rows_done < c.n and t_count < budget_s:
-        hi = min(c.n, rows_done + chunk)
+    del hu
+    work_rows = row_work(c, lv.levels)
+    # pilot: about 1/1024 of the rows, to size the sample to the budget
+    pilot_stride = max(1, c.n // 1024)
+    dt, rows, _ = _strided_estimate(oracle, c, lv.levels, 0, pilot_stride, work_rows)
+    per_row = dt / max(rows, 1)
+    parts = 4
+    stride = max(1, int(math.ceil(c.n * per_row * parts / max(args.cpu_budget, 1e-3))))
+    ests, t_count, sampled = [], 0.0, 0
+    if stride <= parts:
+        # the budget covers the whole count: time it exactly
         t = time.perf_counter()
-        oracle.count_rows(c, lv.levels, rows_done, hi)
-        t_count += time.perf_counter() - t
-        rows_done = hi
-        chunk = min(chunk * 2, max(1, c.n // 64))
-    frac = rows_done / max(c.n, 1)
-    est = t_bfs + t_h + t_count / max(frac, 1e-12)
-    # the cost measures of Alg. 1 on this graph (not timed): the list
-    # elements its intersections would scan, beside the GPU path's own count
+        oracle.count(c, lv.levels, 0)
+        t_count = time.perf_counter() - t
+        ests = [t_count]
+        sampled = c.n
+        stride = 1
+    else:
+        for k in range(parts):
+            phase = (k * stride) // parts + stride // (2 * parts)
+            dt, rows, est = _strided_estimate(oracle, c, lv.levels, phase, stride, work_rows)
+            ests.append(est)
+            t_count += dt
+            sampled += rows
+            log(f"[cpu] sample {k + 1}/{parts}: {rows} rows in {dt:.1f}s -> full count {est:.0f}s")
+    est_count = float(np.mean(ests))
+    est = t_bfs + t_h + est_count
     work = oracle.work_counters(c, lv.levels)
-    try:
-        model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
-    except Exception:
-        model = platform.processor()
-    return {
+    m = c.m
+    spread = (max(ests) - min(ests)) / est_count if len(ests) > 1 else 0.0
+    out = {
         "value": m / est, "unit": "edges/s", "cores": 1, "kind": "oracle",
-        "sample": (f"single-threaded CPU oracle (oracle/oracle.c, gcc -O2) on this host "
-                   f"(1 of {os.cpu_count()} cores, {model}): full BFS {t_bfs:.2f}s + cover edges "
-                   f"{t_h:.2f}s, count over rows [0, {rows_done}) = {100 * frac:.1f}% of the rows "
-                   f"(uniform sample, ids relabelled) in {t_count:.1f}s, scaled to all rows; "
-                   f"estimated full run {est:.1f}s"),
+        "sample": (f"single-threaded CPU oracle (oracle/oracle.c, gcc -O2) on this host (1 of {os.cpu_count()} "
+                   f"cores, {_cpu_model()}) on R-MAT scale {args.scale}: full BFS {t_bfs:.2f}s + cover edges "
+                   f"{t_h:.2f}s, then the count over {len(ests)} systematic row samples (every {stride}th row, "
+                   f"{sampled} rows = {100.0 * sampled / max(c.n, 1):.3f}% in {t_count:.1f}s), each scaled to "
+                   f"all rows by the list elements the rows touch; estimated full run {est:.0f}s"),
         "estimated_full_seconds": est,
+        "count_estimates_s": ests,
+        "estimate_spread": spread,
+        "stride": stride,
         "alg1_work": work,
     }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_validate(args):
+    """How good the sampled estimate is: on R-MAT scale `args.scale` the
+    full oracle count is timed, then systematic row samples at two strides
+    (8 phases each) are scaled to all rows as the CPU baseline does;
+    prints the relative errors as one JSON line."""
+    import graphgen
+    import oracle
+    g = graphgen.rmat(args.scale, args.edge_factor, seed=args.seed)
+    c = oracle.from_graph(g)
+    del g
+    lv = oracle.bfs_levels(c)
+    work_rows = row_work(c, lv.levels)
+    t = time.perf_counter()
+    oracle.count(c, lv.levels, 0)
+    t_full = time.perf_counter() - t
+    log(f"[cpu-check] full oracle count at scale {args.scale}: {t_full:.1f}s")
+    res = {"scale": args.scale, "full_count_s": t_full, "strides": {}}
+    for stride in (32, 512):
+        errs = []
+        for k in range(8):
+            _, _, est = _strided_estimate(oracle, c, lv.levels, (k * stride) // 8, stride, work_rows)
+            errs.append((est - t_full) / t_full)
+        res["strides"][str(stride)] = {"rel_errors": [round(e, 4) for e in errs],
+                                       "max_abs_rel_error": round(max(abs(e) for e in errs), 4)}
+    print(json.dumps(res), flush=True)
 
 
 def bench_list(args):
@@ -319,25 +409,31 @@ def bench_serving(args):
     }
 
 
-COUNT_SRC = os.path.join(ROOT, "paper_2210_00389_amd", "csrc", "count.hip")
+HEAVY_SRCS = [os.path.join(ROOT, "paper_2210_00389_amd", "csrc", f) for f in ("count.hip", "tc_common.h",
+                                                                              "tc_internal.h")]
 
 
-def source_sha(path=COUNT_SRC):
+def source_sha(paths=None):
+    """SHA-256 over the sources the heavy kernels are compiled from."""
     import hashlib
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for p in paths or HEAVY_SRCS:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
 
 
 def traffic_record(scale):
-    """Counter-measured HBM bytes per heavy-stage launch, from the committed
-    summary of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a
-    1 GiB copy; None when missing or taken on another kernel source."""
-    path = os.path.join(ROOT, "profiles", f"heavy_rmat{scale}.json")
+    """Counter-measured DRAM bytes per heavy-stage launch, from the committed
+    summary of rocprofv3 --pmc runs (see summarize_counters); None when
+    missing or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"counters_rmat{scale}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("source_sha256") != source_sha():
+    heavy = rec.get("heavy")
+    if not heavy or heavy.get("source_sha256") != source_sha():
         return None
-    return rec
+    return {"traffic_bytes": heavy.get("traffic_bytes"), "summary": f"profiles/counters_rmat{scale}.md"}
 
 
 def bench_pmc(args):
@@ -372,136 +468,193 @@ def _csv_rows(d, name):
     return out
 
 
-def summarize(args):
-    """Turn rocprofv3 CSV output into the short text summaries kept under
-    profiles/ (kernel statistics, heavy-stage spans, counter traffic)."""
-    out_md = [f"# {args.title}", "", "Command:", "", "```", args.cmd, "```", ""]
-    rec = {}
-    if args.trace_dir:
-        stats = _csv_rows(args.trace_dir, "kernel_stats.csv")
-        stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
-        out_md += ["Top kernels (rocprofv3 --kernel-trace --stats):", "",
-                   "| kernel | calls | total ms | average us | share |", "|---|---|---|---|---|"]
-        for r in stats[:16]:
-            out_md.append(f"| {r['Name'][:60]} | {r['Calls']} | {float(r['TotalDurationNs'])/1e6:.3f} | "
-                          f"{float(r['AverageNs'])/1e3:.1f} | {float(r['Percentage']):.1f}% |")
-        trace = sorted(_csv_rows(args.trace_dir, "kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"]))
-        heavy = [r for r in trace if "heavy_kernel" in r["Kernel_Name"]]
-        spans = []
-        for i in range(0, len(heavy) - 3, 4):  # the four bins of one call run side by side
-            grp = heavy[i:i + 4]
-            spans.append((max(int(r["End_Timestamp"]) for r in grp) - min(int(r["Start_Timestamp"]) for r in grp)) / 1e6)
-        if spans:
-            out_md += ["", f"Heavy stage (the four bin kernels: in sequence for the cover count, side by side for the comparator) span per call, ms: "
-                           f"{', '.join(f'{x:.3f}' for x in spans)}; mean {statistics.mean(spans):.3f}", ""]
-            rec["heavy_span_ms"] = spans
-    if args.fetch_dir and args.write_dir:
-        def per_dispatch(d, counter):
-            rows = _csv_rows(d, "counter_collection.csv")
-            acc = {}
-            for r in rows:
-                if r["Counter_Name"] != counter:
-                    continue
-                k = (int(r["Dispatch_Id"]), r["Kernel_Name"])
-                acc[k] = acc.get(k, 0.0) + float(r["Counter_Value"])
-            return sorted(acc.items())
-        fetch = per_dispatch(args.fetch_dir, "FETCH_SIZE")
-        write = per_dispatch(args.write_dir, "WRITE_SIZE")
-        copy_f = [v for (d, k), v in fetch if "copy" in k.lower()]
-        copy_w = [v for (d, k), v in write if "copy" in k.lower()]
-        hf = [v for (d, k), v in fetch if "heavy_kernel" in k]
-        hw = [v for (d, k), v in write if "heavy_kernel" in k]
-        gib_kib = 2**30 / 1024
-        ff = gib_kib / max(copy_f) if copy_f else None
-        wf = gib_kib / max(copy_w) if copy_w else None
-        steps = len(hf) // 4
-        fetch_launch = [sum(hf[4 * i:4 * i + 4]) * 1024 * ff for i in range(steps)] if ff else []
-        write_launch = [sum(hw[4 * i:4 * i + 4]) * 1024 * wf for i in range(len(hw) // 4)] if wf else []
-        rec.update({"source_sha256": source_sha(), "fetch_factor": ff, "write_factor": wf,
-                    "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
-                    "fetch_bytes_per_launch": fetch_launch, "write_bytes_per_launch": write_launch,
-                    "traffic_bytes": (statistics.mean(fetch_launch[1:] or fetch_launch) +
-                                      statistics.mean(write_launch[1:] or write_launch))
-                    if fetch_launch and write_launch else None})
-        out_md += ["Counter traffic of the heavy stage (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, "
-                   "KiB per dispatch summed over the four bin kernels of a call):", "",
-                   f"- calibration: a 1 GiB device copy reads FETCH_SIZE {copy_f} KiB, WRITE_SIZE {copy_w} KiB "
-                   f"-> factors {ff:.3f} (fetch), {wf:.3f} (write)" if ff and wf else "- calibration missing",
-                   f"- fetch per call (scaled), GB: {', '.join(f'{x/1e9:.3f}' for x in fetch_launch)}",
-                   f"- write per call (scaled), GB: {', '.join(f'{x/1e9:.4f}' for x in write_launch)}",
-                   f"- traffic per call (mean after the first): {rec['traffic_bytes']/1e9:.3f} GB"
-                   if rec.get("traffic_bytes") else "", ""]
-    with open(args.out + ".md", "w") as f:
-        f.write("\n".join(out_md) + "\n")
-    if args.fetch_dir:
-        with open(args.out + ".json", "w") as f:
-            json.dump(rec, f, indent=1)
-    print(json.dumps({"summary": args.out}), flush=True)
-
-
-def summarize_kernels(args):
-    """Per-kernel HBM traffic of one count call from two unfiltered
-    rocprofv3 --pmc runs of the pmc program (FETCH_SIZE, then WRITE_SIZE),
-    scaled by the 1 GiB copy like the heavy-stage record.  A count call is
-    the dispatches from a root_key_kernel to the next stats_kernel; the
-    table covers the last call, and the totals give the time-weighted rate
-    over all of its kernels."""
+def _kname(name):
     import re
+    m = re.match(r"[A-Za-z_0-9]+", name)  # names may be truncated (-T)
+    return m.group(0) if m else name[:40]
 
-    def rows(d, counter):
-        acc, dur, name = {}, {}, {}
+
+# kernels launched with several LDS sizes (the table bins of the heavy
+# kernel) get one row per size
+_MULTI_LDS = ("heavy_kernel",)
+
+
+def _kkey(row):
+    kn = _kname(row["Kernel_Name"])
+    if kn in _MULTI_LDS:
+        lds = _col(row, "LDS_Block_Size")
+        if lds is not None:
+            return f"{kn}[lds={int(lds)}]"
+    return kn
+
+
+def _col(row, *keys):
+    """First present (case-insensitive) column among keys, as a float."""
+    low = {k.lower(): v for k, v in row.items()}
+    for k in keys:
+        v = low.get(k.lower())
+        if v not in (None, ""):
+            try:
+                return float(v)
+            except ValueError:
+                pass
+    return None
+
+
+WAVES_PER_SIMD_MAX = 8     # gfx950: 32 waves per CU, 4 SIMDs
+VGPRS_PER_SIMD_LANE = 512  # unified architectural + accumulation registers
+LDS_PER_CU = 160 * 1024
+
+
+def theoretical_waves_per_simd(vgpr, agpr, lds, wg):
+    """Waves per SIMD a kernel's resources allow on gfx950: registers
+    (granule 8 of the 512 per lane), LDS (whole workgroups in 160 KB per CU)
+    and the 8-wave cap.  Returns (waves, limiter)."""
+    lim = [(WAVES_PER_SIMD_MAX, "cap")]
+    regs = (vgpr or 0) + (agpr or 0)
+    if regs > 0:
+        lim.append((VGPRS_PER_SIMD_LANE // (int(math.ceil(regs / 8.0)) * 8), "vgpr"))
+    waves_wg = max(1, int(math.ceil((wg or 64) / 64.0)))
+    if lds and lds > 0:
+        lim.append(((LDS_PER_CU // int(lds)) * waves_wg / 4.0, "lds"))
+    return min(lim)
+
+
+def summarize_counters(args):
+    """Per-kernel figures of one count call (the last of the pmc program's
+    calls: dispatches from a root_key_kernel to the next stats_kernel) from
+    rocprofv3 --pmc runs (any of TCC_EA0_RDREQ_DRAM_32B,
+    TCC_EA0_WRREQ_WRITE_DRAM_32B, TCC_HIT, TCC_MISS, FETCH_SIZE, WRITE_SIZE,
+    MeanOccupancyPerCU) and a --kernel-trace run (durations, registers, LDS,
+    workgroup size).  DRAM bytes are 32 x the 32-byte request counts, scaled
+    by what they read for the pmc program's plain 1 GiB device copy.  Writes
+    <out>.md and <out>.json; the json's "heavy" entry is the traffic per
+    heavy-stage launch that bench.py reports."""
+    counters = {}  # counter -> {dispatch: value}
+    names, dur = {}, {}
+    for d in args.pmc_dir or []:
         for r in _csv_rows(d, "counter_collection.csv"):
-            if r["Counter_Name"] != counter:
-                continue
             k = int(r["Dispatch_Id"])
-            acc[k] = acc.get(k, 0.0) + float(r["Counter_Value"])
-            dur[k] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
-            m = re.match(r"[A-Za-z_0-9]+", r["Kernel_Name"])  # names are truncated (-T)
-            name[k] = m.group(0) if m else r["Kernel_Name"][:40]
-        return acc, dur, name
+            c = r["Counter_Name"]
+            counters.setdefault(c, {})
+            counters[c][k] = counters[c].get(k, 0.0) + float(r["Counter_Value"])
+            names.setdefault(c, {})[k] = _kkey(r)
+            if "Start_Timestamp" in r and r["Start_Timestamp"]:
+                dur.setdefault(c, {})[k] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
 
-    fa, fdur, fname = rows(args.fetch_dir, "FETCH_SIZE")
-    wa, _, wname = rows(args.write_dir, "WRITE_SIZE")
-    gib_kib = 2**30 / 1024
-    cf = [v for k, v in fa.items() if "copy" in fname[k].lower()]
-    cw = [v for k, v in wa.items() if "copy" in wname[k].lower()]
-    ff, wf = gib_kib / max(cf), gib_kib / max(cw)
-
-    def last_call(names):
-        ids = sorted(names)
-        starts = [k for k in ids if names[k].startswith("root_key_kernel")]
+    def last_call(nm):
+        ids = sorted(nm)
+        starts = [k for k in ids if nm[k].startswith("root_key_kernel")]
+        if not starts:
+            return ids
         a = starts[-1]
-        b = next(k for k in ids if k > a and names[k].startswith("stats_kernel"))
+        b = next((k for k in ids if k > a and nm[k].startswith("stats_kernel")), ids[-1])
         return [k for k in ids if a <= k <= b]
 
-    fc, wc = last_call(fname), last_call(wname)
+    def copy_value(c):
+        v = [x for k, x in counters.get(c, {}).items() if "copy" in names[c][k].lower()]
+        return max(v) if v else None
+
     table = {}
-    for k in fc:
-        t = table.setdefault(fname[k], [0, 0.0, 0.0, 0.0])
-        t[0] += 1
-        t[1] += fdur[k]
-        t[2] += fa[k] * 1024 * ff
-    for k in wc:
-        if wname[k] in table:
-            table[wname[k]][3] += wa[k] * 1024 * wf
-    tot_ms = sum(t[1] for t in table.values())
-    tot_b = sum(t[2] + t[3] for t in table.values())
-    out_md = [f"# {args.title}", "", "Command:", "", "```", args.cmd, "```", "",
-              f"Counter traffic of every kernel of one count call (the last of the program's calls), "
-              f"FETCH_SIZE x {ff:.3f} and WRITE_SIZE x {wf:.3f} (factors from a 1 GiB device copy); "
-              f"kernel times are those of the counter runs.", "",
-              "| kernel | dispatches | kernel ms | fetch GB | write GB | GB/s |", "|---|---|---|---|---|---|"]
-    for nm, t in sorted(table.items(), key=lambda kv: -kv[1][1]):
-        if t[1] < 0.005 * tot_ms:
+
+    def add(kn, field, v):
+        t = table.setdefault(kn, {})
+        t[field] = t.get(field, 0.0) + v
+
+    calib = {}
+    for c, unit, field, expect in (("TCC_EA0_RDREQ_DRAM_32B", 32.0, "dram_read", 2**30),
+                                   ("TCC_EA0_WRREQ_WRITE_DRAM_32B", 32.0, "dram_write", 2**30),
+                                   ("FETCH_SIZE", 1024.0, "fetch", 2**30), ("WRITE_SIZE", 1024.0, "write", 2**30),
+                                   ("TCC_HIT", 1.0, "l2_hit", None), ("TCC_MISS", 1.0, "l2_miss", None)):
+        if c not in counters:
             continue
-        out_md.append(f"| {nm} | {t[0]} | {t[1]:.3f} | {t[2]/1e9:.3f} | {t[3]/1e9:.3f} | "
-                      f"{(t[2] + t[3]) / (t[1] / 1e3) / 1e9:.0f} |")
-    out_md += ["", f"All kernels of the call: {len(fc)} dispatches, {tot_ms:.2f} ms of kernel time, "
-                   f"{tot_b/1e9:.1f} GB moved: {tot_b / (tot_ms / 1e3) / 1e9:.0f} GB/s time-weighted "
-                   f"({tot_b / (tot_ms / 1e3) / 1e9 / HBM_PEAK_GBS:.2f} of 8 TB/s).", ""]
-    rec = {"fetch_factor": ff, "write_factor": wf, "kernel_ms": tot_ms, "bytes": tot_b,
-           "kernels": {nm: {"dispatches": t[0], "ms": t[1], "fetch_bytes": t[2], "write_bytes": t[3]}
-                       for nm, t in table.items()}}
+        f = 1.0
+        if expect:
+            cv = copy_value(c)
+            f = expect / (cv * unit) if cv else 1.0
+            calib[c] = {"copy_reading_bytes": cv * unit if cv else None, "factor": f}
+        for k in last_call(names[c]):
+            add(names[c][k], field, counters[c][k] * unit * f)
+            if field in ("dram_read", "fetch"):
+                add(names[c][k], "n_" + field, 1)
+                add(names[c][k], "ms_" + field, dur.get(c, {}).get(k, 0.0))
+    if "MeanOccupancyPerCU" in counters:
+        c = "MeanOccupancyPerCU"
+        for k in last_call(names[c]):
+            w = dur.get(c, {}).get(k, 1.0)
+            add(names[c][k], "occ_w", counters[c][k] * w)
+            add(names[c][k], "occ_t", w)
+    # durations and resources from the kernel trace (last call)
+    trace = sorted(_csv_rows(args.trace_dir, "kernel_trace.csv"), key=lambda r: int(r["Start_Timestamp"])) \
+        if args.trace_dir else []
+    tnames = {i: _kkey(r) for i, r in enumerate(trace)}
+    res = {}
+    for i in last_call(tnames) if trace else []:
+        r = trace[i]
+        kn = tnames[i]
+        add(kn, "ms", (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+        add(kn, "n", 1)
+        res[kn] = (_col(r, "VGPR_Count", "Arch_VGPR_Count", "vgpr_count"), _col(r, "Accum_VGPR_Count", "agpr_count"),
+                   _col(r, "LDS_Block_Size", "LDS_Size", "Group_Segment_Size", "lds_size"),
+                   _col(r, "Workgroup_Size_X", "Workgroup_Size", "workgroup_size"))
+    for kn, t in table.items():
+        if "ms" not in t:  # no trace: the counter run's own durations
+            t["ms"] = t.get("ms_dram_read", t.get("ms_fetch", 0.0))
+            t["n"] = t.get("n_dram_read", t.get("n_fetch", 0))
+        if kn in res:
+            vg, ag, lds, wg = res[kn]
+            w, why = theoretical_waves_per_simd(vg, ag, lds, wg)
+            t.update(vgpr=vg, agpr=ag, lds=lds, wg=wg, theo_waves_simd=w, theo_limit=why)
+        if t.get("occ_t"):
+            t["achieved_waves_simd"] = t["occ_w"] / t["occ_t"] / 4.0
+        hm = t.get("l2_hit", 0.0) + t.get("l2_miss", 0.0)
+        if hm > 0:
+            t["l2_hit_frac"] = t.get("l2_hit", 0.0) / hm
+    tot_ms = sum(t.get("ms", 0.0) for t in table.values())
+    tot_b = sum(t.get("dram_read", 0.0) + t.get("dram_write", 0.0) for t in table.values())
+    heavy = {}
+    for kn, t in table.items():
+        if kn.startswith("heavy_kernel"):
+            for f in ("n", "ms", "dram_read", "dram_write", "fetch", "write"):
+                heavy[f] = heavy.get(f, 0.0) + t.get(f, 0.0)
+    rec = {"calibration": calib, "kernel_ms": tot_ms, "dram_bytes": tot_b, "kernels": table,
+           "heavy": {"source_sha256": source_sha(), "dispatches": heavy.get("n"), "ms": heavy.get("ms"),
+                     "traffic_bytes": (heavy.get("dram_read", 0.0) + heavy.get("dram_write", 0.0)) or None,
+                     "fetch_write_bytes": (heavy.get("fetch", 0.0) + heavy.get("write", 0.0)) or None}}
+
+    def fmt(v, f):
+        return "" if v is None else f.format(v)
+    out_md = [f"# {args.title}", "", "Command:", "", "```", args.cmd, "```", "",
+              "Every kernel of one count call (the last of the program's calls), one row per kernel name. "
+              "DRAM bytes: 32 x TCC_EA0_RDREQ_DRAM_32B (reads) and 32 x TCC_EA0_WRREQ_WRITE_DRAM_32B (writes), "
+              "each scaled by its reading for a plain 1 GiB device copy "
+              + ", ".join(f"{c}: factor {v['factor']:.3f}" for c, v in calib.items()) + ". "
+              "Requests leaving the L2 for memory include those the 256 MB Infinity Cache serves: "
+              "no counter here separates them. L2 hit = TCC_HIT / (TCC_HIT + TCC_MISS). "
+              "Theoretical waves per SIMD from the kernel's registers, LDS and workgroup size "
+              "(8 at most); achieved = MeanOccupancyPerCU / 4 (time-weighted over dispatches).", "",
+              "| kernel | dispatches | ms | DRAM read GB | DRAM write GB | GB/s | L2 hit | VGPR | LDS B | WG | "
+              "theo. waves/SIMD | achieved waves/SIMD |",
+              "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for kn, t in sorted(table.items(), key=lambda kv: -kv[1].get("ms", 0.0)):
+        if tot_ms and t.get("ms", 0.0) < 0.003 * tot_ms:
+            continue
+        b = t.get("dram_read", 0.0) + t.get("dram_write", 0.0)
+        out_md.append(
+            f"| {kn} | {int(t.get('n', 0))} | {t.get('ms', 0.0):.3f} | {t.get('dram_read', 0.0)/1e9:.3f} | "
+            f"{t.get('dram_write', 0.0)/1e9:.3f} | {fmt(b / (t['ms'] / 1e3) / 1e9 if t.get('ms') else None, '{:.0f}')} | "
+            f"{fmt(t.get('l2_hit_frac'), '{:.2f}')} | {fmt(t.get('vgpr'), '{:.0f}')} | {fmt(t.get('lds'), '{:.0f}')} | "
+            f"{fmt(t.get('wg'), '{:.0f}')} | {fmt(t.get('theo_waves_simd'), '{:.2f}')}"
+            f"{' (' + t['theo_limit'] + ')' if t.get('theo_limit') else ''} | "
+            f"{fmt(t.get('achieved_waves_simd'), '{:.2f}')} |")
+    if tot_ms:
+        out_md += ["", f"All kernels of the call: {tot_ms:.2f} ms of kernel time, {tot_b/1e9:.1f} GB of DRAM "
+                       f"requests: {tot_b / (tot_ms / 1e3) / 1e9:.0f} GB/s time-weighted "
+                       f"({tot_b / (tot_ms / 1e3) / 1e9 / HBM_PEAK_GBS:.2f} of 8 TB/s).", ""]
+    if heavy.get("ms"):
+        out_md += [f"Heavy stage (heavy_kernel, {int(heavy.get('n', 0))} dispatches): {heavy['ms']:.3f} ms, "
+                   f"DRAM traffic {rec['heavy']['traffic_bytes'] / 1e9 if rec['heavy']['traffic_bytes'] else 0:.2f} GB "
+                   f"per call (source sha256 {rec['heavy']['source_sha256'][:16]}).", ""]
     with open(args.out + ".md", "w") as f:
         f.write("\n".join(out_md) + "\n")
     with open(args.out + ".json", "w") as f:
@@ -509,12 +662,215 @@ def summarize_kernels(args):
     print(json.dumps({"summary": args.out}), flush=True)
 
 
+def rmat_line(args, scale, steps, warmup, comparator=True, stream=True, root_candidates=0):
+    """One single-graph line: tc_count on R-MAT `scale` resident in HBM,
+    timed over `steps` calls after `warmup`, beside the comparator, with
+    the dominant stage's roofline and per-stage rates."""
+    import numpy as np
+    import torch
+    import graphgen
+    import paper_2210_00389_amd as tc
+    from paper_2210_00389_amd import comm_model
+    dev = torch.device("cuda:0")
+    log(f"[bench] generating R-MAT scale {scale} ef {args.edge_factor} seed {args.seed}")
+    t = time.perf_counter()
+    g = graphgen.rmat(scale, args.edge_factor, seed=args.seed)
+    t_gen = time.perf_counter() - t
+    t = time.perf_counter()
+    G = tc.from_host_pairs(g.n, g.src, g.dst, device=dev)
+    del g
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t
+    n, m, nnz = G.n, G.m, G.nnz
+    log(f"[bench] n={n} m={m} nnz={nnz} gen {t_gen:.1f}s upload+build {t_build:.2f}s")
+
+    ws = tc.Workspace(dev)
+    res = tc.CountResult(torch.zeros(1, dtype=torch.int64, device=dev), torch.zeros(1, dtype=torch.int64, device=dev),
+                         None, None)
+    tb = torch.zeros(1, dtype=torch.int64, device=dev)
+    step = lambda: tc.count(G, ws=ws, out=res)  # noqa: E731
+    base = lambda: tc.count_edge_baseline(G, ws=ws, out=tb)  # noqa: E731
+
+    tc.profile_enable(True)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done; timing {steps} cover-edge steps")
+    wall, per, stages = run_timed(step, steps, torch.cuda.synchronize)
+    T, h = res.T, res.h
+    st = tc.read_stats(ws)
+    comp = None
+    if comparator:
+        for _ in range(warmup):
+            base()
+        torch.cuda.synchronize()
+        log(f"[bench] timing {steps} comparator steps")
+        wall_b, per_b, stages_b = run_timed(base, steps, torch.cuda.synchronize)
+        Tb = int(tb.item())
+        st_b = tc.read_stats(ws)
+        comp = {
+            "name": "plain direction-oriented edge iterator (same kernels, forward lists N+(x))",
+            "ms_per_step": 1000 * wall_b / steps,
+            "p50_ms": percentile(per_b, 50), "p99_ms": percentile(per_b, 99),
+            "edges_per_s": m / (wall_b / steps), "triangles": Tb, "exact_match": Tb == T,
+            "stream_elems": st_b["stream_elems"], "bin_elems": st_b["bin_elems"],
+            "stages_ms": {k: statistics.mean(v) for k, v in stages_b.items()},
+        }
+        hb = comp["stages_ms"].get("heavy")
+        if hb:
+            comp["heavy_GBps"] = round(stage_bytes("heavy", st_b, n, nnz, False) / (hb / 1e3) / 1e9, 1)
+        comp["element_ratio_vs_cover"] = round(st_b["stream_elems"] / max(st["stream_elems"], 1), 4)
+    tc.profile_enable(False)
+
+    ms = 1000 * wall / steps
+    stage_avg = {k: statistics.mean(v) for k, v in stages.items()}
+    dom = max(stage_avg, key=stage_avg.get)
+    dom_bytes = stage_bytes(dom, st, n, nnz, True)
+    roof = None
+    if dom_bytes is not None:
+        ach = dom_bytes / (stage_avg[dom] / 1000.0) / 1e9
+        tr = traffic_record(scale) if dom == "heavy" else None
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": int(tr["traffic_bytes"]) if tr and tr.get("traffic_bytes") else None,
+                "traffic_source": tr.get("summary") if tr else None,
+                "algorithmic_bytes_per_launch": int(dom_bytes), "avg_launch_ms": round(stage_avg[dom], 4)}
+    stage_roofs = {}
+    for k, v in stage_avg.items():
+        b = stage_bytes(k, st, n, nnz, True)
+        if b is not None and v > 0:
+            stage_roofs[k] = {"ms": round(v, 4), "GB/s": round(b / (v / 1000.0) / 1e9, 1)}
+        else:
+            stage_roofs[k] = {"ms": round(v, 4)}
+
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", f"rmat_s{scale}.json")
+    if args.edge_factor == 16 and args.seed == 1 and os.path.exists(gpath):
+        gd = json.load(open(gpath))
+        golden = {"triangles": gd["triangles"], "h": gd["h"], "match": gd["triangles"] == T and gd["h"] == h}
+        if comp is not None:
+            golden["comparator_match"] = comp["triangles"] == gd["triangles"]
+
+    # Distributed-variant context: the communication model of the parallel
+    # algorithm for this graph's measured k, on one node of 8 GPUs
+    deg = np.diff(G.row_offsets.cpu().numpy())
+    wedges = int((deg * (deg - 1) // 2).sum())
+    cmr = comm_model.volume_for_count(n, m, h, st["num_levels"], p=8, wedges=wedges)
+    comm = {"p": 8, "k": round(cmr.k, 4), "level_bits": cmr.level_bits, "wedges": wedges,
+            "cover_bytes": int(cmr.cover_bytes), "wedge_check_bytes": int(cmr.previous_bytes),
+            "reduction": round(cmr.reduction, 2)}
+
+    sbw = None
+    if stream:
+        log("[bench] copy/read bandwidth reference")
+        sbw = stream_bandwidth(torch, dev)
+        if roof is not None:
+            sbw["dominant_vs_copy"] = round(roof["achieved"] / sbw["copy_GBps"], 4)
+
+    root_choice = None
+    if root_candidates > 0:
+        # the paper's goal of the smallest k: choose the root among the
+        # highest-degree vertices by |H|, then time the count from it
+        log(f"[bench] root choice over {root_candidates} candidates")
+        t0 = time.perf_counter()
+        rc = tc.select_root(G, root_candidates, ws=ws)
+        t_sel = time.perf_counter() - t0
+        res_r = tc.count(G, root=rc.root, ws=ws)
+        wall_r, per_r, _ = run_timed(lambda: tc.count(G, root=rc.root, ws=ws, out=res_r), steps,
+                                     torch.cuda.synchronize)
+        assert res_r.T == T
+        root_choice = {"candidates": rc.candidates, "h": rc.h, "root": rc.root, "k": min(rc.h) / m,
+                       "k_default_root": h / m, "select_ms": 1000 * t_sel,
+                       "count_ms_chosen_root": 1000 * wall_r / steps}
+    del G, ws
+    torch.cuda.empty_cache()
+    return {
+        "metric": "cover-edge TC edges/s", "value": m / (wall / steps), "unit": "edges/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"R-MAT scale {scale}, edge factor {args.edge_factor}, "
+                               f"(0.57,0.19,0.19,0.05), seed {args.seed}, relabelled, symmetrised, deduplicated; "
+                               f"root = largest degree; single-graph cover-edge count",
+                   "n": n, "m": m, "nnz": nnz, "h": h, "k": h / max(m, 1), "triangles": T,
+                   "num_levels": st["num_levels"]},
+        "triangles_per_s": T / (wall / steps),
+        "p50_ms": percentile(per, 50), "p99_ms": percentile(per, 99),
+        "comparator": comp,
+        "speedup_vs_comparator": (comp["ms_per_step"] / ms) if comp else None,
+        "roofline": roof,
+        "stream_bw": sbw,
+        "stages": stage_roofs,
+        "work": st,
+        "golden": golden,
+        "comm_model": comm,
+        "root_choice": root_choice,
+    }
+
+
+def _child(args, mode, scale, budget=None):
+    """Start a CPU-oracle leg (cpu_leg / cpu_validate) of this benchmark as
+    a child process on the host cores; its JSON line comes back on stdout."""
+    cmd = [sys.executable, os.path.abspath(__file__), mode, "--scale", str(scale),
+           "--edge-factor", str(args.edge_factor), "--seed", str(args.seed)]
+    if budget is not None:
+        cmd += ["--cpu-budget", str(budget)]
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    return subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True, env=env)
+
+
+def _collect(proc):
+    out, _ = proc.communicate()
+    lines = [l for l in out.splitlines() if l.startswith("{")]
+    if proc.returncode != 0 or not lines:
+        log(f"[bench] CPU leg failed with status {proc.returncode}")
+        return None
+    return json.loads(lines[-1])
+
+
+def start_cpu_legs(args):
+    """Start the CPU oracle legs; call before anything touches the GPU, so
+    that no child is started from a process that has initialised it."""
+    kids = {}
+    if not args.no_cpu_baseline:
+        kids["cpu"] = _child(args, "--cpu-leg", args.scale, args.cpu_budget)
+        if args.cpu_check_scale > 0:
+            kids["check"] = _child(args, "--cpu-validate", args.cpu_check_scale)
+    return kids
+
+
+def bench_rmat(args, kids):
+    """The headline line (R-MAT at --scale, default 24) with the R-MAT scale
+    20 line nested, and the CPU oracle legs (already started) beside them."""
+    out = rmat_line(args, args.scale, args.steps, args.warmup, comparator=not args.no_comparator,
+                    stream=not args.no_stream, root_candidates=args.root_candidates)
+    if args.nested_scale > 0 and args.nested_scale != args.scale:
+        nest = rmat_line(args, args.nested_scale, args.steps, args.warmup, comparator=not args.no_comparator,
+                         stream=False)
+        out[f"rmat{args.nested_scale}"] = {k: nest[k] for k in (
+            "value", "unit", "ms_per_step", "p50_ms", "p99_ms", "triangles_per_s", "config", "comparator",
+            "speedup_vs_comparator", "roofline", "stages", "golden")}
+    cpu = None
+    if "cpu" in kids:
+        log("[bench] waiting for the CPU oracle legs")
+        cpu = _collect(kids["cpu"])
+        if cpu is not None and "check" in kids:
+            cpu["estimator_check"] = _collect(kids["check"])
+    out["cpu_baseline"] = cpu
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--scale", type=int, default=24)
+    ap.add_argument("--nested-scale", type=int, default=20, help="a second R-MAT line nested in the first (0: none)")
+    ap.add_argument("--cpu-check-scale", type=int, default=20,
+                    help="scale of the full oracle run that checks the sampled CPU estimate (0: none)")
+    ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-validate", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--edge-factor", type=int, default=16)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle count in the CPU sample")
@@ -525,12 +881,10 @@ def main():
     ap.add_argument("--workload", choices=("rmat", "batch", "serving", "pmc", "list"), default="rmat")
     ap.add_argument("--root-candidates", type=int, default=0,
                     help="also choose the root by |H| among this many highest-degree vertices and time it")
-    ap.add_argument("--summarize", action="store_true", help="summarise rocprofv3 output into --out(.md/.json)")
-    ap.add_argument("--summarize-kernels", action="store_true",
-                    help="per-kernel counter traffic of one count call from unfiltered --pmc runs")
+    ap.add_argument("--summarize-counters", action="store_true",
+                    help="per-kernel DRAM traffic, L2 hits and occupancy of one count call from rocprofv3 runs")
     ap.add_argument("--trace-dir", default=None)
-    ap.add_argument("--fetch-dir", default=None)
-    ap.add_argument("--write-dir", default=None)
+    ap.add_argument("--pmc-dir", action="append", default=None, help="a rocprofv3 --pmc output folder (repeatable)")
     ap.add_argument("--out", default=None)
     ap.add_argument("--title", default="rocprofv3 summary")
     ap.add_argument("--cmd", default="")
@@ -543,11 +897,14 @@ def main():
     ap.add_argument("--serve-budget-frac", type=float, default=0.5)
     args = ap.parse_args()
 
-    if args.summarize:
-        summarize(args)
+    if args.summarize_counters:
+        summarize_counters(args)
         return
-    if args.summarize_kernels:
-        summarize_kernels(args)
+    if args.cpu_leg:
+        cpu_leg(args)
+        return
+    if args.cpu_validate:
+        cpu_validate(args)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -556,9 +913,8 @@ def main():
         log("bench.py: only --gpus 1 is supported (the library runs on one GPU)")
         sys.exit(2)
 
+    kids = start_cpu_legs(args) if args.workload == "rmat" else {}
     import torch
-    import graphgen
-    import paper_2210_00389_amd as tc
 
     torch.cuda.set_device(0)
     if args.workload == "pmc":
@@ -572,140 +928,7 @@ def main():
             with open(args.json_out, "w") as f:
                 f.write(line + "\n")
         return
-    dev = torch.device("cuda:0")
-    log(f"[bench] generating R-MAT scale {args.scale} ef {args.edge_factor} seed {args.seed}")
-    t = time.perf_counter()
-    g = graphgen.rmat(args.scale, args.edge_factor, seed=args.seed)
-    t_gen = time.perf_counter() - t
-    t = time.perf_counter()
-    G = tc.from_host_pairs(g.n, g.src, g.dst, device=dev)
-    torch.cuda.synchronize()
-    t_build = time.perf_counter() - t
-    n, m, nnz = G.n, G.m, G.nnz
-    log(f"[bench] n={n} m={m} nnz={nnz} gen {t_gen:.1f}s upload+build {t_build:.2f}s")
-
-    ws = tc.Workspace(dev)
-    ws_b = tc.Workspace(dev)
-    res = tc.CountResult(torch.zeros(1, dtype=torch.int64, device=dev), torch.zeros(1, dtype=torch.int64, device=dev),
-                         None, None)
-    tb = torch.zeros(1, dtype=torch.int64, device=dev)
-    step = lambda: tc.count(G, ws=ws, out=res)  # noqa: E731
-    base = lambda: tc.count_edge_baseline(G, ws=ws_b, out=tb)  # noqa: E731
-
-    tc.profile_enable(True)
-    for _ in range(args.warmup):
-        step()
-        if not args.no_comparator:
-            base()
-    torch.cuda.synchronize()
-    log(f"[bench] warmup done; timing {args.steps} cover-edge steps")
-    wall, per, stages = run_timed(step, args.steps, torch.cuda.synchronize)
-    T, h = res.T, res.h
-    st = tc.read_stats(ws)
-    comp = None
-    if not args.no_comparator:
-        log(f"[bench] timing {args.steps} comparator steps")
-        wall_b, per_b, stages_b = run_timed(base, args.steps, torch.cuda.synchronize)
-        Tb = int(tb.item())
-        st_b = tc.read_stats(ws_b)
-        comp = {
-            "name": "plain direction-oriented edge iterator (same kernels, forward lists N+(x))",
-            "ms_per_step": 1000 * wall_b / args.steps,
-            "p50_ms": percentile(per_b, 50), "p99_ms": percentile(per_b, 99),
-            "edges_per_s": m / (wall_b / args.steps), "triangles": Tb, "exact_match": Tb == T,
-            "stream_elems": st_b["stream_elems"],
-            "stages_ms": {k: statistics.mean(v) for k, v in stages_b.items()},
-        }
-    tc.profile_enable(False)
-
-    ms = 1000 * wall / args.steps
-    stage_avg = {k: statistics.mean(v) for k, v in stages.items()}
-    dom = max(stage_avg, key=stage_avg.get)
-    dom_bytes = stage_bytes(dom, st, n, nnz, True)
-    roof = None
-    if dom_bytes is not None:
-        ach = dom_bytes / (stage_avg[dom] / 1000.0) / 1e9
-        tr = traffic_record(args.scale) if dom == "heavy" else None
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": int(tr["traffic_bytes"]) if tr and tr.get("traffic_bytes") else None,
-                "algorithmic_bytes_per_launch": int(dom_bytes), "avg_launch_ms": round(stage_avg[dom], 4)}
-    stage_roofs = {}
-    for k, v in stage_avg.items():
-        b = stage_bytes(k, st, n, nnz, True)
-        if b is not None and v > 0:
-            stage_roofs[k] = {"ms": round(v, 4), "GB/s": round(b / (v / 1000.0) / 1e9, 1)}
-        else:
-            stage_roofs[k] = {"ms": round(v, 4)}
-
-    golden = None
-    gpath = os.path.join(ROOT, "tests", "golden", f"rmat_s{args.scale}.json")
-    if args.edge_factor == 16 and args.seed == 1 and os.path.exists(gpath):
-        gd = json.load(open(gpath))
-        golden = {"triangles": gd["triangles"], "h": gd["h"], "match": gd["triangles"] == T and gd["h"] == h}
-
-    # Distributed-variant context: the communication model of the parallel
-    # algorithm for this graph's measured k, on one node of 8 GPUs
-    import numpy as np
-    from paper_2210_00389_amd import comm_model
-    deg = np.diff(G.row_offsets.cpu().numpy())
-    wedges = int((deg * (deg - 1) // 2).sum())
-    cmr = comm_model.volume_for_count(n, m, h, st["num_levels"], p=8, wedges=wedges)
-    comm = {"p": 8, "k": round(cmr.k, 4), "level_bits": cmr.level_bits, "wedges": wedges,
-            "cover_bytes": int(cmr.cover_bytes), "wedge_check_bytes": int(cmr.previous_bytes),
-            "reduction": round(cmr.reduction, 2)}
-
-    stream = None
-    if not args.no_stream:
-        log("[bench] copy/read bandwidth reference")
-        stream = stream_bandwidth(torch, dev)
-        if roof is not None:
-            stream["dominant_vs_copy"] = round(roof["achieved"] / stream["copy_GBps"], 4)
-
-    root_choice = None
-    if args.root_candidates > 0:
-        # the paper's goal of the smallest k: choose the root among the
-        # highest-degree vertices by |H|, then time the count from it
-        log(f"[bench] root choice over {args.root_candidates} candidates")
-        t0 = time.perf_counter()
-        rc = tc.select_root(G, args.root_candidates, ws=ws)
-        t_sel = time.perf_counter() - t0
-        res_r = tc.count(G, root=rc.root, ws=ws)
-        wall_r, per_r, _ = run_timed(lambda: tc.count(G, root=rc.root, ws=ws, out=res_r), args.steps,
-                                     torch.cuda.synchronize)
-        assert res_r.T == T
-        root_choice = {"candidates": rc.candidates, "h": rc.h, "root": rc.root, "k": min(rc.h) / m,
-                       "k_default_root": h / m, "select_ms": 1000 * t_sel,
-                       "count_ms_chosen_root": 1000 * wall_r / args.steps}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("[bench] CPU oracle sample")
-        cpu = cpu_baseline(g, n, m, args.cpu_budget)
-
-    out = {
-        "metric": "cover-edge TC edges/s", "value": m / (wall / args.steps), "unit": "edges/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": f"R-MAT scale {args.scale}, edge factor {args.edge_factor}, "
-                               f"(0.57,0.19,0.19,0.05), seed {args.seed}, relabelled, symmetrised, deduplicated; "
-                               f"root = largest degree; single-graph cover-edge count",
-                   "n": n, "m": m, "nnz": nnz, "h": h, "k": h / max(m, 1), "triangles": T,
-                   "num_levels": st["num_levels"]},
-        "triangles_per_s": T / (wall / args.steps),
-        "p50_ms": percentile(per, 50), "p99_ms": percentile(per, 99),
-        "comparator": comp,
-        "speedup_vs_comparator": (comp["ms_per_step"] / ms) if comp else None,
-        "roofline": roof,
-        "stream_bw": stream,
-        "stages": stage_roofs,
-        "work": st,
-        "golden": golden,
-        "comm_model": comm,
-        "root_choice": root_choice,
-        "cpu_baseline": cpu,
-    }
+    out = bench_rmat(args, kids)
     line = json.dumps(out)
     print(line, flush=True)
     if args.json_out:

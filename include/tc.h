@@ -244,10 +244,19 @@ int tc_count_edge_baseline(const tc_csr* g, uint32_t flags, int64_t* triangles, 
 
 /* Cover-edge counts of many small graphs in one persistent launch: per graph,
  * the levels of tc_bfs_levels (root = largest degree), H and T.
- *   triangles    device int64 [G] (output)
- *   h_count      device int64 [G] (nullable output)
+ *   triangles    device int64 [G] (output); -1 for a graph of more than
+ *                TC_BATCH_MAX_N vertices, which is skipped (its levels are
+ *                not written)
+ *   h_count      device int64 [G] (nullable output); -1 as for triangles
  *   levels       device int32 [total_vertices] (nullable output)
- * Issues no host synchronisation (capturable in a hipGraph). */
+ * flags: TC_VALIDATE checks the batch first -- vbase rising from 0 to
+ * total_vertices, every n_g within TC_BATCH_MAX_N (else TC_ERR_TOO_LARGE) and
+ * within max_graph_vertices (else TC_ERR_INVALID_ARG), offsets monotone from
+ * 0 to total_nnz, and each graph a simple undirected CSR in its local ids
+ * (the statuses of tc_validate_csr); the check synchronises `stream`.
+ * Without TC_VALIDATE the call issues no host synchronisation (capturable in
+ * a hipGraph), and a max_graph_vertices above TC_BATCH_MAX_N is still
+ * rejected before any device work. */
 int tc_count_batch(const tc_batch* b, const tc_tuning* tuning, uint32_t flags,
                    int64_t* triangles, int64_t* h_count, int32_t* levels, void* ws,
                    size_t ws_bytes, tc_stream_t stream);

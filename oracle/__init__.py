@@ -100,6 +100,8 @@ def _bind(lib):
     lib.oracle_edge_count.restype = i64
     lib.oracle_count_rows.argtypes = [i64, p, p, p, c_int, i64, i64, p]
     lib.oracle_count_rows.restype = c_int
+    lib.oracle_count_rows_strided.argtypes = [i64, p, p, p, c_int, i64, i64, i64, p]
+    lib.oracle_count_rows_strided.restype = c_int
     lib.oracle_list_triangles.argtypes = [i64, p, p, p, p, i64, p]
     lib.oracle_list_triangles.restype = c_int
     lib.oracle_edge_supports.argtypes = [i64, p, p, p, p]
@@ -238,6 +240,19 @@ def count_rows(csr: CSR, levels: np.ndarray, u_begin: int, u_end: int, mode: int
     T = np.zeros(1, dtype=np.int64)
     _check(_load().oracle_count_rows(csr.n, _p(csr.row_offsets), _p(cols), _p(L), mode, u_begin, u_end,
                                      _p(T)))
+    return int(T[0])
+
+
+def count_rows_strided(csr: CSR, levels: np.ndarray, phase: int, stride: int, mode: int = 0) -> int:
+    """Alg. 1 count restricted to cover edges (u, v) with u = phase (mod
+    stride): the phases of one stride partition the rows."""
+    cols = csr.cols if csr.cols.size else np.zeros(1, dtype=np.int32)
+    L = np.ascontiguousarray(levels, dtype=np.int32)
+    if L.size == 0:
+        L = np.zeros(1, dtype=np.int32)
+    T = np.zeros(1, dtype=np.int64)
+    _check(_load().oracle_count_rows_strided(csr.n, _p(csr.row_offsets), _p(cols), _p(L), mode,
+                                             min(phase, csr.n), csr.n, stride, _p(T)))
     return int(T[0])
 
 

@@ -241,12 +241,14 @@ static inline int counts(const int32_t* L, int32_t u, int32_t v, int32_t w) {
  *                       oracle_cover_edges
  *   per_vertex (null.)  number of counted triangles containing each vertex
  *   mode                0 = direct-address table, 1 = two-pointer merge
- * (count_rows runs the loop over the rows u in [u_begin, u_end) only.) */
+ * (count_rows runs the loop over the rows u = u_begin, u_begin + stride, ...
+ * below u_end only; the full count is stride 1 over [0, n).) */
 static int count_rows(int64_t n, const int64_t* off, const int32_t* cols, const int32_t* L, int mode,
-                      int64_t u_begin, int64_t u_end, int64_t* T, int64_t* per_edge, int64_t* per_vertex) {
+                      int64_t u_begin, int64_t u_end, int64_t stride, int64_t* T, int64_t* per_edge,
+                      int64_t* per_vertex) {
   if (n < 0 || !off || !T || (n > 0 && !L)) return OR_EINVAL;
   if (mode != 0 && mode != 1) return OR_EINVAL;
-  if (u_begin < 0 || u_end > n || u_begin > u_end) return OR_EINVAL;
+  if (u_begin < 0 || u_end > n || u_begin > u_end || stride < 1) return OR_EINVAL;
   int64_t total = 0, hidx = 0;
   int64_t* stamp = NULL;
   if (per_vertex)
@@ -256,7 +258,7 @@ static int count_rows(int64_t n, const int64_t* off, const int32_t* cols, const 
     if (!stamp && n > 0) return OR_ENOMEM;
     for (int64_t v = 0; v < n; ++v) stamp[v] = -1;
   }
-  for (int64_t u = u_begin; u < u_end; ++u) {
+  for (int64_t u = u_begin; u < u_end; u += stride) {
     int stamped = 0;
     for (int64_t i = off[u]; i < off[u + 1]; ++i) {
       int32_t v = cols[i];
@@ -302,7 +304,7 @@ static int count_rows(int64_t n, const int64_t* off, const int32_t* cols, const 
 
 int oracle_count(int64_t n, const int64_t* off, const int32_t* cols, const int32_t* L, int mode,
                  int64_t* T, int64_t* per_edge, int64_t* per_vertex) {
-  return count_rows(n, off, cols, L, mode, 0, n, T, per_edge, per_vertex);
+  return count_rows(n, off, cols, L, mode, 0, n, 1, T, per_edge, per_vertex);
 }
 
 /* The same count restricted to the cover edges (u, v) with u in
@@ -310,7 +312,16 @@ int oracle_count(int64_t n, const int64_t* off, const int32_t* cols, const int32
  * a bounded sample of the work. */
 int oracle_count_rows(int64_t n, const int64_t* off, const int32_t* cols, const int32_t* L, int mode,
                       int64_t u_begin, int64_t u_end, int64_t* T) {
-  return count_rows(n, off, cols, L, mode, u_begin, u_end, T, NULL, NULL);
+  return count_rows(n, off, cols, L, mode, u_begin, u_end, 1, T, NULL, NULL);
+}
+
+/* The same count restricted to the rows u_begin, u_begin + stride, ... below
+ * u_end: the phases 0 .. stride-1 partition the rows, so their counts sum to
+ * T.  A systematic sample across the whole id range, used to time a bounded
+ * share of the work. */
+int oracle_count_rows_strided(int64_t n, const int64_t* off, const int32_t* cols, const int32_t* L, int mode,
+                              int64_t u_begin, int64_t u_end, int64_t stride, int64_t* T) {
+  return count_rows(n, off, cols, L, mode, u_begin, u_end, stride, T, NULL, NULL);
 }
 
 /* c(u, v) for a single horizontal edge u < v, by two-pointer merge.  Used to

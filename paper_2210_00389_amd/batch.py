@@ -46,20 +46,23 @@ class Batch:
     def total_edges(self) -> int:
         return self.total_nnz // 2
 
-    def tc(self) -> L.TcBatch:
-        mx = max((n for n, _ in self.sizes), default=0)
+    def tc(self, max_graph_vertices: int | None = None) -> L.TcBatch:
+        mx = max((n for n, _ in self.sizes), default=0) if max_graph_vertices is None else max_graph_vertices
         return L.TcBatch(self.num_graphs, self.total_vertices, self.total_nnz,
                          self.vbase.data_ptr(), self.row_offsets.data_ptr(),
                          self.cols.data_ptr() if self.total_nnz else None, mx)
 
     @staticmethod
-    def from_graphs(graphs, device="cuda", ws: Workspace | None = None) -> "Batch":
+    def from_graphs(graphs, device="cuda", ws: Workspace | None = None, max_n: int = MAX_N) -> "Batch":
         """Concatenate raw graphs (graphgen.Graph: n, src, dst) into one
         batch: the union is built as one CSR by tc_build_csr (vertex ids of
-        graph g shifted by its base), then columns are made local."""
+        graph g shifted by its base), then columns are made local.  Graphs
+        above `max_n` vertices are refused (the library's limit is MAX_N;
+        a larger `max_n` lets a caller hand the library an oversize graph,
+        which it flags instead of counting)."""
         ns = np.array([g.n for g in graphs], dtype=np.int64)
-        if (ns > MAX_N).any():
-            raise ValueError(f"batched graphs must have at most {MAX_N} vertices")
+        if (ns > max_n).any():
+            raise ValueError(f"batched graphs must have at most {max_n} vertices")
         vb = np.zeros(len(graphs) + 1, dtype=np.int64)
         np.cumsum(ns, out=vb[1:])
         total = int(vb[-1])
@@ -88,7 +91,7 @@ class Batch:
 @dataclass
 class BatchResult:
     triangles: torch.Tensor  # int64 [G]
-    h_count: torch.Tensor    # int64 [G]
+    h_count: torch.Tensor | None  # int64 [G] (None when not asked for)
     levels: torch.Tensor | None = None  # int32 [sum n]
 
 
@@ -101,19 +104,25 @@ def make_tuning(t: dict | None) -> L.TcTuning | None:
 
 @_on_stream
 def count_batch(b: Batch, tuning: dict | None = None, return_levels: bool = False,
-                ws: Workspace | None = None, stream=None, out: BatchResult | None = None) -> BatchResult:
-    """tc_count_batch: exact T and |H| of every graph (device tensors)."""
+                ws: Workspace | None = None, stream=None, out: BatchResult | None = None,
+                with_h: bool = True, validate: bool = False,
+                max_graph_vertices: int | None = None) -> BatchResult:
+    """tc_count_batch: exact T and (with_h) |H| of every graph (device
+    tensors).  validate=True checks the batch's structure first (the call
+    then synchronises).  max_graph_vertices overrides the bound the batch
+    declares (tests of the library's own checks)."""
     lib = L.load()
     dev = b.cols.device
     G = b.num_graphs
     res = out or BatchResult(torch.empty(max(G, 1), dtype=torch.int64, device=dev),
-                             torch.empty(max(G, 1), dtype=torch.int64, device=dev),
+                             torch.empty(max(G, 1), dtype=torch.int64, device=dev) if with_h else None,
                              torch.empty(max(b.total_vertices, 1), dtype=torch.int32, device=dev)
                              if return_levels else None)
     buf = (ws or default_workspace(dev)).get(workspace_bytes(L.OP_COUNT_BATCH, b.total_vertices, b.total_nnz, G))
-    tb = b.tc()
+    tb = b.tc(max_graph_vertices)
     tu = make_tuning(tuning)
-    _check(lib.tc_count_batch(ctypes.byref(tb), ctypes.byref(tu) if tu is not None else None, 0,
+    _check(lib.tc_count_batch(ctypes.byref(tb), ctypes.byref(tu) if tu is not None else None,
+                              L.TC_VALIDATE if validate else 0,
                               _ptr(res.triangles), _ptr(res.h_count), _ptr(res.levels), _ptr(buf), buf.numel(),
                               _stream(stream)), "tc_count_batch")
     return res

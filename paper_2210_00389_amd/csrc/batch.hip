@@ -142,11 +142,14 @@ __global__ __launch_bounds__(kBfsThreads) void batch_bfs_kernel(const int64_t* v
   const int n = static_cast<int>(vbase[g + 1] - v0);
   const int64_t* rows = row_offsets + v0;  // rows[i] = global position of local row i
   const int64_t e0 = rows[0];
+  // a graph beyond the on-chip level array is skipped and flagged with -1
+  // (the host rejects it first when validation is on); it gets no pieces
+  const bool too_big = n > TC_BATCH_MAX_N;
   if (tid == 0) {
-    T[g] = 0;
-    H[g] = 0;
+    T[g] = too_big ? -1 : 0;
+    if (H) H[g] = too_big ? -1 : 0;
   }
-  if (n == 0) return;
+  if (n <= 0 || too_big) return;
   // root: highest degree, smallest id on ties; isolated vertices get level 0
   int64_t key = -1;
   for (int i = tid; i < n; i += nt) {
@@ -356,7 +359,7 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
       hc = block_sum(hc, sh);
       if (tid == 0) {
         if (cnt) atomicAdd(reinterpret_cast<unsigned long long*>(&T[g]), static_cast<unsigned long long>(cnt));
-        if (hc) atomicAdd(reinterpret_cast<unsigned long long*>(&H[g]), static_cast<unsigned long long>(hc));
+        if (hc && H) atomicAdd(reinterpret_cast<unsigned long long*>(&H[g]), static_cast<unsigned long long>(hc));
       }
     }
     __syncthreads();
@@ -407,9 +410,9 @@ size_t batch_ws_bytes(int64_t total_n, int64_t total_nnz, int32_t num_graphs) {
 
 int batch_run(const tc_batch* b, const tc_tuning* t, uint32_t flags, int64_t* triangles, int64_t* h_count,
               int32_t* levels, void* ws, size_t ws_bytes, hipStream_t s) {
-  (void)flags;
   const int G = b->num_graphs;
   if (G == 0) return TC_OK;
+  if (flags & TC_VALIDATE) TC_TRY(validate_batch_run(b, ws, s));
   int threads = 256, piece = 16384, bpc = 0;
   if (t) {
     if (t->batch_block) threads = t->batch_block;

@@ -168,6 +168,11 @@ int build_run(int64_t n, int64_t num_pairs, const int32_t* src, const int32_t* d
 
 size_t validate_ws_bytes(int64_t n, int64_t nnz);
 int validate_run(const tc_csr* g, void* ws, hipStream_t s);
+// Structure of a batch: vertex bases from 0 to total_vertices, every graph
+// within TC_BATCH_MAX_N and max_graph_vertices, offsets monotone, and each
+// graph a simple undirected CSR in its local ids.  Uses the first 256 bytes
+// of ws; synchronises `s`.
+int validate_batch_run(const tc_batch* b, void* ws, hipStream_t s);
 
 // ------------------------------------------------------------ batch
 size_t batch_ws_bytes(int64_t total_n, int64_t total_nnz, int32_t num_graphs);

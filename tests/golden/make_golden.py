@@ -6,11 +6,16 @@ library.  Usage::
 
     python tests/golden/make_golden.py 10 20        # scales to (re)write
     python tests/golden/make_golden.py --batch       # per-graph batch counts
+    python tests/golden/make_golden.py --serving     # the serving request pool
 
 Output: ``tests/golden/rmat_s<scale>.json`` with n, m, |H|, T (Alg. 1 count,
 direct-address mode), the edge-iterator count, level statistics and SHA-256
 digests of the level array and of the horizontal-edge list, plus
-``batch_mix.json`` with every graph's (n, m, |H|, T).
+``batch_mix.json`` with every graph's (n, m, |H|, T), and
+``serving_pool.json`` with every pool graph's (n, m, |H|, T), the SHA-256 of
+its horizontal-edge list and the 64-bit BLAKE2b digest of its levels (the
+digest a served request carries: little-endian int32 levels in vertex
+order).
 """
 import hashlib
 import json
@@ -89,12 +94,51 @@ def batch_golden(workers: int = 6) -> dict:
                 oracle_seconds=time.time() - t0)
 
 
+def _serving_row(item):
+    i, s = item
+    t0 = time.time()
+    c = oracle.from_graph(graphgen.from_spec(s))
+    lv = oracle.bfs_levels(c)
+    hu, hv = oracle.cover_edges(c, lv.levels)
+    T = oracle.count(c, lv.levels, 0).triangles
+    lv32 = np.ascontiguousarray(lv.levels.astype("<i4"))
+    return dict(i=i, spec=s, n=c.n, m=c.m, h=int(hu.size), triangles=T, num_levels=lv.num_levels,
+                levels_blake2b64=hashlib.blake2b(lv32.tobytes(), digest_size=8).hexdigest(),
+                h_sha256=digest(hu.astype("<i4"), hv.astype("<i4")), oracle_seconds=time.time() - t0)
+
+
+def serving_golden(workers: int = 6) -> dict:
+    """Oracle results for every graph of graphgen.serving_specs(128), the
+    largest first so the slowest counts start early."""
+    from multiprocessing import Pool
+    specs = graphgen.serving_specs(128)
+
+    def cost(s):
+        return 2.0 ** s["scale"] * 16 if s["kind"] == "rmat" else s["n"] * 10.0
+    order = sorted(range(len(specs)), key=lambda i: -cost(specs[i]))
+    t0 = time.time()
+    rows = []
+    with Pool(workers) as pool:
+        for r in pool.imap_unordered(_serving_row, [(i, specs[i]) for i in order]):
+            rows.append(r)
+            print(f"serving graph {r['i']} ({len(rows)}/{len(specs)}) {r['oracle_seconds']:.1f}s "
+                  f"T={r['triangles']}", flush=True)
+    rows.sort(key=lambda r: r["i"])
+    return dict(source="CPU oracle on graphgen.serving_specs(128)", graphs=rows,
+                oracle_seconds=time.time() - t0)
+
+
 def main(argv):
     if "--batch" in argv:
         out = batch_golden()
         with open(os.path.join(HERE, "batch_mix.json"), "w") as f:
             json.dump(out, f, indent=1)
         argv = [a for a in argv if a != "--batch"]
+    if "--serving" in argv:
+        out = serving_golden()
+        with open(os.path.join(HERE, "serving_pool.json"), "w") as f:
+            json.dump(out, f, indent=1)
+        argv = [a for a in argv if a != "--serving"]
     for a in argv:
         scale = int(a)
         out = rmat_golden(scale, with_edge_count=scale <= 22)

@@ -77,3 +77,17 @@ def test_argument_errors_without_gpu(lib):
     assert "workspace" in lib.tc_last_error().decode()
     # root out of range
     assert lib.tc_count(ctypes.byref(csr), 10, 0, ctypes.byref(t), None, None, None, None, 1 << 30, None) == -1
+
+
+def test_batch_argument_errors_without_gpu(lib):
+    """tc_count_batch rejects a declared graph size above TC_BATCH_MAX_N, a
+    NULL batch and negative sizes before any device work."""
+    import ctypes
+    from paper_2210_00389_amd import _lib
+    t = ctypes.c_int64(0)
+    b = _lib.TcBatch(1, 70000, 10, 1, 1, 1, 70000)
+    assert lib.tc_count_batch(ctypes.byref(b), None, 0, ctypes.byref(t), None, None, None, 1 << 30, None) == -8
+    assert "65536" in lib.tc_last_error().decode()
+    assert lib.tc_count_batch(None, None, 0, ctypes.byref(t), None, None, None, 0, None) == -1
+    b = _lib.TcBatch(-1, 0, 0, None, None, None, 0)
+    assert lib.tc_count_batch(ctypes.byref(b), None, 0, ctypes.byref(t), None, None, None, 0, None) == -1

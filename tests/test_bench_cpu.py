@@ -33,82 +33,75 @@ def test_more_than_one_gpu_is_refused():
     assert "error" in line and line["n_gpus"] == 2
 
 
-COUNTER_HEADER = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+COUNTER_HEADER = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp",
+                  "LDS_Block_Size"]
+CALLS = (("root_key_kernel", 1.0, 1000), ("resolve_kernel", 100.0, 2000), ("heavy_kernel", 300.0, 4000),
+         ("heavy_kernel", 200.0, 3000), ("stats_kernel", 0.5, 500))
 
 
-def _counter_rows(counter, calls, copy_kib):
-    """Two count calls (root_key, resolve, heavy x2, stats) and a 1 GiB copy;
-    the kernel of the second call reads 10x what the first reads."""
+def _counter_rows(counter, copy_value, scale=1.0):
+    """Two count calls (root_key, resolve, heavy x2, stats) and a 1 GiB
+    copy; the second call's kernels read 10x what the first's read.  Each
+    value is split over two rows (two cache instances) to check the sum."""
     rows, did, t = [], 1, 0
     for call in range(2):
-        for name, kib, ns in (("root_key_kernel", 1.0, 1000), ("resolve_kernel", 100.0, 2000),
-                              ("heavy_kernel", 300.0, 4000), ("heavy_kernel", 200.0, 3000),
-                              ("stats_kernel", 0.5, 500)):
-            val = kib * (10 if call else 1)
-            rows.append([did, name, counter, val, t, t + ns])
+        for name, v, ns in CALLS:
+            val = v * scale * (10 if call else 1)
+            lds = 131072 if name == "heavy_kernel" else 0
+            rows.append([did, name, counter, val / 2, t, t + ns, lds])
+            rows.append([did, name, counter, val / 2, t, t + ns, lds])
             did, t = did + 1, t + ns + 100
-    rows.append([did, "__amd_rocclr_copyBuffer", counter, copy_kib, t, t + 200000])
+    rows.append([did, "__amd_rocclr_copyBuffer", counter, copy_value, t, t + 200000, 0])
     return rows
 
 
-def test_summarize_kernels_synthetic(tmp_path):
-    fd, wd = tmp_path / "fetch", tmp_path / "write"
-    # the copy's 1 GiB reads show as 0.5 GiB of FETCH_SIZE (factor 2), its
-    # writes as 1 GiB of WRITE_SIZE (factor 1)
-    _write(str(fd / "run_counter_collection.csv"), COUNTER_HEADER, _counter_rows("FETCH_SIZE", 2, 524288.0))
-    _write(str(wd / "run_counter_collection.csv"), COUNTER_HEADER, _counter_rows("WRITE_SIZE", 2, 1048576.0))
-    out = tmp_path / "summary"
-    r = _run("--summarize-kernels", "--fetch-dir", str(fd), "--write-dir", str(wd), "--out", str(out),
-             "--title", "t", "--cmd", "c")
-    assert r.returncode == 0, r.stderr
-    rec = json.load(open(str(out) + ".json"))
-    assert rec["fetch_factor"] == pytest.approx(2.0) and rec["write_factor"] == pytest.approx(1.0)
-    k = rec["kernels"]
-    # only the last call counts: its heavy kernel read (300 + 200) * 10 KiB
-    assert k["heavy_kernel"]["dispatches"] == 2
-    assert k["heavy_kernel"]["fetch_bytes"] == pytest.approx(5000 * 1024 * 2)
-    assert k["heavy_kernel"]["write_bytes"] == pytest.approx(5000 * 1024 * 1)
-    assert k["heavy_kernel"]["ms"] == pytest.approx(0.007)
-    assert k["resolve_kernel"]["fetch_bytes"] == pytest.approx(1000 * 1024 * 2)
-    assert "__amd_rocclr_copyBuffer" not in k
-    total_kib = (1 + 100 + 300 + 200 + 0.5) * 10
-    assert rec["bytes"] == pytest.approx(total_kib * 1024 * 3)
-    assert rec["kernel_ms"] == pytest.approx((1000 + 2000 + 4000 + 3000 + 500) / 1e6)
-    md = open(str(out) + ".md").read()
-    assert md.startswith("# t") and "| heavy_kernel | 2 |" in md
-
-
-def test_summarize_heavy_stage_synthetic(tmp_path):
-    """Heavy-stage record: per call the four bin kernels' FETCH_SIZE and
-    WRITE_SIZE (KiB) summed and scaled by the copy's factors; traffic is the
-    mean over the calls after the first."""
-    fd, wd, td = tmp_path / "fetch", tmp_path / "write", tmp_path / "trace"
-    rows_f, rows_w, did = [], [], 1
-    for call, kib in enumerate((100.0, 200.0, 300.0)):
-        for b in range(4):
-            rows_f.append([did, "heavy_kernel", "FETCH_SIZE", kib, 0, 1])
-            rows_w.append([did, "heavy_kernel", "WRITE_SIZE", kib / 10, 0, 1])
-            did += 1
-    rows_f.append([did, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 524288.0, 0, 1])
-    rows_w.append([did, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 1048576.0, 0, 1])
-    _write(str(fd / "run_counter_collection.csv"), COUNTER_HEADER, rows_f)
-    _write(str(wd / "run_counter_collection.csv"), COUNTER_HEADER, rows_w)
-    _write(str(td / "run_kernel_stats.csv"), ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"],
-           [["heavy_kernel", 8, 8000000, 1000000, 90.0], ["resolve_kernel", 2, 800000, 400000, 10.0]])
-    trace = []
+def test_summarize_counters_synthetic(tmp_path):
+    """DRAM bytes per kernel of the last call, scaled by the copy (whose
+    reads show as half their size: factor 2; writes as their size: factor
+    1), the L2 hit share, and occupancy from a synthetic kernel trace."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench", BENCH)
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    rd, wr, l2 = tmp_path / "rd", tmp_path / "wr", tmp_path / "l2"
+    _write(str(rd / "run_counter_collection.csv"), COUNTER_HEADER,
+           _counter_rows("TCC_EA0_RDREQ_DRAM_32B", 2**30 / 32 / 2))
+    _write(str(wr / "run_counter_collection.csv"), COUNTER_HEADER,
+           _counter_rows("TCC_EA0_WRREQ_WRITE_DRAM_32B", 2**30 / 32, scale=0.1))
+    _write(str(l2 / "run_counter_collection.csv"), COUNTER_HEADER,
+           _counter_rows("TCC_HIT", 0.0, scale=3.0) + _counter_rows("TCC_MISS", 0.0, scale=1.0))
+    td = tmp_path / "trace"
+    trace, t = [], 0
     for call in range(2):
-        base = call * 10_000_000
-        for b in range(4):  # bins in sequence, 1 ms each
-            trace.append(["heavy_kernel", base + b * 1_000_000, base + (b + 1) * 1_000_000])
-    _write(str(td / "run_kernel_trace.csv"), ["Kernel_Name", "Start_Timestamp", "End_Timestamp"], trace)
-    out = tmp_path / "heavy"
-    r = _run("--summarize", "--trace-dir", str(td), "--fetch-dir", str(fd), "--write-dir", str(wd),
-             "--out", str(out), "--title", "t", "--cmd", "c")
+        for name, _, ns in CALLS:
+            lds = 131072 if name == "heavy_kernel" else 0
+            trace.append([name, t, t + ns, 52, 0, lds, 1024])
+            t += ns + 100
+    _write(str(td / "run_kernel_trace.csv"), ["Kernel_Name", "Start_Timestamp", "End_Timestamp", "VGPR_Count",
+                                              "Accum_VGPR_Count", "LDS_Block_Size", "Workgroup_Size_X"], trace)
+    out = tmp_path / "summary"
+    r = _run("--summarize-counters", "--trace-dir", str(td), "--pmc-dir", str(rd), "--pmc-dir", str(wr),
+             "--pmc-dir", str(l2), "--out", str(out), "--title", "t", "--cmd", "c")
     assert r.returncode == 0, r.stderr
     rec = json.load(open(str(out) + ".json"))
-    assert rec["heavy_span_ms"] == pytest.approx([4.0, 4.0])
-    assert rec["fetch_bytes_per_launch"] == pytest.approx([4 * k * 1024 * 2 for k in (100, 200, 300)])
-    assert rec["write_bytes_per_launch"] == pytest.approx([4 * k / 10 * 1024 for k in (100, 200, 300)])
-    mean_after_first = (4 * 250 * 1024 * 2) + (4 * 25 * 1024)
-    assert rec["traffic_bytes"] == pytest.approx(mean_after_first)
-    assert len(rec["source_sha256"]) == 64
+    assert rec["calibration"]["TCC_EA0_RDREQ_DRAM_32B"]["factor"] == pytest.approx(2.0)
+    assert rec["calibration"]["TCC_EA0_WRREQ_WRITE_DRAM_32B"]["factor"] == pytest.approx(1.0)
+    k = rec["kernels"]
+    # only the last call counts: its heavy kernels read (300 + 200) * 10 units
+    assert k["heavy_kernel[lds=131072]"]["n"] == 2
+    assert k["heavy_kernel[lds=131072]"]["dram_read"] == pytest.approx(5000 * 32 * 2)
+    assert k["heavy_kernel[lds=131072]"]["dram_write"] == pytest.approx(500 * 32)
+    assert k["heavy_kernel[lds=131072]"]["ms"] == pytest.approx(0.007)
+    assert k["heavy_kernel[lds=131072]"]["l2_hit_frac"] == pytest.approx(0.75)
+    # 52 VGPRs -> 56 -> 9 waves by registers; 128 KB LDS -> 1 block of 16
+    # waves per CU -> 4 waves per SIMD
+    assert k["heavy_kernel[lds=131072]"]["theo_waves_simd"] == pytest.approx(4.0)
+    assert k["heavy_kernel[lds=131072]"]["theo_limit"] == "lds"
+    assert k["resolve_kernel"]["theo_waves_simd"] == pytest.approx(8.0)
+    assert "__amd_rocclr_copyBuffer" not in k
+    assert rec["heavy"]["traffic_bytes"] == pytest.approx(5000 * 32 * 2 + 500 * 32)
+    assert len(rec["heavy"]["source_sha256"]) == 64
+    md = open(str(out) + ".md").read()
+    assert md.startswith("# t") and "| heavy_kernel[lds=131072] | 2 |" in md
+    assert bench.theoretical_waves_per_simd(128, 0, 0, 256) == (4, "vgpr")
+    assert bench.theoretical_waves_per_simd(24, 0, 65536, 256) == (2.0, "lds")

@@ -124,3 +124,83 @@ def test_batch_full_workload_golden():
     bad = [(g["i"], int(T[g["i"]]), g["triangles"]) for g in gold
            if T[g["i"]] != g["triangles"] or H[g["i"]] != g["h"]]
     assert not bad, bad[:5]
+
+
+def test_batch_without_h_count():
+    """h_count may be NULL: the counts equal those of a call that asks for
+    |H| (regression test: both kernels used to write |H| unconditionally)."""
+    import torch
+    import paper_2210_00389_amd as tc
+    print("case: batch with h_count NULL", flush=True)
+    b = tc.Batch.from_graphs(graphgen.batch_mix(24, seed_base=55, n_max=8192))
+    ref = tc.count_batch(b).triangles.cpu()
+    r = tc.count_batch(b, with_h=False)
+    assert r.h_count is None
+    assert torch.equal(r.triangles.cpu(), ref)
+
+
+def test_batch_oversize_graph_flagged():
+    """A graph above 65536 vertices handed over without validation is skipped
+    with T = |H| = -1; the other graphs of the batch are still exact.  With
+    validation the call is rejected before any kernel runs."""
+    import paper_2210_00389_amd as tc
+    big = graphgen.erdos_renyi(70000, 4.0 / 69999, 8)
+    graphs = [graphgen.complete(20), big, graphgen.wheel(50)]
+    print("case: batch with an oversize graph", flush=True)
+    b = tc.Batch.from_graphs(graphs, max_n=70000)
+    r = tc.count_batch(b, max_graph_vertices=65536)
+    T = r.triangles.cpu().tolist()
+    H = r.h_count.cpu().tolist()
+    assert T == [1140, -1, 49] and H[1] == -1
+    assert H[0] == _oracle(graphs[0])[1] and H[2] == _oracle(graphs[2])[1]
+    with pytest.raises(tc.TcError) as e:
+        tc.count_batch(b, max_graph_vertices=65536, validate=True)
+    assert e.value.status == -8
+    with pytest.raises(tc.TcError) as e:
+        tc.count_batch(b, max_graph_vertices=70000)
+    assert e.value.status == -8
+
+
+def test_batch_validation_statuses():
+    """TC_VALIDATE on a batch: a valid batch passes and counts as without
+    it; a declared max_graph_vertices below the real one, a column outside
+    its graph, an asymmetric graph and an unsorted row give their statuses."""
+    import torch
+    import paper_2210_00389_amd as tc
+    graphs = [graphgen.complete(6), graphgen.cycle(9), graphgen.wheel(12)]
+    print("case: batch validation", flush=True)
+    b = tc.Batch.from_graphs(graphs)
+    assert tc.count_batch(b, validate=True).triangles.cpu().tolist() == [20, 0, 11]
+    with pytest.raises(tc.TcError) as e:
+        tc.count_batch(b, validate=True, max_graph_vertices=8)
+    assert e.value.status == -1
+
+    def mutated(fn):
+        cols = b.cols.clone()
+        fn(cols, b.row_offsets.cpu().numpy())
+        return tc.Batch(b.vbase, b.row_offsets, cols, b.sizes)
+
+    def out_of_range(cols, off):   # first entry of cycle(9) row 0 -> local id 9
+        cols[int(off[6])] = 9
+
+    def duplicate(cols, off):      # K6 row 0 is [1..5]: its last entry 5 -> 4 repeats 4
+        cols[int(off[1]) - 1] = 4
+
+    def unsorted(cols, off):       # wheel's local row 1 (degree >= 3): swap its first two entries
+        a = int(off[6 + 9 + 1])
+        x, y = int(cols[a]), int(cols[a + 1])
+        cols[a], cols[a + 1] = y, x
+
+    for fn, want in ((out_of_range, -7), (duplicate, -4), (unsorted, -3)):
+        with pytest.raises(tc.TcError) as e:
+            tc.count_batch(mutated(fn), validate=True)
+        assert e.value.status == want, fn.__name__
+    # an entry whose reverse is missing: row 0 of the cycle points to 2
+    # instead of 1 (rows stay ascending: cycle row 0 is [1, 8])
+    cols = b.cols.clone()
+    off = b.row_offsets.cpu().numpy()
+    cols[int(off[6])] = 2
+    with pytest.raises(tc.TcError) as e:
+        tc.count_batch(tc.Batch(b.vbase, b.row_offsets, cols, b.sizes), validate=True)
+    assert e.value.status == -6
+    torch.cuda.synchronize()

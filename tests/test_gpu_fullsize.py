@@ -1,8 +1,9 @@
 """Parity at the full sizes of the R-MAT workloads (scales 20, 22, 24) in the
 launch configuration the benchmark times, against values the CPU oracle
 stored in tests/golden/ (written by tests/golden/make_golden.py): T, |H|,
-the level array (SHA-256), the comparator's count, and sampled per-vertex
-counts that are recomputed one by one on the CPU."""
+the level array and the horizontal-edge list (SHA-256), the comparator's
+count, and sampled per-vertex counts that are recomputed one by one on the
+CPU."""
 import hashlib
 import json
 import os
@@ -50,6 +51,16 @@ def test_rmat_full_size(scale):
     if "levels_sha256" in gold:
         digest = hashlib.sha256(res.levels.cpu().numpy().astype("<i4").tobytes()).hexdigest()
         assert digest == gold["levels_sha256"]
+    if "h_sha256" in gold:
+        # the explicit cover-edge list of these levels (tc_cover_edges),
+        # lexicographic, against the oracle's list: SHA-256 of h_u then h_v
+        hu, hv = tc.cover_edges(G, res.levels)
+        assert hu.numel() == gold["h"]
+        hsh = hashlib.sha256()
+        hsh.update(hu.cpu().numpy().astype("<i4").tobytes())
+        hsh.update(hv.cpu().numpy().astype("<i4").tobytes())
+        assert hsh.hexdigest() == gold["h_sha256"]
+        del hu, hv
     if "edge_iterator_triangles" in gold:
         assert int(tc.count_edge_baseline(G).item()) == gold["edge_iterator_triangles"]
     if scale == 20:

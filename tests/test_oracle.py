@@ -306,3 +306,22 @@ def test_count_rows_partition_sums_to_T():
     parts = [oracle.count_rows(c, L, a, b) for a, b in zip(cuts, cuts[1:])]
     assert sum(parts) == T
     assert oracle.count_rows(c, L, 0, c.n, mode=1) == T
+
+
+def test_count_rows_strided_phases_sum_to_T():
+    """The strided row samples of one stride partition the rows: their
+    counts sum to T (pinned against brute force) for several strides, in
+    both intersection modes, and stride 1 is the full count."""
+    g = graphgen.rmat(9, 16, seed=4)
+    c = oracle.from_graph(g)
+    L = oracle.bfs_levels(c).levels
+    T = len(brute.triangles(brute.adjacency(g.n, g.src, g.dst)))
+    assert oracle.count(c, L).triangles == T
+    for stride in (1, 2, 7, 64, c.n + 5):
+        for mode in (0, 1):
+            parts = [oracle.count_rows_strided(c, L, ph, stride, mode) for ph in range(stride)]
+            assert sum(parts) == T, (stride, mode)
+    assert oracle.count_rows_strided(c, L, 0, 1) == T
+    # one phase equals the sum of its rows counted one by one
+    rows = range(3, c.n, 11)
+    assert oracle.count_rows_strided(c, L, 3, 11) == sum(oracle.count_rows(c, L, u, u + 1) for u in rows)
