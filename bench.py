@@ -387,13 +387,31 @@ def bench_serving(args):
     # rate would strand each rate's workspaces in the caching allocator,
     # which reuses a freed block only on the stream that allocated it)
     ex = serve.GpuExecutor(pool, args.slots)
+    # the oracle's stored answers for the default pool (tests/golden/serving_pool.json)
+    gold = None
+    gpath = os.path.join(ROOT, "tests", "golden", "serving_pool.json")
+    if os.path.exists(gpath):
+        rows = json.load(open(gpath))["graphs"]
+        if len(rows) == len(specs) and all(r["spec"] == sp for r, sp in zip(rows, specs)):
+            gold = {r["i"]: (r["triangles"], r["h"]) for r in rows}
+    batching = not args.no_batching
+    small = serve.small_request if batching else None
+    ws_fn = lambda n, nnz: serve.request_ws_bytes(n, nnz, batching)  # noqa: E731
+    checked, mismatched = 0, 0
     for rate in args.rates:
-        reqs = serve.make_requests(sizes, serve.count_ws_bytes, rate=rate, count=args.requests, seed=int(rate))
-        st = serve.Server(ex, slots=args.slots, budget_bytes=budget).run(reqs)
+        reqs = serve.make_requests(sizes, ws_fn, rate=rate, count=args.requests, seed=int(rate))
+        st = serve.Server(ex, slots=args.slots, budget_bytes=budget, small=small,
+                          batch_max=args.batch_max).run(reqs)
         torch.cuda.synchronize()
         st["rate_req_s"] = rate
+        if gold is not None:
+            bad = [r.rid for r in reqs if (r.triangles, r.h) != gold[r.graph_id]]
+            checked += len(reqs)
+            mismatched += len(bad)
+            st["golden_mismatches"] = len(bad)
         log(f"[bench] rate {rate}: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms "
-            f"edges/s {st['edges_per_s']:.3e} busy {st['busy_fraction']:.2f}")
+            f"edges/s {st['edges_per_s']:.3e} busy {st['busy_fraction']:.2f} batched {st['batched']} "
+            f"jobs {st['jobs']} failed {st['failed']}")
         runs.append(st)
     top = runs[-1]
     return {
@@ -403,9 +421,15 @@ def bench_serving(args):
         "config": {"workload": f"Poisson arrivals over a pool of {len(specs)} graphs (half R-MAT scale "
                                f"12-{args.serve_scale_max} ef16, half Chung-Lu gamma 2.1 mean degree 20 n "
                                f"1e4-{args.serve_cl_n_max:.0e}); {args.slots} slots; HBM budget "
-                               f"{args.serve_budget_frac:.2f} of free", "rates": args.rates,
-                   "requests_per_rate": args.requests},
+                               f"{args.serve_budget_frac:.2f} of free; "
+                               + (f"small graphs (n <= {serve.SMALL_N}, nnz <= {serve.SMALL_NNZ}) coalesced "
+                                  f"into tc_count_batch launches of up to {args.batch_max}" if batching
+                                  else "no batching"),
+                   "rates": args.rates, "requests_per_rate": args.requests},
         "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"], "runs": runs,
+        "golden": ({"requests_checked": checked, "mismatches": mismatched, "all_match": mismatched == 0
+                    and all(r["failed"] == 0 for r in runs)} if gold is not None else None),
+        "uploads": ex.uploads,
     }
 
 
@@ -753,12 +777,14 @@ def rmat_line(args, scale, steps, warmup, comparator=True, stream=True, root_can
 
     # Distributed-variant context: the communication model of the parallel
     # algorithm for this graph's measured k, on one node of 8 GPUs
-    deg = np.diff(G.row_offsets.cpu().numpy())
-    wedges = int((deg * (deg - 1) // 2).sum())
-    cmr = comm_model.volume_for_count(n, m, h, st["num_levels"], p=8, wedges=wedges)
-    comm = {"p": 8, "k": round(cmr.k, 4), "level_bits": cmr.level_bits, "wedges": wedges,
-            "cover_bytes": int(cmr.cover_bytes), "wedge_check_bytes": int(cmr.previous_bytes),
-            "reduction": round(cmr.reduction, 2)}
+    comm = None
+    if st["num_levels"] > 0 and m > 0:  # the one-workgroup path reports no level count
+        deg = np.diff(G.row_offsets.cpu().numpy())
+        wedges = int((deg * (deg - 1) // 2).sum())
+        cmr = comm_model.volume_for_count(n, m, h, st["num_levels"], p=8, wedges=wedges)
+        comm = {"p": 8, "k": round(cmr.k, 4), "level_bits": cmr.level_bits, "wedges": wedges,
+                "cover_bytes": int(cmr.cover_bytes), "wedge_check_bytes": int(cmr.previous_bytes),
+                "reduction": round(cmr.reduction, 2)}
 
     sbw = None
     if stream:
@@ -844,6 +870,17 @@ def bench_rmat(args, kids):
     20 line nested, and the CPU oracle legs (already started) beside them."""
     out = rmat_line(args, args.scale, args.steps, args.warmup, comparator=not args.no_comparator,
                     stream=not args.no_stream, root_candidates=args.root_candidates)
+    if args.latency_scale > 0:
+        # the small-graph latency floor (1000 counts of R-MAT scale 10)
+        lat = rmat_line(args, args.latency_scale, args.latency_steps, max(args.warmup, 20),
+                        comparator=not args.no_comparator, stream=False)
+        out[f"rmat{args.latency_scale}_latency"] = {k: lat[k] for k in (
+            "ms_per_step", "p50_ms", "p99_ms", "config", "golden")}
+        if lat["comparator"]:
+            out[f"rmat{args.latency_scale}_latency"]["comparator"] = {
+                k: lat["comparator"][k] for k in ("ms_per_step", "p50_ms", "p99_ms", "exact_match")}
+            out[f"rmat{args.latency_scale}_latency"]["p50_speedup_vs_comparator"] = (
+                lat["comparator"]["p50_ms"] / lat["p50_ms"])
     if args.nested_scale > 0 and args.nested_scale != args.scale:
         nest = rmat_line(args, args.nested_scale, args.steps, args.warmup, comparator=not args.no_comparator,
                          stream=False)
@@ -867,6 +904,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--nested-scale", type=int, default=20, help="a second R-MAT line nested in the first (0: none)")
+    ap.add_argument("--latency-scale", type=int, default=10,
+                    help="an R-MAT latency line (small-graph floor) nested in the first (0: none)")
+    ap.add_argument("--latency-steps", type=int, default=1000)
     ap.add_argument("--cpu-check-scale", type=int, default=20,
                     help="scale of the full oracle run that checks the sampled CPU estimate (0: none)")
     ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
@@ -895,6 +935,8 @@ def main():
     ap.add_argument("--serve-scale-max", type=int, default=22)
     ap.add_argument("--serve-cl-n-max", type=int, default=10**6)
     ap.add_argument("--serve-budget-frac", type=float, default=0.5)
+    ap.add_argument("--no-batching", action="store_true", help="serving: one tc_count per request")
+    ap.add_argument("--batch-max", type=int, default=64, help="serving: graphs per coalesced launch")
     args = ap.parse_args()
 
     if args.summarize_counters:

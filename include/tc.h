@@ -105,18 +105,31 @@ typedef struct tc_batch {
 
 #define TC_BATCH_MAX_N 65536
 
-/* Tuning knobs of tc_count_batch; a NULL tc_tuning* (or a zero field) means
- * the compiled-in default.  The autotuner of the Python package picks them
- * per batch shape. */
+/* Tuning knobs; a NULL tc_tuning* (or a zero field) means the compiled-in
+ * default.  None of them changes a result, only how the work is scheduled.
+ * The autotuner of the Python package picks them per batch shape
+ * (tc_count_batch) or per graph class (tc_count_tuned). */
 typedef struct tc_tuning {
+  /* tc_count_batch */
   int32_t batch_block;        /* threads per block of the counting kernel:
                                  256 (default) or 512 */
   int32_t batch_piece;        /* CSR entries per work piece (>= 1024,
                                  default 16384) */
   int32_t batch_blocks_per_cu;/* resident blocks per CU of the persistent
                                  counting kernel (0 = as many as LDS allows) */
-  int32_t reserved[5];
+  /* tc_count_tuned: which path a graph takes */
+  int32_t small_max_n;        /* a graph with 0 < n <= small_max_n and
+                                 nnz <= small_max_nnz is levelled and counted
+                                 by the batched kernels as a batch of one
+                                 (one workgroup, no host synchronisation);
+                                 default TC_SMALL_MAX_N, -1 = never; capped
+                                 at TC_BATCH_MAX_N */
+  int32_t small_max_nnz;      /* default TC_SMALL_MAX_NNZ */
+  int32_t reserved[3];
 } tc_tuning;
+
+#define TC_SMALL_MAX_N 65536
+#define TC_SMALL_MAX_NNZ 65536
 
 /* Bytes of workspace `op` needs for a graph with n vertices and nnz entries
  * (for TC_OP_BUILD_CSR, nnz = number of input pairs; for TC_OP_COUNT_BATCH,
@@ -176,10 +189,22 @@ int tc_cover_edges(const tc_csr* g, const int32_t* levels, int32_t* h_u, int32_t
  *   per_vertex   device int64 [n] (output iff flags & TC_PER_VERTEX): the
  *                number of triangles through each vertex (sums to 3T)
  * Synchronises `stream` during the BFS as tc_bfs_levels does; the rest
- * (relabelling, layout, count) is asynchronous. */
+ * (relabelling, layout, count) is asynchronous.  Graphs within the
+ * small-graph bounds (TC_SMALL_MAX_N vertices, TC_SMALL_MAX_NNZ entries)
+ * take the path of tc_count_tuned, which never synchronises. */
 int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles,
              int64_t* h_count, int32_t* levels, int64_t* per_vertex, void* ws,
              size_t ws_bytes, tc_stream_t stream);
+
+/* tc_count with tuning knobs (NULL = the defaults of tc_count).  A graph
+ * within the small-graph bounds of `tuning` is levelled in one workgroup's
+ * LDS and counted by the kernels of tc_count_batch, with no host
+ * synchronisation; T, |H| and the levels are the same on either path
+ * (TC_PER_VERTEX always takes the general path).  After the small-graph
+ * path tc_read_stats reports n, nnz and |H| only. */
+int tc_count_tuned(const tc_csr* g, int64_t root, uint32_t flags, const tc_tuning* tuning,
+                   int64_t* triangles, int64_t* h_count, int32_t* levels, int64_t* per_vertex,
+                   void* ws, size_t ws_bytes, tc_stream_t stream);
 
 /* Triangle finding (the paper counts and finds triangles; Alg. 1 visits each
  * triangle exactly once, at one horizontal edge and one apex): the same

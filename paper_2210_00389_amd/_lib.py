@@ -33,7 +33,7 @@ STATUS_NAMES = {
 
 EXPORTS = [
     "tc_workspace_bytes", "tc_build_csr", "tc_validate_csr", "tc_bfs_levels", "tc_cover_edges",
-    "tc_count", "tc_list_triangles", "tc_edge_support", "tc_select_root", "tc_count_edge_baseline",
+    "tc_count", "tc_count_tuned", "tc_list_triangles", "tc_edge_support", "tc_select_root", "tc_count_edge_baseline",
     "tc_count_batch",
     "tc_status_string", "tc_last_error",
     "tc_profile_enable", "tc_profile_read", "tc_read_stats",
@@ -54,7 +54,11 @@ class TcBatch(ctypes.Structure):
 
 class TcTuning(ctypes.Structure):
     _fields_ = [("batch_block", ctypes.c_int32), ("batch_piece", ctypes.c_int32),
-                ("batch_blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("batch_blocks_per_cu", ctypes.c_int32), ("small_max_n", ctypes.c_int32),
+                ("small_max_nnz", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+TUNING_FIELDS = ("batch_block", "batch_piece", "batch_blocks_per_cu", "small_max_n", "small_max_nnz")
 
 
 class TcProfile(ctypes.Structure):
@@ -98,6 +102,8 @@ def load(path: str | None = None):
     lib.tc_cover_edges.restype = c_int
     lib.tc_count.argtypes = [ctypes.POINTER(TcCsr), i64, u32, P, P, P, P, P, sz, P]
     lib.tc_count.restype = c_int
+    lib.tc_count_tuned.argtypes = [ctypes.POINTER(TcCsr), i64, u32, ctypes.POINTER(TcTuning), P, P, P, P, P, sz, P]
+    lib.tc_count_tuned.restype = c_int
     lib.tc_list_triangles.argtypes = [ctypes.POINTER(TcCsr), i64, u32, P, i64, P, P, P, P, sz, P]
     lib.tc_list_triangles.restype = c_int
     lib.tc_select_root.argtypes = [ctypes.POINTER(TcCsr), i32, u32, P, P, P, P, sz, P]

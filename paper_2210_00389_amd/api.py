@@ -201,8 +201,10 @@ class CountResult:
 @_on_stream
 def count(g: Graph, root: int = -1, per_vertex: bool = False, validate: bool = False,
           return_levels: bool = False, ws: Workspace | None = None, stream=None,
-          out: CountResult | None = None) -> CountResult:
-    """Cover-edge triangle count (tc_count); results stay on the device."""
+          out: CountResult | None = None, tuning: dict | None = None) -> CountResult:
+    """Cover-edge triangle count (tc_count_tuned; tuning=None gives
+    tc_count's defaults); results stay on the device."""
+    from .batch import make_tuning
     lib = L.load()
     dev = g.cols.device
     res = out or CountResult(torch.zeros(1, dtype=torch.int64, device=dev),
@@ -212,8 +214,10 @@ def count(g: Graph, root: int = -1, per_vertex: bool = False, validate: bool = F
     flags = (L.TC_VALIDATE if validate else 0) | (L.TC_PER_VERTEX if per_vertex else 0)
     buf = (ws or default_workspace(dev)).get(workspace_bytes(L.OP_COUNT, g.n, g.nnz))
     csr = g.csr()
-    _check(lib.tc_count(ctypes.byref(csr), root, flags, _ptr(res.triangles), _ptr(res.h_count),
-                        _ptr(res.levels), _ptr(res.per_vertex), _ptr(buf), buf.numel(), _stream(stream)),
+    tu = make_tuning(tuning)
+    _check(lib.tc_count_tuned(ctypes.byref(csr), root, flags, ctypes.byref(tu) if tu is not None else None,
+                              _ptr(res.triangles), _ptr(res.h_count), _ptr(res.levels), _ptr(res.per_vertex),
+                              _ptr(buf), buf.numel(), _stream(stream)),
            "tc_count")
     if res.levels is not None:
         res.levels = res.levels[: g.n]

@@ -96,10 +96,13 @@ class BatchResult:
 
 
 def make_tuning(t: dict | None) -> L.TcTuning | None:
+    """A tc_tuning from a dict of its fields (missing ones: 0 = default)."""
     if not t:
         return None
-    return L.TcTuning(int(t.get("batch_block", 0)), int(t.get("batch_piece", 0)),
-                      int(t.get("batch_blocks_per_cu", 0)), (ctypes.c_int32 * 5)())
+    unknown = set(t) - set(L.TUNING_FIELDS)
+    if unknown:
+        raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+    return L.TcTuning(*[int(t.get(f, 0)) for f in L.TUNING_FIELDS], (ctypes.c_int32 * 3)())
 
 
 @_on_stream

@@ -32,6 +32,7 @@ constexpr int kBfsThreads = 1024;
 constexpr uint16_t kUnvisited = 0xFFFF;
 constexpr int kBigDeg = 64;      // frontier vertices above this degree are expanded by a wave
 constexpr int kBigCap = 1024;    // LDS list of such vertices per pass (overflow: expanded by the thread)
+constexpr int kRowLoads = 8;     // row entries a thread loads at once in the level passes
 constexpr int kBitmapWords = TC_BATCH_MAX_N / 32;
 constexpr int kPieceMin = 1024;  // smallest piece size accepted (sizes the piece slots)
 constexpr int kClaim = 2;        // pieces a block claims at once
@@ -74,15 +75,26 @@ __device__ void bfs_levels_lds(uint16_t* L, const int64_t* rows, const int32_t* 
     __syncthreads();
     int found = 0;
     const uint16_t cur = static_cast<uint16_t>(level), nxt = static_cast<uint16_t>(level + 1);
+    // rows are read kRowLoads entries at a time (independent loads in
+    // flight together); a bottom-up scan stops after the group holding the
+    // first parent
     if (bottom_up) {
       for (int i = tid; i < n; i += nt) {
         if (L[i] != kUnvisited) continue;
-        for (int64_t k = rows[i]; k < rows[i + 1]; ++k)
-          if (L[cols[k]] == cur) {
+        const int64_t e = rows[i + 1];
+        for (int64_t k = rows[i]; k < e; k += kRowLoads) {
+          int32_t w[kRowLoads];
+#pragma unroll
+          for (int q = 0; q < kRowLoads; ++q) w[q] = k + q < e ? cols[k + q] : -1;
+          bool hit = false;
+#pragma unroll
+          for (int q = 0; q < kRowLoads; ++q) hit |= w[q] >= 0 && L[w[q]] == cur;
+          if (hit) {
             L[i] = nxt;
             ++found;
             break;
           }
+        }
       }
     } else {
       for (int i = tid; i < n; i += nt) {
@@ -95,12 +107,16 @@ __device__ void bfs_levels_lds(uint16_t* L, const int64_t* rows, const int32_t* 
             continue;
           }
         }
-        for (int64_t k = b; k < e; ++k) {
-          const int32_t w = cols[k];
-          if (L[w] == kUnvisited) {
-            L[w] = nxt;
-            ++found;
-          }
+        for (int64_t k = b; k < e; k += kRowLoads) {
+          int32_t w[kRowLoads];
+#pragma unroll
+          for (int q = 0; q < kRowLoads; ++q) w[q] = k + q < e ? cols[k + q] : -1;
+#pragma unroll
+          for (int q = 0; q < kRowLoads; ++q)
+            if (w[q] >= 0 && L[w[q]] == kUnvisited) {
+              L[w[q]] = nxt;
+              ++found;
+            }
         }
       }
       __syncthreads();
@@ -128,10 +144,12 @@ __device__ void bfs_levels_lds(uint16_t* L, const int64_t* rows, const int32_t* 
   }
 }
 
+// root0 >= 0 replaces the default root of graph 0 (the one-graph path of
+// tc_count); batches pass -1.
 __global__ __launch_bounds__(kBfsThreads) void batch_bfs_kernel(const int64_t* vbase, const int64_t* row_offsets,
                                                                 const int32_t* cols, int piece, int32_t* levels,
                                                                 uint32_t* parity, int4* pieces, int64_t* T,
-                                                                int64_t* H) {
+                                                                int64_t* H, int32_t root0) {
   __shared__ uint16_t L[TC_BATCH_MAX_N];
   __shared__ int32_t s_big[kBigCap];
   __shared__ int64_t sh[kBfsThreads / kWave + 1];
@@ -159,21 +177,27 @@ __global__ __launch_bounds__(kBfsThreads) void batch_bfs_kernel(const int64_t* v
     key = k > key ? k : key;
   }
   key = block_max_i64(key, sh);
-  const int root = static_cast<int>(0xFFFFFFFFu - static_cast<uint32_t>(key & 0xFFFFFFFF));
-  if (tid == 0) L[root] = 0;
+  const int root = (g == 0 && root0 >= 0 && root0 < n)
+                       ? root0
+                       : static_cast<int>(0xFFFFFFFFu - static_cast<uint32_t>(key & 0xFFFFFFFF));
+  __syncthreads();
+  if (tid == 0) L[root] = 0;  // a given root of degree 0 is level 0 already
   __syncthreads();
   bfs_levels_lds(L, rows, cols, n, &s_cnt, s_big, &s_nbig, 1);
-  // remaining components, each from its smallest unvisited id
+  // remaining components, each from its smallest unvisited id; every id
+  // below the last such root is visited, so each scan starts there
+  int from = 0;
   for (;;) {
     int64_t cand = -1;  // max of (n - i) over unvisited i = smallest i
-    for (int i = tid; i < n; i += nt)
+    for (int i = from + tid; i < n; i += nt)
       if (L[i] == kUnvisited) {
         cand = n - i;
         break;
       }
     cand = block_max_i64(cand, sh);
     if (cand < 0) break;
-    if (tid == 0) L[n - cand] = 0;
+    from = static_cast<int>(n - cand);
+    if (tid == 0) L[from] = 0;
     __syncthreads();
     bfs_levels_lds(L, rows, cols, n, &s_cnt, s_big, &s_nbig, 1);
   }
@@ -215,6 +239,78 @@ __device__ __forceinline__ uint64_t wave_or_u64(uint64_t x) {
   return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
+// One chunk of up to 64 neighbours v = N(u)[base + lane] of vertex u, in one
+// wave: the cover edges (u, v), v > u with u's parity, are compacted into
+// this wave's LDS lists (s_beg / s_v / s_off / s_len) and their lists N(v)
+// streamed in chunks of kBChunk entries per lane, each entry w counted when
+// its bit is set in the wave's bitmap of N(u) and it passes the test of
+// Alg. 1 (parity of w differs from u's, or w > v).  A short row (du <= 64)
+// passes its neighbours in registers (nbr, one per lane).
+__device__ __forceinline__ void count_chunk(int u, int64_t ru, int64_t du, int64_t base, bool shortrow, int32_t nbr,
+                                            uint32_t pu, const int64_t* rows, const int32_t* cols,
+                                            const uint32_t* s_par, const uint32_t* bm, int64_t* s_beg, int32_t* s_v,
+                                            int32_t* s_off, int32_t* s_len, int64_t& cnt, int64_t& hc) {
+  const int ln = lane();
+  const int64_t k = base + ln;
+  int32_t v = -1;
+  int len = 0;
+  int64_t vb = 0;
+  if (k < du) {
+    v = shortrow ? nbr : cols[ru + k];
+    if (v > u && par_bit(s_par, v) == pu) {
+      vb = rows[v];
+      len = static_cast<int>(rows[v + 1] - vb);
+      ++hc;
+    }
+  }
+  // N(v) of these edges in chunks of kBChunk consecutive entries; the
+  // non-empty streams are compacted in LDS with their first chunk
+  const int nch = (len + kBChunk - 1) / kBChunk;
+  const uint64_t ne = __ballot(nch > 0);
+  const int incl = wave_incl_scan(nch);
+  const int cst = incl - nch;
+  const int C = __shfl(incl, kWave - 1, kWave);
+  if (nch > 0) {
+    const int r = __popcll(ne & lanemask_lt());
+    s_beg[r] = vb;
+    s_v[r] = v;
+    s_off[r] = cst;
+    s_len[r] = len;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  for (int t0 = 0; t0 < C; t0 += kWave) {
+    // streams whose first chunk lies in [t0, t0 + 64): a 64-bit mask of
+    // those first chunks, and the number of streams begun before t0; lane
+    // i's chunk t0 + i then belongs to stream before + |{starts <= i}| - 1
+    const bool starts_here = nch > 0 && cst >= t0 && cst < t0 + kWave;
+    const uint64_t M = wave_or_u64(starts_here ? (1ull << (cst - t0)) : 0ull);
+    const int before = __popcll(__ballot(nch > 0 && cst < t0));
+    const int c = t0 + ln;
+    if (c < C) {
+      const int j = before + __popcll(M & ((2ull << ln) - 1ull)) - 1;
+      const int kk = c - s_off[j];
+      const int64_t p0 = s_beg[j] + static_cast<int64_t>(kk) * kBChunk;
+      const int rem = s_len[j] - kk * kBChunk;
+      const int32_t vv = s_v[j];
+      int32_t w[kBChunk];
+#pragma unroll
+      for (int q = 0; q < kBChunk; ++q) w[q] = q < rem ? cols[p0 + q] : -1;
+#pragma unroll
+      for (int q = 0; q < kBChunk; ++q)
+        if (w[q] >= 0 && ((bm[w[q] >> 5] >> (w[q] & 31)) & 1u) && (par_bit(s_par, w[q]) != pu || w[q] > vv))
+          ++cnt;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Vertices of more than kLongDeg neighbours are left to a phase at the end
+// of the piece in which every wave of the block takes a share of their
+// 64-neighbour chunks (each wave with its own bitmap of N(u)), so one hub
+// does not keep a single wave busy while the others wait.
+constexpr int kLongDeg = 4 * kWave;
+constexpr int kLongCap = 64;  // deferred vertices per piece (more: counted by the claiming wave)
+
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vbase, const int64_t* row_offsets,
                                                               const int32_t* cols, const uint32_t* parity,
@@ -227,8 +323,9 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
   __shared__ int64_t s_beg[NW][kWave];
   __shared__ int32_t s_v[NW][kWave];
   __shared__ int64_t sh[NW + 1];
+  __shared__ int32_t s_long[kLongCap];
   __shared__ unsigned long long s_claim;
-  __shared__ int s_next;
+  __shared__ int s_next, s_nlong;
   const int tid = threadIdx.x, wv = tid / kWave, ln = lane();
   uint32_t* bm = s_bm[wv];
   for (int i = ln; i < kBitmapWords; i += kWave) bm[i] = 0u;
@@ -244,13 +341,14 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
       if (pc.x < 0 || pc.y >= pc.z) continue;  // empty slot (block-uniform)
       const int g = pc.x;
       const int64_t v0 = vbase[g];
-      const int n = static_cast<int>(vbase[g + 1] - v0);
       const int64_t* rows = row_offsets + v0;
       // the graph's parity bits stay in global memory (at most 8 KB, cached):
       // keeping them out of LDS leaves room for more blocks per CU
       const uint32_t* s_par = parity + parity_base(v0, g);
-      (void)n;
-      if (tid == 0) s_next = pc.y;
+      if (tid == 0) {
+        s_next = pc.y;
+        s_nlong = 0;
+      }
       __syncthreads();
       int64_t cnt = 0, hc = 0;
       // one vertex ahead: the next vertex's row bounds, and for a row of at
@@ -275,78 +373,39 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
           run = rows[un];
           dun = rows[un + 1] - run;
         }
-        const uint32_t pu = par_bit(s_par, u);
-        const bool shortrow = du <= kWave;
-        if (shortrow) {
-          if (nbr >= 0) atomicOr(&bm[nbr >> 5], 1u << (nbr & 31));
-        } else {
-          for (int64_t k = ln; k < du; k += kWave) {
-            const int32_t w = cols[ru + k];
-            atomicOr(&bm[w >> 5], 1u << (w & 31));
-          }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        for (int64_t base = 0; base < du; base += kWave) {
-          // cover edges (u, v), v > u, in this chunk of N(u)
-          const int64_t k = base + ln;
-          int32_t v = -1;
-          int len = 0;
-          int64_t vb = 0;
-          if (k < du) {
-            v = shortrow ? nbr : cols[ru + k];
-            if (v > u && par_bit(s_par, v) == pu) {
-              vb = rows[v];
-              len = static_cast<int>(rows[v + 1] - vb);
-              ++hc;
+        int deferred = 0;
+        if (du > kLongDeg) {
+          if (ln == 0) {
+            const int q = atomicAdd(&s_nlong, 1);
+            if (q < kLongCap) {
+              s_long[q] = u;
+              deferred = 1;
             }
           }
-          // N(v) of these edges in chunks of kBChunk consecutive entries;
-          // the non-empty streams are compacted in LDS with their first chunk
-          const int nch = (len + kBChunk - 1) / kBChunk;
-          const uint64_t ne = __ballot(nch > 0);
-          const int incl = wave_incl_scan(nch);
-          const int cst = incl - nch;
-          const int C = __shfl(incl, kWave - 1, kWave);
-          if (nch > 0) {
-            const int r = __popcll(ne & lanemask_lt());
-            s_beg[wv][r] = vb;
-            s_v[wv][r] = v;
-            s_off[wv][r] = cst;
-            s_len[wv][r] = len;
-          }
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          for (int t0 = 0; t0 < C; t0 += kWave) {
-            // streams whose first chunk lies in [t0, t0 + 64): a 64-bit mask of
-            // those first chunks, and the number of streams begun before t0;
-            // lane i's chunk t0 + i then belongs to stream
-            // before + |{starts <= i}| - 1
-            const bool starts_here = nch > 0 && cst >= t0 && cst < t0 + kWave;
-            const uint64_t M = wave_or_u64(starts_here ? (1ull << (cst - t0)) : 0ull);
-            const int before = __popcll(__ballot(nch > 0 && cst < t0));
-            const int c = t0 + ln;
-            if (c < C) {
-              const int j = before + __popcll(M & ((2ull << ln) - 1ull)) - 1;
-              const int kk = c - s_off[wv][j];
-              const int64_t p0 = s_beg[wv][j] + static_cast<int64_t>(kk) * kBChunk;
-              const int rem = s_len[wv][j] - kk * kBChunk;
-              const int32_t vv = s_v[wv][j];
-              int32_t w[kBChunk];
-#pragma unroll
-              for (int q = 0; q < kBChunk; ++q) w[q] = q < rem ? cols[p0 + q] : -1;
-#pragma unroll
-              for (int q = 0; q < kBChunk; ++q)
-                if (w[q] >= 0 && ((bm[w[q] >> 5] >> (w[q] & 31)) & 1u) && (par_bit(s_par, w[q]) != pu || w[q] > vv))
-                  ++cnt;
+          deferred = __shfl(deferred, 0, kWave);
+        }
+        if (!deferred) {
+          const uint32_t pu = par_bit(s_par, u);
+          const bool shortrow = du <= kWave;
+          if (shortrow) {
+            if (nbr >= 0) atomicOr(&bm[nbr >> 5], 1u << (nbr & 31));
+          } else {
+            for (int64_t k = ln; k < du; k += kWave) {
+              const int32_t w = cols[ru + k];
+              atomicOr(&bm[w >> 5], 1u << (w & 31));
             }
           }
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          for (int64_t base = 0; base < du; base += kWave)
+            count_chunk(u, ru, du, base, shortrow, nbr, pu, rows, cols, s_par, bm, s_beg[wv], s_v[wv], s_off[wv],
+                        s_len[wv], cnt, hc);
+          if (shortrow) {
+            if (nbr >= 0) bm[nbr >> 5] = 0u;
+          } else {
+            for (int64_t k = ln; k < du; k += kWave) bm[cols[ru + k] >> 5] = 0u;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
-        if (shortrow) {
-          if (nbr >= 0) bm[nbr >> 5] = 0u;
-        } else {
-          for (int64_t k = ln; k < du; k += kWave) bm[cols[ru + k] >> 5] = 0u;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         // the next vertex's neighbours (short rows) for the next round
         int32_t nbn = -1;
         if (un < pc.z && dun <= kWave && ln < dun) nbn = cols[run + ln];
@@ -354,6 +413,25 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
         ru = run;
         du = dun;
         nbr = nbn;
+      }
+      // the deferred long rows: every wave sets N(u) in its own bitmap and
+      // takes the chunks wv, wv + NW, ... of N(u)
+      __syncthreads();
+      const int nlong = min(s_nlong, kLongCap);
+      for (int j = 0; j < nlong; ++j) {
+        const int lu = s_long[j];
+        const int64_t lr = rows[lu], ld = rows[lu + 1] - lr;
+        const uint32_t pu = par_bit(s_par, lu);
+        for (int64_t k = ln; k < ld; k += kWave) {
+          const int32_t w = cols[lr + k];
+          atomicOr(&bm[w >> 5], 1u << (w & 31));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int64_t base = static_cast<int64_t>(wv) * kWave; base < ld; base += static_cast<int64_t>(NW) * kWave)
+          count_chunk(lu, lr, ld, base, false, -1, pu, rows, cols, s_par, bm, s_beg[wv], s_v[wv], s_off[wv],
+                      s_len[wv], cnt, hc);
+        for (int64_t k = ln; k < ld; k += kWave) bm[cols[lr + k] >> 5] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       }
       cnt = block_sum(cnt, sh);
       hc = block_sum(hc, sh);
@@ -396,7 +474,10 @@ BatchPlan plan_batch(void* base, int64_t total_n, int64_t total_nnz, int32_t G) 
 template <int THREADS>
 int launch_count(const tc_batch* b, const BatchPlan& p, int64_t nslots, int blocks_per_cu, int64_t* T, int64_t* H,
                  hipStream_t s) {
-  batch_count_kernel<THREADS><<<static_cast<unsigned>(num_cus() * blocks_per_cu), THREADS, 0, s>>>(
+  // persistent blocks; no more than there are piece slots to claim
+  const int64_t full = static_cast<int64_t>(num_cus()) * blocks_per_cu;
+  const int64_t blocks = (nslots + kClaim - 1) / kClaim < full ? (nslots + kClaim - 1) / kClaim : full;
+  batch_count_kernel<THREADS><<<static_cast<unsigned>(blocks), THREADS, 0, s>>>(
       b->vbase, b->row_offsets, b->cols, p.parity, p.pieces, nslots, p.ctr, T, H);
   TC_HIP(hipGetLastError());
   return TC_OK;
@@ -409,7 +490,7 @@ size_t batch_ws_bytes(int64_t total_n, int64_t total_nnz, int32_t num_graphs) {
 }
 
 int batch_run(const tc_batch* b, const tc_tuning* t, uint32_t flags, int64_t* triangles, int64_t* h_count,
-              int32_t* levels, void* ws, size_t ws_bytes, hipStream_t s) {
+              int32_t* levels, void* ws, size_t ws_bytes, hipStream_t s, int32_t root0) {
   const int G = b->num_graphs;
   if (G == 0) return TC_OK;
   if (flags & TC_VALIDATE) TC_TRY(validate_batch_run(b, ws, s));
@@ -433,11 +514,79 @@ int batch_run(const tc_batch* b, const tc_tuning* t, uint32_t flags, int64_t* tr
   empty_pieces_kernel<<<grid_for(nslots, 256, 8192), 256, 0, s>>>(p.pieces, nslots);
   TC_HIP(hipGetLastError());
   batch_bfs_kernel<<<static_cast<unsigned>(G), kBfsThreads, 0, s>>>(b->vbase, b->row_offsets, b->cols, piece, levels,
-                                                                    p.parity, p.pieces, triangles, h_count);
+                                                                    p.parity, p.pieces, triangles, h_count, root0);
   TC_HIP(hipGetLastError());
   prof_stage("batch_count");
   if (threads == 256) TC_TRY(launch_count<256>(b, p, nslots, bpc, triangles, h_count, s));
   else TC_TRY(launch_count<512>(b, p, nslots, bpc, triangles, h_count, s));
+  return TC_OK;
+}
+
+namespace {
+
+__global__ void small_setup_kernel(int64_t* vbase, int64_t n) {
+  vbase[0] = 0;
+  vbase[1] = n;
+}
+
+__global__ void small_stats_kernel(int64_t* stats, int64_t n, int64_t nnz, const int64_t* H) {
+  for (int i = 0; i < 24; ++i) stats[i] = 0;
+  stats[0] = n;
+  stats[1] = nnz;
+  stats[2] = *H;
+}
+
+struct SmallPlan {
+  int64_t* stats;  // the tc_stats mirror, first in the workspace like the count plan's
+  int64_t* vbase;  // {0, n}
+  int64_t* h;      // |H| when the caller passes no h_count
+  char* batch;
+  size_t bytes;
+};
+
+SmallPlan plan_small(void* base, int64_t n, int64_t nnz) {
+  SmallPlan p;
+  Carver c(base);
+  p.stats = c.take<int64_t>(24);
+  p.vbase = c.take<int64_t>(2);
+  p.h = c.take<int64_t>(1);
+  p.batch = c.take<char>(0);
+  p.bytes = c.used() + batch_ws_bytes(n, nnz, 1);
+  return p;
+}
+
+}  // namespace
+
+size_t small_ws_bytes(int64_t n, int64_t nnz) { return plan_small(nullptr, n, nnz).bytes; }
+
+bool small_path_fits(int64_t n, int64_t nnz, int64_t max_n, int64_t max_nnz) {
+  return n > 0 && n <= TC_BATCH_MAX_N && n <= max_n && nnz <= max_nnz;
+}
+
+int small_count_run(const tc_csr* g, int64_t root, int64_t* triangles, int64_t* h_count, int32_t* levels, void* ws,
+                    size_t ws_bytes, hipStream_t s) {
+  SmallPlan p = plan_small(ws, g->n, g->nnz);
+  if (ws_bytes < p.bytes) return fail(TC_ERR_WORKSPACE, "tc_count: workspace %zu < %zu", ws_bytes, p.bytes);
+  int64_t* H = h_count ? h_count : p.h;
+  prof_stage("small_count");
+  small_setup_kernel<<<1, 1, 0, s>>>(p.vbase, g->n);
+  TC_HIP(hipGetLastError());
+  tc_batch b;
+  b.num_graphs = 1;
+  b.total_vertices = g->n;
+  b.total_nnz = g->nnz;
+  b.vbase = p.vbase;
+  b.row_offsets = g->row_offsets;
+  b.cols = g->cols;
+  b.max_graph_vertices = static_cast<int32_t>(g->n);
+  // pieces of about a quarter of a block's share, so the CUs all get work
+  tc_tuning t{};
+  const int64_t share = g->nnz / (4 * static_cast<int64_t>(num_cus()));
+  t.batch_piece = static_cast<int32_t>(share < kPieceMin ? kPieceMin : (share > 16384 ? 16384 : share));
+  TC_TRY(batch_run(&b, &t, 0, triangles, H, levels, p.batch, p.bytes - (p.batch - static_cast<char*>(ws)), s,
+                   static_cast<int32_t>(root)));
+  small_stats_kernel<<<1, 1, 0, s>>>(p.stats, g->n, g->nnz, H);
+  TC_HIP(hipGetLastError());
   return TC_OK;
 }
 

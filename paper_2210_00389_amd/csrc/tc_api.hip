@@ -139,7 +139,11 @@ size_t tc_workspace_bytes(int op, int64_t n, int64_t nnz, int32_t num_graphs) {
     case TC_OP_BUILD_CSR: b = build_ws_bytes(n, nnz); break;
     case TC_OP_BFS_LEVELS: b = bfs_bytes(n); break;
     case TC_OP_COVER_EDGES: b = plan_cover(nullptr, n, nnz).bytes; break;
-    case TC_OP_COUNT: b = plan_count(nullptr, n, nnz).bytes; break;
+    case TC_OP_COUNT: {
+      const size_t a = plan_count(nullptr, n, nnz).bytes, sm = small_ws_bytes(n, nnz);
+      b = a > sm ? a : sm;
+      break;
+    }
     case TC_OP_COUNT_BATCH: b = batch_ws_bytes(n, nnz, num_graphs); break;
     case TC_OP_EDGE_BASELINE: b = plan_baseline(nullptr, n, nnz).bytes; break;
     case TC_OP_VALIDATE: b = validate_ws_bytes(n, nnz); break;
@@ -242,18 +246,33 @@ int cover_call(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles
 
 }  // namespace
 
-int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles, int64_t* h_count, int32_t* levels,
-             int64_t* per_vertex, void* ws, size_t ws_bytes, tc_stream_t stream) {
+int tc_count_tuned(const tc_csr* g, int64_t root, uint32_t flags, const tc_tuning* tuning, int64_t* triangles,
+                   int64_t* h_count, int32_t* levels, int64_t* per_vertex, void* ws, size_t ws_bytes,
+                   tc_stream_t stream) {
   TC_TRY(check_csr(g, "tc_count"));
   if (!triangles) return fail(TC_ERR_INVALID_ARG, "tc_count: triangles is NULL");
   if (root >= g->n || root < -1) return fail(TC_ERR_INVALID_ARG, "tc_count: root %lld out of range", (long long)root);
   const bool pv = flags & TC_PER_VERTEX;
   if (pv && g->n > 0 && !per_vertex) return fail(TC_ERR_INVALID_ARG, "tc_count: per_vertex is NULL");
-  const size_t need = plan_count(nullptr, g->n, g->nnz).bytes;
+  const size_t need = tc_workspace_bytes(TC_OP_COUNT, g->n, g->nnz, 0);
   TC_TRY(check_ws(ws, ws_bytes, need, "tc_count"));
+  int64_t small_n = TC_SMALL_MAX_N, small_nnz = TC_SMALL_MAX_NNZ;
+  if (tuning) {
+    if (tuning->small_max_n) small_n = tuning->small_max_n;
+    if (tuning->small_max_nnz) small_nnz = tuning->small_max_nnz;
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   CallScope scope(s);
+  if (!pv && small_path_fits(g->n, g->nnz, small_n, small_nnz)) {
+    TC_TRY(maybe_validate(g, flags, ws, s));
+    return small_count_run(g, root, triangles, h_count, levels, ws, ws_bytes, s);
+  }
   return cover_call(g, root, flags, triangles, h_count, levels, per_vertex, false, nullptr, 0, ws, s);
+}
+
+int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles, int64_t* h_count, int32_t* levels,
+             int64_t* per_vertex, void* ws, size_t ws_bytes, tc_stream_t stream) {
+  return tc_count_tuned(g, root, flags, nullptr, triangles, h_count, levels, per_vertex, ws, ws_bytes, stream);
 }
 
 int tc_list_triangles(const tc_csr* g, int64_t root, uint32_t flags, int32_t* tri, int64_t cap, int64_t* triangles,

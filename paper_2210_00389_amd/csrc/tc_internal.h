@@ -176,7 +176,17 @@ int validate_batch_run(const tc_batch* b, void* ws, hipStream_t s);
 
 // ------------------------------------------------------------ batch
 size_t batch_ws_bytes(int64_t total_n, int64_t total_nnz, int32_t num_graphs);
+// root0 >= 0 replaces the default root of graph 0 (batches pass -1).
 int batch_run(const tc_batch* b, const tc_tuning* t, uint32_t flags, int64_t* triangles,
-              int64_t* h_count, int32_t* levels, void* ws, size_t ws_bytes, hipStream_t s);
+              int64_t* h_count, int32_t* levels, void* ws, size_t ws_bytes, hipStream_t s,
+              int32_t root0 = -1);
+
+// One graph of at most TC_BATCH_MAX_N vertices counted by the batched
+// kernels (one workgroup levels it in LDS, no host synchronisation): T,
+// |H| and the levels of tc_count; stats carries n, nnz and |H| only.
+size_t small_ws_bytes(int64_t n, int64_t nnz);
+bool small_path_fits(int64_t n, int64_t nnz, int64_t max_n, int64_t max_nnz);
+int small_count_run(const tc_csr* g, int64_t root, int64_t* triangles, int64_t* h_count, int32_t* levels,
+                    void* ws, size_t ws_bytes, hipStream_t s);
 
 }  // namespace tc

@@ -34,6 +34,10 @@ def tc():
     return tc
 
 
+SMALL_ON = dict(small_max_n=65536, small_max_nnz=2**31 - 1)
+SMALL_OFF = dict(small_max_n=-1)
+
+
 def to_gpu(tc, g):
     return tc.from_host_pairs(g.n, g.src, g.dst, device="cuda")
 
@@ -61,6 +65,12 @@ def check_graph(tc, g, name="", root=-1, baseline=True, per_vertex=True):
     assert np.array_equal(res.levels.cpu().numpy(), lv.levels)
     if per_vertex:
         assert np.array_equal(res.per_vertex.cpu().numpy(), want.per_vertex)
+    # both paths of tc_count on every graph: the one-workgroup path forced on
+    # (every graph within TC_BATCH_MAX_N vertices takes it) and forced off
+    for tun in (SMALL_ON, SMALL_OFF):
+        r2 = tc.count(G, root=root, return_levels=True, tuning=tun)
+        assert (r2.T, r2.h) == (want.triangles, len(hu)), (name, tun)
+        assert np.array_equal(r2.levels.cpu().numpy(), lv.levels), (name, tun)
     if baseline:
         assert int(tc.count_edge_baseline(G).item()) == want.triangles
     return c, G, want.triangles
@@ -253,3 +263,19 @@ def test_bfs_isolated_vertices_beside_one_component(tc):
     check_graph(tc, g, "K12 + 6 isolated, isolated root", root=int(np.flatnonzero(deg == 0)[0]))
     g2 = graphgen.disjoint_union([graphgen.complete(12), graphgen.complete(7)] + [graphgen.path(1)] * 4)
     check_graph(tc, g2, "K12 + K7 + 4 isolated")
+
+
+def test_small_path_stats_and_workspace(tc):
+    """After the one-workgroup path the work statistics carry n, nnz and |H|
+    (the rest zero); the call runs in a workspace of tc_workspace_bytes."""
+    from paper_2210_00389_amd import _lib
+    g = graphgen.rmat(10, 16, seed=1)
+    G = to_gpu(tc, g)
+    ws = tc.Workspace()
+    r = tc.count(G, ws=ws, tuning=SMALL_ON)
+    st = tc.read_stats(ws)
+    assert (st["n"], st["nnz"], st["h"]) == (G.n, G.nnz, r.h)
+    assert st["heavy_items"] == 0 and st["descriptors"] == 0
+    assert ws.buf.numel() == tc.workspace_bytes(_lib.OP_COUNT, G.n, G.nnz)
+    r_off = tc.count(G, tuning=SMALL_OFF)
+    assert (r.T, r.h) == (r_off.T, r_off.h)

@@ -145,3 +145,83 @@ def test_server_carries_levels_digest():
     reqs = make_requests(sizes, lambda n, nnz: 1000, rate=2000.0, count=30, seed=3)
     Server(DigestExecutor(), slots=2, budget_bytes=40000).run(reqs)
     assert all(r.levels_hash == f"g{r.graph_id}" for r in reqs)
+
+
+class BatchingExecutor(FakeExecutor):
+    """FakeExecutor with run_batch; records the size of every batched job."""
+
+    def __init__(self):
+        super().__init__()
+        self.jobs = []
+
+    def run_batch(self, slot, reqs):
+        self.jobs.append(len(reqs))
+        time.sleep(0.002)
+        return [(r.graph_id * 7 + 1, r.graph_id + 3) for r in reqs]
+
+
+def test_scheduler_coalesces_small_requests():
+    """A slot that starts a small request takes the other waiting small
+    requests that fit; large requests keep a slot each; the slot is free
+    again only when every request of its job is complete."""
+    small = lambda r: r.n <= 100  # noqa: E731
+    s = Scheduler(slots=2, budget_bytes=10_000, small=small, batch_max=3)
+    big = Request(0, 0, 0.0, n=1000, nnz=10, graph_bytes=100, ws_bytes=10)
+    s.submit(big)
+    for i in range(1, 6):
+        s.submit(Request(i, i, 0.0, n=50, nnz=10, graph_bytes=100, ws_bytes=10))
+    started, _ = s.admit(0.0)
+    jobs = {}
+    for r in started:
+        jobs.setdefault(r.job, []).append(r.rid)
+    assert sorted(jobs.values()) == [[0], [1, 2, 3]]  # batch_max 3; two slots
+    assert [r.batched for r in started] == [False, True, True, True]
+    assert len(s.waiting) == 2 and not s.free_slots
+    for r in [x for x in started if x.rid in (1, 2)]:
+        s.complete(r, 1.0)
+    assert not s.free_slots  # request 3 still holds the batch's slot
+    s.complete(next(x for x in started if x.rid == 3), 1.0)
+    (r4, r5), _ = s.admit(1.0)
+    assert r4.job == r5.job and r4.batched and r5.batched
+
+
+def test_server_batches_and_answers_every_request():
+    sizes = {g: ((50 if g % 2 else 5000), 400, 5000) for g in range(12)}
+    reqs = make_requests(sizes, lambda n, nnz: 1000, rate=5000.0, count=150, seed=8)
+    ex = BatchingExecutor()
+    st = Server(ex, slots=3, budget_bytes=200_000, small=lambda r: r.n <= 100, batch_max=16).run(reqs)
+    assert st["failed"] == 0 and st["requests"] == 150
+    assert all(r.triangles == r.graph_id * 7 + 1 and r.h == r.graph_id + 3 for r in reqs)
+    assert st["batched"] == sum(r.n <= 100 for r in reqs) and max(ex.jobs) > 1
+    assert all(r.batched == (r.n <= 100) for r in reqs)
+
+
+class FailingExecutor(BatchingExecutor):
+    """Raises on one graph (alone) and on every batch holding another."""
+
+    def run(self, slot, r, upload):
+        if r.graph_id == 4:
+            raise RuntimeError("device error on graph 4")
+        return super().run(slot, r, upload)
+
+    def run_batch(self, slot, reqs):
+        if any(r.graph_id == 5 for r in reqs):
+            raise RuntimeError("device error in a batch with graph 5")
+        return super().run_batch(slot, reqs)
+
+
+def test_server_isolates_failed_requests():
+    """A failing request is answered with its error, the others complete,
+    and every slot and reserved byte is released; the run does not raise."""
+    sizes = {g: ((50 if g % 2 else 5000), 400, 5000) for g in range(10)}
+    reqs = make_requests(sizes, lambda n, nnz: 1000, rate=3000.0, count=100, seed=4)
+    srv = Server(FailingExecutor(), slots=2, budget_bytes=100_000, small=lambda r: r.n <= 100, batch_max=8)
+    st = srv.run(reqs)
+    failed = [r for r in reqs if r.error]
+    assert st["failed"] == len(failed) > 0 and st["requests"] == 100
+    assert all(r.graph_id == 4 or any(q.graph_id == 5 and q.job == r.job for q in reqs) for r in failed)
+    assert all("device error" in r.error and r.triangles == -1 for r in failed)
+    assert all(r.triangles == r.graph_id * 7 + 1 for r in reqs if not r.error)
+    assert sorted(srv.sched.free_slots) == [0, 1] and srv.sched.reserved == 0 and not srv.sched.running
+    assert all(e["pins"] == 0 for e in srv.sched.cache.entries.values())
+    assert st["p99_ms"] >= st["p50_ms"] > 0
