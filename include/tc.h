@@ -286,6 +286,25 @@ int tc_count_batch(const tc_batch* b, const tc_tuning* tuning, uint32_t flags,
                    int64_t* triangles, int64_t* h_count, int32_t* levels, void* ws,
                    size_t ws_bytes, tc_stream_t stream);
 
+/* tc_count_batch for callers that cannot allocate device memory: code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * results are those of tc_count_batch (same kernels); the scratch that
+ * tc_count_batch takes from `ws` lives instead in a static device array of
+ * tc_noalloc_scratch_bytes() bytes (32 MiB) that each GPU holds until the
+ * process ends.  The call allocates and frees nothing.
+ *   - A batch needing more scratch than that (tc_workspace_bytes(
+ *     TC_OP_COUNT_BATCH, ...) above the array's size) gives TC_ERR_TOO_LARGE
+ *     before any device work; about 1.3 G entries in total fit.
+ *   - TC_VALIDATE is not supported (TC_ERR_INVALID_ARG): check a batch with
+ *     tc_count_batch first.
+ *   - Every call on one GPU shares that GPU's array: calls that overlap on
+ *     one GPU (other streams, other threads) race and give unspecified
+ *     results; serialise them.  No stream synchronisation is issued. */
+int tc_count_batch_noalloc(const tc_batch* b, const tc_tuning* tuning, uint32_t flags,
+                           int64_t* triangles, int64_t* h_count, int32_t* levels,
+                           tc_stream_t stream);
+size_t tc_noalloc_scratch_bytes(void);
+
 /* Text of a status code (static storage). */
 const char* tc_status_string(int status);
 

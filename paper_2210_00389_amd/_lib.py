@@ -34,7 +34,7 @@ STATUS_NAMES = {
 EXPORTS = [
     "tc_workspace_bytes", "tc_build_csr", "tc_validate_csr", "tc_bfs_levels", "tc_cover_edges",
     "tc_count", "tc_count_tuned", "tc_list_triangles", "tc_edge_support", "tc_select_root", "tc_count_edge_baseline",
-    "tc_count_batch",
+    "tc_count_batch", "tc_count_batch_noalloc", "tc_noalloc_scratch_bytes",
     "tc_status_string", "tc_last_error",
     "tc_profile_enable", "tc_profile_read", "tc_read_stats",
 ]
@@ -114,6 +114,10 @@ def load(path: str | None = None):
     lib.tc_count_edge_baseline.restype = c_int
     lib.tc_count_batch.argtypes = [ctypes.POINTER(TcBatch), ctypes.POINTER(TcTuning), u32, P, P, P, P, sz, P]
     lib.tc_count_batch.restype = c_int
+    lib.tc_count_batch_noalloc.argtypes = [ctypes.POINTER(TcBatch), ctypes.POINTER(TcTuning), u32, P, P, P, P]
+    lib.tc_count_batch_noalloc.restype = c_int
+    lib.tc_noalloc_scratch_bytes.argtypes = []
+    lib.tc_noalloc_scratch_bytes.restype = sz
     lib.tc_status_string.argtypes = [c_int]
     lib.tc_status_string.restype = ctypes.c_char_p
     lib.tc_last_error.argtypes = []

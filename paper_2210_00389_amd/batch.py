@@ -109,11 +109,13 @@ def make_tuning(t: dict | None) -> L.TcTuning | None:
 def count_batch(b: Batch, tuning: dict | None = None, return_levels: bool = False,
                 ws: Workspace | None = None, stream=None, out: BatchResult | None = None,
                 with_h: bool = True, validate: bool = False,
-                max_graph_vertices: int | None = None) -> BatchResult:
+                max_graph_vertices: int | None = None, noalloc: bool = False) -> BatchResult:
     """tc_count_batch: exact T and (with_h) |H| of every graph (device
     tensors).  validate=True checks the batch's structure first (the call
     then synchronises).  max_graph_vertices overrides the bound the batch
-    declares (tests of the library's own checks)."""
+    declares (tests of the library's own checks).  noalloc=True calls
+    tc_count_batch_noalloc (scratch in the library's static device array, no
+    workspace; outputs are still allocated here unless `out` is given)."""
     lib = L.load()
     dev = b.cols.device
     G = b.num_graphs
@@ -121,9 +123,14 @@ def count_batch(b: Batch, tuning: dict | None = None, return_levels: bool = Fals
                              torch.empty(max(G, 1), dtype=torch.int64, device=dev) if with_h else None,
                              torch.empty(max(b.total_vertices, 1), dtype=torch.int32, device=dev)
                              if return_levels else None)
-    buf = (ws or default_workspace(dev)).get(workspace_bytes(L.OP_COUNT_BATCH, b.total_vertices, b.total_nnz, G))
     tb = b.tc(max_graph_vertices)
     tu = make_tuning(tuning)
+    if noalloc:
+        _check(lib.tc_count_batch_noalloc(ctypes.byref(tb), ctypes.byref(tu) if tu is not None else None,
+                                          L.TC_VALIDATE if validate else 0, _ptr(res.triangles), _ptr(res.h_count),
+                                          _ptr(res.levels), _stream(stream)), "tc_count_batch_noalloc")
+        return res
+    buf = (ws or default_workspace(dev)).get(workspace_bytes(L.OP_COUNT_BATCH, b.total_vertices, b.total_nnz, G))
     _check(lib.tc_count_batch(ctypes.byref(tb), ctypes.byref(tu) if tu is not None else None,
                               L.TC_VALIDATE if validate else 0,
                               _ptr(res.triangles), _ptr(res.h_count), _ptr(res.levels), _ptr(buf), buf.numel(),
