@@ -470,9 +470,14 @@ def bench_pmc(args):
     G = tc.from_host_pairs(g.n, g.src, g.dst)
     ws = tc.Workspace(torch.device("cuda"))
     for i in range(args.warmup + args.steps):
-        r = tc.count(G, ws=ws)
+        if args.pmc_comparator:
+            # the comparator with its table bins one after another, so that a
+            # trace gives every bin's own duration
+            T = int(tc.count_edge_baseline(G, ws=ws, tuning={"bins_mode": 1}).item())
+        else:
+            T = tc.count(G, ws=ws).T
         torch.cuda.synchronize()
-        log(f"[pmc] count {i}: T={r.T}")
+        log(f"[pmc] count {i}: T={T}")
     x = torch.empty(256 * 2**20, dtype=torch.int32, device="cuda").fill_(1)
     y = torch.empty_like(x)
     torch.cuda.synchronize()
@@ -712,8 +717,24 @@ def rmat_line(args, scale, steps, warmup, comparator=True, stream=True, root_can
     res = tc.CountResult(torch.zeros(1, dtype=torch.int64, device=dev), torch.zeros(1, dtype=torch.int64, device=dev),
                          None, None)
     tb = torch.zeros(1, dtype=torch.int64, device=dev)
-    step = lambda: tc.count(G, ws=ws, out=res)  # noqa: E731
-    base = lambda: tc.count_edge_baseline(G, ws=ws, out=tb)  # noqa: E731
+    tun_c = tun_b = None
+    tune_info = None
+    if args.autotune:
+        # both paths tuned by the library's autotuner before timing (outside
+        # the timed region); the comparator over a shorter search when its
+        # calls are long
+        from paper_2210_00389_amd import tune
+        t0 = time.perf_counter()
+        tun_c = tc.autotune_count(G, "cover", reps=3, ws=ws, use_cache=False)
+        t1 = time.perf_counter()
+        tun_b = (tc.autotune_count(G, "edge", reps=2 if nnz > 2**26 else 3, ws=ws, use_cache=False,
+                                   space=tune.EDGE_SPACE_SHORT if nnz > 2**26 else None) if comparator else None)
+        t2 = time.perf_counter()
+        tune_info = {"cover": tun_c, "comparator": tun_b, "cover_search_s": round(t1 - t0, 1),
+                     "comparator_search_s": round(t2 - t1, 1)}
+        log(f"[bench] autotuned: cover {tun_c} comparator {tun_b}")
+    step = lambda: tc.count(G, ws=ws, out=res, tuning=tun_c)  # noqa: E731
+    base = lambda: tc.count_edge_baseline(G, ws=ws, out=tb, tuning=tun_b)  # noqa: E731
 
     tc.profile_enable(True)
     for _ in range(warmup):
@@ -831,6 +852,7 @@ def rmat_line(args, scale, steps, warmup, comparator=True, stream=True, root_can
         "golden": golden,
         "comm_model": comm,
         "root_choice": root_choice,
+        "tuning": tune_info,
     }
 
 
@@ -886,7 +908,7 @@ def bench_rmat(args, kids):
                          stream=False)
         out[f"rmat{args.nested_scale}"] = {k: nest[k] for k in (
             "value", "unit", "ms_per_step", "p50_ms", "p99_ms", "triangles_per_s", "config", "comparator",
-            "speedup_vs_comparator", "roofline", "stages", "golden")}
+            "speedup_vs_comparator", "roofline", "stages", "golden", "tuning")}
     cpu = None
     if "cpu" in kids:
         log("[bench] waiting for the CPU oracle legs")
@@ -916,6 +938,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle count in the CPU sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="time both single-graph paths with their compiled defaults")
     ap.add_argument("--no-stream", action="store_true", help="skip the copy/read bandwidth reference")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--workload", choices=("rmat", "batch", "serving", "pmc", "list"), default="rmat")
@@ -936,6 +960,8 @@ def main():
     ap.add_argument("--serve-cl-n-max", type=int, default=10**6)
     ap.add_argument("--serve-budget-frac", type=float, default=0.5)
     ap.add_argument("--no-batching", action="store_true", help="serving: one tc_count per request")
+    ap.add_argument("--pmc-comparator", action="store_true",
+                    help="pmc program: count with the comparator (table bins in sequence)")
     ap.add_argument("--batch-max", type=int, default=64, help="serving: graphs per coalesced launch")
     args = ap.parse_args()
 

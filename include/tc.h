@@ -125,6 +125,34 @@ typedef struct tc_tuning {
                                  default TC_SMALL_MAX_N, -1 = never; capped
                                  at TC_BATCH_MAX_N */
   int32_t small_max_nnz;      /* default TC_SMALL_MAX_NNZ */
+  /* tc_count_tuned and tc_count_edge_baseline_tuned: the intersection stage
+   * (every anchor's tasks either merged in registers or streamed against an
+   * on-chip table of its probe set) */
+  int32_t light_max;          /* anchors with a probe set of at most this many
+                                 ids are merged in registers (1..32, default
+                                 32) ... */
+  int32_t dn_light;           /* ... and, in the cover count, at most this many
+                                 down-neighbours (>= 1, default 32) */
+  int32_t bitmap_member_words;/* a heavy anchor's table is a bitmap over its
+                                 probe set's id window when the bitmap's words
+                                 are at most bitmap_member_words * |P| + 64
+                                 (default 4) ... */
+  int32_t bitmap_desc_words;  /* ... or bitmap_desc_words * its task count
+                                 (default 16); else a hash table (1..1024) */
+  int32_t item_log2;          /* work items hold about 2^item_log2 streamed
+                                 elements (12..24, default 19) */
+  int32_t bin0_mode;          /* smallest-table bin: 1 = blocks claim items,
+                                 2 = items round robin (default 2 for the
+                                 cover count below 2^27 entries, else 1) */
+  int32_t bins_mode;          /* table bins 1 = one after another, 2 = side by
+                                 side on forked streams (default 1 for the
+                                 cover count, 2 for the comparator) */
+  int32_t twolevel_sparsity;  /* a probe set too large for an LDS bitmap or
+                                 hash table gets a two-level table (block bits
+                                 in LDS, member words in global memory); one
+                                 that would fill the 128 KB hash table gets it
+                                 too when its id window is at least this many
+                                 times its size (default 64, -1 = never) */
   int32_t reserved[3];
 } tc_tuning;
 
@@ -266,6 +294,10 @@ int tc_edge_support(const tc_csr* g, const int32_t* tri, int64_t num_triangles, 
  * Asynchronous. */
 int tc_count_edge_baseline(const tc_csr* g, uint32_t flags, int64_t* triangles, void* ws,
                            size_t ws_bytes, tc_stream_t stream);
+/* The comparator with the intersection-stage knobs of tc_tuning (NULL = the
+ * defaults of tc_count_edge_baseline). */
+int tc_count_edge_baseline_tuned(const tc_csr* g, uint32_t flags, const tc_tuning* tuning,
+                                 int64_t* triangles, void* ws, size_t ws_bytes, tc_stream_t stream);
 
 /* Cover-edge counts of many small graphs in one persistent launch: per graph,
  * the levels of tc_bfs_levels (root = largest degree), H and T.
@@ -344,6 +376,9 @@ typedef struct tc_stats {
                               32 KB, 128 KB, row search) */
   int64_t bin_items[4];    /* work items per table bin */
   int64_t descriptors;     /* per-vertex task descriptors examined */
+  int64_t twolevel_elems;  /* anchored-kernel elements probed in two-level
+                              tables (block bits in LDS, member words in
+                              global memory; part of bin 2's) */
 } tc_stats;
 
 int tc_read_stats(const void* ws, tc_stats* out, tc_stream_t stream);

@@ -9,3 +9,4 @@ from .api import (CountResult, Graph, ListResult, TcError, Workspace, bfs_levels
                   count_edge_baseline, cover_edges, default_workspace, edge_support, from_host_csr, from_host_pairs,
                   list_triangles, profile_enable, profile_read, read_stats, select_root, validate, workspace_bytes)
 from .batch import Batch, BatchResult, CapturedBatch, autotune, count_batch  # noqa: F401,E402
+from .tune import autotune_count  # noqa: F401,E402

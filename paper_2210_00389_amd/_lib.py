@@ -35,7 +35,7 @@ EXPORTS = [
     "tc_workspace_bytes", "tc_build_csr", "tc_validate_csr", "tc_bfs_levels", "tc_cover_edges",
     "tc_count", "tc_count_tuned", "tc_list_triangles", "tc_edge_support", "tc_select_root", "tc_count_edge_baseline",
     "tc_count_batch", "tc_count_batch_noalloc", "tc_noalloc_scratch_bytes",
-    "tc_status_string", "tc_last_error",
+    "tc_count_edge_baseline_tuned", "tc_status_string", "tc_last_error",
     "tc_profile_enable", "tc_profile_read", "tc_read_stats",
 ]
 
@@ -52,13 +52,14 @@ class TcBatch(ctypes.Structure):
                 ("max_graph_vertices", ctypes.c_int32)]
 
 
+TUNING_FIELDS = ("batch_block", "batch_piece", "batch_blocks_per_cu", "small_max_n", "small_max_nnz",
+                 "light_max", "dn_light", "bitmap_member_words", "bitmap_desc_words", "item_log2", "bin0_mode",
+                 "bins_mode", "twolevel_sparsity")
+TUNING_RESERVED = 3
+
+
 class TcTuning(ctypes.Structure):
-    _fields_ = [("batch_block", ctypes.c_int32), ("batch_piece", ctypes.c_int32),
-                ("batch_blocks_per_cu", ctypes.c_int32), ("small_max_n", ctypes.c_int32),
-                ("small_max_nnz", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
-
-
-TUNING_FIELDS = ("batch_block", "batch_piece", "batch_blocks_per_cu", "small_max_n", "small_max_nnz")
+    _fields_ = [(f, ctypes.c_int32) for f in TUNING_FIELDS] + [("reserved", ctypes.c_int32 * TUNING_RESERVED)]
 
 
 class TcProfile(ctypes.Structure):
@@ -73,7 +74,7 @@ class TcStats(ctypes.Structure):
                 ("heavy_desc", ctypes.c_int64), ("heavy_elems", ctypes.c_int64),
                 ("heavy_builds", ctypes.c_int64), ("light_elems", ctypes.c_int64),
                 ("bin_elems", ctypes.c_int64 * 4), ("bin_items", ctypes.c_int64 * 4),
-                ("descriptors", ctypes.c_int64)]
+                ("descriptors", ctypes.c_int64), ("twolevel_elems", ctypes.c_int64)]
 
 
 _lib = None
@@ -112,6 +113,8 @@ def load(path: str | None = None):
     lib.tc_edge_support.restype = c_int
     lib.tc_count_edge_baseline.argtypes = [ctypes.POINTER(TcCsr), u32, P, P, sz, P]
     lib.tc_count_edge_baseline.restype = c_int
+    lib.tc_count_edge_baseline_tuned.argtypes = [ctypes.POINTER(TcCsr), u32, ctypes.POINTER(TcTuning), P, P, sz, P]
+    lib.tc_count_edge_baseline_tuned.restype = c_int
     lib.tc_count_batch.argtypes = [ctypes.POINTER(TcBatch), ctypes.POINTER(TcTuning), u32, P, P, P, P, sz, P]
     lib.tc_count_batch.restype = c_int
     lib.tc_count_batch_noalloc.argtypes = [ctypes.POINTER(TcBatch), ctypes.POINTER(TcTuning), u32, P, P, P, P]

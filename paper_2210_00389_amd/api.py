@@ -307,15 +307,19 @@ def edge_support(g: Graph, tri: torch.Tensor, stream=None) -> torch.Tensor:
 
 @_on_stream
 def count_edge_baseline(g: Graph, validate: bool = False, ws: Workspace | None = None, stream=None,
-                        out: torch.Tensor | None = None) -> torch.Tensor:
-    """Plain direction-oriented edge-iterator count (tc_count_edge_baseline)."""
+                        out: torch.Tensor | None = None, tuning: dict | None = None) -> torch.Tensor:
+    """Plain direction-oriented edge-iterator count
+    (tc_count_edge_baseline_tuned; tuning=None gives the defaults)."""
+    from .batch import make_tuning
     lib = L.load()
     dev = g.cols.device
     t = out if out is not None else torch.zeros(1, dtype=torch.int64, device=dev)
     buf = (ws or default_workspace(dev)).get(workspace_bytes(L.OP_EDGE_BASELINE, g.n, g.nnz))
     csr = g.csr()
-    _check(lib.tc_count_edge_baseline(ctypes.byref(csr), L.TC_VALIDATE if validate else 0, _ptr(t),
-                                      _ptr(buf), buf.numel(), _stream(stream)), "tc_count_edge_baseline")
+    tu = make_tuning(tuning)
+    _check(lib.tc_count_edge_baseline_tuned(ctypes.byref(csr), L.TC_VALIDATE if validate else 0,
+                                            ctypes.byref(tu) if tu is not None else None, _ptr(t),
+                                            _ptr(buf), buf.numel(), _stream(stream)), "tc_count_edge_baseline")
     return t
 
 
@@ -328,7 +332,7 @@ def read_stats(ws: Workspace | None = None, device=None, stream=None) -> dict:
     _check(lib.tc_read_stats(_ptr(w.buf), ctypes.byref(st), _stream(stream)), "tc_read_stats")
     out = {k: int(getattr(st, k)) for k in ("n", "nnz", "h", "num_levels", "stream_elems", "light_tasks",
                                              "heavy_items", "heavy_desc", "heavy_elems", "heavy_builds",
-                                             "light_elems", "descriptors")}
+                                             "light_elems", "descriptors", "twolevel_elems")}
     out["bin_elems"] = [int(x) for x in st.bin_elems]
     out["bin_items"] = [int(x) for x in st.bin_items]
     return out

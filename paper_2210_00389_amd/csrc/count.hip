@@ -46,8 +46,9 @@ namespace tc {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kDnLight = 32;  // light anchors have at most this many down-neighbours
-constexpr int kLightMax = 32; // and a probe set of at most this many ids
+constexpr int kDnLight = 32;  // default: light anchors have at most this many down-neighbours
+constexpr int kLightMax = 32; // and a probe set of at most this many ids (the register capacity
+                              // of light_kernel, so the tuned bound never exceeds it)
 constexpr int kBins = 4;
 
 // Bins of heavy anchors by the LDS table they need: 2 KB, 32 KB, 128 KB, or
@@ -65,39 +66,65 @@ __host__ __device__ constexpr int bin_words(int b) {
 
 __device__ __forceinline__ int64_t bitmap_words(int64_t R) { return (R + 32) >> 5; }
 
-// Bin of an anchor with window R, probe-set size P and D descriptors;
-// *bitmap tells the table kind.
-__device__ __forceinline__ int choose_bin(int64_t R, int P, int64_t D, bool* bitmap) {
+// Two-level table of a probe set too large for an LDS bitmap or hash table:
+// in LDS one bit per block of 32 ids of the window (set when the block holds
+// a member) and, per 32 such bits, the number of set bits before them; in
+// global memory the 32-bit member word of every non-empty block, in block
+// order.  Words of LDS it needs for a window of R ids:
+__device__ __forceinline__ int64_t twolevel_words(int64_t R) { return 2 * (((R >> 5) + 32) >> 5); }
+
+enum TableKind { kKindHash = 0, kKindBitmap = 1, kKindTwoLevel = 2 };
+
+// Bin of an anchor with window R, probe-set size P, D descriptors and deg
+// row entries; *kind tells the table kind.  A two-level table's block bits
+// are also kept in global memory at the anchor's row positions (so an item
+// copies them instead of inserting |P| ids), hence they must fit in deg
+// words.
+__device__ __forceinline__ int choose_bin(int64_t R, int P, int64_t D, int64_t deg, int* kind,
+                                          const CountParams& prm) {
   const int64_t need = bitmap_words(R);
-  if (need <= 4 * static_cast<int64_t>(P) + 64 || need <= 16 * D) {
+  if (need <= prm.bm_member * static_cast<int64_t>(P) + 64 || need <= prm.bm_desc * D) {
     for (int b = 0; b < 3; ++b)
       if (need <= bin_words(b)) {
-        *bitmap = true;
+        *kind = kKindBitmap;
         return b;
       }
   }
-  *bitmap = false;
+  const int64_t tw = twolevel_words(R);
+  const bool tl_fits = tw <= kBinWords2 && tw / 2 <= deg;
+  *kind = kKindHash;
   for (int b = 0; b < 3; ++b)
-    if (2 * static_cast<int64_t>(P) <= bin_words(b)) return b;
+    if (2 * static_cast<int64_t>(P) <= bin_words(b)) {
+      // a sparse set of the largest hash bin: most probes miss, and a
+      // two-level table rejects them with one LDS read
+      if (b == 2 && tl_fits && prm.tl_sparsity > 0 && R >= static_cast<int64_t>(prm.tl_sparsity) * P)
+        *kind = kKindTwoLevel;
+      return b;
+    }
+  if (tl_fits) {
+    *kind = kKindTwoLevel;
+    return 2;
+  }
   return 3;
 }
 
 enum Acc {
   kAccT = 0, kAccElems = 1, kAccBuild = 3, kAccRecs = 4, kAccItems = 5, kAccHeavyElems = 6,
-  kAccH = 7, kAccBinCount = 8, kAccBinOff = 12, kAccBinCur = 16, kAccBinNext = 20, kAccBinElems = 24
+  kAccH = 7, kAccBinCount = 8, kAccBinOff = 12, kAccBinCur = 16, kAccBinNext = 20, kAccBinElems = 24,
+  kAccTwoLevelElems = 28
 };
-constexpr int kAccSlots = 28;
-constexpr int64_t kElemChunk = 524288;  // elements per work item (target; a power of two)
-constexpr int kElemChunkLog = 19;
-static_assert(kElemChunk == (int64_t(1) << kElemChunkLog), "kElemChunk must be 2^kElemChunkLog");
+constexpr int kAccSlots = 29;
+constexpr int kElemChunkLog = 19;  // default: 2^19 elements per work item (target)
 // stream record flag (in the length word): probe the anchor's Up list
 constexpr int32_t kFlagUp = 1 << 29;
 constexpr int32_t kLenMask = kFlagUp - 1;
-// work item word: stream count | bin << 28 | kItemBitmap
+// work item word: stream count | bin << 28 | kItemBitmap | kItemTwoLevel
 constexpr int32_t kItemCountMask = (1 << 28) - 1;
 constexpr int32_t kItemBitmap = 1 << 30;
-// per-vertex plan byte: kViHeavy | bitmap << 2 | bin
+constexpr int32_t kItemTwoLevel = static_cast<int32_t>(0x80000000u);
+// per-vertex plan byte: kViHeavy | two-level << 3 | bitmap << 2 | bin
 constexpr uint8_t kViHeavy = 0x80;
+constexpr uint8_t kViTwoLevel = 0x08;
 constexpr uint8_t kViBitmap = 0x04;
 
 __device__ __forceinline__ void add_pv(int64_t* pv, int32_t a, int32_t b, int32_t c) {
@@ -165,9 +192,9 @@ __device__ __forceinline__ int probe_size(const VMeta& m) { return m.up + (m.sfe
 
 // Heavy anchors get work items; every task of a light anchor is merged by
 // the planning kernels.  Must be the same predicate everywhere.
-__device__ __forceinline__ bool is_heavy(const VMeta& m, bool cover) {
-  if (probe_size(m) > kLightMax) return true;
-  return cover && (m.sfe - m.hfb) > 0 && (m.deg - m.sfe) > kDnLight;
+__device__ __forceinline__ bool is_heavy(const VMeta& m, bool cover, const CountParams& prm) {
+  if (probe_size(m) > prm.light_max) return true;
+  return cover && (m.sfe - m.hfb) > 0 && (m.deg - m.sfe) > prm.dn_light;
 }
 
 __device__ __forceinline__ void block_acc(unsigned long long* acc, int slot, int64_t v, int64_t* sh) {
@@ -199,7 +226,7 @@ __device__ __forceinline__ void probe_window(const int32_t* lc, const VMeta& m, 
 template <bool kCover>
 __global__ __launch_bounds__(kThreads) void plan_kernel(const int32_t* lc, const VMeta* meta, int64_t n,
                                                         int32_t* ndesc, uint8_t* vinfo,
-                                                        unsigned long long* acc) {
+                                                        unsigned long long* acc, CountParams prm) {
   __shared__ int64_t sh[kThreads / kWave + 1];
   int64_t h = 0;
   for (int64_t x0 = blockIdx.x * (int64_t)blockDim.x; x0 < n; x0 += (int64_t)gridDim.x * blockDim.x) {
@@ -211,13 +238,14 @@ __global__ __launch_bounds__(kThreads) void plan_kernel(const int32_t* lc, const
     const int D = nB + hf + (m.hfb - m.up);
     h += hf;
     uint8_t vi = 0;
-    if (D > 0 && is_heavy(m, kCover)) {
+    if (D > 0 && is_heavy(m, kCover, prm)) {
       int32_t lo;
       int64_t R;
       probe_window(lc, m, lo, R);
-      bool bm = false;
-      const int b = choose_bin(R, probe_size(m), D, &bm);
-      vi = static_cast<uint8_t>(kViHeavy | (bm ? kViBitmap : 0) | b);
+      int kind = kKindHash;
+      const int b = choose_bin(R, probe_size(m), D, m.deg, &kind, prm);
+      vi = static_cast<uint8_t>(kViHeavy | (kind == kKindBitmap ? kViBitmap : 0) |
+                                (kind == kKindTwoLevel ? kViTwoLevel : 0) | b);
     }
     ndesc[x] = D;
     vinfo[x] = vi;
@@ -377,6 +405,63 @@ __device__ __forceinline__ void describe_all(const int32_t* lc, const int32_t* s
   }
 }
 
+// The tables of the two-level anchors (plan byte kViTwoLevel), at anchor x's
+// row positions [begin, begin + deg):
+//   words[begin + r]        the bits of its probe-set members in the r-th
+//                           non-empty block of 32 ids of its window (the
+//                           blocks number at most |P| <= deg(x));
+//   l1[begin + i], i < nw   block bits (bit j of word i: block 32 i + j holds
+//                           a member), copied into LDS by every item of x
+//                           (nw <= deg(x) by the bin rule).
+// One wave per anchor; the anchors are found 64 vertices at a time.
+__global__ void twolevel_words_kernel(const int32_t* lc, const VMeta* meta, const uint8_t* vinfo, int64_t n,
+                                      uint32_t* words, uint32_t* l1) {
+  const int64_t wid = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
+  const int64_t nwv = (static_cast<int64_t>(gridDim.x) * blockDim.x) / kWave;
+  const int ln = lane();
+  for (int64_t x0 = wid * kWave; x0 < n; x0 += nwv * kWave) {
+    const int64_t xl = x0 + ln;
+    uint64_t mask = __ballot(xl < n && (vinfo[xl] & kViTwoLevel));
+    while (mask) {
+      const int j = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+      mask &= mask - 1;
+      const VMeta m = meta[x0 + j];
+      int32_t lo;
+      int64_t R;
+      probe_window(lc, m, lo, R);
+      const int P = probe_size(m);
+      const int nw = static_cast<int>(twolevel_words(R) >> 1);
+      uint32_t* wx = words + m.begin;
+      uint32_t* lx = l1 + m.begin;
+      for (int i = ln; i < P; i += kWave) wx[i] = 0u;
+      for (int i = ln; i < nw; i += kWave) lx[i] = 0u;
+      __threadfence();
+      int carry = 0;       // non-empty blocks before this round
+      int32_t prevb = -1;  // block of the last member of the previous round
+      for (int base = 0; base < P; base += kWave) {
+        const int i = base + ln;
+        int32_t b = -1;
+        uint32_t d = 0;
+        if (i < P) {
+          const int32_t key = i < m.up ? lc[m.begin + i] : lc[m.begin + m.hfb + (i - m.up)];
+          d = static_cast<uint32_t>(key - lo);
+          b = static_cast<int32_t>(d >> 5);
+        }
+        int32_t pb = __shfl_up(b, 1, kWave);
+        if (ln == 0) pb = prevb;
+        const int start = (i < P && b != pb) ? 1 : 0;
+        const int incl = wave_incl_scan(start);
+        if (i < P) {
+          atomicOr(&wx[carry + incl - 1], 1u << (d & 31));
+          if (start) atomicOr(&lx[b >> 5], 1u << (b & 31));
+        }
+        carry += __shfl(incl, kWave - 1, kWave);
+        prevb = __shfl(b, kWave - 1, kWave);  // a later round exists only if all 64 lanes were members
+      }
+    }
+  }
+}
+
 // Column samples for the searches of the resolution: samp[b] = lc[b * kSampStride].
 __global__ void sample_kernel(const int32_t* lc, int64_t nnz, int32_t* samp) {
   const int64_t nb = (nnz + kSampStride - 1) / kSampStride;
@@ -407,7 +492,7 @@ template <bool kCover>
 __global__ __launch_bounds__(kResThreads) void resolve_kernel(
     const int32_t* lc, const int32_t* samp, const VMeta* meta, const uint8_t* vinfo, const int64_t* so,
     const int32_t* cx0, int64_t n, int64_t* sbeg, int32_t* slen, int32_t* soth, int32_t* sx, int4* items_raw,
-    int4* ccnt) {
+    int4* ccnt, int item_log2) {
   __shared__ int64_t sh[kResThreads / kWave + 1];
   __shared__ int64_t s_so[kResSpan];
   __shared__ int32_t s_x[kResRecs];
@@ -529,7 +614,7 @@ __global__ __launch_bounds__(kResThreads) void resolve_kernel(
     }
     __syncthreads();
     // ---- cut into work items: a new item starts where the anchor changes
-    // or the record's element offset enters the next kElemChunk
+    // or the record's element offset enters the next 2^item_log2
     // item starts are numbered in slot order: per descriptor group j (the
     // slots of group j follow all of group j - 1), like the records
     int64_t ns = 0;
@@ -538,7 +623,7 @@ __global__ __launch_bounds__(kResThreads) void resolve_kernel(
       const int cnt = heavy[j] ? (ta[j].len != 0) + (tb[j].len != 0) : 0;
       int64_t nsj = 0;
       for (int q = hslot[j]; q < hslot[j] + cnt; ++q)
-        nsj += (q == 0 || s_x[q] != s_x[q - 1] || (s_pre[q] >> kElemChunkLog) != (s_pre[q - 1] >> kElemChunkLog));
+        nsj += (q == 0 || s_x[q] != s_x[q - 1] || (s_pre[q] >> item_log2) != (s_pre[q - 1] >> item_log2));
       ns |= nsj << (16 * j);  // at most 2 per thread, at most kResRecs per group
     }
     int64_t ns_tot;
@@ -555,7 +640,7 @@ __global__ __launch_bounds__(kResThreads) void resolve_kernel(
       const int cnt = heavy[j] ? (ta[j].len != 0) + (tb[j].len != 0) : 0;
       int it = itj[j];
       for (int q = hslot[j]; q < hslot[j] + cnt; ++q)
-        if (q == 0 || s_x[q] != s_x[q - 1] || (s_pre[q] >> kElemChunkLog) != (s_pre[q - 1] >> kElemChunkLog))
+        if (q == 0 || s_x[q] != s_x[q - 1] || (s_pre[q] >> item_log2) != (s_pre[q - 1] >> item_log2))
           s_first[it++] = q;
     }
     if (tid == 0) {
@@ -568,7 +653,8 @@ __global__ __launch_bounds__(kResThreads) void resolve_kernel(
       const uint8_t vi = vinfo[x];
       const int64_t r0 = rbase + s_first[i];
       const int cntr = s_first[i + 1] - s_first[i];
-      const int32_t w = cntr | ((vi & 3) << 28) | ((vi & kViBitmap) ? kItemBitmap : 0);
+      const int32_t w = cntr | ((vi & 3) << 28) | ((vi & kViBitmap) ? kItemBitmap : 0) |
+                        ((vi & kViTwoLevel) ? kItemTwoLevel : 0);
       items_raw[rbase + i] = make_int4(x, static_cast<int>(r0 & 0xFFFFFFFF), static_cast<int>(r0 >> 32), w);
     }
     __syncthreads();
@@ -731,13 +817,15 @@ __device__ __forceinline__ uint32_t hslot(int32_t key, int shift) {
   return (static_cast<uint32_t>(key) * 0x9E3779B1u) >> shift;
 }
 
-enum ProbeMode { kBitmap = 0, kHash = 1, kSearch = 2 };
+enum ProbeMode { kBitmap = 0, kHash = 1, kSearch = 2, kTwoLevel = 3 };
 
 // Probe set P(x) = Up(x) ∪ Hfwd(x) of the block's current anchor.
 struct ProbeSet {
   const uint32_t* tab;
-  int32_t lo;      // bitmap: id of bit 0
-  uint32_t R;      // bitmap: window length; bit R is kept clear
+  int32_t lo;      // bitmap, two-level: id of bit 0
+  uint32_t R;      // bitmap: window length; bit R is kept clear (two-level: ids >= R miss)
+  int nw;          // two-level: LDS words of block bits (their prefix counts follow)
+  const uint32_t* words;  // two-level: the member words of the non-empty blocks
   int cap, shift;  // hash: slot count (power of two) and hslot shift
   const int32_t* up_row;
   const int32_t* hf_row;
@@ -751,6 +839,14 @@ __device__ __forceinline__ uint32_t probe(const ProbeSet& ps, int32_t t, bool up
   if (MODE == kBitmap) {
     const uint32_t d = min(static_cast<uint32_t>(t) - static_cast<uint32_t>(ps.lo), ps.R);
     return (ps.tab[d >> 5] >> (d & 31)) & 1u;
+  } else if (MODE == kTwoLevel) {
+    const uint32_t d = static_cast<uint32_t>(t) - static_cast<uint32_t>(ps.lo);
+    if (d >= ps.R) return 0u;
+    const uint32_t b = d >> 5;
+    const uint32_t w1 = ps.tab[b >> 5];
+    if (!((w1 >> (b & 31)) & 1u)) return 0u;  // an empty block: no member
+    const uint32_t r = ps.tab[ps.nw + (b >> 5)] + __popc(w1 & ((1u << (b & 31)) - 1u));
+    return (ps.words[r] >> (d & 31)) & 1u;
   } else if (MODE == kHash) {
     uint32_t h = hslot(t, ps.shift);
     int32_t k;
@@ -924,6 +1020,7 @@ template <int WORDS, int THREADS, int D, int WPE, int kOut, bool kRoundRobin>
 __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, const VMeta* meta, int bin,
                                                         const int4* items, const int64_t* sbeg,
                                                         const int32_t* slen, const int32_t* soth,
+                                                        const uint32_t* tl_words, const uint32_t* tl_l1,
                                                         unsigned long long* acc, Out o) {
   constexpr int R = D / THREADS;  // records loaded per thread
   static_assert(R * THREADS == D, "D must be a multiple of THREADS");
@@ -943,7 +1040,7 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
   const unsigned long long first = acc[kAccBinOff + bin];
   const unsigned long long count = acc[kAccBinCount + bin];
   const int tid = threadIdx.x;
-  int64_t cnt = 0, elems = 0, builds = 0;
+  int64_t cnt = 0, elems = 0, builds = 0, tl_elems = 0;
   int32_t cur_x = -1;
   // blocks claim kClaim consecutive items at a time (consecutive items of
   // one anchor share the table); the next claim is fetched while the
@@ -979,16 +1076,44 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
     ps.up_len = mx.up;
     ps.hf_row = lc + mx.begin + mx.hfb;
     ps.hf_len = mx.sfe - mx.hfb;
+    ps.nw = 0;
+    ps.words = tl_words + mx.begin;
     int mode = kSearch;
     if (WORDS > 0) {
       int64_t R64;
       probe_window(lc, mx, ps.lo, R64);
       ps.R = static_cast<uint32_t>(R64);
-      mode = (item.w & kItemBitmap) ? kBitmap : kHash;
+      mode = (item.w & kItemBitmap) ? kBitmap : ((item.w & kItemTwoLevel) ? kTwoLevel : kHash);
       ps.cap = WORDS;
       ps.shift = 32 - __builtin_ctz(WORDS);
+      ps.nw = static_cast<int>(twolevel_words(R64) >> 1);
       if (x != cur_x) {
-        if (mode == kBitmap) {
+        if (WORDS == kBinWords2 && mode == kTwoLevel) {
+          // the block bits as the planning pass wrote them at the anchor's
+          // row positions, then per word the number of set bits before it
+          const uint32_t* lx = tl_l1 + mx.begin;
+          const int nw = ps.nw;
+          constexpr int kPer = WORDS > 0 ? (WORDS / 2 + THREADS - 1) / THREADS : 1;  // words per thread
+          uint32_t wv[kPer];
+          int mine = 0;
+#pragma unroll
+          for (int j = 0; j < kPer; ++j) {
+            const int i = tid * kPer + j;
+            wv[j] = i < nw ? lx[i] : 0u;
+            mine += __popc(wv[j]);
+          }
+          int32_t tot;
+          int run = block_excl_scan(mine, shi, &tot);
+#pragma unroll
+          for (int j = 0; j < kPer; ++j) {
+            const int i = tid * kPer + j;
+            if (i < nw) {
+              tab[i] = wv[j];
+              tab[nw + i] = static_cast<uint32_t>(run);
+            }
+            run += __popc(wv[j]);
+          }
+        } else if (mode == kBitmap) {
           const int words = static_cast<int>(bitmap_words(R64));
           for (int i = tid; i < words; i += THREADS) tab[i] = 0u;
           __syncthreads();
@@ -1009,7 +1134,8 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
         }
         __syncthreads();
         cur_x = x;
-        builds += tid == 0 ? P : 0;
+        // ids inserted (bitmap, hash) or words copied (two-level)
+        builds += tid == 0 ? (mode == kTwoLevel ? ps.nw : P) : 0;
       }
     }
     int64_t ebase = 0;
@@ -1046,6 +1172,7 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
           ++nne;
           nch += (llen[r] + kChunk - 1) / kChunk;
           elems += llen[r];
+          if (mode == kTwoLevel) tl_elems += llen[r];
         }
       }
       int32_t nslots, C;
@@ -1070,6 +1197,9 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
       } else if (mode == kBitmap) {
         got = run_chunks<kBitmap, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
                                                  ebase, &s_pos);
+      } else if (WORDS == kBinWords2 && mode == kTwoLevel) {
+        got = run_chunks<kTwoLevel, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
+                                                   ebase, &s_pos);
       } else {
         got = run_chunks<kHash, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
                                                ebase, &s_pos);
@@ -1094,6 +1224,7 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
   block_acc(acc, kAccHeavyElems, elems, sh);
   block_acc(acc, kAccBinElems + bin, elems, sh);
   block_acc(acc, kAccBuild, builds, sh);
+  block_acc(acc, kAccTwoLevelElems, tl_elems, sh);
 }
 
 
@@ -1114,6 +1245,7 @@ __global__ void finish_kernel(const unsigned long long* acc, const int64_t* so, 
     stats[11 + kBins + b] = static_cast<int64_t>(acc[kAccBinCount + b]);
   }
   stats[19] = n > 0 ? so[n] : 0;
+  stats[20] = static_cast<int64_t>(acc[kAccTwoLevelElems]);
 }
 
 __global__ void forward_meta_kernel(const int64_t* off, const int32_t* cols, int64_t n, VMeta* meta) {
@@ -1132,33 +1264,21 @@ __global__ void forward_meta_kernel(const int64_t* off, const int32_t* cols, int
 template <int WORDS, int THREADS, int D, int WPE, int kOut, bool kRoundRobin = false>
 int launch_heavy(const CountArgs& a, CountWs& w, const Out& o, int bin, int blocks_per_cu, hipStream_t s) {
   heavy_kernel<WORDS, THREADS, D, WPE, kOut, kRoundRobin><<<static_cast<unsigned>(num_cus() * blocks_per_cu), THREADS, 0, s>>>(
-      a.cols, a.meta, bin, w.items, w.sbeg, w.slen, w.soth, w.acc, o);
+      a.cols, a.meta, bin, w.items, w.sbeg, w.slen, w.soth, w.tl_words, w.tl_l1, w.acc, o);
   TC_HIP(hipGetLastError());
   return TC_OK;
 }
 
-// The four bins of heavy items, one after another on the call's stream or
-// side by side on forked streams.  Side by side, the many small blocks of
-// bin 0 can take the CUs before the blocks of a larger bin and the stage
-// time varies from call to call; in sequence each bin has the whole GPU.
-// The cover-edge count runs faster and steadier in sequence (R-MAT S20
-// heavy stage 2.04 ms against a median of 2.28 ms side by side, S24 within
-// 1.5%); the comparator, whose work is spread over the small bins, side by
-// side.
+// The four bins of heavy items, one after another on the call's stream
+// (bins_mode 1) or side by side on forked streams (2).
 template <int kOut>
 int launch_bins(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
-  if (a.cover) {
+  if (a.prm.bins_mode == 1) {
     TC_TRY((launch_heavy<kBinWords2, 1024, 1024, 4, kOut>(a, w, o, 2, 1, s)));
     TC_TRY((launch_heavy<kBinWords1, 512, 1024, 6, kOut>(a, w, o, 1, 3, s)));
-    // Bin 0 (tables of 2 KB): on smaller graphs its items are short (about
-    // 500 elements at R-MAT S20) and two waves per block with half the
-    // blocks finish sooner (0.16 ms of 2.05 at S20), taking the items round
-    // robin: the claim counter's same-address atomics and the spread of
-    // finish times over a 4-item claim cost another 0.1 ms of 0.42 there.
-    // On large graphs (2400 elements per item at S24) the items vary more
-    // and one wave per block, 24 blocks per CU and claims do (round robin
-    // loses 2.4 ms there).
-    if (a.g->nnz < (int64_t(1) << 27)) TC_TRY((launch_heavy<kBinWords0, 128, 256, 6, kOut, true>(a, w, o, 0, 12, s)));
+    // bin 0: two-wave blocks taking items round robin, or one-wave blocks
+    // claiming them (count_params picks by graph size)
+    if (a.prm.bin0_mode == 2) TC_TRY((launch_heavy<kBinWords0, 128, 256, 6, kOut, true>(a, w, o, 0, 12, s)));
     else TC_TRY((launch_heavy<kBinWords0, 64, 256, 6, kOut>(a, w, o, 0, 24, s)));
     return launch_heavy<0, 512, 1024, 4, kOut>(a, w, o, 3, 4, s);
   }
@@ -1167,7 +1287,8 @@ int launch_bins(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
   TC_TRY(fork_begin(f, s));
   TC_TRY((launch_heavy<kBinWords2, 1024, 1024, 4, kOut>(a, w, o, 2, 1, s)));
   TC_TRY((launch_heavy<kBinWords1, 512, 1024, 6, kOut>(a, w, o, 1, 3, f->aux[0])));
-  TC_TRY((launch_heavy<kBinWords0, 64, 256, 6, kOut>(a, w, o, 0, 24, f->aux[1])));
+  if (a.prm.bin0_mode == 2) TC_TRY((launch_heavy<kBinWords0, 128, 256, 6, kOut, true>(a, w, o, 0, 12, f->aux[1])));
+  else TC_TRY((launch_heavy<kBinWords0, 64, 256, 6, kOut>(a, w, o, 0, 24, f->aux[1])));
   TC_TRY((launch_heavy<0, 512, 1024, 4, kOut>(a, w, o, 3, 4, f->aux[2])));
   return fork_end(f, s);
 }
@@ -1193,7 +1314,10 @@ int launch_all(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
   const unsigned gr = static_cast<unsigned>(w.nchunk_cap < gmax ? w.nchunk_cap : gmax);
   const int64_t gct = (w.nchunk_cap + kThreads - 1) / kThreads;
   const unsigned gc = static_cast<unsigned>(gct < gmax ? gct : gmax);
-  plan_kernel<kCover><<<gv, kThreads, 0, s>>>(a.cols, a.meta, n, w.ndesc, w.vinfo, w.acc);
+  plan_kernel<kCover><<<gv, kThreads, 0, s>>>(a.cols, a.meta, n, w.ndesc, w.vinfo, w.acc, a.prm);
+  TC_HIP(hipGetLastError());
+  twolevel_words_kernel<<<grid_for(n, kThreads * kWave, 4096), kThreads, 0, s>>>(a.cols, a.meta, w.vinfo, n,
+                                                                               w.tl_words, w.tl_l1);
   TC_HIP(hipGetLastError());
   {
     Carver sc(w.scratch);
@@ -1206,7 +1330,7 @@ int launch_all(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
   sample_kernel<<<grid_for(a.g->nnz / kSampStride + 1, kThreads, 16384), kThreads, 0, s>>>(a.cols, a.g->nnz,
                                                                                            w.samp);
   resolve_kernel<kCover><<<gr, kResThreads, 0, s>>>(a.cols, w.samp, a.meta, w.vinfo, w.so, w.cx0, n, w.sbeg, w.slen,
-                                                    w.soth, w.sx, w.items_raw, w.ccnt);
+                                                    w.soth, w.sx, w.items_raw, w.ccnt, a.prm.item_log2);
   TC_HIP(hipGetLastError());
   {
     Carver sc(w.scratch);
@@ -1237,6 +1361,52 @@ Out unit_out(CountWs& w) {
 
 }  // namespace
 
+int count_params(const tc_tuning* t, bool cover, int64_t nnz, CountParams* out) {
+  CountParams p;
+  p.light_max = kLightMax;
+  p.dn_light = kDnLight;
+  p.bm_member = 4;
+  p.bm_desc = 16;
+  p.item_log2 = kElemChunkLog;
+  p.tl_sparsity = 64;
+  // Bin 0 (tables of 2 KB): on smaller graphs its items are short (about 500
+  // elements at R-MAT S20) and two waves per block with half the blocks
+  // finish sooner, taking the items round robin (the claim counter's
+  // same-address atomics and the spread of finish times over a 4-item claim
+  // cost 0.1 ms of 0.42 at S20); on large graphs (2400 elements per item at
+  // S24) the items vary more and one wave per block with claims does
+  // (round robin loses 2.4 ms there).
+  p.bin0_mode = cover && nnz < (int64_t(1) << 27) ? 2 : 1;
+  // The table bins one after another or side by side on forked streams:
+  // side by side, bin 0's many small blocks can take the CUs before a
+  // larger bin's and the stage time varies from call to call; the cover
+  // count runs faster and steadier in sequence (R-MAT S20 heavy stage 2.04
+  // ms against a median of 2.28 ms side by side, S24 within 1.5%), the
+  // comparator, whose work is spread over the small bins, side by side.
+  p.bins_mode = cover ? 1 : 2;
+  if (t) {
+    if (t->light_max) p.light_max = t->light_max;
+    if (t->dn_light) p.dn_light = t->dn_light;
+    if (t->bitmap_member_words) p.bm_member = t->bitmap_member_words;
+    if (t->bitmap_desc_words) p.bm_desc = t->bitmap_desc_words;
+    if (t->item_log2) p.item_log2 = t->item_log2;
+    if (t->bin0_mode) p.bin0_mode = t->bin0_mode;
+    if (t->bins_mode) p.bins_mode = t->bins_mode;
+    if (t->twolevel_sparsity) p.tl_sparsity = t->twolevel_sparsity;
+  }
+  if (p.light_max < 1 || p.light_max > kLightMax)
+    return fail(TC_ERR_INVALID_ARG, "tuning: light_max must be in 1..%d", kLightMax);
+  if (p.dn_light < 1) return fail(TC_ERR_INVALID_ARG, "tuning: dn_light must be >= 1");
+  if (p.bm_member < 1 || p.bm_member > 1024 || p.bm_desc < 1 || p.bm_desc > 1024)
+    return fail(TC_ERR_INVALID_ARG, "tuning: bitmap word factors must be in 1..1024");
+  if (p.item_log2 < 12 || p.item_log2 > 24) return fail(TC_ERR_INVALID_ARG, "tuning: item_log2 must be in 12..24");
+  if (p.tl_sparsity < -1) return fail(TC_ERR_INVALID_ARG, "tuning: twolevel_sparsity must be >= 1, or -1");
+  if (p.bin0_mode < 1 || p.bin0_mode > 2 || p.bins_mode < 1 || p.bins_mode > 2)
+    return fail(TC_ERR_INVALID_ARG, "tuning: bin0_mode and bins_mode must be 1 or 2");
+  *out = p;
+  return TC_OK;
+}
+
 CountWs count_reserve(Carver& c, int64_t n, int64_t nnz) {
   CountWs w;
   w.ndesc = c.take<int32_t>(n + 1);
@@ -1258,6 +1428,8 @@ CountWs count_reserve(Carver& c, int64_t n, int64_t nnz) {
   w.ccnt = c.take<int4>(w.nchunk_cap);
   w.lpre = c.take<int64_t>(w.nchunk_cap + 1);
   w.samp = c.take<int32_t>(nnz / kSampStride + 2);
+  w.tl_words = c.take<uint32_t>(nnz + 1);
+  w.tl_l1 = c.take<uint32_t>(nnz + 1);
   w.acc = c.take<unsigned long long>(kAccSlots);
   w.stats = c.take<int64_t>(24);
   // scans over vertices, over chunks and over the work units of triangle finding (<= rcap)

@@ -209,7 +209,8 @@ namespace {
 // BFS, relabel and layout, then the count or (list) triangle finding into
 // tri[3 * cap].
 int cover_call(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles, int64_t* h_count, int32_t* levels,
-               int64_t* per_vertex, bool list, int32_t* tri, int64_t cap, void* ws, hipStream_t s) {
+               int64_t* per_vertex, bool list, int32_t* tri, int64_t cap, void* ws, hipStream_t s,
+               const CountParams& prm) {
   const bool pv = flags & TC_PER_VERTEX;
   TC_TRY(maybe_validate(g, flags, ws, s));
   CountPlan p = plan_count(ws, g->n, g->nnz);
@@ -227,6 +228,7 @@ int cover_call(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles
   if (pv) TC_TRY(fill_i64(p.pv_new, 0, g->n, s));
   CountArgs a;
   a.g = &rg;
+  a.prm = prm;
   a.cols = p.split.scols;
   a.meta = p.split.meta;
   a.cover = true;
@@ -261,13 +263,15 @@ int tc_count_tuned(const tc_csr* g, int64_t root, uint32_t flags, const tc_tunin
     if (tuning->small_max_n) small_n = tuning->small_max_n;
     if (tuning->small_max_nnz) small_nnz = tuning->small_max_nnz;
   }
+  CountParams prm;
+  TC_TRY(count_params(tuning, true, g->nnz, &prm));
   hipStream_t s = static_cast<hipStream_t>(stream);
   CallScope scope(s);
   if (!pv && small_path_fits(g->n, g->nnz, small_n, small_nnz)) {
     TC_TRY(maybe_validate(g, flags, ws, s));
     return small_count_run(g, root, triangles, h_count, levels, ws, ws_bytes, s);
   }
-  return cover_call(g, root, flags, triangles, h_count, levels, per_vertex, false, nullptr, 0, ws, s);
+  return cover_call(g, root, flags, triangles, h_count, levels, per_vertex, false, nullptr, 0, ws, s, prm);
 }
 
 int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles, int64_t* h_count, int32_t* levels,
@@ -285,9 +289,11 @@ int tc_list_triangles(const tc_csr* g, int64_t root, uint32_t flags, int32_t* tr
     return fail(TC_ERR_INVALID_ARG, "tc_list_triangles: root %lld out of range", (long long)root);
   const size_t need = plan_count(nullptr, g->n, g->nnz).bytes;
   TC_TRY(check_ws(ws, ws_bytes, need, "tc_list_triangles"));
+  CountParams prm;
+  TC_TRY(count_params(nullptr, true, g->nnz, &prm));
   hipStream_t s = static_cast<hipStream_t>(stream);
   CallScope scope(s);
-  return cover_call(g, root, flags, triangles, h_count, levels, nullptr, true, tri, cap, ws, s);
+  return cover_call(g, root, flags, triangles, h_count, levels, nullptr, true, tri, cap, ws, s, prm);
 }
 
 int tc_select_root(const tc_csr* g, int32_t num_candidates, uint32_t flags, int64_t* root_out,
@@ -322,8 +328,15 @@ int tc_edge_support(const tc_csr* g, const int32_t* tri, int64_t num_triangles, 
 
 int tc_count_edge_baseline(const tc_csr* g, uint32_t flags, int64_t* triangles, void* ws, size_t ws_bytes,
                            tc_stream_t stream) {
+  return tc_count_edge_baseline_tuned(g, flags, nullptr, triangles, ws, ws_bytes, stream);
+}
+
+int tc_count_edge_baseline_tuned(const tc_csr* g, uint32_t flags, const tc_tuning* tuning, int64_t* triangles,
+                                 void* ws, size_t ws_bytes, tc_stream_t stream) {
   TC_TRY(check_csr(g, "tc_count_edge_baseline"));
   if (!triangles) return fail(TC_ERR_INVALID_ARG, "tc_count_edge_baseline: triangles is NULL");
+  CountParams prm;
+  TC_TRY(count_params(tuning, false, g->nnz, &prm));
   const size_t need = plan_baseline(nullptr, g->n, g->nnz).bytes;
   TC_TRY(check_ws(ws, ws_bytes, need, "tc_count_edge_baseline"));
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -336,6 +349,7 @@ int tc_count_edge_baseline(const tc_csr* g, uint32_t flags, int64_t* triangles, 
     TC_HIP(hipMemcpyAsync(p.cols, g->cols, g->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   CountArgs a;
   a.g = g;
+  a.prm = prm;
   a.cols = p.cols;
   a.meta = p.meta;
   a.cover = false;

@@ -128,6 +128,8 @@ struct CountWs {
   int4* ccnt;          // per chunk: heavy records, light tasks, items
   int64_t* lpre;       // scan of the per-chunk light task counts
   int32_t* samp;       // every 32nd layout column, for the searches of the resolution
+  uint32_t* tl_words;  // member words of two-level anchors, at their rows' positions [nnz + 1]
+  uint32_t* tl_l1;     // LDS part (block bits, prefix counts) of two-level tables, likewise [nnz + 1]
   int64_t nchunk_cap;
   int64_t rcap;
   unsigned long long* acc;
@@ -136,8 +138,24 @@ struct CountWs {
 };
 CountWs count_reserve(Carver& c, int64_t n, int64_t nnz);
 
+// Scheduling choices of the count (none changes a result): see tc_tuning.
+struct CountParams {
+  int light_max;   // anchors with a probe set of at most this many ids are light (<= 32)
+  int dn_light;    // ... and (cover count) at most this many down-neighbours
+  int bm_member;   // bitmap table when its words <= bm_member * |P| + 64 ...
+  int bm_desc;     // ... or <= bm_desc * (descriptors of the anchor); else hash
+  int item_log2;   // work items hold about 2^item_log2 streamed elements
+  int bin0_mode;   // 1: blocks claim items; 2: items round robin
+  int bins_mode;   // 1: table bins one after another; 2: side by side
+  int tl_sparsity; // largest hash bin: two-level table instead when window >= this * |P| (-1: never)
+};
+// The defaults, overridden by the non-zero fields of `t` (nullable);
+// TC_ERR_INVALID_ARG for a value out of range.
+int count_params(const tc_tuning* t, bool cover, int64_t nnz, CountParams* out);
+
 struct CountArgs {
   const tc_csr* g;
+  CountParams prm;
   const int32_t* cols;  // layout columns [nnz + kColPad] (cover: split; comparator: copy)
   const VMeta* meta;
   bool cover;           // cover edges (three classes) or the comparator

@@ -91,3 +91,24 @@ def test_batch_argument_errors_without_gpu(lib):
     assert lib.tc_count_batch(None, None, 0, ctypes.byref(t), None, None, None, 0, None) == -1
     b = _lib.TcBatch(-1, 0, 0, None, None, None, 0)
     assert lib.tc_count_batch(ctypes.byref(b), None, 0, ctypes.byref(t), None, None, None, 0, None) == -1
+
+
+def test_tuning_out_of_range_without_gpu(lib):
+    """Out-of-range knobs of tc_tuning are refused before any device work."""
+    import ctypes
+    from paper_2210_00389_amd import _lib
+    from paper_2210_00389_amd.batch import make_tuning
+    csr = _lib.TcCsr(1000, 20000, 1, 1)
+    t = ctypes.c_int64(0)
+    for bad in (dict(light_max=33), dict(light_max=-1), dict(dn_light=-2), dict(item_log2=11), dict(item_log2=25),
+                dict(bitmap_desc_words=2000), dict(bin0_mode=3), dict(bins_mode=-1)):
+        tu = make_tuning(dict(bad, small_max_n=-1))
+        rc = lib.tc_count_tuned(ctypes.byref(csr), -1, 0, ctypes.byref(tu), ctypes.byref(t), None, None, None,
+                                ctypes.c_void_p(256), 1 << 40, None)
+        assert rc == -1 and "tuning" in lib.tc_last_error().decode(), bad
+        rc = lib.tc_count_edge_baseline_tuned(ctypes.byref(csr), 0, ctypes.byref(tu), ctypes.byref(t),
+                                              ctypes.c_void_p(256), 1 << 40, None)
+        assert rc == -1, bad
+    import pytest
+    with pytest.raises(ValueError):
+        make_tuning(dict(no_such_knob=1))

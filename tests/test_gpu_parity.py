@@ -279,3 +279,94 @@ def test_small_path_stats_and_workspace(tc):
     assert ws.buf.numel() == tc.workspace_bytes(_lib.OP_COUNT, G.n, G.nnz)
     r_off = tc.count(G, tuning=SMALL_OFF)
     assert (r.T, r.h) == (r_off.T, r_off.h)
+
+
+TUNINGS = [dict(light_max=1, dn_light=1), dict(light_max=8, dn_light=4, item_log2=12),
+           dict(bitmap_member_words=1, bitmap_desc_words=1), dict(bitmap_member_words=1024, bitmap_desc_words=1024),
+           dict(item_log2=24, bin0_mode=1, bins_mode=2), dict(item_log2=14, bin0_mode=2, bins_mode=1),
+           dict(light_max=32, dn_light=1000, item_log2=16, bins_mode=2, bin0_mode=2),
+           dict(twolevel_sparsity=1), dict(twolevel_sparsity=-1, bins_mode=1)]
+
+
+def test_determinism_across_tunings(tc):
+    """Every tuning of the intersection stage gives the oracle's T and |H|,
+    for the cover count and the comparator, on graphs that exercise every
+    table bin (R-MAT scales 12-16, a windmill hub, a complete graph beyond
+    the on-chip tables)."""
+    k = 5000
+    hub = np.zeros(2 * k, np.int32)
+    leaves = np.arange(1, 2 * k + 1, dtype=np.int32)
+    windmill = graphgen.Graph(2 * k + 1, np.concatenate([hub, leaves[0::2]]), np.concatenate([leaves, leaves[1::2]]))
+    graphs = [("rmat12", graphgen.rmat(12, 16, seed=5)), ("rmat14", graphgen.rmat(14, 16, seed=6)),
+              ("rmat16", graphgen.rmat(16, 16, seed=7)), ("windmill", windmill), ("K1500", graphgen.complete(1500))]
+    for name, g in graphs:
+        if name == "K1500":  # closed forms: C(n,3) triangles, C(n-1,2) cover edges from any root
+            T, h = math.comb(1500, 3), math.comb(1499, 2)
+        else:
+            c = oracle.from_graph(g)
+            lv = oracle.bfs_levels(c)
+            T = oracle.count(c, lv.levels).triangles
+            h = len(oracle.cover_edges(c, lv.levels)[0])
+        G = to_gpu(tc, g)
+        for t in TUNINGS:
+            say(f"[tuning] {name} {t}")
+            r = tc.count(G, tuning=dict(t, small_max_n=-1))
+            assert (r.T, r.h) == (T, h), (name, t)
+            assert int(tc.count_edge_baseline(G, tuning=t).item()) == T, (name, t)
+
+
+def test_autotune_count(tc):
+    """The autotuner returns tunings whose counts equal the oracle's."""
+    g = graphgen.rmat(13, 16, seed=9)
+    G = to_gpu(tc, g)
+    T = oracle.triangle_count(oracle.from_graph(g))
+    small = {"item_log2": [17, 19], "bins_mode": [1, 2]}
+    for path in ("cover", "edge"):
+        say(f"[autotune] {path}")
+        t = tc.autotune_count(G, path=path, reps=2, space=small, use_cache=False)
+        assert set(t) <= set(small)
+        got = tc.count(G, tuning=t).T if path == "cover" else int(tc.count_edge_baseline(G, tuning=t).item())
+        assert got == T
+
+
+def test_two_level_tables(tc):
+    """Probe sets too large for an LDS bitmap or hash table take the
+    two-level table (block bits in LDS, member words in global memory): a
+    root adjacent to 2M vertices, two vertices B and C two levels down, B
+    with 20000 up-neighbours spread over that level, C adjacent to B and to
+    1000 of them (the cover edge (B, C) makes B the anchor of a two-level
+    table), random edges inside the level, ids permuted (the comparator's
+    root keeps a forward list over the whole id range).  T and |H| equal
+    the oracle's on both paths and the statistics show two-level probes."""
+    rng = np.random.default_rng(42)
+    M = 2_000_000
+    n = M + 3
+    root, B, C = 0, M + 1, M + 2
+    lvl1 = np.arange(1, M + 1)
+    bn = rng.choice(lvl1, size=20_000, replace=False)
+    ea = rng.choice(lvl1, size=300_000)
+    eb = rng.choice(lvl1, size=300_000)
+    src = np.concatenate([np.full(M, root), np.full(bn.size, B), ea, bn[:5000], [B], np.full(1000, C)])
+    dst = np.concatenate([lvl1, bn, eb, bn[5000:10000], [C], bn[10000:11000]])
+    perm = rng.permutation(n)
+    z = int(np.flatnonzero(perm == 0)[0])
+    perm[z], perm[root] = perm[root], 0  # the root takes id 0: its forward list spans every id
+    g = graphgen.Graph(n, perm[src].astype(np.int32), perm[dst].astype(np.int32))
+    say("[two-level] hub graph")
+    c = oracle.from_graph(g)
+    lv = oracle.bfs_levels(c)
+    T = oracle.count(c, lv.levels).triangles
+    h = len(oracle.cover_edges(c, lv.levels)[0])
+    say(f"[two-level] oracle T={T} |H|={h}")
+    G = to_gpu(tc, g)
+    ws = tc.Workspace()
+    r = tc.count(G, ws=ws)
+    st = tc.read_stats(ws)
+    say(f"[two-level] cover stats {st}")
+    assert (r.T, r.h) == (T, h)
+    wb = tc.Workspace()
+    Tb = int(tc.count_edge_baseline(G, ws=wb).item())
+    stb = tc.read_stats(wb)
+    say(f"[two-level] comparator stats {stb}")
+    assert Tb == T
+    assert st["twolevel_elems"] > 0 and stb["twolevel_elems"] > 0
