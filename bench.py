@@ -367,6 +367,7 @@ def bench_batch(args):
 
 def bench_serving(args):
     """Poisson request stream over a pool of R-MAT and Chung-Lu graphs."""
+    import numpy as np
     import torch
     import graphgen
     from paper_2210_00389_amd import serve
@@ -387,6 +388,27 @@ def bench_serving(args):
     # rate would strand each rate's workspaces in the caching allocator,
     # which reuses a freed block only on the stream that allocated it)
     ex = serve.GpuExecutor(pool, args.slots)
+    # every pool graph counted alone (median of 3 device times, the path
+    # tc_count picks): the offered load of a rate is rate x the mean of these
+    # over its requests, in GPU-seconds per second
+    import paper_2210_00389_amd as tc
+    alone_ms = {}
+    wsa = tc.Workspace(torch.device("cuda"))
+    for gid, (off, cols) in pool.items():
+        G = tc.Graph(sizes[gid][0], off.to("cuda"), cols.to("cuda"))
+        ts = []
+        for _ in range(4):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            tc.count(G, ws=wsa)
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        alone_ms[gid] = statistics.median(ts[1:])
+        del G
+    del wsa
+    torch.cuda.empty_cache()
+    log(f"[bench] pool counted alone: {sum(alone_ms.values()):.1f} ms in all")
     # the oracle's stored answers for the default pool (tests/golden/serving_pool.json)
     gold = None
     gpath = os.path.join(ROOT, "tests", "golden", "serving_pool.json")
@@ -404,12 +426,13 @@ def bench_serving(args):
                           batch_max=args.batch_max).run(reqs)
         torch.cuda.synchronize()
         st["rate_req_s"] = rate
+        st["offered_load"] = rate * float(np.mean([alone_ms[r.graph_id] for r in reqs])) / 1000.0
         if gold is not None:
             bad = [r.rid for r in reqs if (r.triangles, r.h) != gold[r.graph_id]]
             checked += len(reqs)
             mismatched += len(bad)
             st["golden_mismatches"] = len(bad)
-        log(f"[bench] rate {rate}: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms "
+        log(f"[bench] rate {rate}: offered load {st['offered_load']:.2f} p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms "
             f"edges/s {st['edges_per_s']:.3e} busy {st['busy_fraction']:.2f} batched {st['batched']} "
             f"jobs {st['jobs']} failed {st['failed']}")
         runs.append(st)
@@ -429,6 +452,8 @@ def bench_serving(args):
         "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"], "runs": runs,
         "golden": ({"requests_checked": checked, "mismatches": mismatched, "all_match": mismatched == 0
                     and all(r["failed"] == 0 for r in runs)} if gold is not None else None),
+        "pool_alone_ms": {"sum": sum(alone_ms.values()), "mean_per_graph": float(np.mean(list(alone_ms.values()))),
+                          "max": max(alone_ms.values())},
         "uploads": ex.uploads,
     }
 
