@@ -35,6 +35,7 @@ constexpr int kBigCap = 1024;    // LDS list of such vertices per pass (overflow
 constexpr int kRowLoads = 8;     // row entries a thread loads at once in the level passes
 constexpr int kBitmapWords = TC_BATCH_MAX_N / 32;
 constexpr int kPieceMin = 1024;  // smallest piece size accepted (sizes the piece slots)
+constexpr int kSmallPieceMin = 64;  // the same for the one-graph path of tc_count
 constexpr int kClaim = 2;        // pieces a block claims at once
 
 // Piece slots of graph g start at row_offsets[vbase[g]] / piece + g, parity
@@ -460,12 +461,12 @@ struct BatchPlan {
   size_t bytes;
 };
 
-BatchPlan plan_batch(void* base, int64_t total_n, int64_t total_nnz, int32_t G) {
+BatchPlan plan_batch(void* base, int64_t total_n, int64_t total_nnz, int32_t G, int piece_min = kPieceMin) {
   BatchPlan p;
   Carver c(base);
   p.ctr = c.take<unsigned long long>(4);
   p.parity = c.take<uint32_t>(total_n / 32 + G + 2);
-  p.nslots_cap = total_nnz / kPieceMin + G + 2;
+  p.nslots_cap = total_nnz / piece_min + G + 2;
   p.pieces = c.take<int4>(p.nslots_cap);
   p.bytes = c.used();
   return p;
@@ -485,12 +486,12 @@ int launch_count(const tc_batch* b, const BatchPlan& p, int64_t nslots, int bloc
 
 }  // namespace
 
-size_t batch_ws_bytes(int64_t total_n, int64_t total_nnz, int32_t num_graphs) {
-  return plan_batch(nullptr, total_n, total_nnz, num_graphs).bytes;
+size_t batch_ws_bytes(int64_t total_n, int64_t total_nnz, int32_t num_graphs, int piece_min) {
+  return plan_batch(nullptr, total_n, total_nnz, num_graphs, piece_min).bytes;
 }
 
 int batch_run(const tc_batch* b, const tc_tuning* t, uint32_t flags, int64_t* triangles, int64_t* h_count,
-              int32_t* levels, void* ws, size_t ws_bytes, hipStream_t s, int32_t root0) {
+              int32_t* levels, void* ws, size_t ws_bytes, hipStream_t s, int32_t root0, int piece_min) {
   const int G = b->num_graphs;
   if (G == 0) return TC_OK;
   if (flags & TC_VALIDATE) TC_TRY(validate_batch_run(b, ws, s));
@@ -502,11 +503,11 @@ int batch_run(const tc_batch* b, const tc_tuning* t, uint32_t flags, int64_t* tr
   }
   if (threads != 256 && threads != 512)
     return fail(TC_ERR_INVALID_ARG, "tc_count_batch: batch_block must be 256 or 512 (got %d)", threads);
-  if (piece < kPieceMin) return fail(TC_ERR_INVALID_ARG, "tc_count_batch: batch_piece must be >= %d", kPieceMin);
+  if (piece < piece_min) return fail(TC_ERR_INVALID_ARG, "tc_count_batch: batch_piece must be >= %d", piece_min);
   // LDS per block: one bitmap per wave of 8 KB, plus staging
   const int max_bpc = threads == 256 ? 4 : 2;  // blocks that fit a CU's LDS
   if (bpc <= 0 || bpc > max_bpc) bpc = max_bpc;
-  BatchPlan p = plan_batch(ws, b->total_vertices, b->total_nnz, G);
+  BatchPlan p = plan_batch(ws, b->total_vertices, b->total_nnz, G, piece_min);
   if (ws_bytes < p.bytes) return fail(TC_ERR_WORKSPACE, "tc_count_batch: workspace %zu < %zu", ws_bytes, p.bytes);
   const int64_t nslots = b->total_nnz / piece + G + 2;
   prof_stage("batch_bfs");
@@ -551,7 +552,7 @@ SmallPlan plan_small(void* base, int64_t n, int64_t nnz) {
   p.vbase = c.take<int64_t>(2);
   p.h = c.take<int64_t>(1);
   p.batch = c.take<char>(0);
-  p.bytes = c.used() + batch_ws_bytes(n, nnz, 1);
+  p.bytes = c.used() + batch_ws_bytes(n, nnz, 1, kSmallPieceMin);
   return p;
 }
 
@@ -579,12 +580,13 @@ int small_count_run(const tc_csr* g, int64_t root, int64_t* triangles, int64_t* 
   b.row_offsets = g->row_offsets;
   b.cols = g->cols;
   b.max_graph_vertices = static_cast<int32_t>(g->n);
-  // pieces of about a quarter of a block's share, so the CUs all get work
+  // pieces of about a quarter of a block's share of the CSR entries (at
+  // least kSmallPieceMin), so that a small graph still spreads over the CUs
   tc_tuning t{};
   const int64_t share = g->nnz / (4 * static_cast<int64_t>(num_cus()));
-  t.batch_piece = static_cast<int32_t>(share < kPieceMin ? kPieceMin : (share > 16384 ? 16384 : share));
+  t.batch_piece = static_cast<int32_t>(share < kSmallPieceMin ? kSmallPieceMin : (share > 16384 ? 16384 : share));
   TC_TRY(batch_run(&b, &t, 0, triangles, H, levels, p.batch, p.bytes - (p.batch - static_cast<char*>(ws)), s,
-                   static_cast<int32_t>(root)));
+                   static_cast<int32_t>(root), kSmallPieceMin));
   small_stats_kernel<<<1, 1, 0, s>>>(p.stats, g->n, g->nnz, H);
   TC_HIP(hipGetLastError());
   return TC_OK;

@@ -193,11 +193,13 @@ int validate_run(const tc_csr* g, void* ws, hipStream_t s);
 int validate_batch_run(const tc_batch* b, void* ws, hipStream_t s);
 
 // ------------------------------------------------------------ batch
-size_t batch_ws_bytes(int64_t total_n, int64_t total_nnz, int32_t num_graphs);
+// piece_min: the smallest work piece (CSR entries) the call may use; it
+// sizes the piece slots of the workspace.
+size_t batch_ws_bytes(int64_t total_n, int64_t total_nnz, int32_t num_graphs, int piece_min = 1024);
 // root0 >= 0 replaces the default root of graph 0 (batches pass -1).
 int batch_run(const tc_batch* b, const tc_tuning* t, uint32_t flags, int64_t* triangles,
               int64_t* h_count, int32_t* levels, void* ws, size_t ws_bytes, hipStream_t s,
-              int32_t root0 = -1);
+              int32_t root0 = -1, int piece_min = 1024);
 
 // One graph of at most TC_BATCH_MAX_N vertices counted by the batched
 // kernels (one workgroup levels it in LDS, no host synchronisation): T,

@@ -24,6 +24,10 @@ import torch
 from .api import Graph, TcError, Workspace, count, count_edge_baseline
 
 SPACE = {
+    # which path: the one-workgroup path for graphs within 65536 vertices
+    # never, or whatever their entry count (no effect on larger graphs)
+    "small_max_n": [-1],
+    "small_max_nnz": [2**31 - 1],
     "item_log2": [16, 17, 18, 19, 20, 21],
     "light_max": [16, 24, 32],
     "dn_light": [8, 16, 32, 64],
@@ -33,8 +37,8 @@ SPACE = {
     "bins_mode": [1, 2],
     "twolevel_sparsity": [-1, 16, 256],
 }
-# the comparator has no down class
-EDGE_SPACE = {k: v for k, v in SPACE.items() if k != "dn_light"}
+# the comparator has no down class and no one-workgroup path
+EDGE_SPACE = {k: v for k, v in SPACE.items() if k not in ("dn_light", "small_max_n", "small_max_nnz")}
 # a shorter search for graphs whose calls take long (the benchmark's
 # comparator at R-MAT scale 24): the knobs that moved it in measurements
 EDGE_SPACE_SHORT = {"item_log2": [16, 17, 18], "bitmap_desc_words": [32], "bins_mode": [1],
