@@ -576,7 +576,8 @@ def theoretical_waves_per_simd(vgpr, agpr, lds, wg):
 
 def summarize_counters(args):
     """Per-kernel figures of one count call (the last of the pmc program's
-    calls: dispatches from a root_key_kernel to the next stats_kernel) from
+    calls: dispatches from the last --call-start kernel, root_key_kernel by
+    default, to the next stats_kernel) from
     rocprofv3 --pmc runs (any of TCC_EA0_RDREQ_DRAM_32B,
     TCC_EA0_WRREQ_WRITE_DRAM_32B, TCC_HIT, TCC_MISS, FETCH_SIZE, WRITE_SIZE,
     MeanOccupancyPerCU) and a --kernel-trace run (durations, registers, LDS,
@@ -598,7 +599,7 @@ def summarize_counters(args):
 
     def last_call(nm):
         ids = sorted(nm)
-        starts = [k for k in ids if nm[k].startswith("root_key_kernel")]
+        starts = [k for k in ids if nm[k].startswith(args.call_start)]
         if not starts:
             return ids
         a = starts[-1]
@@ -690,22 +691,37 @@ def summarize_counters(args):
               "| kernel | dispatches | ms | DRAM read GB | DRAM write GB | GB/s | L2 hit | VGPR | LDS B | WG | "
               "theo. waves/SIMD | achieved waves/SIMD |",
               "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    has_dram = "TCC_EA0_RDREQ_DRAM_32B" in counters
     for kn, t in sorted(table.items(), key=lambda kv: -kv[1].get("ms", 0.0)):
         if tot_ms and t.get("ms", 0.0) < 0.003 * tot_ms:
             continue
         b = t.get("dram_read", 0.0) + t.get("dram_write", 0.0)
+        rd = t.get("dram_read", 0.0) / 1e9 if has_dram else None
+        wr = t.get("dram_write", 0.0) / 1e9 if has_dram else None
         out_md.append(
-            f"| {kn} | {int(t.get('n', 0))} | {t.get('ms', 0.0):.3f} | {t.get('dram_read', 0.0)/1e9:.3f} | "
-            f"{t.get('dram_write', 0.0)/1e9:.3f} | {fmt(b / (t['ms'] / 1e3) / 1e9 if t.get('ms') else None, '{:.0f}')} | "
+            f"| {kn} | {int(t.get('n', 0))} | {t.get('ms', 0.0):.3f} | {fmt(rd, '{:.3f}')} | "
+            f"{fmt(wr, '{:.3f}')} | {fmt(b / (t['ms'] / 1e3) / 1e9 if t.get('ms') and has_dram else None, '{:.0f}')} | "
             f"{fmt(t.get('l2_hit_frac'), '{:.2f}')} | {fmt(t.get('vgpr'), '{:.0f}')} | {fmt(t.get('lds'), '{:.0f}')} | "
             f"{fmt(t.get('wg'), '{:.0f}')} | {fmt(t.get('theo_waves_simd'), '{:.2f}')}"
             f"{' (' + t['theo_limit'] + ')' if t.get('theo_limit') else ''} | "
             f"{fmt(t.get('achieved_waves_simd'), '{:.2f}')} |")
-    if tot_ms:
+    if tot_ms and not has_dram:
+        out_md += ["", f"All kernels of the call: {tot_ms:.2f} ms of kernel time (no counters taken).", ""]
+    if tot_ms and has_dram:
         out_md += ["", f"All kernels of the call: {tot_ms:.2f} ms of kernel time, {tot_b/1e9:.1f} GB of DRAM "
                        f"requests: {tot_b / (tot_ms / 1e3) / 1e9:.0f} GB/s time-weighted "
                        f"({tot_b / (tot_ms / 1e3) / 1e9 / HBM_PEAK_GBS:.2f} of 8 TB/s).", ""]
-    if heavy.get("ms"):
+    stats = _csv_rows(args.trace_dir, "kernel_stats.csv") if args.trace_dir else []
+    if stats:
+        stats.sort(key=lambda r: -float(r["TotalDurationNs"]))
+        out_md += ["Top kernels of the whole traced run (rocprofv3 --kernel-trace --stats; every call of the "
+                   "program, warm-up included):", "",
+                   "| kernel | calls | total ms | average us | share |", "|---|---|---|---|---|"]
+        for r in stats[:14]:
+            out_md.append(f"| {r['Name'][:60]} | {r['Calls']} | {float(r['TotalDurationNs'])/1e6:.3f} | "
+                          f"{float(r['AverageNs'])/1e3:.1f} | {float(r['Percentage']):.1f}% |")
+        out_md.append("")
+    if heavy.get("ms") and has_dram:
         out_md += [f"Heavy stage (heavy_kernel, {int(heavy.get('n', 0))} dispatches): {heavy['ms']:.3f} ms, "
                    f"DRAM traffic {rec['heavy']['traffic_bytes'] / 1e9 if rec['heavy']['traffic_bytes'] else 0:.2f} GB "
                    f"per call (source sha256 {rec['heavy']['source_sha256'][:16]}).", ""]
@@ -974,6 +990,8 @@ def main():
                     help="per-kernel DRAM traffic, L2 hits and occupancy of one count call from rocprofv3 runs")
     ap.add_argument("--trace-dir", default=None)
     ap.add_argument("--pmc-dir", action="append", default=None, help="a rocprofv3 --pmc output folder (repeatable)")
+    ap.add_argument("--call-start", default="root_key_kernel",
+                    help="summaries: the first kernel of a call (forward_meta_kernel for the comparator)")
     ap.add_argument("--out", default=None)
     ap.add_argument("--title", default="rocprofv3 summary")
     ap.add_argument("--cmd", default="")
