@@ -599,6 +599,8 @@ def summarize_counters(args):
 
     def last_call(nm):
         ids = sorted(nm)
+        if args.whole_run:
+            return ids
         starts = [k for k in ids if nm[k].startswith(args.call_start)]
         if not starts:
             return ids
@@ -680,7 +682,8 @@ def summarize_counters(args):
     def fmt(v, f):
         return "" if v is None else f.format(v)
     out_md = [f"# {args.title}", "", "Command:", "", "```", args.cmd, "```", "",
-              "Every kernel of one count call (the last of the program's calls), one row per kernel name. "
+              ("Every kernel of the traced run (all its calls), one row per kernel name. " if args.whole_run else
+               "Every kernel of one count call (the last of the program's calls), one row per kernel name. ") +
               "DRAM bytes: 32 x TCC_EA0_RDREQ_DRAM_32B (reads) and 32 x TCC_EA0_WRREQ_WRITE_DRAM_32B (writes), "
               "each scaled by its reading for a plain 1 GiB device copy "
               + ", ".join(f"{c}: factor {v['factor']:.3f}" for c, v in calib.items()) + ". "
@@ -706,7 +709,8 @@ def summarize_counters(args):
             f"{' (' + t['theo_limit'] + ')' if t.get('theo_limit') else ''} | "
             f"{fmt(t.get('achieved_waves_simd'), '{:.2f}')} |")
     if tot_ms and not has_dram:
-        out_md += ["", f"All kernels of the call: {tot_ms:.2f} ms of kernel time (no counters taken).", ""]
+        out_md += ["", f"All kernels {'of the run' if args.whole_run else 'of the call'}: {tot_ms:.2f} ms of "
+                       f"kernel time (no counters taken).", ""]
     if tot_ms and has_dram:
         out_md += ["", f"All kernels of the call: {tot_ms:.2f} ms of kernel time, {tot_b/1e9:.1f} GB of DRAM "
                        f"requests: {tot_b / (tot_ms / 1e3) / 1e9:.0f} GB/s time-weighted "
@@ -990,6 +994,7 @@ def main():
                     help="per-kernel DRAM traffic, L2 hits and occupancy of one count call from rocprofv3 runs")
     ap.add_argument("--trace-dir", default=None)
     ap.add_argument("--pmc-dir", action="append", default=None, help="a rocprofv3 --pmc output folder (repeatable)")
+    ap.add_argument("--whole-run", action="store_true", help="summaries: every dispatch of the run, not one call")
     ap.add_argument("--call-start", default="root_key_kernel",
                     help="summaries: the first kernel of a call (forward_meta_kernel for the comparator)")
     ap.add_argument("--out", default=None)
