@@ -72,13 +72,14 @@ def stage_bytes(name, st, n, nnz, cover):
     if name == "forward_lists":
         return 8 * (n + 1) + 4 * nnz + 4 * nnz + 32 * n
     if name == "plan":
-        # vertex records + descriptor counts + plan bytes + scan
-        return 32 * n + 4 * n + n + 12 * n
+        # vertex records + descriptor counts + plan bytes + scan + the 16-byte
+        # records the resolution reads of neighbours
+        return 32 * n + 4 * n + n + 12 * n + 16 * n
     if name == "resolve":
-        # per descriptor: its column entry + the other endpoint's record;
-        # light merges; records written; items written, read and regrouped
+        # per descriptor: its column entry + the other endpoint's 16-byte
+        # record; light merges; records written; items written, read and regrouped
         d = st.get("descriptors", 0)
-        return 36 * d + 4 * st["light_elems"] + 16 * st["heavy_desc"] + 48 * st["heavy_items"]
+        return 20 * d + 4 * st["light_elems"] + 16 * st["heavy_desc"] + 48 * st["heavy_items"]
     if name == "heavy":
         # streamed list elements + records + probe-set inserts + items
         return 4 * st["heavy_elems"] + 16 * st["heavy_desc"] + 4 * st["heavy_builds"] + 16 * st["heavy_items"]

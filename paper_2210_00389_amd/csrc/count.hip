@@ -220,12 +220,42 @@ __device__ __forceinline__ void probe_window(const int32_t* lc, const VMeta& m, 
 }
 
 
+// The fields of a vertex record that the resolution reads of a neighbour
+// (begin, up, hfb, sfe) in one 16-byte word, so that the random read of a
+// neighbour's record is one request instead of two:
+//   x = begin bits 0..31, y = begin bits 32..39 | up << 8, z = hfb, w = sfe.
+// A record whose begin needs more than 40 bits or whose up is 2^24 - 1 or
+// more gets y = kPmFull: the reader then takes the full record.
+constexpr uint32_t kPmFull = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint4 pack_record(const VMeta& m) {
+  const uint64_t b = static_cast<uint64_t>(m.begin);
+  if ((b >> 40) != 0 || m.up >= 0xFFFFFF) return make_uint4(0u, kPmFull, 0u, 0u);
+  return make_uint4(static_cast<uint32_t>(b), static_cast<uint32_t>(b >> 32) | (static_cast<uint32_t>(m.up) << 8),
+                    static_cast<uint32_t>(m.hfb), static_cast<uint32_t>(m.sfe));
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // loaded whole, in one instruction
+
+// Record of vertex v for the resolution from its packed word q = pm[v]
+// (deg is not filled in).
+__device__ __forceinline__ VMeta unpack_record(u32x4 q, const VMeta* meta, int32_t v) {
+  VMeta m;
+  m.begin = static_cast<int64_t>(q.x | (static_cast<uint64_t>(q.y & 0xFFu) << 32));
+  m.up = static_cast<int32_t>(q.y >> 8);
+  m.hfb = static_cast<int32_t>(q.z);
+  m.sfe = static_cast<int32_t>(q.w);
+  m.deg = 0;
+  if (q.y == kPmFull) m = meta[v];
+  return m;
+}
+
 // ------------------------------------------------------------ planning
 // One thread per vertex: descriptor count, |Hfwd| (for |H|), and for heavy
 // anchors the table bin.
 template <bool kCover>
 __global__ __launch_bounds__(kThreads) void plan_kernel(const int32_t* lc, const VMeta* meta, int64_t n,
-                                                        int32_t* ndesc, uint8_t* vinfo,
+                                                        int32_t* ndesc, uint8_t* vinfo, uint4* pm,
                                                         unsigned long long* acc, CountParams prm) {
   __shared__ int64_t sh[kThreads / kWave + 1];
   int64_t h = 0;
@@ -249,6 +279,7 @@ __global__ __launch_bounds__(kThreads) void plan_kernel(const int32_t* lc, const
     }
     ndesc[x] = D;
     vinfo[x] = vi;
+    pm[x] = pack_record(m);
   }
   block_acc(acc, kAccH, h, sh);
 }
@@ -280,37 +311,36 @@ enum DescKind { kDown = 0, kFwd = 1, kBwd = 2, kNone = 3 };
 // id, its record, the search of x in Hfwd(u)) are in flight together.
 template <bool kCover>
 __device__ __forceinline__ void describe_all(const int32_t* lc, const int32_t* samp, const VMeta* meta,
-                                             const int32_t* x, const VMeta* mx, const int* kin, Task* ta, Task* tb) {
+                                             const uint4* pm, const int32_t* x, const VMeta* mx, const int* kin,
+                                             Task* ta, Task* tb) {
   int kind[kResPer], k[kResPer];
   int32_t nb[kResPer];
+  int64_t pos[kResPer];
+  // positions first, without branches, so that the column loads of all
+  // descriptors are in flight together (an idle slot reads column 0)
 #pragma unroll
   for (int j = 0; j < kResPer; ++j) {
     ta[j] = Task{0, 0, 0};
     tb[j] = Task{0, 0, 0};
-    kind[j] = kNone;
-    k[j] = kin[j];
-    if (k[j] < 0) continue;
     const int hf = mx[j].sfe - mx[j].hfb;
     const int nB = (kCover && hf > 0) ? mx[j].deg - mx[j].sfe : 0;
-    int64_t pos;
-    if (k[j] < nB) {
-      kind[j] = kDown;
-      pos = mx[j].begin + mx[j].sfe + k[j];
-    } else if (k[j] - nB < hf) {
-      kind[j] = kFwd;
-      k[j] -= nB;
-      pos = mx[j].begin + mx[j].hfb + k[j];
-    } else {
-      kind[j] = kBwd;
-      k[j] -= nB + hf;
-      pos = mx[j].begin + mx[j].up + k[j];
-    }
-    nb[j] = lc[pos];
+    const int kk = kin[j];
+    const bool dn = kk < nB, fw = !dn && kk - nB < hf;
+    kind[j] = kk < 0 ? kNone : (dn ? kDown : (fw ? kFwd : kBwd));
+    k[j] = dn ? kk : (fw ? kk - nB : kk - nB - hf);
+    const int32_t seg = dn ? mx[j].sfe : (fw ? mx[j].hfb : mx[j].up);
+    pos[j] = kk < 0 ? 0 : mx[j].begin + seg + k[j];
   }
+#pragma unroll
+  for (int j = 0; j < kResPer; ++j) nb[j] = lc[pos[j]];
+  // the neighbours' packed records, all loads issued before any is used
+  u32x4 q[kResPer];
+#pragma unroll
+  for (int j = 0; j < kResPer; ++j) q[j] = *reinterpret_cast<const u32x4*>(pm + (kind[j] != kNone ? nb[j] : 0));
   VMeta mo[kResPer];
 #pragma unroll
   for (int j = 0; j < kResPer; ++j)
-    if (kind[j] != kNone) mo[j] = meta[nb[j]];
+    if (kind[j] != kNone) mo[j] = unpack_record(q[j], meta, nb[j]);
   // backward same class needs a = |Hfwd(u) ∩ (x, inf)|: joint lower bound
   int64_t lo[kResPer], hi[kResPer];
   bool srch[kResPer];
@@ -490,9 +520,9 @@ __global__ void chunk_start_kernel(const int64_t* so, int64_t n, int32_t* cx0) {
 // descriptor order (j-major).
 template <bool kCover>
 __global__ __launch_bounds__(kResThreads) void resolve_kernel(
-    const int32_t* lc, const int32_t* samp, const VMeta* meta, const uint8_t* vinfo, const int64_t* so,
-    const int32_t* cx0, int64_t n, int64_t* sbeg, int32_t* slen, int32_t* soth, int32_t* sx, int4* items_raw,
-    int4* ccnt, int item_log2) {
+    const int32_t* lc, const int32_t* samp, const VMeta* meta, const uint4* pm, const uint8_t* vinfo,
+    const int64_t* so, const int32_t* cx0, int64_t n, int64_t* sbeg, int32_t* slen, int32_t* soth, int32_t* sx,
+    int4* items_raw, int4* ccnt, int item_log2) {
   __shared__ int64_t sh[kResThreads / kWave + 1];
   __shared__ int64_t s_so[kResSpan];
   __shared__ int32_t s_x[kResRecs];
@@ -538,14 +568,16 @@ __global__ __launch_bounds__(kResThreads) void resolve_kernel(
       kk[j] = static_cast<int>(d - xb);
     }
     VMeta mx[kResPer];
+    uint8_t vi[kResPer];
 #pragma unroll
-    for (int j = 0; j < kResPer; ++j) {
-      if (kk[j] < 0) continue;
+    for (int j = 0; j < kResPer; ++j) {  // loads of all slots together (an idle slot reads vertex 0's)
       mx[j] = meta[xi[j]];
-      heavy[j] = (vinfo[xi[j]] & kViHeavy) != 0;
+      vi[j] = vinfo[xi[j]];
     }
+#pragma unroll
+    for (int j = 0; j < kResPer; ++j) heavy[j] = kk[j] >= 0 && (vi[j] & kViHeavy) != 0;
     Task ta[kResPer], tb[kResPer];
-    describe_all<kCover>(lc, samp, meta, xi, mx, kk, ta, tb);
+    describe_all<kCover>(lc, samp, meta, pm, xi, mx, kk, ta, tb);
     // ---- counts: light tasks, heavy records, heavy elements (per j, j-major)
     int64_t nl = 0, nh = 0;
     int64_t he[kResPer];
@@ -864,14 +896,18 @@ __device__ __forceinline__ uint32_t probe(const ProbeSet& ps, int32_t t, bool up
 constexpr int kChunk = 8;
 constexpr int kWinIters = 8;  // chunk rounds of the block per window
 constexpr int kClaim = 4;     // work items a block claims at once
+// Chunk slots per lane whose loads are in flight together: two where the
+// registers allow (the 128 KB bin and row search, whose blocks are limited
+// by LDS or run four waves per SIMD), one in the small-table bins compiled
+// for six waves per SIMD (a second slot spills there).
+template <int WORDS>
+constexpr int ahead_of() { return (WORDS == kBinWords2 || WORDS == 0) ? 2 : 1; }
 static_assert(kChunk <= kColPad, "chunk tail must stay inside the padded columns");
 
+// Hits of one chunk whose entries v (len of them valid) are loaded.
 template <int MODE, int kOut>
-__device__ __forceinline__ uint32_t chunk_hits(const int32_t* p, int len, const ProbeSet& ps, bool up_side,
-                                               int32_t x, int32_t oth, const Out& o, int64_t ebase, int* s_pos) {
-  int32_t v[kChunk];
-#pragma unroll
-  for (int q = 0; q < kChunk; ++q) v[q] = p[q];
+__device__ __forceinline__ uint32_t chunk_probe(const int32_t (&v)[kChunk], int len, const ProbeSet& ps, bool up_side,
+                                                int32_t x, int32_t oth, const Out& o, int64_t ebase, int* s_pos) {
   const uint32_t lenmask = len >= kChunk ? ((1u << kChunk) - 1u) : ((1u << len) - 1u);
   uint32_t hits = 0;
   if (MODE == kHash) {
@@ -930,13 +966,22 @@ __device__ __forceinline__ uint32_t chunk_hits(const int32_t* p, int len, const 
   return static_cast<uint32_t>(__popc(hits));
 }
 
+template <int MODE, int kOut>
+__device__ __forceinline__ uint32_t chunk_hits(const int32_t* p, int len, const ProbeSet& ps, bool up_side,
+                                               int32_t x, int32_t oth, const Out& o, int64_t ebase, int* s_pos) {
+  int32_t v[kChunk];
+#pragma unroll
+  for (int q = 0; q < kChunk; ++q) v[q] = p[q];
+  return chunk_probe<MODE, kOut>(v, len, ps, up_side, x, oth, o, ebase, s_pos);
+}
+
 // All chunks of one batch of streams.  The chunk space [0, C) is walked in
 // windows of THREADS * kWinIters chunks; a window is split into tiles of 64
 // chunks, one per wave and round, and for each tile the block first records
 // the number of streams that start before it (s_tb) and a 64-bit mask of the
 // streams that start inside it (s_M).  Lane i of a wave then finds the
 // stream of its chunk as s_tb + popcount(mask bits <= i) - 1, with no search.
-template <int MODE, int THREADS, int kOut>
+template <int MODE, int THREADS, int kOut, int kAhead>
 __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_cl, const int64_t* s_beg,
                                                const int32_t* s_oth, const uint8_t* s_up, uint64_t* s_M,
                                                int32_t* s_tb, const int32_t* lc, const ProbeSet& ps, int32_t x,
@@ -968,13 +1013,72 @@ __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_
       }
     }
     __syncthreads();
+    if (kOut != kOutEmit && kAhead == 1) {
 #pragma unroll 2
-    for (int i = 0; i < kWinIters; ++i) {
-      const int rel = i * THREADS + tid;
-      const int c = w0 + rel;
-      if (kOut == kOutEmit) {
-        // the whole wave takes part (the writes are placed by a wave scan);
-        // lanes past the end probe nothing
+      for (int i = 0; i < kWinIters; ++i) {
+        const int rel = i * THREADS + tid;
+        const int c = w0 + rel;
+        if (c < C) {
+          const int t = rel >> 6;
+          const uint64_t M = s_M[t];
+          const int below = static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+              static_cast<uint32_t>(M >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(M), 0u)));
+          const int j = s_tb[t] + below + static_cast<int>((M >> ln) & 1ull) - 1;
+          const int2 cl = s_cl[j];
+          const int k = c - cl.x;
+          const int32_t* p = lc + s_beg[j] + static_cast<int64_t>(k) * kChunk;
+          cnt += chunk_hits<MODE, kOut>(p, cl.y - k * kChunk, ps, MODE == kSearch && s_up[j] != 0, x,
+                                        needs_oth(kOut) ? s_oth[j] : 0, o, ebase, s_pos);
+        }
+      }
+    } else if (kOut != kOutEmit) {
+      // kAhead chunk slots per lane at a time: every slot's loads are issued
+      // before any is probed (a slot past the end reads entry 0 and probes
+      // nothing), so a wave keeps kAhead chunks of memory reads in flight
+      for (int i = 0; i < kWinIters; i += kAhead) {
+        if (w0 + i * THREADS >= C) break;  // the block's remaining slots are all past the end
+        int len[kAhead];
+        int64_t e[kAhead];
+        int32_t oth[kAhead];
+        bool up[kAhead];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+          const int rel = (i + u) * THREADS + tid;
+          const int c = w0 + rel;
+          len[u] = 0;
+          e[u] = 0;
+          oth[u] = 0;
+          up[u] = false;
+          if (c < C) {
+            const int t = rel >> 6;
+            const uint64_t M = s_M[t];
+            const int below = static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+                static_cast<uint32_t>(M >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(M), 0u)));
+            const int j = s_tb[t] + below + static_cast<int>((M >> ln) & 1ull) - 1;
+            const int2 cl = s_cl[j];
+            const int k = c - cl.x;
+            e[u] = s_beg[j] + static_cast<int64_t>(k) * kChunk;
+            len[u] = cl.y - k * kChunk;
+            if (needs_oth(kOut)) oth[u] = s_oth[j];
+            if (MODE == kSearch) up[u] = s_up[j] != 0;
+          }
+        }
+        int32_t v[kAhead][kChunk];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+#pragma unroll
+          for (int q = 0; q < kChunk; ++q) v[u][q] = lc[e[u] + q];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+          cnt += chunk_probe<MODE, kOut>(v[u], len[u], ps, up[u], x, oth[u], o, ebase, s_pos);
+      }
+    } else {
+      // writing triangles: the whole wave takes part in every round (the
+      // writes are placed by a wave scan); lanes past the end probe nothing
+#pragma unroll 2
+      for (int i = 0; i < kWinIters; ++i) {
+        const int rel = i * THREADS + tid;
+        const int c = w0 + rel;
         const int32_t* p = lc;
         int len = 0;
         int32_t ot = 0;
@@ -993,17 +1097,6 @@ __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_
           upside = MODE == kSearch && s_up[j] != 0;
         }
         cnt += chunk_hits<MODE, kOut>(p, len, ps, upside, x, ot, o, ebase, s_pos);
-      } else if (c < C) {
-        const int t = rel >> 6;
-        const uint64_t M = s_M[t];
-        const int below = static_cast<int>(__builtin_amdgcn_mbcnt_hi(
-            static_cast<uint32_t>(M >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(M), 0u)));
-        const int j = s_tb[t] + below + static_cast<int>((M >> ln) & 1ull) - 1;
-        const int2 cl = s_cl[j];
-        const int k = c - cl.x;
-        const int32_t* p = lc + s_beg[j] + static_cast<int64_t>(k) * kChunk;
-        cnt += chunk_hits<MODE, kOut>(p, cl.y - k * kChunk, ps, MODE == kSearch && s_up[j] != 0, x,
-                                      needs_oth(kOut) ? s_oth[j] : 0, o, ebase, s_pos);
       }
     }
     __syncthreads();
@@ -1192,16 +1285,16 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
       __syncthreads();
       uint32_t got;
       if (WORDS == 0) {
-        got = run_chunks<kSearch, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
+        got = run_chunks<kSearch, THREADS, kOut, ahead_of<WORDS>()>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
                                                  ebase, &s_pos);
       } else if (mode == kBitmap) {
-        got = run_chunks<kBitmap, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
+        got = run_chunks<kBitmap, THREADS, kOut, ahead_of<WORDS>()>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
                                                  ebase, &s_pos);
       } else if (WORDS == kBinWords2 && mode == kTwoLevel) {
-        got = run_chunks<kTwoLevel, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
+        got = run_chunks<kTwoLevel, THREADS, kOut, ahead_of<WORDS>()>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
                                                    ebase, &s_pos);
       } else {
-        got = run_chunks<kHash, THREADS, kOut>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
+        got = run_chunks<kHash, THREADS, kOut, ahead_of<WORDS>()>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
                                                ebase, &s_pos);
       }
       // the per-item count is kept only where it is recorded
@@ -1314,7 +1407,7 @@ int launch_all(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
   const unsigned gr = static_cast<unsigned>(w.nchunk_cap < gmax ? w.nchunk_cap : gmax);
   const int64_t gct = (w.nchunk_cap + kThreads - 1) / kThreads;
   const unsigned gc = static_cast<unsigned>(gct < gmax ? gct : gmax);
-  plan_kernel<kCover><<<gv, kThreads, 0, s>>>(a.cols, a.meta, n, w.ndesc, w.vinfo, w.acc, a.prm);
+  plan_kernel<kCover><<<gv, kThreads, 0, s>>>(a.cols, a.meta, n, w.ndesc, w.vinfo, w.pm, w.acc, a.prm);
   TC_HIP(hipGetLastError());
   twolevel_words_kernel<<<grid_for(n, kThreads * kWave, 4096), kThreads, 0, s>>>(a.cols, a.meta, w.vinfo, n,
                                                                                w.tl_words, w.tl_l1);
@@ -1329,8 +1422,8 @@ int launch_all(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
   prof_stage("resolve");
   sample_kernel<<<grid_for(a.g->nnz / kSampStride + 1, kThreads, 16384), kThreads, 0, s>>>(a.cols, a.g->nnz,
                                                                                            w.samp);
-  resolve_kernel<kCover><<<gr, kResThreads, 0, s>>>(a.cols, w.samp, a.meta, w.vinfo, w.so, w.cx0, n, w.sbeg, w.slen,
-                                                    w.soth, w.sx, w.items_raw, w.ccnt, a.prm.item_log2);
+  resolve_kernel<kCover><<<gr, kResThreads, 0, s>>>(a.cols, w.samp, a.meta, w.pm, w.vinfo, w.so, w.cx0, n, w.sbeg,
+                                                    w.slen, w.soth, w.sx, w.items_raw, w.ccnt, a.prm.item_log2);
   TC_HIP(hipGetLastError());
   {
     Carver sc(w.scratch);
@@ -1428,6 +1521,7 @@ CountWs count_reserve(Carver& c, int64_t n, int64_t nnz) {
   w.ccnt = c.take<int4>(w.nchunk_cap);
   w.lpre = c.take<int64_t>(w.nchunk_cap + 1);
   w.samp = c.take<int32_t>(nnz / kSampStride + 2);
+  w.pm = c.take<uint4>(n + 1);
   w.tl_words = c.take<uint32_t>(nnz + 1);
   w.tl_l1 = c.take<uint32_t>(nnz + 1);
   w.acc = c.take<unsigned long long>(kAccSlots);

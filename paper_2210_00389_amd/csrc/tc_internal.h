@@ -128,6 +128,7 @@ struct CountWs {
   int4* ccnt;          // per chunk: heavy records, light tasks, items
   int64_t* lpre;       // scan of the per-chunk light task counts
   int32_t* samp;       // every 32nd layout column, for the searches of the resolution
+  uint4* pm;           // per vertex: the record fields the resolution reads of a neighbour, in 16 bytes [n + 1]
   uint32_t* tl_words;  // member words of two-level anchors, at their rows' positions [nnz + 1]
   uint32_t* tl_l1;     // LDS part (block bits, prefix counts) of two-level tables, likewise [nnz + 1]
   int64_t nchunk_cap;
