@@ -845,9 +845,25 @@ __global__ void bin_offsets_kernel(unsigned long long* acc) {
 }
 
 // ------------------------------------------------------------ streaming
+// Multiplicative hash on the top bits of a 32-bit product; the id's bits
+// above 24 are folded in first so that the multiply is the full-rate 24-bit
+// one (a 32-bit integer multiply issues at a quarter of the rate).  HIP's
+// __umul24 returns int: the product is taken as unsigned before the shift,
+// so that the slot stays below 2^(32 - shift).
 __device__ __forceinline__ uint32_t hslot(int32_t key, int shift) {
-  return (static_cast<uint32_t>(key) * 0x9E3779B1u) >> shift;
+  const uint32_t k = static_cast<uint32_t>(key);
+  return static_cast<uint32_t>(__umul24(k ^ (k >> 24), 0x9E3779u)) >> shift;
 }
+
+// Hash tables (linear probing, at most half full) hold the ids in the low
+// 31 bits of a slot; kHashEmpty is no vertex id (ids are below 2^31 - 1).
+// Bit 31 of a slot says that a key whose home is this slot was placed
+// further on: a probe that finds another key in its home slot with that
+// bit clear is a miss at once, and only a flagged home is walked until the
+// key or an empty slot.  (Keys are never removed, so a key lies before the
+// first empty slot after its home.)
+constexpr uint32_t kHashEmpty = 0x7FFFFFFFu;
+constexpr uint32_t kHashMoved = 0x80000000u;
 
 enum ProbeMode { kBitmap = 0, kHash = 1, kSearch = 2, kTwoLevel = 3 };
 
@@ -881,9 +897,15 @@ __device__ __forceinline__ uint32_t probe(const ProbeSet& ps, int32_t t, bool up
     return (ps.words[r] >> (d & 31)) & 1u;
   } else if (MODE == kHash) {
     uint32_t h = hslot(t, ps.shift);
-    int32_t k;
-    while ((k = static_cast<int32_t>(ps.tab[h])) != t && k != -1) h = (h + 1) & (ps.cap - 1);
-    return k == t ? 1u : 0u;
+    const uint32_t w = ps.tab[h];
+    if ((w & kHashEmpty) == static_cast<uint32_t>(t)) return 1u;
+    if (!(w & kHashMoved)) return 0u;
+    for (;;) {
+      h = (h + 1) & (ps.cap - 1);
+      const uint32_t k = ps.tab[h] & kHashEmpty;
+      if (k == static_cast<uint32_t>(t)) return 1u;
+      if (k == kHashEmpty) return 0u;
+    }
   }
   return (up_side ? gsearch(ps.up_row, ps.up_len, t) : gsearch(ps.hf_row, ps.hf_len, t)) ? 1u : 0u;
 }
@@ -911,17 +933,18 @@ __device__ __forceinline__ uint32_t chunk_probe(const int32_t (&v)[kChunk], int 
   const uint32_t lenmask = len >= kChunk ? ((1u << kChunk) - 1u) : ((1u << len) - 1u);
   uint32_t hits = 0;
   if (MODE == kHash) {
-    // all first probes in flight together; collision chains (rare at load
-    // factor <= 1/2) are walked afterwards, one slot per round for all
+    // all first probes in flight together; the chains of flagged homes are
+    // walked afterwards, one slot per round for all
     uint32_t h[kChunk];
     uint32_t pend = 0;
 #pragma unroll
     for (int q = 0; q < kChunk; ++q) h[q] = hslot(v[q], ps.shift);
 #pragma unroll
     for (int q = 0; q < kChunk; ++q) {
-      const int32_t k = static_cast<int32_t>(ps.tab[h[q]]);
-      hits |= static_cast<uint32_t>(k == v[q]) << q;
-      pend |= static_cast<uint32_t>(k != v[q] && k != -1) << q;
+      const uint32_t w = ps.tab[h[q]];
+      const bool eq = (w & kHashEmpty) == static_cast<uint32_t>(v[q]);
+      hits |= static_cast<uint32_t>(eq) << q;
+      pend |= static_cast<uint32_t>(!eq && (w & kHashMoved) != 0) << q;
     }
     pend &= lenmask;
     while (pend) {
@@ -929,9 +952,10 @@ __device__ __forceinline__ uint32_t chunk_probe(const int32_t (&v)[kChunk], int 
       for (int q = 0; q < kChunk; ++q) {
         const uint32_t pb = (pend >> q) & 1u;
         h[q] = (h[q] + pb) & static_cast<uint32_t>(ps.cap - 1);
-        const int32_t k = static_cast<int32_t>(ps.tab[h[q]]);
-        hits |= (pb & static_cast<uint32_t>(k == v[q])) << q;
-        pend &= ~(static_cast<uint32_t>(k == v[q] || k == -1) << q);
+        const uint32_t k = ps.tab[h[q]] & kHashEmpty;
+        const bool eq = k == static_cast<uint32_t>(v[q]);
+        hits |= (pb & static_cast<uint32_t>(eq)) << q;
+        pend &= ~(static_cast<uint32_t>(eq || k == kHashEmpty) << q);
       }
     }
   } else {
@@ -1216,13 +1240,15 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
             atomicOr(&tab[d >> 5], 1u << (d & 31));
           }
         } else {
-          for (int i = tid; i < ps.cap; i += THREADS) tab[i] = 0xFFFFFFFFu;
+          for (int i = tid; i < ps.cap; i += THREADS) tab[i] = kHashEmpty;
           __syncthreads();
           for (int i = tid; i < P; i += THREADS) {
             const int32_t key = i < mx.up ? lc[mx.begin + i] : lc[mx.begin + mx.hfb + (i - mx.up)];
-            uint32_t h = hslot(key, ps.shift);
-            while (atomicCAS(&tab[h], 0xFFFFFFFFu, static_cast<uint32_t>(key)) != 0xFFFFFFFFu)
+            const uint32_t h0 = hslot(key, ps.shift);
+            uint32_t h = h0;
+            while (atomicCAS(&tab[h], kHashEmpty, static_cast<uint32_t>(key)) != kHashEmpty)
               h = (h + 1) & (ps.cap - 1);
+            if (h != h0) atomicOr(&tab[h0], kHashMoved);  // the home is occupied, so it stays a key
           }
         }
         __syncthreads();
