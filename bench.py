@@ -559,6 +559,10 @@ def _col(row, *keys):
 WAVES_PER_SIMD_MAX = 8     # gfx950: 32 waves per CU, 4 SIMDs
 VGPRS_PER_SIMD_LANE = 512  # unified architectural + accumulation registers
 LDS_PER_CU = 160 * 1024
+# rocprofv3's kernel-trace VGPR_Count on gfx950 counts register pairs: for the
+# same kernels the compiler's kernel-resource-usage report gives twice the
+# figure (32, 80 and 128 allocated registers appear as 16, 40 and 64)
+TRACE_VGPR_UNIT = 2
 
 
 def theoretical_waves_per_simd(vgpr, agpr, lds, wg):
@@ -652,7 +656,10 @@ def summarize_counters(args):
         kn = tnames[i]
         add(kn, "ms", (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
         add(kn, "n", 1)
-        res[kn] = (_col(r, "VGPR_Count", "Arch_VGPR_Count", "vgpr_count"), _col(r, "Accum_VGPR_Count", "agpr_count"),
+        vg_trace = _col(r, "VGPR_Count", "Arch_VGPR_Count", "vgpr_count")
+        ag_trace = _col(r, "Accum_VGPR_Count", "agpr_count")
+        res[kn] = (vg_trace * TRACE_VGPR_UNIT if vg_trace is not None else None,
+                   ag_trace * TRACE_VGPR_UNIT if ag_trace is not None else None,
                    _col(r, "LDS_Block_Size", "LDS_Size", "Group_Segment_Size", "lds_size"),
                    _col(r, "Workgroup_Size_X", "Workgroup_Size", "workgroup_size"))
     for kn, t in table.items():
@@ -690,7 +697,8 @@ def summarize_counters(args):
               + ", ".join(f"{c}: factor {v['factor']:.3f}" for c, v in calib.items()) + ". "
               "Requests leaving the L2 for memory include those the 256 MB Infinity Cache serves: "
               "no counter here separates them. L2 hit = TCC_HIT / (TCC_HIT + TCC_MISS). "
-              "Theoretical waves per SIMD from the kernel's registers, LDS and workgroup size "
+              "Theoretical waves per SIMD from the kernel's registers (the trace's VGPR_Count, which "
+              "counts register pairs on gfx950, times 2), LDS and workgroup size "
               "(8 at most); achieved = MeanOccupancyPerCU / 4 (time-weighted over dispatches).", "",
               "| kernel | dispatches | ms | DRAM read GB | DRAM write GB | GB/s | L2 hit | VGPR | LDS B | WG | "
               "theo. waves/SIMD | achieved waves/SIMD |",

@@ -93,11 +93,14 @@ def test_summarize_counters_synthetic(tmp_path):
     assert k["heavy_kernel[lds=131072]"]["dram_write"] == pytest.approx(500 * 32)
     assert k["heavy_kernel[lds=131072]"]["ms"] == pytest.approx(0.007)
     assert k["heavy_kernel[lds=131072]"]["l2_hit_frac"] == pytest.approx(0.75)
-    # 52 VGPRs -> 56 -> 9 waves by registers; 128 KB LDS -> 1 block of 16
-    # waves per CU -> 4 waves per SIMD
+    # a trace VGPR_Count of 52 is 104 registers (pairs on gfx950) -> 4 waves
+    # by registers; 128 KB LDS -> 1 block of 16 waves per CU -> 4 waves per
+    # SIMD too; resolve (no LDS) is limited by its registers
+    assert k["heavy_kernel[lds=131072]"]["vgpr"] == pytest.approx(104)
     assert k["heavy_kernel[lds=131072]"]["theo_waves_simd"] == pytest.approx(4.0)
     assert k["heavy_kernel[lds=131072]"]["theo_limit"] == "lds"
-    assert k["resolve_kernel"]["theo_waves_simd"] == pytest.approx(8.0)
+    assert k["resolve_kernel"]["theo_waves_simd"] == pytest.approx(4.0)
+    assert k["resolve_kernel"]["theo_limit"] == "vgpr"
     assert "__amd_rocclr_copyBuffer" not in k
     assert rec["heavy"]["traffic_bytes"] == pytest.approx(5000 * 32 * 2 + 500 * 32)
     assert len(rec["heavy"]["source_sha256"]) == 64
