@@ -935,16 +935,18 @@ __device__ __forceinline__ uint32_t chunk_probe(const int32_t (&v)[kChunk], int 
   if (MODE == kHash) {
     // all first probes in flight together; the chains of flagged homes are
     // walked afterwards, one slot per round for all
-    uint32_t h[kChunk];
+    uint32_t h[kChunk], w[kChunk];
     uint32_t pend = 0;
 #pragma unroll
     for (int q = 0; q < kChunk; ++q) h[q] = hslot(v[q], ps.shift);
+    // every home slot's read is issued before any is compared
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) w[q] = ps.tab[h[q]];
 #pragma unroll
     for (int q = 0; q < kChunk; ++q) {
-      const uint32_t w = ps.tab[h[q]];
-      const bool eq = (w & kHashEmpty) == static_cast<uint32_t>(v[q]);
+      const bool eq = (w[q] & kHashEmpty) == static_cast<uint32_t>(v[q]);
       hits |= static_cast<uint32_t>(eq) << q;
-      pend |= static_cast<uint32_t>(!eq && (w & kHashMoved) != 0) << q;
+      pend |= static_cast<uint32_t>(!eq && (w[q] & kHashMoved) != 0) << q;
     }
     pend &= lenmask;
     while (pend) {
