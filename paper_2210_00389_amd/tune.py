@@ -31,8 +31,8 @@ SPACE = {
     "item_log2": [16, 17, 18, 19, 20, 21],
     "light_max": [16, 24, 32],
     "dn_light": [8, 16, 32, 64],
-    "bitmap_member_words": [2, 4, 8],
-    "bitmap_desc_words": [8, 16, 32, 64],
+    "bitmap_member_words": [2, 4, 8, 32, 64],
+    "bitmap_desc_words": [8, 16, 32, 64, 128],
     "bin0_mode": [1, 2],
     "bins_mode": [1, 2],
     "twolevel_sparsity": [-1, 16, 256],
