@@ -928,8 +928,11 @@ static_assert(kChunk <= kColPad, "chunk tail must stay inside the padded columns
 
 // Hits of one chunk whose entries v (len of them valid) are loaded.
 template <int MODE, int kOut>
+// Called by every lane of the wave (a lane with no chunk passes len = 0);
+// wq: the wave's queue of kWave ids in LDS (hash tables, counting only).
 __device__ __forceinline__ uint32_t chunk_probe(const int32_t (&v)[kChunk], int len, const ProbeSet& ps, bool up_side,
-                                                int32_t x, int32_t oth, const Out& o, int64_t ebase, int* s_pos) {
+                                                int32_t x, int32_t oth, const Out& o, int64_t ebase, int* s_pos,
+                                                int32_t* wq) {
   const uint32_t lenmask = len >= kChunk ? ((1u << kChunk) - 1u) : ((1u << len) - 1u);
   uint32_t hits = 0;
   if (MODE == kHash) {
@@ -949,6 +952,45 @@ __device__ __forceinline__ uint32_t chunk_probe(const int32_t (&v)[kChunk], int 
       pend |= static_cast<uint32_t>(!eq && (w[q] & kHashMoved) != 0) << q;
     }
     pend &= lenmask;
+    if (kOut == kOutNone || kOut == kOutRec) {
+      // Counting only: the ids still pending in the whole wave (about 1% of
+      // them) go to the wave's queue, kWave at a time, and each lane walks
+      // at most one chain from the home slot on, instead of every lane
+      // stepping all 8 of its slots until the wave's longest walk ends.
+      const int np = __popc(pend);
+      const int incl = wave_incl_scan(np);
+      const int total = __shfl(incl, kWave - 1, kWave);
+      uint32_t walked = 0;
+      for (int base = 0; base < total; base += kWave) {  // uniform across the wave
+        int pos = incl - np - base;
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q)
+          if ((pend >> q) & 1u) {
+            if (pos >= 0 && pos < kWave) wq[pos] = v[q];
+            ++pos;
+          }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (base + lane() < total) {
+          const int32_t t = wq[lane()];
+          uint32_t hq = hslot(t, ps.shift);
+          for (;;) {
+            hq = (hq + 1) & static_cast<uint32_t>(ps.cap - 1);
+            const uint32_t k = ps.tab[hq] & kHashEmpty;
+            if (k == static_cast<uint32_t>(t)) {
+              ++walked;
+              break;
+            }
+            if (k == kHashEmpty) break;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();  // the next batch overwrites the queue
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+      return static_cast<uint32_t>(__popc(hits & lenmask)) + walked;
+    }
     while (pend) {
 #pragma unroll
       for (int q = 0; q < kChunk; ++q) {
@@ -994,11 +1036,12 @@ __device__ __forceinline__ uint32_t chunk_probe(const int32_t (&v)[kChunk], int 
 
 template <int MODE, int kOut>
 __device__ __forceinline__ uint32_t chunk_hits(const int32_t* p, int len, const ProbeSet& ps, bool up_side,
-                                               int32_t x, int32_t oth, const Out& o, int64_t ebase, int* s_pos) {
+                                               int32_t x, int32_t oth, const Out& o, int64_t ebase, int* s_pos,
+                                               int32_t* wq) {
   int32_t v[kChunk];
 #pragma unroll
   for (int q = 0; q < kChunk; ++q) v[q] = p[q];
-  return chunk_probe<MODE, kOut>(v, len, ps, up_side, x, oth, o, ebase, s_pos);
+  return chunk_probe<MODE, kOut>(v, len, ps, up_side, x, oth, o, ebase, s_pos, wq);
 }
 
 // All chunks of one batch of streams.  The chunk space [0, C) is walked in
@@ -1011,7 +1054,7 @@ template <int MODE, int THREADS, int kOut, int kAhead>
 __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_cl, const int64_t* s_beg,
                                                const int32_t* s_oth, const uint8_t* s_up, uint64_t* s_M,
                                                int32_t* s_tb, const int32_t* lc, const ProbeSet& ps, int32_t x,
-                                               const Out& o, int64_t ebase, int* s_pos) {
+                                               const Out& o, int64_t ebase, int* s_pos, int32_t* s_q) {
   constexpr int kWin = THREADS * kWinIters;
   constexpr int kTiles = kWin / kWave;
   static_assert(THREADS % kWave == 0, "block must be whole waves");
@@ -1039,11 +1082,20 @@ __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_
       }
     }
     __syncthreads();
+    int32_t* wq = s_q + (tid & ~(kWave - 1));  // this wave's queue
     if (kOut != kOutEmit && kAhead == 1) {
+      // every lane of a wave with work takes part (a lane past the end
+      // probes nothing); a wave with none skips the round
 #pragma unroll 2
       for (int i = 0; i < kWinIters; ++i) {
+        if (w0 + i * THREADS >= C) break;  // the block's remaining slots are all past the end
         const int rel = i * THREADS + tid;
         const int c = w0 + rel;
+        if (__ballot(c < C) == 0) continue;
+        const int32_t* p = lc;
+        int len = 0;
+        int32_t ot = 0;
+        bool upside = false;
         if (c < C) {
           const int t = rel >> 6;
           const uint64_t M = s_M[t];
@@ -1052,10 +1104,12 @@ __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_
           const int j = s_tb[t] + below + static_cast<int>((M >> ln) & 1ull) - 1;
           const int2 cl = s_cl[j];
           const int k = c - cl.x;
-          const int32_t* p = lc + s_beg[j] + static_cast<int64_t>(k) * kChunk;
-          cnt += chunk_hits<MODE, kOut>(p, cl.y - k * kChunk, ps, MODE == kSearch && s_up[j] != 0, x,
-                                        needs_oth(kOut) ? s_oth[j] : 0, o, ebase, s_pos);
+          p = lc + s_beg[j] + static_cast<int64_t>(k) * kChunk;
+          len = cl.y - k * kChunk;
+          if (needs_oth(kOut)) ot = s_oth[j];
+          upside = MODE == kSearch && s_up[j] != 0;
         }
+        cnt += chunk_hits<MODE, kOut>(p, len, ps, upside, x, ot, o, ebase, s_pos, wq);
       }
     } else if (kOut != kOutEmit) {
       // kAhead chunk slots per lane at a time: every slot's loads are issued
@@ -1096,7 +1150,7 @@ __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_
           for (int q = 0; q < kChunk; ++q) v[u][q] = lc[e[u] + q];
 #pragma unroll
         for (int u = 0; u < kAhead; ++u)
-          cnt += chunk_probe<MODE, kOut>(v[u], len[u], ps, up[u], x, oth[u], o, ebase, s_pos);
+          cnt += chunk_probe<MODE, kOut>(v[u], len[u], ps, up[u], x, oth[u], o, ebase, s_pos, wq);
       }
     } else {
       // writing triangles: the whole wave takes part in every round (the
@@ -1122,7 +1176,7 @@ __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_
           ot = s_oth[j];
           upside = MODE == kSearch && s_up[j] != 0;
         }
-        cnt += chunk_hits<MODE, kOut>(p, len, ps, upside, x, ot, o, ebase, s_pos);
+        cnt += chunk_hits<MODE, kOut>(p, len, ps, upside, x, ot, o, ebase, s_pos, wq);
       }
     }
     __syncthreads();
@@ -1152,6 +1206,7 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
   __shared__ uint8_t s_up[WORDS == 0 ? D : 1];
   __shared__ uint64_t s_M[kTiles];
   __shared__ int32_t s_tb[kTiles];
+  __shared__ int32_t s_q[WORDS > 0 ? THREADS : 1];  // per wave: its queue of pending hash probes
   __shared__ int64_t sh[THREADS / kWave + 1];
   __shared__ int32_t shi[THREADS / kWave + 1];
   __shared__ unsigned long long s_item;
@@ -1314,16 +1369,16 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
       uint32_t got;
       if (WORDS == 0) {
         got = run_chunks<kSearch, THREADS, kOut, ahead_of<WORDS>()>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
-                                                 ebase, &s_pos);
+                                                 ebase, &s_pos, s_q);
       } else if (mode == kBitmap) {
         got = run_chunks<kBitmap, THREADS, kOut, ahead_of<WORDS>()>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
-                                                 ebase, &s_pos);
+                                                 ebase, &s_pos, s_q);
       } else if (WORDS == kBinWords2 && mode == kTwoLevel) {
         got = run_chunks<kTwoLevel, THREADS, kOut, ahead_of<WORDS>()>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
-                                                   ebase, &s_pos);
+                                                   ebase, &s_pos, s_q);
       } else {
         got = run_chunks<kHash, THREADS, kOut, ahead_of<WORDS>()>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
-                                               ebase, &s_pos);
+                                               ebase, &s_pos, s_q);
       }
       // the per-item count is kept only where it is recorded
       if (kOut == kOutRec) icnt += got;
