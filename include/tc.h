@@ -153,7 +153,11 @@ typedef struct tc_tuning {
                                  that would fill the 128 KB hash table gets it
                                  too when its id window is at least this many
                                  times its size (default 64, -1 = never) */
-  int32_t reserved[3];
+  int32_t bin0_max_desc;      /* an anchor with more task descriptors than
+                                 this skips the smallest-table bin (its items
+                                 are streamed by one wave each there):
+                                 default 1024, -1 = no limit */
+  int32_t reserved[2];
 } tc_tuning;
 
 #define TC_SMALL_MAX_N 65536

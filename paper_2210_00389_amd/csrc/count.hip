@@ -75,16 +75,19 @@ __device__ __forceinline__ int64_t twolevel_words(int64_t R) { return 2 * (((R >
 
 enum TableKind { kKindHash = 0, kKindBitmap = 1, kKindTwoLevel = 2 };
 
-// Bin of an anchor with window R, probe-set size P, D descriptors and deg
-// row entries; *kind tells the table kind.  A two-level table's block bits
+// Bin of an anchor whose bitmap (two parts) takes `need` words, with joint
+// window R, probe-set size P, D descriptors and deg row entries; *kind
+// tells the table kind.  A two-level table's block bits
 // are also kept in global memory at the anchor's row positions (so an item
 // copies them instead of inserting |P| ids), hence they must fit in deg
 // words.
-__device__ __forceinline__ int choose_bin(int64_t R, int P, int64_t D, int64_t deg, int* kind,
+__device__ __forceinline__ int choose_bin(int64_t need, int64_t R, int P, int64_t D, int64_t deg, int* kind,
                                           const CountParams& prm) {
-  const int64_t need = bitmap_words(R);
+  // the smallest-table bin streams an item with one wave: only anchors with
+  // few tasks go there
+  const int b0 = (prm.bin0_max_desc >= 0 && D > prm.bin0_max_desc) ? 1 : 0;
   if (need <= prm.bm_member * static_cast<int64_t>(P) + 64 || need <= prm.bm_desc * D) {
-    for (int b = 0; b < 3; ++b)
+    for (int b = b0; b < 3; ++b)
       if (need <= bin_words(b)) {
         *kind = kKindBitmap;
         return b;
@@ -93,7 +96,7 @@ __device__ __forceinline__ int choose_bin(int64_t R, int P, int64_t D, int64_t d
   const int64_t tw = twolevel_words(R);
   const bool tl_fits = tw <= kBinWords2 && tw / 2 <= deg;
   *kind = kKindHash;
-  for (int b = 0; b < 3; ++b)
+  for (int b = b0; b < 3; ++b)
     if (2 * static_cast<int64_t>(P) <= bin_words(b)) {
       // a sparse set of the largest hash bin: most probes miss, and a
       // two-level table rejects them with one LDS read
@@ -118,6 +121,8 @@ constexpr int kElemChunkLog = 19;  // default: 2^19 elements per work item (targ
 // stream record flag (in the length word): probe the anchor's Up list
 constexpr int32_t kFlagUp = 1 << 29;
 constexpr int32_t kLenMask = kFlagUp - 1;
+// stream slot in LDS (s_cl.y): length | kClUp when the stream probes Up(x)
+constexpr int32_t kClUp = 1 << 30;
 // work item word: stream count | bin << 28 | kItemBitmap | kItemTwoLevel
 constexpr int32_t kItemCountMask = (1 << 28) - 1;
 constexpr int32_t kItemBitmap = 1 << 30;
@@ -219,6 +224,50 @@ __device__ __forceinline__ void probe_window(const int32_t* lc, const VMeta& m, 
   R = mx >= mn ? static_cast<int64_t>(mx) - mn + 1 : 0;
 }
 
+// A bitmap table is two bitmaps, one over the id window of Up(x) and one
+// over that of Hfwd(x), each with its always-clear bit R (a part with no
+// member is one word): a streamed list meets only one of the two segments
+// (it lies on one level), and each part's window is usually far narrower
+// than the window of both, which spans the gap between the two levels.
+struct SplitWindow {
+  int32_t lo_up, lo_hf;
+  int64_t R_up, R_hf;
+};
+
+__device__ __forceinline__ SplitWindow split_window(const int32_t* lc, const VMeta& m) {
+  SplitWindow w{0, 0, 0, 0};
+  const int hf = m.sfe - m.hfb;
+  if (m.up > 0) {
+    w.lo_up = lc[m.begin];
+    w.R_up = static_cast<int64_t>(lc[m.begin + m.up - 1]) - w.lo_up + 1;
+  }
+  if (hf > 0) {
+    w.lo_hf = lc[m.begin + m.hfb];
+    w.R_hf = static_cast<int64_t>(lc[m.begin + m.sfe - 1]) - w.lo_hf + 1;
+  }
+  return w;
+}
+
+// Words of the two bitmaps.
+__device__ __forceinline__ int64_t split_words(const SplitWindow& w) {
+  return bitmap_words(w.R_up) + bitmap_words(w.R_hf);
+}
+
+// The window of the whole probe set (for two-level tables), from its parts.
+__device__ __forceinline__ void joint_window(const SplitWindow& w, int32_t& lo, int64_t& R) {
+  int64_t mn = 0x7FFFFFFFFFFFFFFFll, mx = -1;
+  if (w.R_up > 0) {
+    mn = w.lo_up;
+    mx = w.lo_up + w.R_up - 1;
+  }
+  if (w.R_hf > 0) {
+    mn = min(mn, static_cast<int64_t>(w.lo_hf));
+    mx = max(mx, w.lo_hf + w.R_hf - 1);
+  }
+  lo = mx >= 0 ? static_cast<int32_t>(mn) : 0x7FFFFFFF;
+  R = mx >= 0 ? mx - mn + 1 : 0;
+}
+
 
 // The fields of a vertex record that the resolution reads of a neighbour
 // (begin, up, hfb, sfe) in one 16-byte word, so that the random read of a
@@ -269,11 +318,12 @@ __global__ __launch_bounds__(kThreads) void plan_kernel(const int32_t* lc, const
     h += hf;
     uint8_t vi = 0;
     if (D > 0 && is_heavy(m, kCover, prm)) {
+      const SplitWindow sw = split_window(lc, m);
       int32_t lo;
       int64_t R;
-      probe_window(lc, m, lo, R);
+      joint_window(sw, lo, R);
       int kind = kKindHash;
-      const int b = choose_bin(R, probe_size(m), D, m.deg, &kind, prm);
+      const int b = choose_bin(split_words(sw), R, probe_size(m), D, m.deg, &kind, prm);
       vi = static_cast<uint8_t>(kViHeavy | (kind == kKindBitmap ? kViBitmap : 0) |
                                 (kind == kKindTwoLevel ? kViTwoLevel : 0) | b);
     }
@@ -870,8 +920,11 @@ enum ProbeMode { kBitmap = 0, kHash = 1, kSearch = 2, kTwoLevel = 3 };
 // Probe set P(x) = Up(x) ∪ Hfwd(x) of the block's current anchor.
 struct ProbeSet {
   const uint32_t* tab;
-  int32_t lo;      // bitmap, two-level: id of bit 0
-  uint32_t R;      // bitmap: window length; bit R is kept clear (two-level: ids >= R miss)
+  int32_t lo;      // two-level: id of bit 0 of the joint window
+  uint32_t R;      // two-level: window length (ids >= R miss)
+  int32_t lo_up, lo_hf;  // bitmap: id of bit 0 of the Up and the Hfwd part
+  uint32_t R_up, R_hf;   // bitmap: window lengths; bit R of each part is kept clear
+  uint32_t off_hf;       // bitmap: first word of the Hfwd part
   int nw;          // two-level: LDS words of block bits (their prefix counts follow)
   const uint32_t* words;  // two-level: the member words of the non-empty blocks
   int cap, shift;  // hash: slot count (power of two) and hslot shift
@@ -885,8 +938,12 @@ struct ProbeSet {
 template <int MODE>
 __device__ __forceinline__ uint32_t probe(const ProbeSet& ps, int32_t t, bool up_side) {
   if (MODE == kBitmap) {
-    const uint32_t d = min(static_cast<uint32_t>(t) - static_cast<uint32_t>(ps.lo), ps.R);
-    return (ps.tab[d >> 5] >> (d & 31)) & 1u;
+    // the part of the stream's segment (uniform over a chunk)
+    const uint32_t lo = static_cast<uint32_t>(up_side ? ps.lo_up : ps.lo_hf);
+    const uint32_t R = up_side ? ps.R_up : ps.R_hf;
+    const uint32_t* tb = up_side ? ps.tab : ps.tab + ps.off_hf;
+    const uint32_t d = min(static_cast<uint32_t>(t) - lo, R);
+    return (tb[d >> 5] >> (d & 31)) & 1u;
   } else if (MODE == kTwoLevel) {
     const uint32_t d = static_cast<uint32_t>(t) - static_cast<uint32_t>(ps.lo);
     if (d >= ps.R) return 0u;
@@ -1052,7 +1109,7 @@ __device__ __forceinline__ uint32_t chunk_hits(const int32_t* p, int len, const 
 // stream of its chunk as s_tb + popcount(mask bits <= i) - 1, with no search.
 template <int MODE, int THREADS, int kOut, int kAhead>
 __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_cl, const int64_t* s_beg,
-                                               const int32_t* s_oth, const uint8_t* s_up, uint64_t* s_M,
+                                               const int32_t* s_oth, uint64_t* s_M,
                                                int32_t* s_tb, const int32_t* lc, const ProbeSet& ps, int32_t x,
                                                const Out& o, int64_t ebase, int* s_pos, int32_t* s_q) {
   constexpr int kWin = THREADS * kWinIters;
@@ -1105,9 +1162,9 @@ __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_
           const int2 cl = s_cl[j];
           const int k = c - cl.x;
           p = lc + s_beg[j] + static_cast<int64_t>(k) * kChunk;
-          len = cl.y - k * kChunk;
+          len = (cl.y & kLenMask) - k * kChunk;
           if (needs_oth(kOut)) ot = s_oth[j];
-          upside = MODE == kSearch && s_up[j] != 0;
+          upside = (cl.y & kClUp) != 0;
         }
         cnt += chunk_hits<MODE, kOut>(p, len, ps, upside, x, ot, o, ebase, s_pos, wq);
       }
@@ -1138,9 +1195,9 @@ __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_
             const int2 cl = s_cl[j];
             const int k = c - cl.x;
             e[u] = s_beg[j] + static_cast<int64_t>(k) * kChunk;
-            len[u] = cl.y - k * kChunk;
+            len[u] = (cl.y & kLenMask) - k * kChunk;
             if (needs_oth(kOut)) oth[u] = s_oth[j];
-            if (MODE == kSearch) up[u] = s_up[j] != 0;
+            up[u] = (cl.y & kClUp) != 0;
           }
         }
         int32_t v[kAhead][kChunk];
@@ -1172,9 +1229,9 @@ __device__ __forceinline__ uint32_t run_chunks(int C, int nslots, const int2* s_
           const int2 cl = s_cl[j];
           const int k = c - cl.x;
           p = lc + s_beg[j] + static_cast<int64_t>(k) * kChunk;
-          len = cl.y - k * kChunk;
+          len = (cl.y & kLenMask) - k * kChunk;
           ot = s_oth[j];
-          upside = MODE == kSearch && s_up[j] != 0;
+          upside = (cl.y & kClUp) != 0;
         }
         cnt += chunk_hits<MODE, kOut>(p, len, ps, upside, x, ot, o, ebase, s_pos, wq);
       }
@@ -1203,7 +1260,6 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
   __shared__ int2 s_cl[D + 1];  // (first chunk, length) of each non-empty stream
   __shared__ int32_t s_oth[needs_oth(kOut) ? D : 1];
   __shared__ int s_pos;  // triangles of the current item written so far (kOutEmit)
-  __shared__ uint8_t s_up[WORDS == 0 ? D : 1];
   __shared__ uint64_t s_M[kTiles];
   __shared__ int32_t s_tb[kTiles];
   __shared__ int32_t s_q[WORDS > 0 ? THREADS : 1];  // per wave: its queue of pending hash probes
@@ -1254,9 +1310,15 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
     ps.words = tl_words + mx.begin;
     int mode = kSearch;
     if (WORDS > 0) {
+      const SplitWindow sw = split_window(lc, mx);
       int64_t R64;
-      probe_window(lc, mx, ps.lo, R64);
+      joint_window(sw, ps.lo, R64);
       ps.R = static_cast<uint32_t>(R64);
+      ps.lo_up = sw.lo_up;
+      ps.lo_hf = sw.lo_hf;
+      ps.R_up = static_cast<uint32_t>(sw.R_up);
+      ps.R_hf = static_cast<uint32_t>(sw.R_hf);
+      ps.off_hf = static_cast<uint32_t>(bitmap_words(sw.R_up));
       mode = (item.w & kItemBitmap) ? kBitmap : ((item.w & kItemTwoLevel) ? kTwoLevel : kHash);
       ps.cap = WORDS;
       ps.shift = 32 - __builtin_ctz(WORDS);
@@ -1288,13 +1350,14 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
             run += __popc(wv[j]);
           }
         } else if (mode == kBitmap) {
-          const int words = static_cast<int>(bitmap_words(R64));
+          const int words = static_cast<int>(ps.off_hf + bitmap_words(sw.R_hf));
           for (int i = tid; i < words; i += THREADS) tab[i] = 0u;
           __syncthreads();
           for (int i = tid; i < P; i += THREADS) {
-            const int32_t key = i < mx.up ? lc[mx.begin + i] : lc[mx.begin + mx.hfb + (i - mx.up)];
-            const uint32_t d = static_cast<uint32_t>(key - ps.lo);
-            atomicOr(&tab[d >> 5], 1u << (d & 31));
+            const bool upm = i < mx.up;
+            const int32_t key = upm ? lc[mx.begin + i] : lc[mx.begin + mx.hfb + (i - mx.up)];
+            const uint32_t d = static_cast<uint32_t>(key - (upm ? ps.lo_up : ps.lo_hf));
+            atomicOr(&tab[(upm ? 0u : ps.off_hf) + (d >> 5)], 1u << (d & 31));
           }
         } else {
           for (int i = tid; i < ps.cap; i += THREADS) tab[i] = kHashEmpty;
@@ -1357,10 +1420,9 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (llen[r] <= 0) continue;
-        s_cl[slot] = make_int2(cb, llen[r]);
+        s_cl[slot] = make_int2(cb, llen[r] | (lup[r] ? kClUp : 0));
         s_beg[slot] = lbeg[r];
         if (needs_oth(kOut)) s_oth[slot] = loth[r];
-        if (WORDS == 0) s_up[slot] = lup[r] ? 1 : 0;
         cb += (llen[r] + kChunk - 1) / kChunk;
         ++slot;
       }
@@ -1368,16 +1430,16 @@ __global__ __launch_bounds__(THREADS, WPE) void heavy_kernel(const int32_t* lc, 
       __syncthreads();
       uint32_t got;
       if (WORDS == 0) {
-        got = run_chunks<kSearch, THREADS, kOut, ahead_of<WORDS>()>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
+        got = run_chunks<kSearch, THREADS, kOut, ahead_of<WORDS>()>(C, nslots, s_cl, s_beg, s_oth, s_M, s_tb, lc, ps, hx, o,
                                                  ebase, &s_pos, s_q);
       } else if (mode == kBitmap) {
-        got = run_chunks<kBitmap, THREADS, kOut, ahead_of<WORDS>()>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
+        got = run_chunks<kBitmap, THREADS, kOut, ahead_of<WORDS>()>(C, nslots, s_cl, s_beg, s_oth, s_M, s_tb, lc, ps, hx, o,
                                                  ebase, &s_pos, s_q);
       } else if (WORDS == kBinWords2 && mode == kTwoLevel) {
-        got = run_chunks<kTwoLevel, THREADS, kOut, ahead_of<WORDS>()>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
+        got = run_chunks<kTwoLevel, THREADS, kOut, ahead_of<WORDS>()>(C, nslots, s_cl, s_beg, s_oth, s_M, s_tb, lc, ps, hx, o,
                                                    ebase, &s_pos, s_q);
       } else {
-        got = run_chunks<kHash, THREADS, kOut, ahead_of<WORDS>()>(C, nslots, s_cl, s_beg, s_oth, s_up, s_M, s_tb, lc, ps, hx, o,
+        got = run_chunks<kHash, THREADS, kOut, ahead_of<WORDS>()>(C, nslots, s_cl, s_beg, s_oth, s_M, s_tb, lc, ps, hx, o,
                                                ebase, &s_pos, s_q);
       }
       // the per-item count is kept only where it is recorded
@@ -1560,6 +1622,10 @@ int count_params(const tc_tuning* t, bool cover, int64_t nnz, CountParams* out) 
   // ms against a median of 2.28 ms side by side, S24 within 1.5%), the
   // comparator, whose work is spread over the small bins, side by side.
   p.bins_mode = cover ? 1 : 2;
+  // an anchor with more than 1024 task descriptors skips the smallest-table
+  // bin: its items would be streamed by one wave each (R-MAT S22 15.9 ->
+  // 14.5 ms, S20 3.89 -> 3.72 ms; S24, 72.0 ms without the limit, 72.4)
+  p.bin0_max_desc = 1024;
   if (t) {
     if (t->light_max) p.light_max = t->light_max;
     if (t->dn_light) p.dn_light = t->dn_light;
@@ -1569,6 +1635,7 @@ int count_params(const tc_tuning* t, bool cover, int64_t nnz, CountParams* out) 
     if (t->bin0_mode) p.bin0_mode = t->bin0_mode;
     if (t->bins_mode) p.bins_mode = t->bins_mode;
     if (t->twolevel_sparsity) p.tl_sparsity = t->twolevel_sparsity;
+    if (t->bin0_max_desc) p.bin0_max_desc = t->bin0_max_desc;
   }
   if (p.light_max < 1 || p.light_max > kLightMax)
     return fail(TC_ERR_INVALID_ARG, "tuning: light_max must be in 1..%d", kLightMax);
@@ -1577,6 +1644,7 @@ int count_params(const tc_tuning* t, bool cover, int64_t nnz, CountParams* out) 
     return fail(TC_ERR_INVALID_ARG, "tuning: bitmap word factors must be in 1..1024");
   if (p.item_log2 < 12 || p.item_log2 > 24) return fail(TC_ERR_INVALID_ARG, "tuning: item_log2 must be in 12..24");
   if (p.tl_sparsity < -1) return fail(TC_ERR_INVALID_ARG, "tuning: twolevel_sparsity must be >= 1, or -1");
+  if (p.bin0_max_desc < -1) return fail(TC_ERR_INVALID_ARG, "tuning: bin0_max_desc must be >= 1, or -1");
   if (p.bin0_mode < 1 || p.bin0_mode > 2 || p.bins_mode < 1 || p.bins_mode > 2)
     return fail(TC_ERR_INVALID_ARG, "tuning: bin0_mode and bins_mode must be 1 or 2");
   *out = p;

@@ -149,6 +149,7 @@ struct CountParams {
   int bin0_mode;   // 1: blocks claim items; 2: items round robin
   int bins_mode;   // 1: table bins one after another; 2: side by side
   int tl_sparsity; // largest hash bin: two-level table instead when window >= this * |P| (-1: never)
+  int bin0_max_desc; // anchors with more descriptors skip the smallest-table bin (-1: no limit)
 };
 // The defaults, overridden by the non-zero fields of `t` (nullable);
 // TC_ERR_INVALID_ARG for a value out of range.

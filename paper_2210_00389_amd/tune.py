@@ -36,6 +36,7 @@ SPACE = {
     "bin0_mode": [1, 2],
     "bins_mode": [1, 2],
     "twolevel_sparsity": [-1, 16, 256],
+    "bin0_max_desc": [-1, 256, 4096],
 }
 # the comparator has no down class and no one-workgroup path
 EDGE_SPACE = {k: v for k, v in SPACE.items() if k not in ("dn_light", "small_max_n", "small_max_nnz")}

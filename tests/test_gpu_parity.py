@@ -285,7 +285,8 @@ TUNINGS = [dict(light_max=1, dn_light=1), dict(light_max=8, dn_light=4, item_log
            dict(bitmap_member_words=1, bitmap_desc_words=1), dict(bitmap_member_words=1024, bitmap_desc_words=1024),
            dict(item_log2=24, bin0_mode=1, bins_mode=2), dict(item_log2=14, bin0_mode=2, bins_mode=1),
            dict(light_max=32, dn_light=1000, item_log2=16, bins_mode=2, bin0_mode=2),
-           dict(twolevel_sparsity=1), dict(twolevel_sparsity=-1, bins_mode=1)]
+           dict(twolevel_sparsity=1), dict(twolevel_sparsity=-1, bins_mode=1), dict(bin0_max_desc=1),
+           dict(bin0_max_desc=-1, bitmap_member_words=64)]
 
 
 def test_determinism_across_tunings(tc):
