@@ -157,7 +157,13 @@ typedef struct tc_tuning {
                                  this skips the smallest-table bin (its items
                                  are streamed by one wave each there):
                                  default 1024, -1 = no limit */
-  int32_t reserved[2];
+  int32_t up_anchor_min;      /* cover count, a pair (x, w) with w one level
+                                 below x and Hfwd(x) non-empty: x streams Up(w)
+                                 against its table, unless |Up(w)| exceeds both
+                                 up_anchor_min and |Hfwd(x)|; then w streams
+                                 Hfwd(x) against the Up part of its table
+                                 (>= 32; default -1 = x always) */
+  int32_t reserved[1];
 } tc_tuning;
 
 #define TC_SMALL_MAX_N 65536

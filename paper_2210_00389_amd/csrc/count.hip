@@ -314,7 +314,8 @@ __global__ __launch_bounds__(kThreads) void plan_kernel(const int32_t* lc, const
     const VMeta m = meta[x];
     const int hf = m.sfe - m.hfb;
     const int nB = (kCover && hf > 0) ? m.deg - m.sfe : 0;
-    const int D = nB + hf + (m.hfb - m.up);
+    const int nU = (kCover && prm.up_anchor_min >= 0 && m.up > prm.up_anchor_min) ? m.up : 0;
+    const int D = nB + hf + (m.hfb - m.up) + nU;
     h += hf;
     uint8_t vi = 0;
     if (D > 0 && is_heavy(m, kCover, prm)) {
@@ -353,16 +354,19 @@ struct Task {
   int32_t oth;  // vertex whose list is streamed
 };
 
-enum DescKind { kDown = 0, kFwd = 1, kBwd = 2, kNone = 3 };
+enum DescKind { kDown = 0, kFwd = 1, kBwd = 2, kNone = 3, kUpD = 4 };
 
 // Tasks of kResPer descriptors (vertex x[j], index k[j] in its descriptor
 // space) with x[j] as the anchor of every returned task.  The steps run in
 // lockstep over the descriptors so that their dependent loads (neighbour
 // id, its record, the search of x in Hfwd(u)) are in flight together.
+// A vertex's descriptors are [down | fwd | bwd | upd]: one per vertex of
+// Down(x) (when Hfwd(x) is not empty), of Hfwd(x), of the same-level
+// neighbours below x, and (cover count, |Up(x)| > upa) of Up(x).
 template <bool kCover>
 __device__ __forceinline__ void describe_all(const int32_t* lc, const int32_t* samp, const VMeta* meta,
                                              const uint4* pm, const int32_t* x, const VMeta* mx, const int* kin,
-                                             Task* ta, Task* tb) {
+                                             int upa, Task* ta, Task* tb) {
   int kind[kResPer], k[kResPer];
   int32_t nb[kResPer];
   int64_t pos[kResPer];
@@ -374,11 +378,13 @@ __device__ __forceinline__ void describe_all(const int32_t* lc, const int32_t* s
     tb[j] = Task{0, 0, 0};
     const int hf = mx[j].sfe - mx[j].hfb;
     const int nB = (kCover && hf > 0) ? mx[j].deg - mx[j].sfe : 0;
+    const int nS = mx[j].hfb - mx[j].up;
     const int kk = kin[j];
     const bool dn = kk < nB, fw = !dn && kk - nB < hf;
-    kind[j] = kk < 0 ? kNone : (dn ? kDown : (fw ? kFwd : kBwd));
-    k[j] = dn ? kk : (fw ? kk - nB : kk - nB - hf);
-    const int32_t seg = dn ? mx[j].sfe : (fw ? mx[j].hfb : mx[j].up);
+    const bool bw = !dn && !fw && (!kCover || kk - nB - hf < nS);
+    kind[j] = kk < 0 ? kNone : (dn ? kDown : (fw ? kFwd : (bw ? kBwd : kUpD)));
+    k[j] = dn ? kk : (fw ? kk - nB : (bw ? kk - nB - hf : kk - nB - hf - nS));
+    const int32_t seg = dn ? mx[j].sfe : (fw ? mx[j].hfb : (bw ? mx[j].up : 0));
     pos[j] = kk < 0 ? 0 : mx[j].begin + seg + k[j];
   }
 #pragma unroll
@@ -469,8 +475,15 @@ __device__ __forceinline__ void describe_all(const int32_t* lc, const int32_t* s
     const VMeta& m = mx[j];
     const VMeta& o = mo[j];
     const int hf = m.sfe - m.hfb;
-    if (kind[j] == kDown) {  // stream Up(w)
-      if (o.up > 0) ta[j] = Task{o.begin, o.up, nb[j]};
+    if (kind[j] == kDown) {  // stream Up(w), unless w anchors the pair (see kUpD)
+      if (o.up > 0 && !(upa >= 0 && o.up > upa && o.up > hf)) ta[j] = Task{o.begin, o.up, nb[j]};
+    } else if (kind[j] == kUpD) {
+      // u = nb in Up(x), x one level below u: when Up(x) (longer than upa)
+      // is also longer than Hfwd(u), x anchors the down-class pair (u, x)
+      // and streams Hfwd(u) against the Up part of its table; every cover
+      // edge (u, v) with v in Up(x) closes a triangle
+      const int hu = o.sfe - o.hfb;
+      if (kCover && hu > 0 && m.up > hu) ta[j] = Task{o.begin + o.hfb, hu | kFlagUp, nb[j]};
     } else if (kind[j] == kFwd) {  // forward cover edge (x, v)
       if (kCover && o.up > 0 && o.up <= m.up) ta[j] = Task{o.begin, o.up | kFlagUp, nb[j]};
       const int a = hf - k[j] - 1, b = o.sfe - o.hfb;
@@ -572,7 +585,7 @@ template <bool kCover>
 __global__ __launch_bounds__(kResThreads) void resolve_kernel(
     const int32_t* lc, const int32_t* samp, const VMeta* meta, const uint4* pm, const uint8_t* vinfo,
     const int64_t* so, const int32_t* cx0, int64_t n, int64_t* sbeg, int32_t* slen, int32_t* soth, int32_t* sx,
-    int4* items_raw, int4* ccnt, int item_log2) {
+    int4* items_raw, int4* ccnt, int item_log2, int upa) {
   __shared__ int64_t sh[kResThreads / kWave + 1];
   __shared__ int64_t s_so[kResSpan];
   __shared__ int32_t s_x[kResRecs];
@@ -627,7 +640,7 @@ __global__ __launch_bounds__(kResThreads) void resolve_kernel(
 #pragma unroll
     for (int j = 0; j < kResPer; ++j) heavy[j] = kk[j] >= 0 && (vi[j] & kViHeavy) != 0;
     Task ta[kResPer], tb[kResPer];
-    describe_all<kCover>(lc, samp, meta, pm, xi, mx, kk, ta, tb);
+    describe_all<kCover>(lc, samp, meta, pm, xi, mx, kk, upa, ta, tb);
     // ---- counts: light tasks, heavy records, heavy elements (per j, j-major)
     int64_t nl = 0, nh = 0;
     int64_t he[kResPer];
@@ -1568,7 +1581,8 @@ int launch_all(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
   sample_kernel<<<grid_for(a.g->nnz / kSampStride + 1, kThreads, 16384), kThreads, 0, s>>>(a.cols, a.g->nnz,
                                                                                            w.samp);
   resolve_kernel<kCover><<<gr, kResThreads, 0, s>>>(a.cols, w.samp, a.meta, w.pm, w.vinfo, w.so, w.cx0, n, w.sbeg,
-                                                    w.slen, w.soth, w.sx, w.items_raw, w.ccnt, a.prm.item_log2);
+                                                    w.slen, w.soth, w.sx, w.items_raw, w.ccnt, a.prm.item_log2,
+                                                    a.prm.up_anchor_min);
   TC_HIP(hipGetLastError());
   {
     Carver sc(w.scratch);
@@ -1626,6 +1640,12 @@ int count_params(const tc_tuning* t, bool cover, int64_t nnz, CountParams* out) 
   // bin: its items would be streamed by one wave each (R-MAT S22 15.9 ->
   // 14.5 ms, S20 3.89 -> 3.72 ms; S24, 72.0 ms without the limit, 72.4)
   p.bin0_max_desc = 1024;
+  // A down-class pair (x, w) may stream the shorter of Up(w) and Hfwd(x)
+  // when Up(w) is long (w then holds one task descriptor per vertex of
+  // Up(w)).  Off by default: at R-MAT S24 it streams 6% fewer elements and
+  // takes 1.0 ms off 72.5 (up_anchor_min 256), at S22 and S20 it costs 1%
+  // (the new anchors' tables and tasks outweigh the shorter streams).
+  p.up_anchor_min = -1;
   if (t) {
     if (t->light_max) p.light_max = t->light_max;
     if (t->dn_light) p.dn_light = t->dn_light;
@@ -1636,6 +1656,7 @@ int count_params(const tc_tuning* t, bool cover, int64_t nnz, CountParams* out) 
     if (t->bins_mode) p.bins_mode = t->bins_mode;
     if (t->twolevel_sparsity) p.tl_sparsity = t->twolevel_sparsity;
     if (t->bin0_max_desc) p.bin0_max_desc = t->bin0_max_desc;
+    if (t->up_anchor_min) p.up_anchor_min = t->up_anchor_min;
   }
   if (p.light_max < 1 || p.light_max > kLightMax)
     return fail(TC_ERR_INVALID_ARG, "tuning: light_max must be in 1..%d", kLightMax);
@@ -1645,6 +1666,9 @@ int count_params(const tc_tuning* t, bool cover, int64_t nnz, CountParams* out) 
   if (p.item_log2 < 12 || p.item_log2 > 24) return fail(TC_ERR_INVALID_ARG, "tuning: item_log2 must be in 12..24");
   if (p.tl_sparsity < -1) return fail(TC_ERR_INVALID_ARG, "tuning: twolevel_sparsity must be >= 1, or -1");
   if (p.bin0_max_desc < -1) return fail(TC_ERR_INVALID_ARG, "tuning: bin0_max_desc must be >= 1, or -1");
+  // w must be a heavy anchor (a probe set above every light bound)
+  if (p.up_anchor_min != -1 && p.up_anchor_min < kLightMax)
+    return fail(TC_ERR_INVALID_ARG, "tuning: up_anchor_min must be >= %d, or -1", kLightMax);
   if (p.bin0_mode < 1 || p.bin0_mode > 2 || p.bins_mode < 1 || p.bins_mode > 2)
     return fail(TC_ERR_INVALID_ARG, "tuning: bin0_mode and bins_mode must be 1 or 2");
   *out = p;

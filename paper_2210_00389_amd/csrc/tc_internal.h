@@ -150,6 +150,7 @@ struct CountParams {
   int bins_mode;   // 1: table bins one after another; 2: side by side
   int tl_sparsity; // largest hash bin: two-level table instead when window >= this * |P| (-1: never)
   int bin0_max_desc; // anchors with more descriptors skip the smallest-table bin (-1: no limit)
+  int up_anchor_min; // down-class pair (x, w): w anchors it when |Up(w)| > this and > |Hfwd(x)| (-1: never)
 };
 // The defaults, overridden by the non-zero fields of `t` (nullable);
 // TC_ERR_INVALID_ARG for a value out of range.

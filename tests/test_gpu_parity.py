@@ -286,7 +286,8 @@ TUNINGS = [dict(light_max=1, dn_light=1), dict(light_max=8, dn_light=4, item_log
            dict(item_log2=24, bin0_mode=1, bins_mode=2), dict(item_log2=14, bin0_mode=2, bins_mode=1),
            dict(light_max=32, dn_light=1000, item_log2=16, bins_mode=2, bin0_mode=2),
            dict(twolevel_sparsity=1), dict(twolevel_sparsity=-1, bins_mode=1), dict(bin0_max_desc=1),
-           dict(bin0_max_desc=-1, bitmap_member_words=64)]
+           dict(bin0_max_desc=-1, bitmap_member_words=64), dict(up_anchor_min=32),
+           dict(up_anchor_min=32, light_max=8, dn_light=4, bitmap_member_words=1, bitmap_desc_words=1)]
 
 
 def test_determinism_across_tunings(tc):
@@ -330,6 +331,32 @@ def test_autotune_count(tc):
         assert got == T
 
 
+def test_up_anchor_pairs(tc):
+    """Down-class pairs (x, w) anchored at w (up_anchor_min): w streams
+    Hfwd(x) against the Up part of its table when Up(w) is the longer list.
+    T, |H| and the per-vertex counts equal the oracle's, and the statistics
+    show the changed work: more task descriptors, fewer streamed elements."""
+    for scale, seed in [(12, 3), (14, 7), (16, 1)]:
+        g = graphgen.rmat(scale, 16, seed=seed)
+        say(f"[up-anchor] rmat{scale}")
+        c = oracle.from_graph(g)
+        lv = oracle.bfs_levels(c)
+        want = oracle.count(c, lv.levels, per_vertex=scale <= 14)
+        G = to_gpu(tc, g)
+        ws = tc.Workspace()
+        r0 = tc.count(G, ws=ws, tuning=dict(small_max_n=-1, up_anchor_min=-1))
+        st0 = tc.read_stats(ws)
+        for upa in (32, 64, 256):
+            r = tc.count(G, ws=ws, per_vertex=scale <= 14, tuning=dict(small_max_n=-1, up_anchor_min=upa))
+            st = tc.read_stats(ws)
+            assert (r.T, r.h) == (want.triangles, r0.h) == (r0.T, r0.h), (scale, upa)
+            if scale <= 14:
+                assert np.array_equal(r.per_vertex.cpu().numpy(), want.per_vertex), (scale, upa)
+            if upa == 32:
+                assert st["descriptors"] > st0["descriptors"], (scale, st, st0)
+                assert sum(st["bin_elems"]) + st["light_elems"] < sum(st0["bin_elems"]) + st0["light_elems"]
+
+
 def test_two_level_tables(tc):
     """Probe sets too large for an LDS bitmap or hash table take the
     two-level table (block bits in LDS, member words in global memory): a
@@ -365,6 +392,9 @@ def test_two_level_tables(tc):
     st = tc.read_stats(ws)
     say(f"[two-level] cover stats {st}")
     assert (r.T, r.h) == (T, h)
+    # B (20000 up-neighbours, a two-level table) anchors its down-class pairs
+    r2 = tc.count(G, ws=ws, tuning={"up_anchor_min": 32})
+    assert (r2.T, r2.h) == (T, h)
     wb = tc.Workspace()
     Tb = int(tc.count_edge_baseline(G, ws=wb).item())
     stb = tc.read_stats(wb)
