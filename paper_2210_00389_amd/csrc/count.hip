@@ -397,17 +397,36 @@ __device__ __forceinline__ void describe_all(const int32_t* lc, const int32_t* s
 #pragma unroll
   for (int j = 0; j < kResPer; ++j)
     if (kind[j] != kNone) mo[j] = unpack_record(q[j], meta, nb[j]);
-  // backward same class needs a = |Hfwd(u) ∩ (x, inf)|: joint lower bound
-  int64_t lo[kResPer], hi[kResPer];
-  bool srch[kResPer];
+  // Backward same class, cover edge (u, x) with u < x: the rule compares
+  // a = |Hfwd(u) ∩ (x, inf)| with b = |Hfwd(x)|.  The entry b + 1 places
+  // before the end of Hfwd(u) decides it with one load: above x, a > b and
+  // the forward descriptor of u takes the pair; equal to x, a = b; below,
+  // x lies among the last b entries, and only they are searched for it.
+  int64_t lo[kResPer], hi[kResPer], pp[kResPer];
+  bool srch[kResPer], prb[kResPer];
 #pragma unroll
   for (int j = 0; j < kResPer; ++j) {
-    srch[j] = false;
-    lo[j] = hi[j] = 0;
-    if (kind[j] == kBwd && mx[j].sfe > mx[j].hfb && mo[j].sfe > mo[j].hfb) {
+    srch[j] = prb[j] = false;
+    lo[j] = hi[j] = pp[j] = 0;
+    const int b = mx[j].sfe - mx[j].hfb, lu = mo[j].sfe - mo[j].hfb;
+    if (kind[j] == kBwd && b > 0 && lu > 0) {
       srch[j] = true;
       lo[j] = mo[j].begin + mo[j].hfb;
       hi[j] = mo[j].begin + mo[j].sfe;
+      prb[j] = b + 1 < lu;
+      pp[j] = prb[j] ? hi[j] - b - 1 : 0;
+    }
+  }
+  {
+    int32_t pv[kResPer];
+#pragma unroll
+    for (int j = 0; j < kResPer; ++j) pv[j] = lc[pp[j]];  // an idle slot reads column 0
+#pragma unroll
+    for (int j = 0; j < kResPer; ++j) {
+      if (!prb[j]) continue;
+      if (pv[j] > x[j]) srch[j] = false;
+      else if (pv[j] == x[j]) lo[j] = hi[j] = pp[j];
+      else lo[j] = pp[j] + 1;
     }
   }
   // First over the column samples (every kSampStride-th column, a compact
