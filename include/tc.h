@@ -138,7 +138,8 @@ typedef struct tc_tuning {
                                  are at most bitmap_member_words * |P| + 64
                                  (default 4) ... */
   int32_t bitmap_desc_words;  /* ... or bitmap_desc_words * its task count
-                                 (default 16); else a hash table (1..1024) */
+                                 (default 8 for the cover count, 16 for the
+                                 comparator); else a hash table (1..1024) */
   int32_t item_log2;          /* work items hold about 2^item_log2 streamed
                                  elements (12..24, default 19) */
   int32_t bin0_mode;          /* smallest-table bin: 1 = blocks claim items,
@@ -162,7 +163,8 @@ typedef struct tc_tuning {
                                  against its table, unless |Up(w)| exceeds both
                                  up_anchor_min and |Hfwd(x)|; then w streams
                                  Hfwd(x) against the Up part of its table
-                                 (>= 32; default -1 = x always) */
+                                 (>= 32; -1 = x always; default 256 for
+                                 graphs of at least 2^28 entries, else -1) */
   int32_t reserved[1];
 } tc_tuning;
 

@@ -1637,7 +1637,9 @@ int count_params(const tc_tuning* t, bool cover, int64_t nnz, CountParams* out) 
   p.light_max = kLightMax;
   p.dn_light = kDnLight;
   p.bm_member = 4;
-  p.bm_desc = 16;
+  // cover count: 8 words per task (R-MAT S24 71.3 -> 69.7 ms, S20 3.71 ->
+  // 3.63 ms, S22 within 0.5%); the comparator keeps 16
+  p.bm_desc = cover ? 8 : 16;
   p.item_log2 = kElemChunkLog;
   p.tl_sparsity = 64;
   // Bin 0 (tables of 2 KB): on smaller graphs its items are short (about 500
@@ -1661,10 +1663,11 @@ int count_params(const tc_tuning* t, bool cover, int64_t nnz, CountParams* out) 
   p.bin0_max_desc = 1024;
   // A down-class pair (x, w) may stream the shorter of Up(w) and Hfwd(x)
   // when Up(w) is long (w then holds one task descriptor per vertex of
-  // Up(w)).  Off by default: at R-MAT S24 it streams 6% fewer elements and
-  // takes 1.0 ms off 72.5 (up_anchor_min 256), at S22 and S20 it costs 1%
-  // (the new anchors' tables and tasks outweigh the shorter streams).
-  p.up_anchor_min = -1;
+  // Up(w)).  On for graphs of at least 2^28 entries: at R-MAT S24 it streams
+  // 6% fewer elements (69.7 -> 68.5 ms at 256, with the bitmap rule above);
+  // at S22 and S20 it costs up to 1.5% (the new anchors' tables and tasks
+  // outweigh the shorter streams).
+  p.up_anchor_min = cover && nnz >= (int64_t(1) << 28) ? 256 : -1;
   if (t) {
     if (t->light_max) p.light_max = t->light_max;
     if (t->dn_light) p.dn_light = t->dn_light;
