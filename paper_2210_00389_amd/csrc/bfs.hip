@@ -365,22 +365,36 @@ __global__ void uf_hook_kernel(const int64_t* off, const int32_t* cols, int64_t 
 
 // Roots of the unreached components start the multi-source BFS at level 0
 // (bits in the level-0 frontier bitmap); isolated vertices get level 0 and
-// need no expansion.  Per-block counts go to part.
+// need no expansion.  Per-block counts go to part.  A wave takes 64
+// consecutive vertices from a multiple of 64, i.e. two whole bitmap words
+// that no other wave of this kernel touches: its roots are gathered by
+// ballot and one lane updates each word, with no atomics.
 __global__ __launch_bounds__(kThreads) void uf_roots_kernel(const int64_t* off, int64_t n, int32_t* parent,
                                                             int32_t* L, uint32_t* vis, uint32_t* bm0,
                                                             int64_t* part) {
+  static_assert(kThreads % kWave == 0, "waves start at multiples of 64 vertices");
   __shared__ int64_t sh[kThreads / kWave + 1];
   int64_t cnt = 0, edg = 0;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    if ((vis[v >> 5] >> (v & 31)) & 1u) continue;
-    if (uf_find(parent, static_cast<int32_t>(v)) != v) continue;
-    L[v] = 0;
-    atomicOr(&vis[v >> 5], 1u << (v & 31));
-    const int64_t d = row_deg(off, v);
-    if (d > 0) {
-      atomicOr(&bm0[v >> 5], 1u << (v & 31));
-      ++cnt;
-      edg += d;
+  for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = v0 + threadIdx.x;
+    bool root = false, expand = false;
+    if (v < n && !((vis[v >> 5] >> (v & 31)) & 1u) && uf_find(parent, static_cast<int32_t>(v)) == v) {
+      root = true;
+      L[v] = 0;
+      const int64_t d = row_deg(off, v);
+      if (d > 0) {
+        expand = true;
+        ++cnt;
+        edg += d;
+      }
+    }
+    const uint64_t rm = __ballot(root), em = __ballot(expand);
+    if (lane() == 0 && rm) {
+      const int64_t w = (v - lane()) >> 5;  // the wave's first word
+      if (static_cast<uint32_t>(rm)) vis[w] |= static_cast<uint32_t>(rm);
+      if (rm >> 32) vis[w + 1] |= static_cast<uint32_t>(rm >> 32);
+      if (static_cast<uint32_t>(em)) bm0[w] |= static_cast<uint32_t>(em);
+      if (em >> 32) bm0[w + 1] |= static_cast<uint32_t>(em >> 32);
     }
   }
   block_partial(cnt, edg, part, sh);
