@@ -164,7 +164,7 @@ typedef struct tc_tuning {
                                  up_anchor_min and |Hfwd(x)|; then w streams
                                  Hfwd(x) against the Up part of its table
                                  (>= 32; -1 = x always; default 256 for
-                                 graphs of at least 2^28 entries, else -1) */
+                                 graphs of at least 2^26 entries, else -1) */
   int32_t reserved[1];
 } tc_tuning;
 

@@ -1663,11 +1663,10 @@ int count_params(const tc_tuning* t, bool cover, int64_t nnz, CountParams* out) 
   p.bin0_max_desc = 1024;
   // A down-class pair (x, w) may stream the shorter of Up(w) and Hfwd(x)
   // when Up(w) is long (w then holds one task descriptor per vertex of
-  // Up(w)).  On for graphs of at least 2^28 entries: at R-MAT S24 it streams
-  // 6% fewer elements (69.7 -> 68.5 ms at 256, with the bitmap rule above);
-  // at S22 and S20 it costs up to 1.5% (the new anchors' tables and tasks
-  // outweigh the shorter streams).
-  p.up_anchor_min = cover && nnz >= (int64_t(1) << 28) ? 256 : -1;
+  // Up(w)).  On for graphs of at least 2^26 entries: with the layout's
+  // degree-ordered levels, R-MAT S24 67.8 -> 66.7 ms and S22 14.59 -> 14.31
+  // ms at 256; at S20 it gains nothing (3.77 -> 3.76 ms).
+  p.up_anchor_min = cover && nnz >= (int64_t(1) << 26) ? 256 : -1;
   if (t) {
     if (t->light_max) p.light_max = t->light_max;
     if (t->dn_light) p.dn_light = t->dn_light;
