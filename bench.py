@@ -163,10 +163,13 @@ def row_work(c, levels):
 def _strided_estimate(oracle, c, levels, phase, stride, work):
     """Time the oracle count over the rows phase, phase + stride, ... and
     scale it to all rows by the elements those rows touch (a ratio
-    estimate: time per element of the sample times all elements)."""
-    t = time.perf_counter()
+    estimate: time per element of the sample times all elements).  Times
+    are the process's CPU time: the oracle is single-threaded, and the legs
+    run beside the GPU benchmark, whose host work would otherwise be
+    counted as the oracle's."""
+    t = time.process_time()
     oracle.count_rows_strided(c, levels, phase, stride)
-    dt = time.perf_counter() - t
+    dt = time.process_time() - t
     rows = len(range(phase, c.n, stride))
     w_s = float(work[phase::stride].sum())
     return dt, rows, dt * float(work.sum()) / max(w_s, 1.0)
@@ -186,12 +189,12 @@ def cpu_leg(args):
     c = oracle.from_graph(g)
     del g
     log(f"[cpu] oracle CSR of R-MAT scale {args.scale} built")
-    t = time.perf_counter()
+    t = time.process_time()  # CPU time of this single-threaded process (see _strided_estimate)
     lv = oracle.bfs_levels(c)
-    t_bfs = time.perf_counter() - t
-    t = time.perf_counter()
+    t_bfs = time.process_time() - t
+    t = time.process_time()
     hu, _ = oracle.cover_edges(c, lv.levels)
-    t_h = time.perf_counter() - t
+    t_h = time.process_time() - t
     del hu
     work_rows = row_work(c, lv.levels)
     # pilot: about 1/1024 of the rows, to size the sample to the budget
@@ -203,9 +206,9 @@ def cpu_leg(args):
     ests, t_count, sampled = [], 0.0, 0
     if stride <= parts:
         # the budget covers the whole count: time it exactly
-        t = time.perf_counter()
+        t = time.process_time()
         oracle.count(c, lv.levels, 0)
-        t_count = time.perf_counter() - t
+        t_count = time.process_time() - t
         ests = [t_count]
         sampled = c.n
         stride = 1
@@ -225,7 +228,7 @@ def cpu_leg(args):
     out = {
         "value": m / est, "unit": "edges/s", "cores": 1, "kind": "oracle",
         "sample": (f"single-threaded CPU oracle (oracle/oracle.c, gcc -O2) on this host (1 of {os.cpu_count()} "
-                   f"cores, {_cpu_model()}) on R-MAT scale {args.scale}: full BFS {t_bfs:.2f}s + cover edges "
+                   f"cores, {_cpu_model()}; process CPU time) on R-MAT scale {args.scale}: full BFS {t_bfs:.2f}s + cover edges "
                    f"{t_h:.2f}s, then the count over {len(ests)} systematic row samples (every {stride}th row, "
                    f"{sampled} rows = {100.0 * sampled / max(c.n, 1):.3f}% in {t_count:.1f}s), each scaled to "
                    f"all rows by the list elements the rows touch; estimated full run {est:.0f}s"),
@@ -250,9 +253,9 @@ def cpu_validate(args):
     del g
     lv = oracle.bfs_levels(c)
     work_rows = row_work(c, lv.levels)
-    t = time.perf_counter()
+    t = time.process_time()  # CPU time, as the estimates (see _strided_estimate)
     oracle.count(c, lv.levels, 0)
-    t_full = time.perf_counter() - t
+    t_full = time.process_time() - t
     log(f"[cpu-check] full oracle count at scale {args.scale}: {t_full:.1f}s")
     res = {"scale": args.scale, "full_count_s": t_full, "strides": {}}
     for stride in (32, 512):
