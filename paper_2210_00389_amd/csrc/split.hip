@@ -15,12 +15,13 @@
 // Two layouts share the row engine:
 //   * identity: same vertex ids, classes from the given int32 levels (any
 //     level function; used for the explicit cover-edge list);
-//   * relabelled (for counting): vertices renumbered by (virtual level, id),
-//     columns rewritten to the new ids, classes read off the new id ranges.
-//     Within one (component, level) class the new order is the old order,
-//     and the method only compares ids inside such a class, so H and every
-//     count are unchanged; each level becomes a contiguous id range, which
-//     keeps the probe sets of the counting kernels inside a small id window.
+//   * relabelled (for counting): vertices renumbered by (virtual level,
+//     degree group, id), columns rewritten to the new ids, classes read off
+//     the new id ranges.  The method only compares ids inside one
+//     (component, level) class, and any total order there gives the same H
+//     (as a set), T and per-vertex counts; each level becomes a contiguous
+//     id range, which keeps the probe sets of the counting kernels inside a
+//     small id window.
 //
 // Rows of up to kShort entries are handled by one thread each; longer rows of
 // up to kMidCap entries by one wave, of up to kBigCap by one block, each held

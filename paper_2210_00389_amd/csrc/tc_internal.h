@@ -77,17 +77,17 @@ SplitWs split_reserve(Carver& c, int64_t n, int64_t nnz);
 // otherwise use packed residues (requires |L(u) - L(v)| <= 1 on edges).
 int split_run(const tc_csr* g, const int32_t* L, bool full_levels, SplitWs& w, hipStream_t s);
 
-// Relabelled layout for counting: vertices renumbered by (virtual level, id)
-// where the virtual level is L(v) in r0's component and L(v) + D0 elsewhere
-// (D0 = level count from r0).  The order is monotone within every
-// (component, level) class, and the method only ever compares ids of one
-// class, so cover edges, the counting test and every per-edge count are
-// unchanged.  Each level becomes a contiguous id range.
+// Relabelled layout for counting: vertices renumbered by (virtual level,
+// degree group, id) where the virtual level is L(v) in r0's component and
+// L(v) + D0 elsewhere (D0 = level count from r0).  The method only ever
+// compares ids of one (component, level) class, and any total order there
+// gives the same cover edges (as a set), T, per-vertex counts and triangle
+// set.  Each level becomes a contiguous id range.
 struct RelabelWs {
   int32_t* order;     // new id -> old id
   int32_t* perm;      // old id -> new id
   int64_t* off;       // relabelled row offsets [n + 1]
-  int32_t* lstart_cnt;  // histogram of (virtual level, hub) groups
+  int32_t* lstart_cnt;  // histogram of (virtual level, degree group) groups
   int64_t* lstart;    // first new id of each group
   uint64_t* keys;
   uint64_t* keys_tmp;
