@@ -176,9 +176,7 @@ template <class Lay>
 __global__ __launch_bounds__(kThreads) void lay_short_kernel(Lay lay, const int32_t* cols, int64_t n, int32_t* out,
                                                              VMeta* meta, int32_t* nseg, int32_t* rcat) {
   constexpr int G = Lay::kG, NG = 3 * G;
-  constexpr int kSegCntN = NG + 1;
   using Ctx = typename Lay::Ctx;
-  (void)kSegCntN;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const Ctx c = lay.ctx(i);
     const int32_t deg = static_cast<int32_t>(c.ie - c.ib);
@@ -356,9 +354,7 @@ template <class Lay, int R>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void lay_mid_kernel(Lay lay, const int32_t* cols, const typename Lay::Ctx* rows,
                                                            const int64_t* count, int32_t* out, VMeta* meta) {
   constexpr int G = Lay::kG, NG = 3 * G;
-  constexpr int kSegCntN = NG + 1;
   using Ctx = typename Lay::Ctx;
-  (void)kSegCntN;
   static_assert(R * kWave < (1 << 16), "part counts are packed in 16-bit fields");
   const int64_t nrows = *count & 0xFFFFFFFFll;
   const int64_t nw = (int64_t)gridDim.x * (kThreads / kWave);
@@ -402,9 +398,7 @@ template <class Lay, int WPR, int R>
 __global__ __launch_bounds__(WPR * kWave) __attribute__((amdgpu_waves_per_eu(5))) void lay_block_kernel(Lay lay, const int32_t* cols, const typename Lay::Ctx* rows,
                                                                 const int64_t* count, int32_t* out, VMeta* meta) {
   constexpr int G = Lay::kG, NG = 3 * G;
-  constexpr int kSegCntN = NG + 1;
   using Ctx = typename Lay::Ctx;
-  (void)kSegCntN;
   constexpr int kPart = R * kWave;
   static_assert(WPR * kPart < (1 << 16), "row counts are packed in 16-bit fields");
   __shared__ uint64_t s_w[WPR][CountsT<NG>::kWords];
@@ -467,9 +461,8 @@ __global__ __launch_bounds__(kThreads) void lay_seg_count_kernel(Lay lay, const 
                                                                  const int64_t* seg_off, const int32_t* seg_vtx,
                                                                  int32_t* seg_cnt, int32_t* stash) {
   constexpr int G = Lay::kG, NG = 3 * G;
-  constexpr int kSegCntN = NG + 1;
   using Ctx = typename Lay::Ctx;
-  (void)kSegCntN;
+  constexpr int kSegCnt = NG + 1;  // per segment: the group counts, then same-below-x
   const int64_t nsegs = seg_off[n];
   const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -501,12 +494,12 @@ __global__ __launch_bounds__(kThreads) void lay_seg_count_kernel(Lay lay, const 
         slt += __popcll(__ballot(is_same<G>(k) & (v < c.self)));
       }
     }
-    if (lane() < kSegCntN) {
+    if (lane() < kSegCnt) {
       int x = slt;
 #pragma unroll
       for (int g = 0; g < NG; ++g)
         if (lane() == g) x = cnt[g];
-      seg_cnt[kSegCntN * sg + lane()] = x;
+      seg_cnt[kSegCnt * sg + lane()] = x;
     }
   }
 }
@@ -517,9 +510,8 @@ template <class Lay>
 __global__ void lay_seg_prefix_kernel(Lay lay, int64_t n, const int32_t* nseg, const int64_t* seg_off,
                                       const int32_t* seg_cnt, int64_t* seg_pre, VMeta* meta) {
   constexpr int G = Lay::kG, NG = 3 * G;
-  constexpr int kSegCntN = NG + 1;
   using Ctx = typename Lay::Ctx;
-  (void)kSegCntN;
+  constexpr int kSegCnt = NG + 1;  // per segment: the group counts, then same-below-x
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int k = nseg[i];
     if (k == 0) continue;
@@ -527,7 +519,7 @@ __global__ void lay_seg_prefix_kernel(Lay lay, int64_t n, const int32_t* nseg, c
     int tot[NG] = {};
     int slt = 0;
     for (int j = 0; j < k; ++j) {
-      const int32_t* sc = seg_cnt + kSegCntN * (s0 + j);
+      const int32_t* sc = seg_cnt + kSegCnt * (s0 + j);
 #pragma unroll
       for (int g = 0; g < NG; ++g) tot[g] += sc[g];
       slt += sc[NG];
@@ -538,7 +530,7 @@ __global__ void lay_seg_prefix_kernel(Lay lay, int64_t n, const int32_t* nseg, c
     const int zero[NG] = {};
     group_starts(c.ob, tot, zero, p);
     for (int j = 0; j < k; ++j) {
-      const int32_t* sc = seg_cnt + kSegCntN * (s0 + j);
+      const int32_t* sc = seg_cnt + kSegCnt * (s0 + j);
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
         seg_pre[NG * (s0 + j) + g] = p[g];
@@ -554,9 +546,7 @@ __global__ __launch_bounds__(kThreads) void lay_seg_write_kernel(Lay lay, const 
                                                                  const int64_t* seg_off, const int32_t* seg_vtx,
                                                                  const int64_t* seg_pre, int32_t* out) {
   constexpr int G = Lay::kG, NG = 3 * G;
-  constexpr int kSegCntN = NG + 1;
   using Ctx = typename Lay::Ctx;
-  (void)kSegCntN;
   const int64_t nsegs = seg_off[n];
   const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
