@@ -165,7 +165,11 @@ typedef struct tc_tuning {
                                  Hfwd(x) against the Up part of its table
                                  (>= 32; -1 = x always; default 256 for
                                  graphs of at least 2^26 entries, else -1) */
-  int32_t reserved[1];
+  int32_t degree_groups;      /* cover count: the relabel orders each level by
+                                 this many degree groups (2: degree up to 2048,
+                                 then the rest; 4: up to 511, 512-2047,
+                                 2048-8191, 8192 and above); default 4 for
+                                 graphs of at least 2^26 entries, else 2 */
 } tc_tuning;
 
 #define TC_SMALL_MAX_N 65536

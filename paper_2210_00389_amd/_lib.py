@@ -54,12 +54,11 @@ class TcBatch(ctypes.Structure):
 
 TUNING_FIELDS = ("batch_block", "batch_piece", "batch_blocks_per_cu", "small_max_n", "small_max_nnz",
                  "light_max", "dn_light", "bitmap_member_words", "bitmap_desc_words", "item_log2", "bin0_mode",
-                 "bins_mode", "twolevel_sparsity", "bin0_max_desc", "up_anchor_min")
-TUNING_RESERVED = 1
+                 "bins_mode", "twolevel_sparsity", "bin0_max_desc", "up_anchor_min", "degree_groups")
 
 
 class TcTuning(ctypes.Structure):
-    _fields_ = [(f, ctypes.c_int32) for f in TUNING_FIELDS] + [("reserved", ctypes.c_int32 * TUNING_RESERVED)]
+    _fields_ = [(f, ctypes.c_int32) for f in TUNING_FIELDS]
 
 
 class TcProfile(ctypes.Structure):

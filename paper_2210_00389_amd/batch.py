@@ -102,7 +102,7 @@ def make_tuning(t: dict | None) -> L.TcTuning | None:
     unknown = set(t) - set(L.TUNING_FIELDS)
     if unknown:
         raise ValueError(f"unknown tuning fields {sorted(unknown)}")
-    return L.TcTuning(*[int(t.get(f, 0)) for f in L.TUNING_FIELDS], (ctypes.c_int32 * L.TUNING_RESERVED)())
+    return L.TcTuning(*[int(t.get(f, 0)) for f in L.TUNING_FIELDS])
 
 
 @_on_stream

@@ -795,11 +795,12 @@ int relabel_groups(const tc_csr* g, const int32_t* L, const uint32_t* comp0, int
 
 }  // namespace
 
-int relabel_run(const tc_csr* g, const int32_t* L, const uint32_t* comp0, int32_t d0, int32_t nvl, RelabelWs& w,
-                SplitWs& sp, hipStream_t s) {
+int relabel_run(const tc_csr* g, const int32_t* L, const uint32_t* comp0, int32_t d0, int32_t nvl,
+                int degree_groups, RelabelWs& w, SplitWs& sp, hipStream_t s) {
   if (g->n == 0) return TC_OK;
-  if (g->nnz >= (int64_t(1) << 26)) return relabel_groups<4>(g, L, comp0, d0, nvl, w, sp, s);
-  return relabel_groups<2>(g, L, comp0, d0, nvl, w, sp, s);
+  if (degree_groups == 4) return relabel_groups<4>(g, L, comp0, d0, nvl, w, sp, s);
+  if (degree_groups == 2) return relabel_groups<2>(g, L, comp0, d0, nvl, w, sp, s);
+  return fail(TC_ERR_INVALID_ARG, "relabel: degree_groups must be 2 or 4");
 }
 
 int hlist_run(const tc_csr* g, const VMeta* meta, const int32_t* cols, int64_t* h_off, int32_t* h_u, int32_t* h_v,

@@ -221,7 +221,7 @@ int cover_call(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles
   tc_csr rg = *g;  // the relabelled graph
   if (g->n > 0) {
     prof_stage("relabel");
-    TC_TRY(relabel_run(g, L, p.comp0, d0, d0 + nl + 1, p.relabel, p.split, s));
+    TC_TRY(relabel_run(g, L, p.comp0, d0, d0 + nl + 1, prm.degree_groups, p.relabel, p.split, s));
     rg.row_offsets = p.relabel.off;
     rg.cols = p.split.scols;
   }

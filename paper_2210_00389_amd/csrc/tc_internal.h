@@ -97,8 +97,9 @@ struct RelabelWs {
 RelabelWs relabel_reserve(Carver& c, int64_t n, int64_t max_vlevels);
 // Writes the relabelled rows into split.scols and records into split.meta
 // (indexed by new ids); fills w.off, w.order, w.perm.
+// degree_groups: 2 or 4 degree groups per level (see tc_tuning).
 int relabel_run(const tc_csr* g, const int32_t* L, const uint32_t* comp0, int32_t d0, int32_t max_vl,
-                RelabelWs& w, SplitWs& sp, hipStream_t s);
+                int degree_groups, RelabelWs& w, SplitWs& sp, hipStream_t s);
 
 // Explicit horizontal-edge list from the layout: h_off = scan of
 // (sfe - hfb), then (x, scols[..]) for every cover edge, lexicographic.
@@ -151,6 +152,7 @@ struct CountParams {
   int tl_sparsity; // largest hash bin: two-level table instead when window >= this * |P| (-1: never)
   int bin0_max_desc; // anchors with more descriptors skip the smallest-table bin (-1: no limit)
   int up_anchor_min; // down-class pair (x, w): w anchors it when |Up(w)| > this and > |Hfwd(x)| (-1: never)
+  int degree_groups; // cover count: degree groups per level of the relabel (2 or 4)
 };
 // The defaults, overridden by the non-zero fields of `t` (nullable);
 // TC_ERR_INVALID_ARG for a value out of range.

@@ -38,9 +38,11 @@ SPACE = {
     "twolevel_sparsity": [-1, 16, 256],
     "bin0_max_desc": [-1, 256, 4096],
     "up_anchor_min": [-1, 256],
+    "degree_groups": [2, 4],
 }
 # the comparator has no down class and no one-workgroup path
-EDGE_SPACE = {k: v for k, v in SPACE.items() if k not in ("dn_light", "small_max_n", "small_max_nnz", "up_anchor_min")}
+EDGE_SPACE = {k: v for k, v in SPACE.items() if k not in ("dn_light", "small_max_n", "small_max_nnz", "up_anchor_min",
+                                                          "degree_groups")}
 # a shorter search for graphs whose calls take long (the benchmark's
 # comparator at R-MAT scale 24): the knobs that moved it in measurements
 EDGE_SPACE_SHORT = {"item_log2": [16, 17, 18], "bitmap_desc_words": [32], "bins_mode": [1],

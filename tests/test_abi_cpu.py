@@ -102,7 +102,7 @@ def test_tuning_out_of_range_without_gpu(lib):
     t = ctypes.c_int64(0)
     for bad in (dict(light_max=33), dict(light_max=-1), dict(dn_light=-2), dict(item_log2=11), dict(item_log2=25),
                 dict(bitmap_desc_words=2000), dict(bin0_mode=3), dict(bins_mode=-1), dict(bin0_max_desc=-2),
-                dict(up_anchor_min=31), dict(up_anchor_min=-2)):
+                dict(up_anchor_min=31), dict(up_anchor_min=-2), dict(degree_groups=3)):
         tu = make_tuning(dict(bad, small_max_n=-1))
         rc = lib.tc_count_tuned(ctypes.byref(csr), -1, 0, ctypes.byref(tu), ctypes.byref(t), None, None, None,
                                 ctypes.c_void_p(256), 1 << 40, None)

@@ -287,7 +287,8 @@ TUNINGS = [dict(light_max=1, dn_light=1), dict(light_max=8, dn_light=4, item_log
            dict(light_max=32, dn_light=1000, item_log2=16, bins_mode=2, bin0_mode=2),
            dict(twolevel_sparsity=1), dict(twolevel_sparsity=-1, bins_mode=1), dict(bin0_max_desc=1),
            dict(bin0_max_desc=-1, bitmap_member_words=64), dict(up_anchor_min=32),
-           dict(up_anchor_min=32, light_max=8, dn_light=4, bitmap_member_words=1, bitmap_desc_words=1)]
+           dict(up_anchor_min=32, light_max=8, dn_light=4, bitmap_member_words=1, bitmap_desc_words=1),
+           dict(degree_groups=4), dict(degree_groups=4, up_anchor_min=32, bitmap_desc_words=1)]
 
 
 def test_determinism_across_tunings(tc):
