@@ -59,7 +59,8 @@ typedef enum tc_status {
   TC_ERR_SELF_LOOP = -5,     /* u in N(u) (TC_VALIDATE) */
   TC_ERR_NOT_SYMMETRIC = -6, /* v in N(u) but u not in N(v) (TC_VALIDATE) */
   TC_ERR_OUT_OF_RANGE = -7,  /* an id outside [0, n) */
-  TC_ERR_TOO_LARGE = -8,     /* n or nnz beyond the int32-id / int64 limits */
+  TC_ERR_TOO_LARGE = -8,     /* n or nnz beyond the int32-id / int64 limits, or
+                                a degree that could reach 2^29 (counting calls) */
   TC_ERR_HIP = -9,           /* a HIP runtime call failed */
   TC_ERR_BAD_OFFSETS = -10   /* row_offsets not monotone or not from 0 to nnz */
 } tc_status;
@@ -235,7 +236,10 @@ int tc_cover_edges(const tc_csr* g, const int32_t* levels, int32_t* h_u, int32_t
  * Synchronises `stream` during the BFS as tc_bfs_levels does; the rest
  * (relabelling, layout, count) is asynchronous.  Graphs within the
  * small-graph bounds (TC_SMALL_MAX_N vertices, TC_SMALL_MAX_NNZ entries)
- * take the path of tc_count_tuned, which never synchronises. */
+ * take the path of tc_count_tuned, which never synchronises.  A graph in
+ * which a vertex could reach degree 2^29 (n - 1 and nnz / 2 both at least
+ * 2^29) gives TC_ERR_TOO_LARGE: the count keeps list lengths below 2^29
+ * (tc_list_triangles and tc_count_edge_baseline share the limit). */
 int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles,
              int64_t* h_count, int32_t* levels, int64_t* per_vertex, void* ws,
              size_t ws_bytes, tc_stream_t stream);

@@ -21,6 +21,19 @@ int check_csr(const tc_csr* g, const char* fn) {
   return TC_OK;
 }
 
+// The count kernels keep a list length below 2^29 beside a flag bit in each
+// stream record, so the counting calls refuse graphs in which a vertex could
+// reach degree 2^29.  A degree is at most n - 1 and at most nnz / 2 (every
+// edge is stored in both rows): only graphs beyond both bounds are refused.
+constexpr int64_t kMaxListLen = int64_t(1) << 29;
+
+int check_degree_bound(const tc_csr* g, const char* fn) {
+  if (g->n - 1 >= kMaxListLen && g->nnz / 2 >= kMaxListLen)
+    return fail(TC_ERR_TOO_LARGE, "%s: n - 1 and nnz / 2 both reach 2^29, so a degree could exceed the longest list "
+                "a stream record holds", fn);
+  return TC_OK;
+}
+
 int check_ws(void* ws, size_t ws_bytes, size_t need, const char* fn) {
   if (ws_bytes < need)
     return fail(TC_ERR_WORKSPACE, "%s: workspace of %zu bytes, %zu needed", fn, ws_bytes, need);
@@ -252,6 +265,7 @@ int tc_count_tuned(const tc_csr* g, int64_t root, uint32_t flags, const tc_tunin
                    int64_t* h_count, int32_t* levels, int64_t* per_vertex, void* ws, size_t ws_bytes,
                    tc_stream_t stream) {
   TC_TRY(check_csr(g, "tc_count"));
+  TC_TRY(check_degree_bound(g, "tc_count"));
   if (!triangles) return fail(TC_ERR_INVALID_ARG, "tc_count: triangles is NULL");
   if (root >= g->n || root < -1) return fail(TC_ERR_INVALID_ARG, "tc_count: root %lld out of range", (long long)root);
   const bool pv = flags & TC_PER_VERTEX;
@@ -282,6 +296,7 @@ int tc_count(const tc_csr* g, int64_t root, uint32_t flags, int64_t* triangles, 
 int tc_list_triangles(const tc_csr* g, int64_t root, uint32_t flags, int32_t* tri, int64_t cap, int64_t* triangles,
                       int64_t* h_count, int32_t* levels, void* ws, size_t ws_bytes, tc_stream_t stream) {
   TC_TRY(check_csr(g, "tc_list_triangles"));
+  TC_TRY(check_degree_bound(g, "tc_list_triangles"));
   if (!triangles) return fail(TC_ERR_INVALID_ARG, "tc_list_triangles: triangles is NULL");
   if (cap < 0 || (cap > 0 && !tri)) return fail(TC_ERR_INVALID_ARG, "tc_list_triangles: bad output buffer");
   if (flags & TC_PER_VERTEX) return fail(TC_ERR_INVALID_ARG, "tc_list_triangles: TC_PER_VERTEX not supported");
@@ -334,6 +349,7 @@ int tc_count_edge_baseline(const tc_csr* g, uint32_t flags, int64_t* triangles, 
 int tc_count_edge_baseline_tuned(const tc_csr* g, uint32_t flags, const tc_tuning* tuning, int64_t* triangles,
                                  void* ws, size_t ws_bytes, tc_stream_t stream) {
   TC_TRY(check_csr(g, "tc_count_edge_baseline"));
+  TC_TRY(check_degree_bound(g, "tc_count_edge_baseline"));
   if (!triangles) return fail(TC_ERR_INVALID_ARG, "tc_count_edge_baseline: triangles is NULL");
   CountParams prm;
   TC_TRY(count_params(tuning, false, g->nnz, &prm));

@@ -77,6 +77,17 @@ def test_argument_errors_without_gpu(lib):
     assert "workspace" in lib.tc_last_error().decode()
     # root out of range
     assert lib.tc_count(ctypes.byref(csr), 10, 0, ctypes.byref(t), None, None, None, None, 1 << 30, None) == -1
+    # a degree could reach 2^29 (n - 1 and nnz / 2 both at least 2^29): refused
+    # by the counting calls, before the workspace is looked at
+    big = _lib.TcCsr((1 << 29) + 1, 1 << 30, 1, 1)
+    assert lib.tc_count(ctypes.byref(big), -1, 0, ctypes.byref(t), None, None, None, None, 0, None) == -8
+    assert "2^29" in lib.tc_last_error().decode()
+    assert lib.tc_count_edge_baseline(ctypes.byref(big), 0, ctypes.byref(t), None, 0, None) == -8
+    assert lib.tc_list_triangles(ctypes.byref(big), -1, 0, None, 0, ctypes.byref(t), None, None, None, 0, None) == -8
+    # one entry fewer (nnz / 2 below 2^29), or one vertex fewer: past this check
+    for n, nnz in (((1 << 29) + 1, (1 << 30) - 2), (1 << 29, 1 << 30)):
+        ok = _lib.TcCsr(n, nnz, 1, 1)
+        assert lib.tc_count(ctypes.byref(ok), -1, 0, ctypes.byref(t), None, None, None, None, 16, None) == -2
 
 
 def test_batch_argument_errors_without_gpu(lib):
