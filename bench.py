@@ -845,6 +845,12 @@ def rmat_line(args, scale, steps, warmup, comparator=True, stream=True, root_can
         else:
             stage_roofs[k] = {"ms": round(v, 4)}
 
+    # the whole path: every stage's algorithmic bytes over the time per count
+    path_bytes = sum(b for b in (stage_bytes(k, st, n, nnz, True) for k in stage_avg) if b is not None)
+    path_gbs = path_bytes / (ms / 1000.0) / 1e9
+    end_to_end = {"algorithmic_bytes": int(path_bytes), "ms": round(ms, 4), "GB/s": round(path_gbs, 1),
+                  "frac": round(path_gbs / HBM_PEAK_GBS, 4)}
+
     golden = None
     gpath = os.path.join(ROOT, "tests", "golden", f"rmat_s{scale}.json")
     if args.edge_factor == 16 and args.seed == 1 and os.path.exists(gpath):
@@ -903,6 +909,7 @@ def rmat_line(args, scale, steps, warmup, comparator=True, stream=True, root_can
         "comparator": comp,
         "speedup_vs_comparator": (comp["ms_per_step"] / ms) if comp else None,
         "roofline": roof,
+        "end_to_end": end_to_end,
         "stream_bw": sbw,
         "stages": stage_roofs,
         "work": st,
@@ -965,7 +972,7 @@ def bench_rmat(args, kids):
                          stream=False)
         out[f"rmat{args.nested_scale}"] = {k: nest[k] for k in (
             "value", "unit", "ms_per_step", "p50_ms", "p99_ms", "triangles_per_s", "config", "comparator",
-            "speedup_vs_comparator", "roofline", "stages", "golden", "tuning")}
+            "speedup_vs_comparator", "roofline", "end_to_end", "stages", "golden", "tuning")}
     cpu = None
     if "cpu" in kids:
         log("[bench] waiting for the CPU oracle legs")
