@@ -748,7 +748,7 @@ def summarize_counters(args):
     print(json.dumps({"summary": args.out}), flush=True)
 
 
-def rmat_line(args, scale, steps, warmup, comparator=True, stream=True, root_candidates=0):
+def rmat_line(args, scale, steps, warmup, comparator=True, stream=True, root_candidates=0, profile=True):
     """One single-graph line: tc_count on R-MAT `scale` resident in HBM,
     timed over `steps` calls after `warmup`, beside the comparator, with
     the dominant stage's roofline and per-stage rates."""
@@ -793,7 +793,9 @@ def rmat_line(args, scale, steps, warmup, comparator=True, stream=True, root_can
     step = lambda: tc.count(G, ws=ws, out=res, tuning=tun_c)  # noqa: E731
     base = lambda: tc.count_edge_baseline(G, ws=ws, out=tb, tuning=tun_b)  # noqa: E731
 
-    tc.profile_enable(True)
+    # per-stage HIP events (for the stage rates and the roofline); the
+    # latency line times both paths without them
+    tc.profile_enable(profile)
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
@@ -826,8 +828,8 @@ def rmat_line(args, scale, steps, warmup, comparator=True, stream=True, root_can
 
     ms = 1000 * wall / steps
     stage_avg = {k: statistics.mean(v) for k, v in stages.items()}
-    dom = max(stage_avg, key=stage_avg.get)
-    dom_bytes = stage_bytes(dom, st, n, nnz, True)
+    dom = max(stage_avg, key=stage_avg.get) if stage_avg else None
+    dom_bytes = stage_bytes(dom, st, n, nnz, True) if dom else None
     roof = None
     if dom_bytes is not None:
         ach = dom_bytes / (stage_avg[dom] / 1000.0) / 1e9
@@ -848,8 +850,8 @@ def rmat_line(args, scale, steps, warmup, comparator=True, stream=True, root_can
     # the whole path: every stage's algorithmic bytes over the time per count
     path_bytes = sum(b for b in (stage_bytes(k, st, n, nnz, True) for k in stage_avg) if b is not None)
     path_gbs = path_bytes / (ms / 1000.0) / 1e9
-    end_to_end = {"algorithmic_bytes": int(path_bytes), "ms": round(ms, 4), "GB/s": round(path_gbs, 1),
-                  "frac": round(path_gbs / HBM_PEAK_GBS, 4)}
+    end_to_end = ({"algorithmic_bytes": int(path_bytes), "ms": round(ms, 4), "GB/s": round(path_gbs, 1),
+                   "frac": round(path_gbs / HBM_PEAK_GBS, 4)} if path_bytes else None)
 
     golden = None
     gpath = os.path.join(ROOT, "tests", "golden", f"rmat_s{scale}.json")
@@ -959,7 +961,7 @@ def bench_rmat(args, kids):
     if args.latency_scale > 0:
         # the small-graph latency floor (1000 counts of R-MAT scale 10)
         lat = rmat_line(args, args.latency_scale, args.latency_steps, max(args.warmup, 20),
-                        comparator=not args.no_comparator, stream=False)
+                        comparator=not args.no_comparator, stream=False, profile=False)
         out[f"rmat{args.latency_scale}_latency"] = {k: lat[k] for k in (
             "ms_per_step", "p50_ms", "p99_ms", "config", "golden")}
         if lat["comparator"]:

@@ -113,6 +113,7 @@ typedef struct tc_batch {
 typedef struct tc_tuning {
   /* tc_count_batch */
   int32_t batch_block;        /* threads per block of the counting kernel:
+                                 64 (one block per piece, not persistent),
                                  256 (default) or 512 */
   int32_t batch_piece;        /* CSR entries per work piece (>= 1024,
                                  default 16384) */

@@ -12,11 +12,13 @@
 // The block writes the level parity as a bit array (Lemma 1: for adjacent
 // vertices L(x) = L(y) iff their parities agree, so the parity is all the
 // count needs), the optional int32 levels, and the graph's work pieces:
-// vertex ranges holding about `piece` CSR entries each.
+// piece p is the range [p * piece, (p + 1) * piece) of the graph's CSR
+// entries, so a vertex of large degree is spread over several pieces.
 //
 // Kernel 2 (persistent, pieces claimed from a counter): a wave takes one
-// vertex u at a time, sets the bits of N(u) in its own 65536-bit LDS bitmap,
-// and for every cover edge (u, v), v > u with equal parity, streams N(v) in
+// vertex u of the piece at a time, sets the bits of N(u) in its own
+// 65536-bit LDS bitmap, and for every cover edge (u, v), v > u with equal
+// parity, whose entry v of N(u) lies in the piece, streams N(v) in
 // chunks of kBChunk consecutive entries per lane (the stream of a lane's
 // chunk comes from a 64-bit mask of stream starts, no search) and counts the
 // w whose bit is set and that pass the test of Alg. 1 (parity of w differs
@@ -35,8 +37,8 @@ constexpr int kBigCap = 1024;    // LDS list of such vertices per pass (overflow
 constexpr int kRowLoads = 8;     // row entries a thread loads at once in the level passes
 constexpr int kBitmapWords = TC_BATCH_MAX_N / 32;
 constexpr int kPieceMin = 1024;  // smallest piece size accepted (sizes the piece slots)
-constexpr int kSmallPieceMin = 64;  // the same for the one-graph path of tc_count
-constexpr int kClaim = 2;        // pieces a block claims at once
+constexpr int kSmallPieceMin = 16;  // the same for the one-graph path of tc_count
+constexpr int kClaim = 2;        // pieces a block of 256 or 512 threads claims at once
 
 // Piece slots of graph g start at row_offsets[vbase[g]] / piece + g, parity
 // words at vbase[g] / 32 + g: both leave room for ceil(size / unit) entries.
@@ -219,10 +221,14 @@ __global__ __launch_bounds__(kBfsThreads) void batch_bfs_kernel(const int64_t* v
   const int64_t np = (nnz + piece - 1) / piece;
   int4* pc = pieces + piece_base(e0, piece, g);
   for (int64_t p = tid; p < np; p += nt) {
-    // piece p: first vertex whose row starts at or after e0 + p * piece
-    const int vb = p == 0 ? 0 : static_cast<int>(lower_bound_dev(rows, 0, n, e0 + p * piece));
-    const int ve = p + 1 == np ? n : static_cast<int>(lower_bound_dev(rows, 0, n, e0 + (p + 1) * piece));
-    pc[p] = make_int4(g, vb, ve, 0);
+    // piece p holds the entries [ps, ps + piece): its vertices run from the
+    // one whose row holds entry ps (the last row starting at or before it;
+    // rows[n] > ps, so that row is not empty) up to the last row starting
+    // before ps + piece (ve: the first row starting at or after it, or n)
+    const int64_t ps = e0 + p * piece;
+    const int vb = static_cast<int>(upper_bound_dev(rows, 0, static_cast<int64_t>(n) + 1, ps)) - 1;
+    const int ve = static_cast<int>(lower_bound_dev(rows, 0, static_cast<int64_t>(n), ps + piece));
+    pc[p] = make_int4(g, vb, ve, static_cast<int>(p));
   }
 }
 
@@ -240,14 +246,16 @@ __device__ __forceinline__ uint64_t wave_or_u64(uint64_t x) {
   return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
-// One chunk of up to 64 neighbours v = N(u)[base + lane] of vertex u, in one
+// One chunk of up to 64 neighbours v = N(u)[base + lane], kept when base +
+// lane lies in [klo, khi), of vertex u, in one
 // wave: the cover edges (u, v), v > u with u's parity, are compacted into
 // this wave's LDS lists (s_beg / s_v / s_off / s_len) and their lists N(v)
 // streamed in chunks of kBChunk entries per lane, each entry w counted when
 // its bit is set in the wave's bitmap of N(u) and it passes the test of
 // Alg. 1 (parity of w differs from u's, or w > v).  A short row (du <= 64)
 // passes its neighbours in registers (nbr, one per lane).
-__device__ __forceinline__ void count_chunk(int u, int64_t ru, int64_t du, int64_t base, bool shortrow, int32_t nbr,
+__device__ __forceinline__ void count_chunk(int u, int64_t ru, int64_t klo, int64_t khi, int64_t base, bool shortrow,
+                                            int32_t nbr,
                                             uint32_t pu, const int64_t* rows, const int32_t* cols,
                                             const uint32_t* s_par, const uint32_t* bm, int64_t* s_beg, int32_t* s_v,
                                             int32_t* s_off, int32_t* s_len, int64_t& cnt, int64_t& hc) {
@@ -256,7 +264,7 @@ __device__ __forceinline__ void count_chunk(int u, int64_t ru, int64_t du, int64
   int32_t v = -1;
   int len = 0;
   int64_t vb = 0;
-  if (k < du) {
+  if (k >= klo && k < khi) {
     v = shortrow ? nbr : cols[ru + k];
     if (v > u && par_bit(s_par, v) == pu) {
       vb = rows[v];
@@ -305,18 +313,19 @@ __device__ __forceinline__ void count_chunk(int u, int64_t ru, int64_t du, int64
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-// Vertices of more than kLongDeg neighbours are left to a phase at the end
-// of the piece in which every wave of the block takes a share of their
-// 64-neighbour chunks (each wave with its own bitmap of N(u)), so one hub
-// does not keep a single wave busy while the others wait.
+// Vertices with more than kLongDeg neighbours inside the piece are left to
+// a phase at the end of the piece in which every wave of the block takes a
+// share of their 64-neighbour chunks (each wave with its own bitmap of
+// N(u)), so one hub does not keep a single wave busy while the others wait.
 constexpr int kLongDeg = 4 * kWave;
 constexpr int kLongCap = 64;  // deferred vertices per piece (more: counted by the claiming wave)
 
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vbase, const int64_t* row_offsets,
                                                               const int32_t* cols, const uint32_t* parity,
-                                                              const int4* pieces, int64_t nslots,
-                                                              unsigned long long* ctr, int64_t* T, int64_t* H) {
+                                                              const int4* pieces, int64_t nslots, int piece,
+                                                              int claim_n, unsigned long long* ctr, int64_t* T,
+                                                              int64_t* H) {
   constexpr int NW = THREADS / kWave;
   __shared__ uint32_t s_bm[NW][kBitmapWords];
   __shared__ int32_t s_off[NW][kWave];  // first chunk of each compacted stream
@@ -330,13 +339,21 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
   const int tid = threadIdx.x, wv = tid / kWave, ln = lane();
   uint32_t* bm = s_bm[wv];
   for (int i = ln; i < kBitmapWords; i += kWave) bm[i] = 0u;
-  if (tid == 0) s_claim = atomicAdd(ctr, static_cast<unsigned long long>(kClaim));
+  // claim_n > 0: persistent blocks claim claim_n slots at a time from the
+  // counter; claim_n = 0: block b takes slot b alone (one block per slot,
+  // no shared counter for a single small graph's many one-wave blocks)
+  if (tid == 0)
+    s_claim = claim_n > 0 ? atomicAdd(ctr, static_cast<unsigned long long>(claim_n))
+                          : static_cast<unsigned long long>(blockIdx.x);
   __syncthreads();
   unsigned long long claim = s_claim;
   while (claim < static_cast<unsigned long long>(nslots)) {
     unsigned long long next = 0;
-    if (tid == 0) next = atomicAdd(ctr, static_cast<unsigned long long>(kClaim));
-    const unsigned long long cend = min(claim + kClaim, static_cast<unsigned long long>(nslots));
+    if (tid == 0)
+      next = claim_n > 0 ? atomicAdd(ctr, static_cast<unsigned long long>(claim_n))
+                         : static_cast<unsigned long long>(nslots);
+    const unsigned long long cend =
+        min(claim + static_cast<unsigned long long>(claim_n > 0 ? claim_n : 1), static_cast<unsigned long long>(nslots));
     for (unsigned long long sl = claim; sl < cend; ++sl) {
       const int4 pc = pieces[sl];
       if (pc.x < 0 || pc.y >= pc.z) continue;  // empty slot (block-uniform)
@@ -346,6 +363,9 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
       // the graph's parity bits stay in global memory (at most 8 KB, cached):
       // keeping them out of LDS leaves room for more blocks per CU
       const uint32_t* s_par = parity + parity_base(v0, g);
+      // the piece's entries [ps, ps + piece): vertex u takes the neighbours
+      // N(u)[k] with ru + k inside them (its whole row sets the bitmap)
+      const int64_t ps = rows[0] + static_cast<int64_t>(pc.w) * piece;
       if (tid == 0) {
         s_next = pc.y;
         s_nlong = 0;
@@ -374,8 +394,10 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
           run = rows[un];
           dun = rows[un + 1] - run;
         }
+        const int64_t klo = ps > ru ? ps - ru : 0;
+        const int64_t khi = ps + piece - ru < du ? ps + piece - ru : du;
         int deferred = 0;
-        if (du > kLongDeg) {
+        if (khi - klo > kLongDeg) {
           if (ln == 0) {
             const int q = atomicAdd(&s_nlong, 1);
             if (q < kLongCap) {
@@ -397,9 +419,11 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
             }
           }
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          for (int64_t base = 0; base < du; base += kWave)
-            count_chunk(u, ru, du, base, shortrow, nbr, pu, rows, cols, s_par, bm, s_beg[wv], s_v[wv], s_off[wv],
-                        s_len[wv], cnt, hc);
+          // a short row's neighbours sit in lanes 0 .. du - 1 (one chunk
+          // from 0); a long row's chunks start at klo
+          for (int64_t base = shortrow ? 0 : klo; base < khi; base += kWave)
+            count_chunk(u, ru, klo, khi, base, shortrow, nbr, pu, rows, cols, s_par, bm, s_beg[wv], s_v[wv],
+                        s_off[wv], s_len[wv], cnt, hc);
           if (shortrow) {
             if (nbr >= 0) bm[nbr >> 5] = 0u;
           } else {
@@ -422,14 +446,17 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
       for (int j = 0; j < nlong; ++j) {
         const int lu = s_long[j];
         const int64_t lr = rows[lu], ld = rows[lu + 1] - lr;
+        const int64_t klo = ps > lr ? ps - lr : 0;
+        const int64_t khi = ps + piece - lr < ld ? ps + piece - lr : ld;
         const uint32_t pu = par_bit(s_par, lu);
         for (int64_t k = ln; k < ld; k += kWave) {
           const int32_t w = cols[lr + k];
           atomicOr(&bm[w >> 5], 1u << (w & 31));
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        for (int64_t base = static_cast<int64_t>(wv) * kWave; base < ld; base += static_cast<int64_t>(NW) * kWave)
-          count_chunk(lu, lr, ld, base, false, -1, pu, rows, cols, s_par, bm, s_beg[wv], s_v[wv], s_off[wv],
+        for (int64_t base = klo + static_cast<int64_t>(wv) * kWave; base < khi;
+             base += static_cast<int64_t>(NW) * kWave)
+          count_chunk(lu, lr, klo, khi, base, false, -1, pu, rows, cols, s_par, bm, s_beg[wv], s_v[wv], s_off[wv],
                       s_len[wv], cnt, hc);
         for (int64_t k = ln; k < ld; k += kWave) bm[cols[lr + k] >> 5] = 0u;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -448,9 +475,18 @@ __global__ __launch_bounds__(THREADS) void batch_count_kernel(const int64_t* vba
   }
 }
 
-__global__ void empty_pieces_kernel(int4* pieces, int64_t nslots) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nslots; i += (int64_t)gridDim.x * blockDim.x)
-    pieces[i] = make_int4(-1, 0, 0, 0);
+// Clears the claim counters and marks every piece slot empty, in one launch;
+// the one-graph path of tc_count also has its vertex bases {0, n} written
+// here (vbase not null).
+__global__ void batch_prep_kernel(unsigned long long* ctr, int4* pieces, int64_t nslots, int64_t* vbase,
+                                  int64_t one_n) {
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t0 < 4) ctr[t0] = 0ull;
+  if (vbase && t0 == 0) {
+    vbase[0] = 0;
+    vbase[1] = one_n;
+  }
+  for (int64_t i = t0; i < nslots; i += (int64_t)gridDim.x * blockDim.x) pieces[i] = make_int4(-1, 0, 0, 0);
 }
 
 struct BatchPlan {
@@ -473,13 +509,18 @@ BatchPlan plan_batch(void* base, int64_t total_n, int64_t total_nnz, int32_t G, 
 }
 
 template <int THREADS>
-int launch_count(const tc_batch* b, const BatchPlan& p, int64_t nslots, int blocks_per_cu, int64_t* T, int64_t* H,
-                 hipStream_t s) {
-  // persistent blocks; no more than there are piece slots to claim
+int launch_count(const tc_batch* b, const BatchPlan& p, int64_t nslots, int piece, int blocks_per_cu, int64_t* T,
+                 int64_t* H, hipStream_t s) {
+  // persistent blocks, no more than there are piece slots to claim; or,
+  // for one-wave blocks, one block per slot with no shared counter (the
+  // pieces of a single small graph then spread over as many waves as there
+  // are pieces, and no claim waits on thousands of others)
+  const int claim_n = THREADS == kWave ? 0 : kClaim;
   const int64_t full = static_cast<int64_t>(num_cus()) * blocks_per_cu;
-  const int64_t blocks = (nslots + kClaim - 1) / kClaim < full ? (nslots + kClaim - 1) / kClaim : full;
+  const int64_t want = claim_n > 0 ? (nslots + claim_n - 1) / claim_n : nslots;
+  const int64_t blocks = claim_n == 0 || want < full ? want : full;
   batch_count_kernel<THREADS><<<static_cast<unsigned>(blocks), THREADS, 0, s>>>(
-      b->vbase, b->row_offsets, b->cols, p.parity, p.pieces, nslots, p.ctr, T, H);
+      b->vbase, b->row_offsets, b->cols, p.parity, p.pieces, nslots, piece, claim_n, p.ctr, T, H);
   TC_HIP(hipGetLastError());
   return TC_OK;
 }
@@ -490,45 +531,52 @@ size_t batch_ws_bytes(int64_t total_n, int64_t total_nnz, int32_t num_graphs, in
   return plan_batch(nullptr, total_n, total_nnz, num_graphs, piece_min).bytes;
 }
 
-int batch_run(const tc_batch* b, const tc_tuning* t, uint32_t flags, int64_t* triangles, int64_t* h_count,
-              int32_t* levels, void* ws, size_t ws_bytes, hipStream_t s, int32_t root0, int piece_min) {
+namespace {
+
+// The launches of a batch (tuning checked here, validation done by the
+// caller); one_vbase: the one-graph path's vertex bases, written first.
+int batch_launch(const tc_batch* b, const tc_tuning* t, int64_t* triangles, int64_t* h_count, int32_t* levels,
+                 void* ws, size_t ws_bytes, hipStream_t s, int32_t root0, int piece_min, int64_t* one_vbase) {
   const int G = b->num_graphs;
-  if (G == 0) return TC_OK;
-  if (flags & TC_VALIDATE) TC_TRY(validate_batch_run(b, ws, s));
   int threads = 256, piece = 16384, bpc = 0;
   if (t) {
     if (t->batch_block) threads = t->batch_block;
     if (t->batch_piece) piece = t->batch_piece;
     bpc = t->batch_blocks_per_cu;
   }
-  if (threads != 256 && threads != 512)
-    return fail(TC_ERR_INVALID_ARG, "tc_count_batch: batch_block must be 256 or 512 (got %d)", threads);
+  if (threads != kWave && threads != 256 && threads != 512)
+    return fail(TC_ERR_INVALID_ARG, "tc_count_batch: batch_block must be 64, 256 or 512 (got %d)", threads);
   if (piece < piece_min) return fail(TC_ERR_INVALID_ARG, "tc_count_batch: batch_piece must be >= %d", piece_min);
   // LDS per block: one bitmap per wave of 8 KB, plus staging
-  const int max_bpc = threads == 256 ? 4 : 2;  // blocks that fit a CU's LDS
+  const int max_bpc = threads == kWave ? 16 : (threads == 256 ? 4 : 2);  // blocks that fit a CU's LDS
   if (bpc <= 0 || bpc > max_bpc) bpc = max_bpc;
   BatchPlan p = plan_batch(ws, b->total_vertices, b->total_nnz, G, piece_min);
   if (ws_bytes < p.bytes) return fail(TC_ERR_WORKSPACE, "tc_count_batch: workspace %zu < %zu", ws_bytes, p.bytes);
   const int64_t nslots = b->total_nnz / piece + G + 2;
   prof_stage("batch_bfs");
-  TC_TRY(fill_i64(reinterpret_cast<int64_t*>(p.ctr), 0, 4, s));
-  empty_pieces_kernel<<<grid_for(nslots, 256, 8192), 256, 0, s>>>(p.pieces, nslots);
+  batch_prep_kernel<<<grid_for(nslots, 256, 8192), 256, 0, s>>>(p.ctr, p.pieces, nslots, one_vbase,
+                                                                 b->total_vertices);
   TC_HIP(hipGetLastError());
   batch_bfs_kernel<<<static_cast<unsigned>(G), kBfsThreads, 0, s>>>(b->vbase, b->row_offsets, b->cols, piece, levels,
                                                                     p.parity, p.pieces, triangles, h_count, root0);
   TC_HIP(hipGetLastError());
   prof_stage("batch_count");
-  if (threads == 256) TC_TRY(launch_count<256>(b, p, nslots, bpc, triangles, h_count, s));
-  else TC_TRY(launch_count<512>(b, p, nslots, bpc, triangles, h_count, s));
+  if (threads == kWave) TC_TRY(launch_count<kWave>(b, p, nslots, piece, bpc, triangles, h_count, s));
+  else if (threads == 256) TC_TRY(launch_count<256>(b, p, nslots, piece, bpc, triangles, h_count, s));
+  else TC_TRY(launch_count<512>(b, p, nslots, piece, bpc, triangles, h_count, s));
   return TC_OK;
 }
 
-namespace {
+}  // namespace
 
-__global__ void small_setup_kernel(int64_t* vbase, int64_t n) {
-  vbase[0] = 0;
-  vbase[1] = n;
+int batch_run(const tc_batch* b, const tc_tuning* t, uint32_t flags, int64_t* triangles, int64_t* h_count,
+              int32_t* levels, void* ws, size_t ws_bytes, hipStream_t s, int32_t root0, int piece_min) {
+  if (b->num_graphs == 0) return TC_OK;
+  if (flags & TC_VALIDATE) TC_TRY(validate_batch_run(b, ws, s));
+  return batch_launch(b, t, triangles, h_count, levels, ws, ws_bytes, s, root0, piece_min, nullptr);
 }
+
+namespace {
 
 __global__ void small_stats_kernel(int64_t* stats, int64_t n, int64_t nnz, const int64_t* H) {
   for (int i = 0; i < 24; ++i) stats[i] = 0;
@@ -570,8 +618,6 @@ int small_count_run(const tc_csr* g, int64_t root, int64_t* triangles, int64_t* 
   if (ws_bytes < p.bytes) return fail(TC_ERR_WORKSPACE, "tc_count: workspace %zu < %zu", ws_bytes, p.bytes);
   int64_t* H = h_count ? h_count : p.h;
   prof_stage("small_count");
-  small_setup_kernel<<<1, 1, 0, s>>>(p.vbase, g->n);
-  TC_HIP(hipGetLastError());
   tc_batch b;
   b.num_graphs = 1;
   b.total_vertices = g->n;
@@ -580,13 +626,16 @@ int small_count_run(const tc_csr* g, int64_t root, int64_t* triangles, int64_t* 
   b.row_offsets = g->row_offsets;
   b.cols = g->cols;
   b.max_graph_vertices = static_cast<int32_t>(g->n);
-  // pieces of about a quarter of a block's share of the CSR entries (at
-  // least kSmallPieceMin), so that a small graph still spreads over the CUs
+  // one-wave counting blocks (sixteen per CU), each taking one piece at a
+  // time, and pieces of one such block's share of the CSR entries (at least
+  // kSmallPieceMin): a graph's vertices of large degree are cut across many
+  // waves instead of keeping one block busy
   tc_tuning t{};
-  const int64_t share = g->nnz / (4 * static_cast<int64_t>(num_cus()));
+  t.batch_block = kWave;
+  const int64_t share = g->nnz / (16 * static_cast<int64_t>(num_cus()));
   t.batch_piece = static_cast<int32_t>(share < kSmallPieceMin ? kSmallPieceMin : (share > 16384 ? 16384 : share));
-  TC_TRY(batch_run(&b, &t, 0, triangles, H, levels, p.batch, p.bytes - (p.batch - static_cast<char*>(ws)), s,
-                   static_cast<int32_t>(root), kSmallPieceMin));
+  TC_TRY(batch_launch(&b, &t, triangles, H, levels, p.batch, p.bytes - (p.batch - static_cast<char*>(ws)), s,
+                      static_cast<int32_t>(root), kSmallPieceMin, p.vbase));
   small_stats_kernel<<<1, 1, 0, s>>>(p.stats, g->n, g->nnz, H);
   TC_HIP(hipGetLastError());
   return TC_OK;

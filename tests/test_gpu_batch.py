@@ -72,7 +72,8 @@ def test_batch_closed_forms_and_edge_cases():
 
 
 @pytest.mark.parametrize("tuning", [dict(batch_block=256, batch_piece=1024), dict(batch_block=512, batch_piece=4096),
-                                    dict(batch_block=256, batch_piece=65536, batch_blocks_per_cu=1)])
+                                    dict(batch_block=256, batch_piece=65536, batch_blocks_per_cu=1),
+                                    dict(batch_block=64, batch_piece=1024)])
 def test_batch_tunings_agree(tuning):
     print(f"case: tuning {tuning}", flush=True)
     _check(graphgen.batch_mix(48, seed_base=777, n_max=16384), tuning, levels=False)
