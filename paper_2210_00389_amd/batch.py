@@ -170,6 +170,8 @@ _TUNE_CANDIDATES = [
     dict(batch_block=256, batch_piece=65536), dict(batch_block=512, batch_piece=4096),
     dict(batch_block=512, batch_piece=16384), dict(batch_block=512, batch_piece=65536),
     dict(batch_block=256, batch_piece=16384, batch_blocks_per_cu=2),
+    dict(batch_block=64, batch_piece=1024), dict(batch_block=64, batch_piece=2048),
+    dict(batch_block=64, batch_piece=4096),
 ]
 
 
