@@ -454,7 +454,10 @@ class GpuExecutor:
             cols = torch.cat([g.cols for g in graphs]) if eb[-1] > 0 else torch.zeros(1, dtype=torch.int32,
                                                                                         device=self.dev)
             b = B.Batch(vbase, row_offsets, cols[: int(eb[-1])], list(zip(ns, zs)))
-            res = B.count_batch(b, ws=self.ws[slot], stream=s, return_levels=self.levels_hash)
+            # one-wave counting blocks over pieces of 1024 entries: a handful of
+            # small graphs then spreads over many waves instead of one block
+            # per graph
+            res = B.count_batch(b, BATCH_TUNING, ws=self.ws[slot], stream=s, return_levels=self.levels_hash)
             T = res.triangles[: len(reqs)].cpu().tolist()
             H = res.h_count[: len(reqs)].cpu().tolist()
             if self.levels_hash:
@@ -468,6 +471,7 @@ class GpuExecutor:
 
 
 SMALL_N = 65536        # the batched kernels' per-graph vertex limit
+BATCH_TUNING = {"batch_block": 64, "batch_piece": 1024}  # coalesced launches of a few graphs
 SMALL_NNZ = 1 << 18    # entries up to which a graph is coalesced into a batch
 
 
