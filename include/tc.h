@@ -175,7 +175,7 @@ typedef struct tc_tuning {
 } tc_tuning;
 
 #define TC_SMALL_MAX_N 65536
-#define TC_SMALL_MAX_NNZ 131072
+#define TC_SMALL_MAX_NNZ 262144
 
 /* Bytes of workspace `op` needs for a graph with n vertices and nnz entries
  * (for TC_OP_BUILD_CSR, nnz = number of input pairs; for TC_OP_COUNT_BATCH,
