@@ -54,7 +54,10 @@ __global__ void root_key_kernel(const int64_t* off, int64_t n, unsigned long lon
 }
 
 
-constexpr int kBig = 4096;         // frontier rows above this length are expanded edge-balanced
+// frontier rows above this length are expanded edge-balanced over the grid
+// (a row below it is expanded by one wave: R-MAT S14's root, 3644 entries,
+// took 0.12 ms that way under a bound of 4096, against 5 us listed)
+constexpr int kBig = 1024;
 constexpr int kBigCap = 4096;      // listed rows per level (more: expanded by their thread)
 constexpr int kMaxParts = 4096;    // blocks of the step kernels (partials per kernel)
 // levels launched between two reads of the state: six covers a small-world
