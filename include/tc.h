@@ -143,7 +143,8 @@ typedef struct tc_tuning {
                                  (default 8 for the cover count, 16 for the
                                  comparator); else a hash table (1..1024) */
   int32_t item_log2;          /* work items hold about 2^item_log2 streamed
-                                 elements (12..24, default 19) */
+                                 elements (12..24, default 14 below 2^24
+                                 entries, else 19) */
   int32_t bin0_mode;          /* smallest-table bin: 1 = blocks claim items,
                                  2 = items round robin (default 2 for the
                                  cover count below 2^27 entries, else 1) */

@@ -1586,8 +1586,10 @@ int launch_all(const CountArgs& a, CountWs& w, const Out& o, hipStream_t s) {
   const unsigned gc = static_cast<unsigned>(gct < gmax ? gct : gmax);
   plan_kernel<kCover><<<gv, kThreads, 0, s>>>(a.cols, a.meta, n, w.ndesc, w.vinfo, w.pm, w.acc, a.prm);
   TC_HIP(hipGetLastError());
-  twolevel_words_kernel<<<grid_for(n, kThreads * kWave, 4096), kThreads, 0, s>>>(a.cols, a.meta, w.vinfo, n,
-                                                                               w.tl_words, w.tl_l1);
+  // a wave scans 64 vertices per round: about two rounds per wave (one
+  // block of a graph of 16 K vertices scanned them in 19 us)
+  twolevel_words_kernel<<<grid_for(n, kThreads * 2, 4096), kThreads, 0, s>>>(a.cols, a.meta, w.vinfo, n,
+                                                                           w.tl_words, w.tl_l1);
   TC_HIP(hipGetLastError());
   {
     Carver sc(w.scratch);
@@ -1640,7 +1642,11 @@ int count_params(const tc_tuning* t, bool cover, int64_t nnz, CountParams* out) 
   // cover count: 8 words per task (R-MAT S24 71.3 -> 69.7 ms, S20 3.71 ->
   // 3.63 ms, S22 within 0.5%); the comparator keeps 16
   p.bm_desc = cover ? 8 : 16;
-  p.item_log2 = kElemChunkLog;
+  // work items of 2^14 elements below 2^24 entries, where the heavy work is
+  // too small to fill the chip in 2^19-element items (R-MAT S14 0.708 ->
+  // 0.682 ms, S16 0.886 -> 0.842, Chung-Lu n = 10^5 0.844 -> 0.834; S18
+  // unchanged)
+  p.item_log2 = nnz < (int64_t(1) << 24) ? 14 : kElemChunkLog;
   p.tl_sparsity = 64;
   // Bin 0 (tables of 2 KB): on smaller graphs its items are short (about 500
   // elements at R-MAT S20) and two waves per block with half the blocks
