@@ -15,7 +15,8 @@
 // piece p is the range [p * piece, (p + 1) * piece) of the graph's CSR
 // entries, so a vertex of large degree is spread over several pieces.
 //
-// Kernel 2 (persistent, pieces claimed from a counter): a wave takes one
+// Kernel 2 (persistent blocks of 256 or 512 threads claiming pieces from a
+// counter, or one 64-thread block per piece): a wave takes one
 // vertex u of the piece at a time, sets the bits of N(u) in its own
 // 65536-bit LDS bitmap, and for every cover edge (u, v), v > u with equal
 // parity, whose entry v of N(u) lies in the piece, streams N(v) in
