@@ -515,8 +515,9 @@ int launch_count(const tc_batch* b, const BatchPlan& p, int64_t nslots, int piec
   // persistent blocks, no more than there are piece slots to claim; or,
   // for one-wave blocks, one block per slot with no shared counter (the
   // pieces of a single small graph then spread over as many waves as there
-  // are pieces, and no claim waits on thousands of others)
-  const int claim_n = THREADS == kWave ? 0 : kClaim;
+  // are pieces, and no claim waits on thousands of others) while that grid
+  // stays far below 2^32 work-items
+  const int claim_n = THREADS == kWave && nslots <= (int64_t(1) << 24) ? 0 : kClaim;
   const int64_t full = static_cast<int64_t>(num_cus()) * blocks_per_cu;
   const int64_t want = claim_n > 0 ? (nslots + claim_n - 1) / claim_n : nslots;
   const int64_t blocks = claim_n == 0 || want < full ? want : full;
