@@ -19,8 +19,12 @@
  *     in the method is integer order on these ids.
  *   - Pointers marked "device" are HIP device (or managed) memory; "host"
  *     pointers are ordinary host memory.  The caller owns every buffer; the
- *     library allocates and frees no memory and keeps no state between calls
- *     except the thread-local error text and the profiling switch.
+ *     library allocates and frees no device memory and keeps no state
+ *     between calls except the thread-local error text, the profiling
+ *     switch, per-device auxiliary streams and events (created on first use,
+ *     for table bins run side by side), one small pinned host buffer per
+ *     calling thread (the BFS state read back between groups of levels) and
+ *     the static device array of tc_count_batch_noalloc.
  *   - `ws` is a caller-provided device workspace of at least
  *     tc_workspace_bytes(op, ...) bytes, 256-byte aligned.  Its contents on
  *     entry are ignored; on return they are scratch.

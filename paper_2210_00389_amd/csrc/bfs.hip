@@ -433,6 +433,23 @@ unsigned step_grid(int64_t n) {
   return static_cast<unsigned>(g < 1 ? 1 : g);
 }
 
+// Pinned host copy of the BFS state, one per host thread (allocated on
+// first use, kept until the process ends; null if it cannot be had, and the
+// state is then read into pageable memory): a readback into pageable memory
+// goes through a staging copy and took about 13 us more per level group
+// (R-MAT S14 BFS 0.26 -> 0.24 ms, S20 0.31 -> 0.28 ms).
+BfsState* pinned_state() {
+  thread_local BfsState* p = nullptr;
+  thread_local bool tried = false;
+  if (!tried) {
+    tried = true;
+    void* q = nullptr;
+    if (hipHostMalloc(&q, sizeof(BfsState), hipHostMallocDefault) == hipSuccess) p = static_cast<BfsState*>(q);
+    else (void)hipGetLastError();  // the fallback needs no error left behind
+  }
+  return p;
+}
+
 // Runs the levels of the BFS whose state and level-0 bitmap are set, in
 // groups of kLevelsPerSync, until the frontier is empty.  Returns its level
 // count and, in *rest_out (nullable), the row entries of the vertices it
@@ -454,9 +471,12 @@ int bfs_levels_loop(const tc_csr* g, int32_t* L, BfsWs& w, int group, int32_t* l
       decide_kernel<<<1, kThreads, 0, s>>>(g->n, st, w.part, static_cast<int>(2 * gs));
     }
     TC_HIP(hipGetLastError());
-    BfsState h;
-    TC_HIP(hipMemcpyAsync(&h, st, sizeof h, hipMemcpyDeviceToHost, s));
+    BfsState* pin = pinned_state();
+    BfsState local;
+    BfsState* dst = pin ? pin : &local;
+    TC_HIP(hipMemcpyAsync(dst, st, sizeof(BfsState), hipMemcpyDeviceToHost, s));
     TC_HIP(hipStreamSynchronize(s));
+    const BfsState h = *dst;
     if (h.done) {
       *levels_out = h.num_levels;
       if (rest_out) *rest_out = h.unexplored;
