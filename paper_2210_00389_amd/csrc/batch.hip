@@ -125,14 +125,24 @@ __device__ void bfs_levels_lds(uint16_t* L, const int64_t* rows, const int32_t* 
       }
       __syncthreads();
       const int nbig = min(*s_nbig, kBigCap);
+      // a listed row is expanded by one wave, kRowLoads entries a lane at a
+      // time (independent loads in flight)
       for (int q = wv; q < nbig; q += nw) {
         const int i = s_big[q];
-        for (int64_t k = rows[i] + ln; k < rows[i + 1]; k += kWave) {
-          const int32_t w = cols[k];
-          if (L[w] == kUnvisited) {
-            L[w] = nxt;
-            ++found;
+        const int64_t e = rows[i + 1];
+        for (int64_t k0 = rows[i] + ln; k0 < e; k0 += static_cast<int64_t>(kWave) * kRowLoads) {
+          int32_t w[kRowLoads];
+#pragma unroll
+          for (int u = 0; u < kRowLoads; ++u) {
+            const int64_t k = k0 + static_cast<int64_t>(u) * kWave;
+            w[u] = k < e ? cols[k] : -1;
           }
+#pragma unroll
+          for (int u = 0; u < kRowLoads; ++u)
+            if (w[u] >= 0 && L[w[u]] == kUnvisited) {
+              L[w[u]] = nxt;
+              ++found;
+            }
         }
       }
     }
