@@ -298,6 +298,20 @@ __global__ void copy_words_kernel(const uint32_t* src, uint32_t* dst, int64_t wo
     dst[i] = src[i];
 }
 
+// Clears the state of a BFS in one launch: levels to -1, the visited and
+// frontier bitmaps, the root key and the step kernels' partials.
+__global__ void clear_state_kernel(int32_t* L, int64_t n, uint32_t* vis, int64_t words, uint32_t* bms,
+                                   unsigned long long* key, int64_t* part, int64_t nparts) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n || i < 3 * words || i < nparts;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < n) L[i] = -1;
+    if (i < words) vis[i] = 0u;
+    if (i < 3 * words) bms[i] = 0u;
+    if (i < nparts) part[i] = 0;
+    if (i == 0) *key = 0ull;
+  }
+}
+
 // Starts the BFS from one root (either the argmax key or a given root).
 // The partials must be zero beforehand.
 __global__ void start_kernel(const int64_t* off, const unsigned long long* key, int64_t given_root, int32_t* L,
@@ -498,16 +512,15 @@ int bfs_run(const tc_csr* g, int64_t root, int32_t* L, int32_t* num_levels, BfsW
   const int64_t words = (n + 31) / 32 + 1;
   BfsState* st = reinterpret_cast<BfsState*>(w.st);
   const unsigned gs = step_grid(g->n);
-  TC_TRY(fill_i32(L, -1, n, s));
-  TC_TRY(fill_i32(reinterpret_cast<int32_t*>(w.vis), 0, words, s));
-  TC_TRY(fill_i32(reinterpret_cast<int32_t*>(w.bms), 0, 3 * words, s));
+  const int64_t clear = n > 3 * words ? n : 3 * words;
+  clear_state_kernel<<<grid_for(clear, kThreads, 16384), kThreads, 0, s>>>(L, n, w.vis, words, w.bms, w.key,
+                                                                         w.part, 4 * static_cast<int64_t>(gs));
+  TC_HIP(hipGetLastError());
   if (root < 0) {
-    TC_TRY(fill_i64(reinterpret_cast<int64_t*>(w.key), 0, 1, s));
     root_key_kernel<<<grid_for(n, kThreads, static_cast<unsigned>(num_cus() * 2)), kThreads, 0, s>>>(
         g->row_offsets, n, w.key);
     TC_HIP(hipGetLastError());
   }
-  TC_TRY(fill_i64(w.part, 0, 4 * static_cast<int64_t>(gs), s));
   start_kernel<<<1, 1, 0, s>>>(g->row_offsets, w.key, root, L, w.vis, w.bms, w.part, w.root);
   init_state_kernel<<<1, kThreads, 0, s>>>(n, st, w.part, static_cast<int>(2 * gs), g->nnz);
   TC_HIP(hipGetLastError());
